@@ -1,0 +1,182 @@
+"""Seeded synthetic inputs shaped like the paper's workloads.
+
+This module only draws inputs (wavenumber fields, point sources, receiver
+positions, problem sizes).  It holds none of the method's arithmetic and is
+shared by the GPU path's tests/benchmark and by the CPU oracle's tests.
+
+Shapes follow the paper's constant-k model (Sec. 4.1: unit square, centre
+point source, absorbing layer) extended with a smooth heterogeneous medium:
+
+* ``grf``: a zero-mean Gaussian random field with Gaussian covariance
+  exp(-r^2 / (2 ell^2)), made by filtering seeded white noise in Fourier space
+  on a zero-padded periodic grid of 2(n+1) points per axis, cropped to the
+  n^d interior nodes, scaled to unit sample standard deviation.
+* ``heterogeneous_k2``: k = k0 (1 + amp g), g = clip(grf, -1, 1),
+  k0 chosen so that max(k) h equals a target kh (0.625: ten points per
+  wavelength, Sec. 4.1).  Returns k^2 (the operator takes k^2).
+* point sources at seeded uniform interior nodes inside the physical region;
+  unit value, no 1/h^d scaling (Sec. 4.1).
+
+Arrays are NumPy float64 / complex128 shaped (n_z, n_y, n_x) or (n_y, n_x),
+i.e. x fastest.
+"""
+
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass
+
+import numpy as np
+
+
+def grf(n: int, dim: int, ell: float, seed: int) -> np.ndarray:
+    """Unit-variance Gaussian random field on the n^dim interior nodes of the
+    unit cube, correlation length ell (Gaussian covariance)."""
+    rng = np.random.default_rng(seed)
+    h = 1.0 / (n + 1)
+    m = 2 * (n + 1)
+    noise = rng.standard_normal((m,) * dim)
+    freqs = np.fft.fftfreq(m, d=h)
+    grids = np.meshgrid(*([freqs] * dim), indexing="ij")
+    xi2 = sum(g * g for g in grids)
+    # the spectral density of exp(-r^2/(2 ell^2)) is proportional to
+    # exp(-2 pi^2 ell^2 |xi|^2); filter with its square root
+    filt = np.exp(-math.pi ** 2 * ell ** 2 * xi2)
+    field = np.real(np.fft.ifftn(np.fft.fftn(noise) * filt))
+    crop = field[(slice(0, n),) * dim]
+    crop = crop - crop.mean()
+    return crop / crop.std()
+
+
+def heterogeneous_k2(n: int, dim: int, seed: int, amp: float = 0.3,
+                     ell: float = 0.1, kh_max: float = 0.625) -> np.ndarray:
+    """k^2 of k = k0 (1 + amp clip(grf, -1, 1)) with max(k) h = kh_max."""
+    h = 1.0 / (n + 1)
+    g = np.clip(grf(n, dim, ell, seed), -1.0, 1.0)
+    shape = 1.0 + amp * g
+    k0 = kh_max / (h * shape.max())
+    return (k0 * shape) ** 2
+
+
+def perturbed_k2(k2: np.ndarray, seed: int, amp: float = 0.05,
+                 ell: float = 0.1) -> np.ndarray:
+    """k_true = k (1 + amp g2), g2 an independent field (adjoint workload)."""
+    n = k2.shape[-1]
+    g2 = np.clip(grf(n, k2.ndim, ell, seed), -1.0, 1.0)
+    return k2 * (1.0 + amp * g2) ** 2
+
+
+def constant_k2(n: int, dim: int, k: float) -> np.ndarray:
+    return np.full((n,) * dim, float(k) ** 2)
+
+
+def source_nodes(n: int, dim: int, count: int, seed: int, lo: int, hi: int,
+                 max_y: int | None = None) -> np.ndarray:
+    """``count`` distinct interior nodes, each coordinate uniform in [lo, hi].
+
+    Rows are (i_x, i_y[, i_z]).  ``max_y`` optionally bounds i_y from above.
+    """
+    rng = np.random.default_rng(seed)
+    out, seen = [], set()
+    while len(out) < count:
+        p = tuple(int(v) for v in rng.integers(lo, hi + 1, size=dim))
+        if max_y is not None and p[1] > max_y:
+            continue
+        if p not in seen:
+            seen.add(p)
+            out.append(p)
+    return np.array(out, dtype=np.int64)
+
+
+def point_sources(n, nodes) -> np.ndarray:
+    """Stack of unit point-source right-hand sides, shape (count, *grid)."""
+    n = tuple(n)                          # x first
+    dim = len(n)
+    shape = tuple(reversed(n))            # array order: slowest first
+    f = np.zeros((len(nodes),) + shape, dtype=np.complex128)
+    for s, p in enumerate(nodes):
+        f[(s,) + tuple(reversed(tuple(int(v) for v in p[:dim])))] = 1.0
+    return f
+
+
+def centre_source(n) -> np.ndarray:
+    """Unit source at the centre node (n-1)/2 of every axis (Sec. 4.1)."""
+    n = tuple(n)
+    return point_sources(n, [tuple((m - 1) // 2 for m in n)])[0]
+
+
+def receiver_nodes(n: int, count: int = 128, row: int = 460) -> np.ndarray:
+    """Nodes on the line i_y = row nearest x = 1/32 + (r + 1/2) (15/16) / count."""
+    h = 1.0 / (n + 1)
+    xs = 1.0 / 32 + (np.arange(count) + 0.5) * (15.0 / 16.0) / count
+    ix = np.rint(xs / h).astype(np.int64) - 1          # interior index of node
+    return np.stack([ix, np.full(count, row, dtype=np.int64)], axis=1)
+
+
+# ---------------------------------------------------------------------------
+# Named workloads
+# ---------------------------------------------------------------------------
+
+@dataclass
+class Workload:
+    name: str
+    n: tuple              # interior points per axis, x first
+    k2: np.ndarray        # shaped like the grid, slowest axis first
+    f: np.ndarray         # (nrhs, *grid) complex128
+    ecs: int              # complex-scaled cells on every side (0 = Dirichlet)
+    ecs_angle: float = math.pi / 4
+    theta_max: float = math.pi / 6
+
+    @property
+    def h(self):
+        return tuple(1.0 / (m + 1) for m in self.n)
+
+    @property
+    def dofs(self) -> int:
+        return int(np.prod(self.n)) * self.f.shape[0]
+
+
+def dirichlet_constant_2d(n: int = 63, k: float = 40.0) -> Workload:
+    """Constant k, homogeneous Dirichlet, centre source (63^2, k = 40)."""
+    return Workload("dirichlet_const_2d_%d" % n, (n, n), constant_k2(n, 2, k),
+                    centre_source((n, n))[None], ecs=0)
+
+
+def heterogeneous_2d(n: int = 1023, nrhs: int = 8, ecs: int | None = None,
+                     field_seed: int = 2, source_seed: int = 3) -> Workload:
+    """GRF medium (+-30 %, ell = 0.1, max kh = 0.625), ECS layer of
+    (n+1)/32 cells, ``nrhs`` unit sources in the physical region."""
+    if ecs is None:
+        ecs = (n + 1) // 32
+    k2 = heterogeneous_k2(n, 2, field_seed)
+    nodes = source_nodes(n, 2, nrhs, source_seed, ecs, n - 1 - ecs)
+    return Workload("grf_2d_%d_x%d" % (n, nrhs), (n, n), k2,
+                    point_sources((n, n), nodes), ecs=ecs)
+
+
+def constant_3d(n: int = 255, kh: float = 0.5, ecs: int = 16) -> Workload:
+    """Constant k with k h = kh, 7-point, ECS layer, centre source."""
+    k = kh * (n + 1)
+    return Workload("const_3d_%d" % n, (n, n, n), constant_k2(n, 3, k),
+                    centre_source((n, n, n))[None], ecs=ecs)
+
+
+def constant_2d(n: int, kh: float, ecs: int | None = None) -> Workload:
+    if ecs is None:
+        ecs = (n + 1) // 32
+    k = kh * (n + 1)
+    return Workload("const_2d_%d" % n, (n, n), constant_k2(n, 2, k),
+                    centre_source((n, n))[None], ecs=ecs)
+
+
+UNEVEN_SIZES = sorted({m * 2 ** q - 1 for m in (4, 5, 6, 7) for q in range(3, 9)
+                       if 127 <= m * 2 ** q - 1 <= 1023})
+
+
+def uneven_batch(count: int = 24, seed: int = 5):
+    """Sizes drawn with replacement from {m 2^q - 1 in [127, 1023], m = 4..7}
+    and a constant kh ~ U[0.3, 0.625] each; centre source; ECS (n+1)/32."""
+    rng = np.random.default_rng(seed)
+    sizes = rng.choice(UNEVEN_SIZES, size=count, replace=True)
+    khs = rng.uniform(0.3, 0.625, size=count)
+    return [constant_2d(int(n), float(kh)) for n, kh in zip(sizes, khs)]
