@@ -1,0 +1,189 @@
+/*
+ * mg.h -- C ABI of the MI355X (gfx950) level-dependent complex-shifted
+ * multigrid solver for the indefinite Helmholtz equation
+ *
+ *     (-Delta^h - k^2) u = f                                   (Sec. 2, eq. HH)
+ *
+ * after S. Cools, B. Reps, W. Vanroose, "A new level-dependent coarse grid
+ * correction scheme for indefinite Helmholtz problems" (NLAA 2013).
+ *
+ * Method.  Level l (0 = finest, h_l = 2^l h_0) is rediscretised as
+ *     A~_l = -Delta^{h_l} - sigma_l k_l^2,   sigma_0 = 1       (Sec. 3.1, eq. cslvariant)
+ * with sigma_l = exp(i l theta_max / L) by default (Sec. 3.1: d-theta =
+ * theta_max / p, p the number of levels).  One V(1,1) cycle is:
+ * omega-Jacobi pre-smoothing (Sec. 3.2.1, eq. wjacobi), residual, full
+ * weighting to the next level, recursion with a zero initial guess, a dense
+ * direct solve on the coarsest level, (bi/tri)linear interpolation of the
+ * correction (Sec. 2.1), omega-Jacobi post-smoothing.  The cycle is used as a
+ * solver (Sec. 4.1 "LVL-MG") or as the preconditioner of restarted GMRES,
+ * one cycle per outer step (Sec. 4.1, Table 3).
+ *
+ * Discretisation.  Vertex-centred grid of n[a] interior points per axis with
+ * homogeneous Dirichlet ghosts; optional exterior-complex-scaled (ECS)
+ * absorbing layers of ecs_lo[a] / ecs_hi[a] cells (Sec. 2.4): node x is
+ * mapped to a + (x - a) e^{i phi} left of the layer start a (and likewise on
+ * the right), and -d^2/dz^2 is discretised by the 3-point formula on the
+ * mapped nodes.  Coarse levels sample k^2 at their own nodes.
+ *
+ * Layout of every grid vector at this ABI: interleaved complex double
+ * (re, im), x fastest, then y, then z, then the right-hand side index:
+ *     v[2 * (i_x + n_x (i_y + n_y (i_z + n_z r))) + {0,1}]
+ * interior points only.  Real fields (k^2, gradients) use the same order
+ * without the (re, im) pair and without the right-hand side index.
+ *
+ * Memory and streams.  Pointers named *_dev are device pointers on the
+ * current HIP device; pointers without the suffix are host memory.  Every
+ * call is stream-ordered on the stream given to mg_setup; calls that return
+ * host values (iteration counts, histories, res_before) synchronise that
+ * stream before returning.  The caller owns all vectors it passes; the
+ * context owns the hierarchy and all work space.  Use one context per stream
+ * and per host thread.  No exception or abort crosses this ABI; failures are
+ * reported by the returned status.
+ */
+#ifndef MG_H
+#define MG_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum mg_status {
+    MG_OK = 0,
+    MG_NOT_CONVERGED = 1,   /* maxit reached; outputs hold the last iterate */
+    MG_E_INVAL = -1,        /* invalid argument or dimensions               */
+    MG_E_NOMEM = -2,        /* device or host allocation failed             */
+    MG_E_DEVICE = -3,       /* a HIP runtime call failed                    */
+    MG_E_DIVERGED = -4,     /* residual ratio above 1e8 or not finite       */
+    MG_E_STATE = -5         /* call not valid for this context              */
+} mg_status;
+
+enum mg_precision {
+    MG_PREC_C128 = 0,       /* every step in complex double                 */
+    MG_PREC_MIXED = 1       /* cycle in complex float, coarsest solve, outer
+                               residual / correction / GMRES in double       */
+};
+
+enum mg_mode {
+    MG_MODE_STANDALONE = 0, /* repeated V-cycles (Sec. 4.1, LVL-MG)          */
+    MG_MODE_GMRES = 1       /* restarted GMRES(restart), right-preconditioned
+                               by one V-cycle from a zero guess per step     */
+};
+
+typedef struct mg_params {
+    int ndim;               /* 2 or 3                                        */
+    int n[3];               /* interior points per axis, x first; each axis
+                               must be odd on every level except the last    */
+    double h[3];            /* grid spacing per axis                         */
+    int nlevels;            /* 0 = automatic: coarsen while every axis is odd
+                               and the next size is >= 2                     */
+    int ecs_lo[3];          /* ECS cells at the low end of each axis         */
+    int ecs_hi[3];          /* ECS cells at the high end of each axis        */
+    double ecs_angle;       /* rotation phi of the ECS contour (radians)     */
+    const double *sigma;    /* host, 2 * nlevels doubles (re, im) of sigma_l,
+                               sigma[0] must be 1; NULL = default schedule   */
+    double theta_max;       /* default schedule sigma_l = exp(i l theta_max/L) */
+    int nu1, nu2;           /* smoothing sweeps; this build supports 1, 1    */
+    double omega[2];        /* complex Jacobi weight (re, im)                */
+    int precision;          /* enum mg_precision                             */
+    int nrhs;               /* right-hand sides handled by every call (>= 1) */
+} mg_params;
+
+typedef struct mg_ctx mg_ctx;
+
+/* Fill *p with the defaults of the paper's setting: V(1,1), omega = 2/3,
+ * theta_max = pi/6, phi = pi/4, no ECS, automatic levels, C128, one rhs. */
+void mg_params_default(mg_params *p);
+
+/* Build the level hierarchy (Sec. 3.1): per-level spacing, ECS coefficients
+ * of the forward and conjugate-transposed operators, sigma_l, k^2 sampled on
+ * every level, and the LU factors of the coarsest operator and of its
+ * conjugate transpose.  k2_dev: n_x n_y n_z doubles on the device, copied
+ * (the caller may free it after the call returns).  stream: a hipStream_t
+ * (NULL = the null stream).  Errors: MG_E_INVAL for inconsistent dimensions,
+ * sigma[0] != 1, unsupported nu1/nu2, nrhs < 1 or a coarsest level above
+ * 4096 unknowns; MG_E_NOMEM; MG_E_DEVICE.  *out is NULL on error. */
+mg_status mg_setup(const mg_params *p, const double *k2_dev, void *stream,
+                   mg_ctx **out);
+
+/* One V(nu1, nu2) cycle for all nrhs right-hand sides, in place on u_dev
+ * (A~_0 u = f).  res_before: NULL or host array of nrhs doubles receiving
+ * ||f - A u|| of the incoming u (unscaled 2-norm), computed inside the
+ * cycle; when non-NULL the call synchronises. */
+mg_status mg_cycle(mg_ctx *c, double *u_dev, const double *f_dev,
+                   double *res_before);
+
+/* Solve A u = f for all right-hand sides to ||f - A u|| / ||f|| <= rtol.
+ * u_dev holds the initial guess on entry (zeros for a cold start) and the
+ * result on exit.  mode: enum mg_mode.  maxit counts V-cycles (standalone)
+ * or outer GMRES steps; restart is the GMRES(m) restart length (1..64,
+ * ignored in standalone mode).  iters: NULL or host int[nrhs] receiving the
+ * count per rhs.  hist: NULL or host double[nrhs * (maxit + 1)] receiving
+ * per rhs the relative residual history (standalone: the ratio of the iterate
+ * entering each cycle; GMRES: the initial ratio then the estimate after each
+ * step), unused tail entries set to -1.  Standalone mode stops after the
+ * first cycle whose incoming iterate met rtol.  Returns MG_OK when every rhs
+ * converged, MG_NOT_CONVERGED when one reached maxit, MG_E_DIVERGED when
+ * one diverged (others still hold their last iterate). */
+mg_status mg_solve(mg_ctx *c, double *u_dev, const double *f_dev, int mode,
+                   double rtol, int maxit, int restart, int *iters,
+                   double *hist);
+
+/* Same as mg_solve for the adjoint system A^H lambda = g (extension, not in
+ * the paper): the identical cycle on the conjugate-transposed hierarchy
+ * {A~_l^H} (shifts conj(sigma_l)). */
+mg_status mg_solve_adjoint(mg_ctx *c, double *lam_dev, const double *g_dev,
+                           int mode, double rtol, int maxit, int restart,
+                           int *iters, double *hist);
+
+/* grad_dev[i] += sum_r Re(conj(lam_r[i]) u_r[i]): the gradient of a real loss
+ * with respect to k^2 when lam = A^{-H} dL/d(conj u) (extension).  grad_dev is
+ * a real field of n_x n_y n_z doubles. */
+mg_status mg_grad_k2(mg_ctx *c, const double *u_dev, const double *lam_dev,
+                     double *grad_dev);
+
+/* y = A~_l x (adjoint != 0: A~_l^H x) for all right-hand sides on level l,
+ * vectors laid out like the ABI vectors with level-l sizes (mg_level_dims).
+ * The level operator of Sec. 3.1; exposed for parity tests. */
+mg_status mg_apply(mg_ctx *c, int level, int adjoint, const double *x_dev,
+                   double *y_dev);
+
+/* Number of levels and the interior sizes of one level (n[3], x first). */
+int mg_num_levels(const mg_ctx *c);
+mg_status mg_level_dims(const mg_ctx *c, int level, int n[3]);
+/* Copy the per-level shifts into host sigma[2 * nlevels]. */
+mg_status mg_get_sigma(const mg_ctx *c, double *sigma);
+
+/* Kernel timing with HIP events on the context's stream.  enable != 0 starts
+ * recording (and clears earlier records); mg_profile_read returns the summed
+ * milliseconds and the launch count of kernel class `which`
+ * (enum mg_kernel_class) since then, synchronising the stream. */
+enum mg_kernel_class {
+    MG_K_SMOOTH_RESTRICT_FINE = 0,  /* pre-smooth + residual + restriction, level 0 */
+    MG_K_PROLONG_SMOOTH_FINE = 1,   /* prolongation + correction + post-smooth, level 0 */
+    MG_K_COARSE_LEVELS = 2,         /* the same two kernels on levels >= 1 */
+    MG_K_COARSEST_SOLVE = 3,
+    MG_K_RESIDUAL = 4,
+    MG_K_MATVEC_DOT = 5,            /* GMRES: w = A z fused with <v_i, w> */
+    MG_K_UPDATE_DOT = 6,            /* GMRES: w -= V h fused with <v_i, w> */
+    MG_K_UPDATE_NORM = 7,           /* GMRES: w -= V h fused with ||w|| */
+    MG_K_REDUCE = 8,
+    MG_K_COMBINE = 9,               /* GMRES: t = V y */
+    MG_K_OTHER = 10,
+    MG_K_NUM_CLASSES = 11
+};
+mg_status mg_profile(mg_ctx *c, int enable);
+mg_status mg_profile_read(mg_ctx *c, int which, double *total_ms,
+                          long long *count);
+
+/* Release everything the context owns.  NULL is accepted; calling it twice
+ * on the same pointer is not. */
+void mg_destroy(mg_ctx *c);
+
+/* Static description of a status code. */
+const char *mg_status_str(mg_status s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MG_H */

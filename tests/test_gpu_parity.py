@@ -1,0 +1,333 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Bars: operator application 1e-12 relative; one V-cycle 1e-11 relative;
+residual histories 1e-8 relative (standalone until the ratio passes 1e3);
+converged solutions 1e-10 relative L2 (FP64).  Mixed precision: the final
+error against the FP64 oracle solution at most 1e-6 relative.  Sizes span
+several tiles with ragged tails (tiles are 64 x 16 in 2D, 16 x 8 x 4 in 3D).
+"""
+
+import math
+
+import numpy as np
+import pytest
+
+from oracle import adjoint as AD
+from oracle import cycle as C
+from oracle import helmholtz as H
+from oracle import krylov as K
+from paper_1211_4752_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+def _mg():
+    from paper_1211_4752_amd import mg
+    mg.lib()          # fail loudly if the library is missing
+    return mg
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def problem_of(wl):
+    d = len(wl.n)
+    return H.Problem(wl.n, wl.h, wl.k2, (wl.ecs,) * d, (wl.ecs,) * d, wl.ecs_angle)
+
+
+def solver_of(wl, nrhs=None, **kw):
+    mg = _mg()
+    dev = _dev()
+    k2 = torch.tensor(wl.k2, dtype=torch.float64, device=dev)
+    return mg.Solver(wl.n, wl.h, k2, ecs=wl.ecs, ecs_angle=wl.ecs_angle, theta_max=wl.theta_max,
+                     nrhs=nrhs or wl.f.shape[0], **kw)
+
+
+def gpu(a):
+    return torch.tensor(np.ascontiguousarray(a), dtype=torch.complex128, device=_dev())
+
+
+def rnd(shape, seed):
+    rng = np.random.default_rng(seed)
+    return rng.standard_normal(shape) + 1j * rng.standard_normal(shape)
+
+
+CASES = {
+    "dirichlet_63": lambda: W.dirichlet_constant_2d(63, 40.0),
+    "grf_127_ecs4": lambda: W.heterogeneous_2d(127, 2, ecs=4),
+    "grf_159_ecs5": lambda: W.heterogeneous_2d(159, 1, ecs=5),     # uneven: coarsest 4 x 4
+    "const3d_31": lambda: W.constant_3d(31, 0.5, 2),
+    "const3d_47": lambda: W.constant_3d(47, 0.5, 3),                # coarsest 5^3
+}
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_apply_every_level(name):
+    say("case", name)
+    wl = CASES[name]()
+    s = solver_of(wl)
+    levels = H.build_hierarchy(problem_of(wl))
+    assert s.num_levels == len(levels)
+    np.testing.assert_allclose(s.sigma(), [lv.sigma for lv in levels], atol=1e-15)
+    nrhs = s.nrhs
+    for l, lv in enumerate(levels):
+        x = rnd((nrhs,) + tuple(reversed(lv.n)), 10 + l)
+        for adj in (False, True):
+            y = s.apply(gpu(x), level=l, adjoint=adj).cpu().numpy().reshape(nrhs, -1)
+            A = lv.A.conj().T if adj else lv.A
+            want = np.stack([A @ x[r].ravel() for r in range(nrhs)])
+            err = np.abs(y - want).max() / np.abs(want).max()
+            assert err < 1e-12, (l, adj, err)
+    s.close()
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_one_cycle(name):
+    say("case", name)
+    wl = CASES[name]()
+    s = solver_of(wl)
+    levels = H.build_hierarchy(problem_of(wl))
+    vc = C.VCycle(levels)
+    shape = (s.nrhs,) + tuple(reversed(wl.n))
+    u0, f = rnd(shape, 1), rnd(shape, 2)
+    u = gpu(u0)
+    res = s.cycle(u, gpu(f), residual=True)
+    got = u.cpu().numpy()
+    for r in range(s.nrhs):
+        want = vc(u0[r].ravel(), f[r].ravel())
+        err = np.abs(got[r].ravel() - want).max() / np.abs(want).max()
+        assert err < 1e-11, err
+        rw = np.linalg.norm(f[r].ravel() - levels[0].A @ u0[r].ravel())
+        assert res[r] == pytest.approx(rw, rel=1e-11)
+    s.close()
+
+
+def test_cycle_is_deterministic():
+    wl = CASES["grf_127_ecs4"]()
+    s = solver_of(wl)
+    shape = (s.nrhs,) + tuple(reversed(wl.n))
+    f = gpu(rnd(shape, 3))
+    outs = []
+    for _ in range(2):
+        u = gpu(rnd(shape, 4))
+        s.solve(u, f, mode="gmres", rtol=1e-9, maxit=60, restart=20)
+        outs.append(u.cpu().numpy())
+    assert np.array_equal(outs[0], outs[1])
+    s.close()
+
+
+def _compare_hist(got, want, tol=1e-8, stop=None):
+    m = min(len(got), len(want))
+    if stop is not None:
+        above = np.nonzero(np.asarray(want[:m]) > stop)[0]
+        if len(above):
+            m = min(m, above[0] + 1)
+    g, w = np.asarray(got[:m]), np.asarray(want[:m])
+    rel = np.abs(g - w) / np.maximum(np.abs(w), 1e-300)
+    assert rel.max() < tol, (rel.max(), int(rel.argmax()), m)
+    return m
+
+
+@pytest.mark.parametrize("name,maxit", [("dirichlet_63", 60), ("grf_127_ecs4", 60), ("const3d_31", 40)])
+def test_standalone_history(name, maxit):
+    say("case", name)
+    wl = CASES[name]()
+    s = solver_of(wl)
+    levels = H.build_hierarchy(problem_of(wl))
+    vc = C.VCycle(levels)
+    u = s.empty()
+    status, its, hists = s.solve(u, gpu(wl.f), mode="standalone", rtol=1e-6, maxit=maxit)
+    for r in range(s.nrhs):
+        uo, hist, it, st = C.standalone(vc, wl.f[r].ravel(), rtol=1e-6, maxit=maxit)
+        say(name, r, "standalone", st, it, "gpu", status, its[r])
+        _compare_hist(hists[r], hist, 1e-8, stop=1e3)
+        if st == "diverged":
+            assert status == "diverged"
+        else:
+            assert its[r] == it
+            if hist[-1] < 1e3:
+                err = np.linalg.norm(u[r].cpu().numpy().ravel() - uo) / np.linalg.norm(uo)
+                assert err < 1e-10, err
+    s.close()
+
+
+@pytest.mark.parametrize("name,rtol,maxit", [
+    ("grf_127_ecs4", 1e-6, 3000), ("grf_159_ecs5", 1e-6, 3000), ("const3d_31", 1e-8, 500),
+    ("const3d_47", 1e-6, 500)])
+def test_gmres_history_and_solution(name, rtol, maxit):
+    say("case", name)
+    wl = CASES[name]()
+    s = solver_of(wl)
+    levels = H.build_hierarchy(problem_of(wl))
+    vc = C.VCycle(levels)
+    u = s.empty()
+    status, its, hists = s.solve(u, gpu(wl.f), mode="gmres", rtol=rtol, maxit=maxit, restart=20)
+    got = u.cpu().numpy()
+    for r in range(s.nrhs):
+        x, hist, it, st = K.gmres(levels[0].A, vc.precondition, wl.f[r].ravel(), rtol=rtol, restart=20,
+                                  maxit=maxit)
+        say(name, r, "gmres", st, it, "gpu", status, its[r])
+        assert st == "converged" and status == "converged"
+        assert its[r] == it
+        _compare_hist(hists[r], hist, 1e-8)
+        err = np.linalg.norm(got[r].ravel() - x) / np.linalg.norm(x)
+        assert err < 1e-10, err
+        true = np.linalg.norm(wl.f[r].ravel() - levels[0].A @ got[r].ravel()) / np.linalg.norm(wl.f[r])
+        assert true <= rtol * (1 + 1e-6)
+    s.close()
+
+
+def test_gmres_dirichlet_63():
+    """The Dirichlet constant-k case: the standalone cycle stagnates, the
+    preconditioned GMRES(20) converges (Sec. 3.1.2 notes Dirichlet is the
+    hard case)."""
+    wl = CASES["dirichlet_63"]()
+    s = solver_of(wl)
+    levels = H.build_hierarchy(problem_of(wl))
+    vc = C.VCycle(levels)
+    u = s.empty()
+    status, its, hists = s.solve(u, gpu(wl.f), mode="gmres", rtol=1e-6, maxit=8000, restart=20)
+    x, hist, it, st = K.gmres(levels[0].A, vc.precondition, wl.f[0].ravel(), rtol=1e-6, restart=20, maxit=8000)
+    say("dirichlet gmres", st, it, "gpu", status, its[0])
+    assert status == st == "converged"
+    assert abs(its[0] - it) <= max(2, it // 100)
+    true = np.linalg.norm(wl.f[0].ravel() - levels[0].A @ u[0].cpu().numpy().ravel())
+    assert true / np.linalg.norm(wl.f[0]) <= 1e-6 * (1 + 1e-6)
+    err = np.linalg.norm(u[0].cpu().numpy().ravel() - x) / np.linalg.norm(x)
+    assert err < 1e-6, err
+    s.close()
+
+
+def test_adjoint_and_gradient():
+    wl = W.heterogeneous_2d(127, 3, ecs=4)
+    s = solver_of(wl)
+    levels = H.build_hierarchy(problem_of(wl))
+    vca = C.VCycle(levels, adjoint=True)
+    AH = levels[0].A.conj().T.tocsr()
+    g = rnd(wl.f.shape, 7)
+    lam = s.empty()
+    status, its, hists = s.solve_adjoint(lam, gpu(g), mode="gmres", rtol=1e-10, maxit=3000, restart=20)
+    assert status == "converged"
+    lam_h = lam.cpu().numpy()
+    for r in range(3):
+        x, hist, it, st = K.gmres(AH, vca.precondition, g[r].ravel(), rtol=1e-10, restart=20, maxit=3000)
+        assert its[r] == it
+        _compare_hist(hists[r], hist, 1e-8)
+        assert np.linalg.norm(lam_h[r].ravel() - x) / np.linalg.norm(x) < 1e-10
+    u = gpu(rnd(wl.f.shape, 8))
+    grad = torch.zeros(wl.k2.shape, dtype=torch.float64, device=_dev())
+    s.grad_k2(u, lam, grad)
+    want = AD.grad_k2([u[r].cpu().numpy().ravel() for r in range(3)], [lam_h[r].ravel() for r in range(3)])
+    np.testing.assert_allclose(grad.cpu().numpy().ravel(), want, rtol=1e-13, atol=1e-13 * np.abs(want).max())
+    s.close()
+
+
+def test_mixed_precision_error_bound():
+    wl = W.heterogeneous_2d(127, 2, ecs=4)
+    s = solver_of(wl, precision="mixed")
+    levels = H.build_hierarchy(problem_of(wl))
+    vc = C.VCycle(levels)
+    u = s.empty()
+    status, its, hists = s.solve(u, gpu(wl.f), mode="gmres", rtol=1e-10, maxit=4000, restart=20)
+    assert status == "converged"
+    got = u.cpu().numpy()
+    vc32 = C.VCycle(levels, dtype=np.complex64)
+    for r in range(2):
+        x, hist, it, st = K.gmres(levels[0].A, vc.precondition, wl.f[r].ravel(), rtol=1e-12, restart=20,
+                                  maxit=6000)
+        err = np.linalg.norm(got[r].ravel() - x) / np.linalg.norm(x)
+        say("mixed", r, its[r], "error vs fp64 oracle", err)
+        assert err <= 1e-6
+        # the inner complex64 cycle follows the oracle's complex64 cycle
+        x32, h32, it32, _ = K.gmres(levels[0].A, lambda v: vc32.precondition(v).astype(np.complex128),
+                                    wl.f[r].ravel(), rtol=1e-10, restart=20, maxit=4000)
+        _compare_hist(hists[r][:30], h32[:30], 1e-3)
+    # standalone refinement form on a case where the cycle converges
+    wl2 = W.constant_2d(127, 0.3, ecs=16)
+    s2 = solver_of(wl2, precision="mixed")
+    lv2 = H.build_hierarchy(problem_of(wl2))
+    u = s2.empty()
+    st2, its2, h2 = s2.solve(u, gpu(wl2.f), mode="standalone", rtol=1e-6, maxit=400)
+    uo, ho, ito, sto = C.standalone(C.VCycle(lv2), wl2.f[0].ravel(), rtol=1e-6, maxit=400)
+    say("mixed standalone", st2, its2, sto, ito)
+    _compare_hist(h2[0][:50], ho[:50], 1e-3)
+    s.close()
+    s2.close()
+
+
+def test_edge_cases():
+    mg = _mg()
+    # smallest hierarchy: 7 -> 3 (two levels), zero right-hand side in slot 1
+    wl = W.constant_2d(7, 0.5, ecs=1)
+    s = solver_of(wl, nrhs=2)
+    f = np.concatenate([wl.f, np.zeros_like(wl.f)])
+    u = gpu(rnd(f.shape, 5))
+    status, its, hists = s.solve(u, gpu(f), mode="gmres", rtol=1e-10, maxit=100, restart=5)
+    assert status == "converged"
+    assert np.abs(u[1].cpu().numpy()).max() == 0.0 and hists[1][0] == 0.0
+    A = H.build_hierarchy(problem_of(wl))[0].A
+    assert np.linalg.norm(wl.f[0].ravel() - A @ u[0].cpu().numpy().ravel()) <= 1e-10 * (1 + 1e-6)
+    s.close()
+    # maxit reached
+    wl = CASES["grf_127_ecs4"]()
+    s = solver_of(wl)
+    u = s.empty()
+    status, its, hists = s.solve(u, gpu(wl.f), mode="gmres", rtol=1e-12, maxit=7, restart=3)
+    assert status == "not_converged" and its == [7, 7] and len(hists[0]) == 8
+    with pytest.raises(ValueError):
+        s.solve(u[:1], gpu(wl.f))
+    with pytest.raises(mg.MGError):
+        s.solve(u, gpu(wl.f), mode="gmres", restart=40)
+    s.close()
+
+
+def test_many_rhs_two_launch_groups():
+    """40 right-hand sides run as two launch groups (at most 32 per launch)."""
+    n = 31
+    wl = W.heterogeneous_2d(n, 40, ecs=2)
+    s = solver_of(wl)
+    levels = H.build_hierarchy(problem_of(wl))
+    vc = C.VCycle(levels)
+    u = s.empty()
+    status, its, hists = s.solve(u, gpu(wl.f), mode="gmres", rtol=1e-8, maxit=500, restart=20)
+    got = u.cpu().numpy()
+    for r in (0, 17, 31, 32, 39):
+        x, hist, it, st = K.gmres(levels[0].A, vc.precondition, wl.f[r].ravel(), rtol=1e-8, restart=20,
+                                  maxit=500)
+        assert its[r] == it
+        _compare_hist(hists[r], hist, 1e-8)
+        assert np.linalg.norm(got[r].ravel() - x) / np.linalg.norm(x) < 1e-10
+    s.close()
+
+
+def test_full_size_cycle_and_gmres_prefix():
+    """1023^2 heterogeneous medium, ECS 32, 8 sources (the benchmark
+    workload): one cycle compared in full and the first GMRES(20) steps."""
+    wl = W.heterogeneous_2d(1023, 8)
+    s = solver_of(wl)
+    levels = H.build_hierarchy(problem_of(wl))
+    vc = C.VCycle(levels)
+    shape = (8,) + tuple(reversed(wl.n))
+    u0 = rnd(shape, 9)
+    u = gpu(u0)
+    res = s.cycle(u, gpu(wl.f), residual=True)
+    got = u.cpu().numpy()
+    for r in (0, 7):
+        want = vc(u0[r].ravel(), wl.f[r].ravel())
+        err = np.abs(got[r].ravel() - want).max() / np.abs(want).max()
+        assert err < 1e-11, err
+        assert res[r] == pytest.approx(np.linalg.norm(wl.f[r].ravel() - levels[0].A @ u0[r].ravel()), rel=1e-11)
+    u = s.empty()
+    status, its, hists = s.solve(u, gpu(wl.f), mode="gmres", rtol=1e-6, maxit=12, restart=20)
+    x, hist, it, st = K.gmres(levels[0].A, vc.precondition, wl.f[3].ravel(), rtol=1e-6, restart=20, maxit=12)
+    _compare_hist(hists[3], hist, 1e-8)
+    s.close()
