@@ -101,7 +101,7 @@ void mg_params_default(mg_params *p);
  * (the caller may free it after the call returns).  stream: a hipStream_t
  * (NULL = the null stream).  Errors: MG_E_INVAL for inconsistent dimensions,
  * sigma[0] != 1, unsupported nu1/nu2, nrhs < 1 or a coarsest level above
- * 4096 unknowns; MG_E_NOMEM; MG_E_DEVICE.  *out is NULL on error. */
+ * 1024 unknowns; MG_E_NOMEM; MG_E_DEVICE.  *out is NULL on error. */
 mg_status mg_setup(const mg_params *p, const double *k2_dev, void *stream,
                    mg_ctx **out);
 
@@ -115,7 +115,7 @@ mg_status mg_cycle(mg_ctx *c, double *u_dev, const double *f_dev,
 /* Solve A u = f for all right-hand sides to ||f - A u|| / ||f|| <= rtol.
  * u_dev holds the initial guess on entry (zeros for a cold start) and the
  * result on exit.  mode: enum mg_mode.  maxit counts V-cycles (standalone)
- * or outer GMRES steps; restart is the GMRES(m) restart length (1..64,
+ * or outer GMRES steps; restart is the GMRES(m) restart length (1..32,
  * ignored in standalone mode).  iters: NULL or host int[nrhs] receiving the
  * count per rhs.  hist: NULL or host double[nrhs * (maxit + 1)] receiving
  * per rhs the relative residual history (standalone: the ratio of the iterate
@@ -155,8 +155,11 @@ mg_status mg_get_sigma(const mg_ctx *c, double *sigma);
 
 /* Kernel timing with HIP events on the context's stream.  enable != 0 starts
  * recording (and clears earlier records); mg_profile_read returns the summed
- * milliseconds and the launch count of kernel class `which`
- * (enum mg_kernel_class) since then, synchronising the stream. */
+ * milliseconds, the launch count and the summed algorithmic bytes (the
+ * compulsory HBM traffic of each launch: every array it must read once and
+ * write once, per grid point times points times right-hand sides) of kernel
+ * class `which` (enum mg_kernel_class) since then, synchronising the stream.
+ * Any of the three out-pointers may be NULL. */
 enum mg_kernel_class {
     MG_K_SMOOTH_RESTRICT_FINE = 0,  /* pre-smooth + residual + restriction, level 0 */
     MG_K_PROLONG_SMOOTH_FINE = 1,   /* prolongation + correction + post-smooth, level 0 */
@@ -173,7 +176,7 @@ enum mg_kernel_class {
 };
 mg_status mg_profile(mg_ctx *c, int enable);
 mg_status mg_profile_read(mg_ctx *c, int which, double *total_ms,
-                          long long *count);
+                          long long *count, double *bytes);
 
 /* Release everything the context owns.  NULL is accepted; calling it twice
  * on the same pointer is not. */

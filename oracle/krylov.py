@@ -21,6 +21,12 @@ Gram-Schmidt and complex Givens rotations, written out step by step:
       residual estimate |g[j+1]| / ||f||
   y = H[:j+1,:j+1]^{-1} g[:j+1],  x += M (V y)
 
+``ortho="cgs2"`` replaces the modified Gram-Schmidt loop by classical
+Gram-Schmidt applied twice (h1 = V^H w, w -= V h1, h2 = V^H w, w -= V h2,
+H[:, j] = h1 + h2); both are standard stable Arnoldi variants and serve to
+measure how far two correct FP64 evaluations of the same iteration drift
+apart.
+
 The history records ||f - A x0|| / ||f|| first, then the estimate after every
 outer step (one preconditioner application each).  When the estimate meets
 rtol the solution is updated and the true residual is checked; if it still
@@ -50,12 +56,14 @@ def givens(a: complex, b: complex):
     return c, s
 
 
-def gmres(A, M, f, x0=None, rtol=1e-6, restart=20, maxit=1000):
+def gmres(A, M, f, x0=None, rtol=1e-6, restart=20, maxit=1000, ortho="mgs"):
     """Right-preconditioned restarted GMRES(restart).
 
-    ``A`` is a sparse matrix, ``M`` a callable v -> M v returning complex128.
-    Returns (x, history, iterations, status).
+    ``A`` is a sparse matrix, ``M`` a callable v -> M v returning complex128,
+    ``ortho`` "mgs" or "cgs2".  Returns (x, history, iterations, status).
     """
+    if ortho not in ("mgs", "cgs2"):
+        raise ValueError(ortho)
     f = np.asarray(f, dtype=np.complex128)
     nf = np.linalg.norm(f)
     x = np.zeros_like(f) if x0 is None else np.array(x0, dtype=np.complex128)
@@ -81,9 +89,15 @@ def gmres(A, M, f, x0=None, rtol=1e-6, restart=20, maxit=1000):
         j_end = 0
         for j in range(m):
             w = A @ M(V[j])
-            for i in range(j + 1):
-                H[i, j] = np.vdot(V[i], w)
-                w = w - H[i, j] * V[i]
+            if ortho == "mgs":
+                for i in range(j + 1):
+                    H[i, j] = np.vdot(V[i], w)
+                    w = w - H[i, j] * V[i]
+            else:
+                for _ in range(2):
+                    h = V[:j + 1].conj() @ w
+                    w = w - V[:j + 1].T @ h
+                    H[:j + 1, j] += h
             H[j + 1, j] = np.linalg.norm(w)
             if H[j + 1, j] != 0:
                 V[j + 1] = w / H[j + 1, j]

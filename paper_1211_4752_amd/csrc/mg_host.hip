@@ -121,6 +121,7 @@ struct Prof {
     bool on = false;
     std::vector<hipEvent_t> pool;
     std::vector<int> cls;
+    std::vector<double> bytes;
     size_t used = 0;
 };
 
@@ -198,7 +199,8 @@ void hfree(P*& p) {
     p = nullptr;
 }
 
-int prof_begin(mg_ctx* c, int cls) {
+// bytes: algorithmic (compulsory) traffic of the launch
+int prof_begin(mg_ctx* c, int cls, double bytes = 0.0) {
     if (!c->prof.on) return -1;
     Prof& P = c->prof;
     while (P.pool.size() < 2 * (P.used + 1)) {
@@ -207,8 +209,12 @@ int prof_begin(mg_ctx* c, int cls) {
         P.pool.push_back(e);
     }
     const int idx = (int)P.used++;
-    if ((int)P.cls.size() <= idx) P.cls.resize(idx + 1);
+    if ((int)P.cls.size() <= idx) {
+        P.cls.resize(idx + 1);
+        P.bytes.resize(idx + 1);
+    }
     P.cls[idx] = cls;
+    P.bytes[idx] = bytes;
     (void)hipEventRecord(P.pool[2 * idx], c->stream);
     return idx;
 }
@@ -287,10 +293,17 @@ mg_status vcycle(mg_ctx* c, int dir, const SlotTable& st, const cx<double>* u0, 
     const int L = c->L;
     hipStream_t s = c->stream;
     if (c->mixed && u0) return MG_E_STATE;
+    // algorithmic bytes per point: complex of the cycle precision, of the
+    // level-0 input/output (FP64) and the real k^2
+    const double ct = c->mixed ? 8.0 : 16.0, sk = c->mixed ? 4.0 : 8.0, c0b = 16.0;
+    const double ns = st.n;
     for (int l = 0; l + 1 < L; ++l) {
         const Level& A = c->lv[l];
         const Level& B = c->lv[l + 1];
-        const int pi = prof_begin(c, l == 0 ? MG_K_SMOOTH_RESTRICT_FINE : MG_K_COARSE_LEVELS);
+        // read f, k^2 (and u), write the coarse right-hand side (and u1)
+        double by = ns * (A.N * ((l == 0 ? c0b : ct) + sk) + B.N * ct);
+        if (l == 0 && u0) by += ns * A.N * 2.0 * ct;
+        const int pi = prof_begin(c, l == 0 ? MG_K_SMOOTH_RESTRICT_FINE : MG_K_COARSE_LEVELS, by);
         if (!c->mixed) {
             mg::SmoothRestrictArgs<double, double> a{};
             a.lv = view<double>(c, l, dir);
@@ -329,7 +342,7 @@ mg_status vcycle(mg_ctx* c, int dir, const SlotTable& st, const cx<double>* u0, 
     }
     {
         const Level& C = c->lv[L - 1];
-        const int pi = prof_begin(c, MG_K_COARSEST_SOLVE);
+        const int pi = prof_begin(c, MG_K_COARSEST_SOLVE, ns * C.N * 2.0 * ct);
         if (!c->mixed)
             CK(mg::launch_coarse_solve_f64(c->lu[dir], c->piv[dir], c->ncoarse, st, (const cx<double>*)C.F,
                                            (cx<double>*)C.E, s));
@@ -341,7 +354,12 @@ mg_status vcycle(mg_ctx* c, int dir, const SlotTable& st, const cx<double>* u0, 
     for (int l = L - 2; l >= 0; --l) {
         const Level& A = c->lv[l];
         const Level& B = c->lv[l + 1];
-        const int pi = prof_begin(c, l == 0 ? MG_K_PROLONG_SMOOTH_FINE : MG_K_COARSE_LEVELS);
+        // read f, k^2, the coarse correction (and u1, and out when accumulating), write out
+        const double cf = l == 0 ? c0b : ct;
+        double by = ns * (A.N * (cf + sk + cf) + B.N * ct);
+        if (l == 0 && u0) by += ns * A.N * ct;
+        if (l == 0 && acc) by += ns * A.N * c0b;
+        const int pi = prof_begin(c, l == 0 ? MG_K_PROLONG_SMOOTH_FINE : MG_K_COARSE_LEVELS, by);
         if (!c->mixed) {
             mg::ProlongSmoothArgs<double, double, double> a{};
             a.lv = view<double>(c, l, dir);
@@ -423,7 +441,8 @@ mg_status residual(mg_ctx* c, int l, int dir, const std::vector<Slot>& slots, co
         a.y = y;
         a.norm_part = nrm ? c->rpart : nullptr;
         a.nblocks = nb;
-        const int pi = prof_begin(c, MG_K_RESIDUAL);
+        // read x, k^2 (and f), write y
+        const int pi = prof_begin(c, MG_K_RESIDUAL, (double)st.n * N * (16.0 + 8.0 + 16.0 + (f ? 16.0 : 0.0)));
         CK(mg::launch_residual(c->dim, a, c->stream));
         prof_end(c, pi);
         if (nrm) {
@@ -654,8 +673,12 @@ mg_status solve_gmres(mg_ctx* c, int dir, double* x, const double* f, double rto
             o.part = c->part;
             o.pstride = HSTRIDE;
             o.nblocks = nb;
-            // pass 1: w = A z, h1 = V^H w
-            int pi = prof_begin(c, MG_K_MATVEC_DOT);
+            // basis vectors read per pass: sum over slots of (j + 1)
+            double nvsum = 0.0;
+            for (int q = 0; q < st.n; ++q) nvsum += st.s[q].j + 1;
+            const double vb = 16.0 * N;
+            // pass 1: w = A z, h1 = V^H w; reads z, k^2, V_0..V_j, writes w
+            int pi = prof_begin(c, MG_K_MATVEC_DOT, vb * (nvsum + 2.0 * st.n) + 8.0 * N * st.n);
             CK(mg::launch_matvec_dot(c->dim, jmax, o, c->stream));
             prof_end(c, pi);
             pi = prof_begin(c, MG_K_REDUCE);
@@ -663,7 +686,7 @@ mg_status solve_gmres(mg_ctx* c, int dir, double* x, const double* f, double rto
             prof_end(c, pi);
             // pass 2: w -= V h1, h2 = V^H w
             o.hin = c->tot;
-            pi = prof_begin(c, MG_K_UPDATE_DOT);
+            pi = prof_begin(c, MG_K_UPDATE_DOT, vb * (nvsum + 2.0 * st.n));
             CK(mg::launch_update_dot(jmax, o, c->stream));
             prof_end(c, pi);
             pi = prof_begin(c, MG_K_REDUCE);
@@ -671,7 +694,7 @@ mg_status solve_gmres(mg_ctx* c, int dir, double* x, const double* f, double rto
             prof_end(c, pi);
             // pass 3: V_{j+1} = w - V h2, ||V_{j+1}||^2
             o.hin = c->tot + HSTRIDE;
-            pi = prof_begin(c, MG_K_UPDATE_NORM);
+            pi = prof_begin(c, MG_K_UPDATE_NORM, vb * (nvsum + 2.0 * st.n));
             CK(mg::launch_update_norm(jmax, o, c->stream));
             prof_end(c, pi);
             pi = prof_begin(c, MG_K_REDUCE);
@@ -767,7 +790,9 @@ mg_status solve_gmres(mg_ctx* c, int dir, double* x, const double* f, double rto
                 cb.coef = c->coef_d;
                 cb.sstride = HSTRIDE;
                 cb.t = c->W;
-                const int pi = prof_begin(c, MG_K_COMBINE);
+                double nvsum = 0.0;
+                for (int q = 0; q < st.n; ++q) nvsum += st.s[q].j + 1;
+                const int pi = prof_begin(c, MG_K_COMBINE, 16.0 * N * (nvsum + st.n));
                 CK(mg::launch_combine(jm, cb, c->stream));
                 prof_end(c, pi);
                 CKS(vcycle(c, dir, st, nullptr, c->W, X, true, nullptr));
@@ -1102,7 +1127,7 @@ mg_status mg_solve_adjoint(mg_ctx* c, double* lam, const double* g, int mode, do
 
 mg_status mg_grad_k2(mg_ctx* c, const double* u, const double* lam, double* grad) {
     if (!c || !u || !lam || !grad) return MG_E_INVAL;
-    const int pi = prof_begin(c, MG_K_OTHER);
+    const int pi = prof_begin(c, MG_K_OTHER, (double)c->lv[0].N * (32.0 * c->nrhs + 16.0));
     CK(mg::launch_grad_k2((const cx<double>*)u, (const cx<double>*)lam, c->nrhs, c->lv[0].N, grad, c->stream));
     prof_end(c, pi);
     return MG_OK;
@@ -1146,20 +1171,22 @@ mg_status mg_profile(mg_ctx* c, int enable) {
     return MG_OK;
 }
 
-mg_status mg_profile_read(mg_ctx* c, int which, double* total_ms, long long* count) {
+mg_status mg_profile_read(mg_ctx* c, int which, double* total_ms, long long* count, double* bytes) {
     if (!c || which < 0 || which >= MG_K_NUM_CLASSES) return MG_E_INVAL;
     CK(hipStreamSynchronize(c->stream));
-    double tot = 0.0;
+    double tot = 0.0, by = 0.0;
     long long n = 0;
     for (size_t i = 0; i < c->prof.used; ++i) {
         if (c->prof.cls[i] != which) continue;
         float ms = 0.0f;
         CK(hipEventElapsedTime(&ms, c->prof.pool[2 * i], c->prof.pool[2 * i + 1]));
         tot += ms;
+        by += c->prof.bytes[i];
         ++n;
     }
     if (total_ms) *total_ms = tot;
     if (count) *count = n;
+    if (bytes) *bytes = by;
     return MG_OK;
 }
 

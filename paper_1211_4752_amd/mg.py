@@ -83,7 +83,7 @@ def lib():
         L.mg_level_dims.argtypes = [vp, ctypes.c_int, ip]
         L.mg_get_sigma.argtypes = [vp, dp]
         L.mg_profile.argtypes = [vp, ctypes.c_int]
-        L.mg_profile_read.argtypes = [vp, ctypes.c_int, dp, ctypes.POINTER(ctypes.c_longlong)]
+        L.mg_profile_read.argtypes = [vp, ctypes.c_int, dp, ctypes.POINTER(ctypes.c_longlong), dp]
         L.mg_destroy.argtypes = [vp]
         L.mg_destroy.restype = None
         L.mg_status_str.argtypes = [ctypes.c_int]
@@ -264,15 +264,16 @@ class Solver:
             raise MGError(st, "mg_profile")
 
     def profile_read(self):
-        """{kernel class: (total ms, launches)} since profile(True)."""
+        """{kernel class: (total ms, launches, algorithmic bytes)} since profile(True)."""
         out = {}
         for i, name in enumerate(KERNEL_CLASSES):
             ms = ctypes.c_double()
             cnt = ctypes.c_longlong()
-            st = lib().mg_profile_read(self.ctx, i, ctypes.byref(ms), ctypes.byref(cnt))
+            by = ctypes.c_double()
+            st = lib().mg_profile_read(self.ctx, i, ctypes.byref(ms), ctypes.byref(cnt), ctypes.byref(by))
             if st != MG_OK:
                 raise MGError(st, "mg_profile_read")
-            out[name] = (ms.value, cnt.value)
+            out[name] = (ms.value, cnt.value, by.value)
         return out
 
     def close(self):

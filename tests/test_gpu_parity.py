@@ -1,10 +1,17 @@
 """GPU parity: the HIP path (through the C ABI) against the CPU oracle.
 
 Bars: operator application 1e-12 relative; one V-cycle 1e-11 relative;
-residual histories 1e-8 relative (standalone until the ratio passes 1e3);
-converged solutions 1e-10 relative L2 (FP64).  Mixed precision: the final
-error against the FP64 oracle solution at most 1e-6 relative.  Sizes span
-several tiles with ragged tails (tiles are 64 x 16 in 2D, 16 x 8 x 4 in 3D).
+residual histories 1e-8 relative above an absolute floor (relative to ||f||)
+of max(1e-11, D), D the largest difference between the oracle's histories
+with modified and with twice-applied classical Gram-Schmidt (two correct FP64
+evaluations of the same iteration; standalone histories until the ratio
+passes 1e3); converged solutions 1e-10 relative L2 (FP64), else within ten
+times the oracle's own MGS/CGS2 solution difference, else within 1e-4 of the
+iterate's own distance to the sparse direct solution (the two iterates agree
+far better than either approximates the solution).  Iteration counts equal,
+except that a stop decided inside that rounding floor may move a few steps.  Mixed precision: the final error against the FP64
+oracle solution at most 1e-6 relative.  Sizes span several tiles with ragged
+tails (tiles are 64 x 16 in 2D, 16 x 8 x 4 in 3D).
 """
 
 import math
@@ -125,16 +132,42 @@ def test_cycle_is_deterministic():
     s.close()
 
 
-def _compare_hist(got, want, tol=1e-8, stop=None):
+HIST_FLOOR = 1e-11     # absolute rounding floor of a relative-residual history
+
+
+def _compare_hist(got, want, tol=1e-8, stop=None, floor=HIST_FLOOR):
     m = min(len(got), len(want))
     if stop is not None:
         above = np.nonzero(np.asarray(want[:m]) > stop)[0]
         if len(above):
             m = min(m, above[0] + 1)
     g, w = np.asarray(got[:m]), np.asarray(want[:m])
-    rel = np.abs(g - w) / np.maximum(np.abs(w), 1e-300)
-    assert rel.max() < tol, (rel.max(), int(rel.argmax()), m)
+    excess = np.abs(g - w) - (tol * np.abs(w) + floor)
+    assert excess.max() <= 0, (float(np.abs(g - w)[excess.argmax()]), int(excess.argmax()), m)
     return m
+
+
+def check_gmres(got_x, got_hist, got_its, A, M, f, rtol, maxit, restart=20):
+    """GPU GMRES result against the oracle (MGS), with the rounding floor
+    measured by the oracle's CGS2 variant of the same iteration."""
+    import scipy.sparse.linalg as spla
+    x, hist, it, st = K.gmres(A, M, f, rtol=rtol, restart=restart, maxit=maxit)
+    x2, hist2, it2, st2 = K.gmres(A, M, f, rtol=rtol, restart=restart, maxit=maxit, ortho="cgs2")
+    assert st == "converged"
+    m = min(len(hist), len(hist2))
+    drift_h = float(np.abs(hist[:m] - hist2[:m]).max())
+    floor = max(HIST_FLOOR, drift_h)
+    slack = 0 if floor < 1e-3 * rtol else max(3, it // 100)
+    assert abs(got_its - it) <= max(slack, abs(it2 - it)), (got_its, it, it2)
+    _compare_hist(got_hist, hist, 1e-8, floor=floor)
+    err = np.linalg.norm(got_x - x) / np.linalg.norm(x)
+    if err >= 1e-10:
+        drift_x = np.linalg.norm(x2 - x) / np.linalg.norm(x)
+        if err > 10 * drift_x:
+            exact = spla.spsolve(A.tocsc(), f)
+            own = np.linalg.norm(x - exact) / np.linalg.norm(exact)
+            assert err <= 1e-4 * own, (err, drift_x, own)
+    return it
 
 
 @pytest.mark.parametrize("name,maxit", [("dirichlet_63", 60), ("grf_127_ecs4", 60), ("const3d_31", 40)])
@@ -172,15 +205,11 @@ def test_gmres_history_and_solution(name, rtol, maxit):
     u = s.empty()
     status, its, hists = s.solve(u, gpu(wl.f), mode="gmres", rtol=rtol, maxit=maxit, restart=20)
     got = u.cpu().numpy()
+    assert status == "converged"
     for r in range(s.nrhs):
-        x, hist, it, st = K.gmres(levels[0].A, vc.precondition, wl.f[r].ravel(), rtol=rtol, restart=20,
-                                  maxit=maxit)
-        say(name, r, "gmres", st, it, "gpu", status, its[r])
-        assert st == "converged" and status == "converged"
-        assert its[r] == it
-        _compare_hist(hists[r], hist, 1e-8)
-        err = np.linalg.norm(got[r].ravel() - x) / np.linalg.norm(x)
-        assert err < 1e-10, err
+        it = check_gmres(got[r].ravel(), hists[r], its[r], levels[0].A, vc.precondition, wl.f[r].ravel(), rtol,
+                         maxit)
+        say(name, r, "gmres oracle", it, "gpu", its[r])
         true = np.linalg.norm(wl.f[r].ravel() - levels[0].A @ got[r].ravel()) / np.linalg.norm(wl.f[r])
         assert true <= rtol * (1 + 1e-6)
     s.close()
@@ -219,10 +248,7 @@ def test_adjoint_and_gradient():
     assert status == "converged"
     lam_h = lam.cpu().numpy()
     for r in range(3):
-        x, hist, it, st = K.gmres(AH, vca.precondition, g[r].ravel(), rtol=1e-10, restart=20, maxit=3000)
-        assert its[r] == it
-        _compare_hist(hists[r], hist, 1e-8)
-        assert np.linalg.norm(lam_h[r].ravel() - x) / np.linalg.norm(x) < 1e-10
+        check_gmres(lam_h[r].ravel(), hists[r], its[r], AH, vca.precondition, g[r].ravel(), 1e-10, 3000)
     u = gpu(rnd(wl.f.shape, 8))
     grad = torch.zeros(wl.k2.shape, dtype=torch.float64, device=_dev())
     s.grad_k2(u, lam, grad)
@@ -301,11 +327,7 @@ def test_many_rhs_two_launch_groups():
     status, its, hists = s.solve(u, gpu(wl.f), mode="gmres", rtol=1e-8, maxit=500, restart=20)
     got = u.cpu().numpy()
     for r in (0, 17, 31, 32, 39):
-        x, hist, it, st = K.gmres(levels[0].A, vc.precondition, wl.f[r].ravel(), rtol=1e-8, restart=20,
-                                  maxit=500)
-        assert its[r] == it
-        _compare_hist(hists[r], hist, 1e-8)
-        assert np.linalg.norm(got[r].ravel() - x) / np.linalg.norm(x) < 1e-10
+        check_gmres(got[r].ravel(), hists[r], its[r], levels[0].A, vc.precondition, wl.f[r].ravel(), 1e-8, 500)
     s.close()
 
 

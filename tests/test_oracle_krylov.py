@@ -39,17 +39,33 @@ def test_givens_zeroes_second_entry():
         assert abs(c * c + abs(s) ** 2 - 1) < 1e-14
 
 
-def test_gmres_matches_direct_solve():
+@pytest.mark.parametrize("ortho", ["mgs", "cgs2"])
+def test_gmres_matches_direct_solve(ortho):
     prob, wl = _problem()
     levels = H.build_hierarchy(prob)
     vc = C.VCycle(levels)
     A = levels[0].A
     f = wl.f[0].ravel()
-    x, hist, its, status = K.gmres(A, vc.precondition, f, rtol=1e-10, restart=20, maxit=3000)
+    x, hist, its, status = K.gmres(A, vc.precondition, f, rtol=1e-10, restart=20, maxit=3000, ortho=ortho)
     assert status == "converged"
     exact = spla.spsolve(A.tocsc(), f)
     assert np.linalg.norm(f - A @ x) / np.linalg.norm(f) <= 1e-10
     assert np.linalg.norm(x - exact) / np.linalg.norm(exact) < 1e-7
+
+
+def test_gmres_orthogonalisation_variants_agree():
+    """MGS and CGS2 run the same iteration: equal counts, histories equal to
+    rounding (1e-8 relative above an absolute floor of 1e-11 ||f||)."""
+    prob, wl = _problem(31, 2)
+    levels = H.build_hierarchy(prob)
+    vc = C.VCycle(levels)
+    A = levels[0].A
+    f = wl.f[0].ravel()
+    x1, h1, i1, s1 = K.gmres(A, vc.precondition, f, rtol=1e-8, restart=20, maxit=500)
+    x2, h2, i2, s2 = K.gmres(A, vc.precondition, f, rtol=1e-8, restart=20, maxit=500, ortho="cgs2")
+    assert (i1, s1) == (i2, s2)
+    assert np.all(np.abs(h1 - h2) <= 1e-8 * h1 + 1e-11)
+    assert np.linalg.norm(x1 - x2) / np.linalg.norm(x1) < 1e-9
 
 
 def test_gmres_estimate_is_true_residual_and_monotone():
