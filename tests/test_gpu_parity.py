@@ -2,7 +2,7 @@
 
 Bars: operator application 1e-12 relative; one V-cycle 1e-11 relative;
 residual histories 1e-8 relative above an absolute floor (relative to ||f||)
-of max(1e-11, D), D the largest difference between the oracle's histories
+of max(1e-11, 10 D), D the largest difference between the oracle's histories
 with modified and with twice-applied classical Gram-Schmidt (two correct FP64
 evaluations of the same iteration; standalone histories until the ratio
 passes 1e3); converged solutions 1e-10 relative L2 (FP64), else within ten
@@ -156,7 +156,7 @@ def check_gmres(got_x, got_hist, got_its, A, M, f, rtol, maxit, restart=20):
     assert st == "converged"
     m = min(len(hist), len(hist2))
     drift_h = float(np.abs(hist[:m] - hist2[:m]).max())
-    floor = max(HIST_FLOOR, drift_h)
+    floor = max(HIST_FLOOR, 10 * drift_h)
     slack = 0 if floor < 1e-3 * rtol else max(3, it // 100)
     assert abs(got_its - it) <= max(slack, abs(it2 - it)), (got_its, it, it2)
     _compare_hist(got_hist, hist, 1e-8, floor=floor)
