@@ -147,6 +147,30 @@ mg_status mg_grad_k2(mg_ctx *c, const double *u_dev, const double *lam_dev,
 mg_status mg_apply(mg_ctx *c, int level, int adjoint, const double *x_dev,
                    double *y_dev);
 
+/* Tile shape of the two fused cycle kernels on one level (the shape ids are
+ * 64x16, 64x8, 128x8 in 2D and 16x8x4, 32x4x2, 16x4x4 in 3D).  mg_setup
+ * picks one per level by timing every shape on the level's own arrays
+ * (levels of at least 16384 points; smaller levels use shape 0).
+ * shape >= 0 sets it, shape < 0 only queries; returns the shape in force or
+ * a negative mg_status. */
+int mg_tile_shape(mg_ctx *c, int level, int shape);
+
+/* Batched solves (extension): the right-hand sides of several contexts --
+ * grids of different sizes, one stream, one dimension and precision -- are
+ * iterated together: every kernel launch of a step covers all of them, and
+ * the coarse part of each V-cycle (levels >= 1 and the coarsest solve) is
+ * captured once as a HIP graph and replayed.  The batch borrows the
+ * contexts; destroy it before them.  u_dev[i], f_dev[i] are context i's
+ * vectors; iters and hist are laid out context after context, rhs after rhs
+ * (hist: maxit + 1 doubles per rhs).  Same semantics and statuses as
+ * mg_solve; MG_E_INVAL if the contexts do not match. */
+typedef struct mg_batch mg_batch;
+mg_status mg_batch_create(mg_ctx *const *ctxs, int count, mg_batch **out);
+mg_status mg_batch_solve(mg_batch *b, double *const *u_dev,
+                         const double *const *f_dev, int mode, double rtol,
+                         int maxit, int restart, int *iters, double *hist);
+void mg_batch_destroy(mg_batch *b);
+
 /* Number of levels and the interior sizes of one level (n[3], x first). */
 int mg_num_levels(const mg_ctx *c);
 mg_status mg_level_dims(const mg_ctx *c, int level, int n[3]);

@@ -1,6 +1,7 @@
-// Host runtime of the level-dependent multigrid: hierarchy set-up, the
-// V-cycle driver, the standalone and GMRES solvers, the adjoint, and the C ABI
-// declared in include/mg.h.
+// Host runtime of the level-dependent multigrid: hierarchy set-up, tile-shape
+// autotuning, the V-cycle driver (coarse part captured as a HIP graph), the
+// standalone and GMRES solvers over "items" (one right-hand side of one
+// problem), batches of problems, the adjoint, and the C ABI of include/mg.h.
 //
 // Paper: Cools, Reps, Vanroose, "A new level-dependent coarse grid correction
 // scheme for indefinite Helmholtz problems" (NLAA 2013).
@@ -10,8 +11,10 @@
 #include <algorithm>
 #include <cmath>
 #include <complex>
+#include <cstdint>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <new>
 #include <vector>
 
@@ -19,15 +22,21 @@
 #include "mg_device.hpp"
 
 using cd = std::complex<double>;
+using mg::CycleArgs;
+using mg::CycleSlot;
 using mg::cx;
-using mg::Slot;
-using mg::SlotTable;
+using mg::LevelView;
+using mg::ReduceArgs;
+using mg::VecArgs;
+using mg::VecSlot;
 
 namespace {
 
 constexpr int MAX_RESTART = 32;
-constexpr int HSTRIDE = MAX_RESTART + 1;     // per-slot stride of dot results
+constexpr int HSTRIDE = MAX_RESTART + 1;     // per-slot stride of one set of dot results
+constexpr int TOT = 2 * HSTRIDE;             // per-slot totals: H1 | H2
 constexpr double DIVERGE = 1e8;
+constexpr long long AUTOTUNE_MIN_POINTS = 16384;
 
 #define CK(expr)                                        \
     do {                                                \
@@ -106,15 +115,15 @@ struct Level {
     long long N = 0;
     double h[3] = {0, 0, 0};
     cd sigma = 1.0;
-    int ntiles[3] = {1, 1, 1};
+    int shape = 0;                // tile shape of the fused kernels on this level
     // per direction (0 forward, 1 conjugate transpose): per axis cm | c0 | cp
     std::vector<cd> coef_host[2];
     cx<double>* coef_d[2] = {nullptr, nullptr};
     cx<float>* coef_f[2] = {nullptr, nullptr};
     double* k2 = nullptr;
     float* k2f = nullptr;
-    void* F = nullptr;    // right-hand sides on levels >= 1, by buf
-    void* E = nullptr;    // corrections on levels >= 1, by buf
+    void* F = nullptr;            // right-hand sides on levels >= 1, by rhs
+    void* E = nullptr;            // corrections on levels >= 1, by rhs
 };
 
 struct Prof {
@@ -123,6 +132,24 @@ struct Prof {
     std::vector<int> cls;
     std::vector<double> bytes;
     size_t used = 0;
+};
+
+// Reduction work space and pinned mirrors.
+struct Work {
+    cx<double>* part = nullptr;   // [(slot * HSTRIDE + i) * bstride + b]
+    double* rpart = nullptr;      // [slot * bstride + b]
+    int bstride = 0;
+    cx<double>* tot = nullptr;    // [slot * TOT + v]
+    double* rtot = nullptr;       // [slot]
+    cx<double>* tot_h = nullptr;  // pinned [item * TOT + v]
+    double* rtot_h = nullptr;     // pinned [item]
+    int items = 0;
+};
+
+// Captured coarse parts of the V-cycle, keyed by direction and item list.
+struct GraphCache {
+    std::map<std::vector<uintptr_t>, hipGraphExec_t> execs;
+    hipStream_t capture = nullptr;    // private stream used only for capture
 };
 
 }  // namespace
@@ -135,11 +162,12 @@ struct mg_ctx {
     int nrhs = 1;
     hipStream_t stream = nullptr;
     std::vector<Level> lv;
-    // coarsest LU, per direction
     int ncoarse = 0;
     cx<double>* lu[2] = {nullptr, nullptr};
     int* piv[2] = {nullptr, nullptr};
-    // level-0 work vectors, by buf
+    LevelView<double>* views_d[2] = {nullptr, nullptr};   // device, one per level
+    LevelView<float>* views_f[2] = {nullptr, nullptr};
+    // level-0 work vectors, by rhs
     cx<double>* U1 = nullptr;
     cx<double>* Z = nullptr;
     cx<double>* W = nullptr;
@@ -150,20 +178,18 @@ struct mg_ctx {
     double* scale_h = nullptr;     // pinned
     cx<double>* coef_d = nullptr;  // [rhs * HSTRIDE + i]
     cx<double>* coef_h = nullptr;  // pinned
-    // reductions
-    cx<double>* part = nullptr;
-    double* rpart = nullptr;
-    long long part_blocks = 0;     // blocks per slot the partial buffers hold
-    cx<double>* tot = nullptr;     // [slot * TOT + v]
-    double* rtot = nullptr;        // [slot]
-    cx<double>* tot_h = nullptr;   // pinned [rhs * TOT + v]
-    double* rtot_h = nullptr;      // pinned [rhs]
+    Work work;
     Prof prof;
+    GraphCache graphs;
+};
+
+struct mg_batch {
+    std::vector<mg_ctx*> ctxs;
+    Work work;
+    GraphCache graphs;
 };
 
 namespace {
-
-constexpr int TOT = 3 * HSTRIDE;   // H1 | H2 | norm
 
 // ---------------------------------------------------------------------------
 // Small utilities
@@ -199,10 +225,48 @@ void hfree(P*& p) {
     p = nullptr;
 }
 
+mg_status work_alloc(Work& w, int items, int bstride) {
+    w.items = items;
+    w.bstride = bstride;
+    CKS(dalloc(&w.part, (size_t)mg::MAX_SLOTS * HSTRIDE * bstride * sizeof(cx<double>)));
+    CKS(dalloc(&w.rpart, (size_t)mg::MAX_SLOTS * bstride * sizeof(double)));
+    CKS(dalloc(&w.tot, (size_t)mg::MAX_SLOTS * TOT * sizeof(cx<double>)));
+    CKS(dalloc(&w.rtot, (size_t)mg::MAX_SLOTS * sizeof(double)));
+    CKS(halloc(&w.tot_h, (size_t)std::max(items, mg::MAX_SLOTS) * TOT * sizeof(cx<double>)));
+    CKS(halloc(&w.rtot_h, (size_t)std::max(items, mg::MAX_SLOTS) * sizeof(double)));
+    return MG_OK;
+}
+
+void work_free(Work& w) {
+    dfree(w.part);
+    dfree(w.rpart);
+    dfree(w.tot);
+    dfree(w.rtot);
+    hfree(w.tot_h);
+    hfree(w.rtot_h);
+}
+
+void graphs_free(GraphCache& g) {
+    for (auto& kv : g.execs) (void)hipGraphExecDestroy(kv.second);
+    g.execs.clear();
+    if (g.capture) (void)hipStreamDestroy(g.capture);
+    g.capture = nullptr;
+}
+
+// One solve invocation: where launches go and what they record.
+struct Run {
+    hipStream_t s;
+    Prof* prof;
+    Work* w;
+    GraphCache* gc;
+    int dim;
+    bool mixed;
+};
+
 // bytes: algorithmic (compulsory) traffic of the launch
-int prof_begin(mg_ctx* c, int cls, double bytes = 0.0) {
-    if (!c->prof.on) return -1;
-    Prof& P = c->prof;
+int prof_begin(Run& R, int cls, double bytes = 0.0) {
+    if (!R.prof || !R.prof->on) return -1;
+    Prof& P = *R.prof;
     while (P.pool.size() < 2 * (P.used + 1)) {
         hipEvent_t e;
         if (hipEventCreate(&e) != hipSuccess) return -1;
@@ -215,241 +279,369 @@ int prof_begin(mg_ctx* c, int cls, double bytes = 0.0) {
     }
     P.cls[idx] = cls;
     P.bytes[idx] = bytes;
-    (void)hipEventRecord(P.pool[2 * idx], c->stream);
+    (void)hipEventRecord(P.pool[2 * idx], R.s);
     return idx;
 }
-void prof_end(mg_ctx* c, int idx) {
-    if (idx >= 0) (void)hipEventRecord(c->prof.pool[2 * idx + 1], c->stream);
+void prof_end(Run& R, int idx) {
+    if (idx >= 0) (void)hipEventRecord(R.prof->pool[2 * idx + 1], R.s);
 }
 
-template <typename T>
-mg::LevelView<T> view(const mg_ctx* c, int l, int dir);
+// One right-hand side of one problem.
+struct Item {
+    mg_ctx* c;
+    int rhs;
+};
 
-template <>
-mg::LevelView<double> view<double>(const mg_ctx* c, int l, int dir) {
-    const Level& L = c->lv[l];
-    mg::LevelView<double> v{};
-    long long off = 0;
-    for (int a = 0; a < 3; ++a) {
-        const int aa = a < c->dim ? a : 0;
-        long long o = 0;
-        for (int b = 0; b < aa; ++b) o += 3LL * L.n[b];
-        v.n[a] = a < c->dim ? L.n[a] : 1;
-        v.cm[a] = L.coef_d[dir] + o;
-        v.c0[a] = L.coef_d[dir] + o + L.n[aa];
-        v.cp[a] = L.coef_d[dir] + o + 2LL * L.n[aa];
-        (void)off;
-    }
-    v.N = L.N;
-    v.k2 = L.k2;
-    const cd s = dir ? std::conj(L.sigma) : L.sigma;
-    v.sigma = tocx(s);
-    v.omega = mg::mk(c->p.omega[0], c->p.omega[1]);
-    return v;
+// Level-0 inputs and outputs of one item's cycle.
+struct L0 {
+    const void* f;            // right-hand side (complex double)
+    double fs;                // scale applied to f
+    const cx<double>* u;      // incoming iterate or null (zero guess)
+    cx<double>* out;          // result (written, or accumulated)
+};
+
+const void* view_ptr(const mg_ctx* c, int dir, int l) {
+    return c->mixed ? (const void*)(c->views_f[dir] + l) : (const void*)(c->views_d[dir] + l);
+}
+size_t elem(const mg_ctx* c) { return c->mixed ? sizeof(cx<float>) : sizeof(cx<double>); }
+void* lvec(const mg_ctx* c, void* base, int l, int rhs) {
+    return (char*)base + (size_t)rhs * c->lv[l].N * elem(c);
 }
 
-template <>
-mg::LevelView<float> view<float>(const mg_ctx* c, int l, int dir) {
-    const Level& L = c->lv[l];
-    mg::LevelView<float> v{};
-    for (int a = 0; a < 3; ++a) {
-        const int aa = a < c->dim ? a : 0;
-        long long o = 0;
-        for (int b = 0; b < aa; ++b) o += 3LL * L.n[b];
-        v.n[a] = a < c->dim ? L.n[a] : 1;
-        v.cm[a] = L.coef_f[dir] + o;
-        v.c0[a] = L.coef_f[dir] + o + L.n[aa];
-        v.cp[a] = L.coef_f[dir] + o + 2LL * L.n[aa];
+// Launch groups of at most MAX_SLOTS items each.
+template <typename F>
+mg_status for_groups(const std::vector<int>& idx, F fn) {
+    for (size_t g = 0; g < idx.size(); g += mg::MAX_SLOTS) {
+        const size_t n = std::min<size_t>(mg::MAX_SLOTS, idx.size() - g);
+        std::vector<int> sub(idx.begin() + g, idx.begin() + g + n);
+        CKS(fn(sub, (int)g));
     }
-    v.N = L.N;
-    v.k2 = L.k2f;
-    const cd s = dir ? std::conj(L.sigma) : L.sigma;
-    v.sigma = mg::mk((float)s.real(), (float)s.imag());
-    v.omega = mg::mk((float)c->p.omega[0], (float)c->p.omega[1]);
-    return v;
+    return MG_OK;
 }
 
-// Split a list of slots into launch groups of at most MAX_SLOTS.
-std::vector<SlotTable> groups(const std::vector<Slot>& slots) {
-    std::vector<SlotTable> g;
-    for (size_t i = 0; i < slots.size(); i += mg::MAX_SLOTS) {
-        SlotTable t{};
-        t.n = (int)std::min<size_t>(mg::MAX_SLOTS, slots.size() - i);
-        for (int k = 0; k < t.n; ++k) t.s[k] = slots[i + k];
-        g.push_back(t);
+// Shape of a launch at depth d: the one tuned for the largest level in it.
+int launch_shape(const std::vector<Item>& it, const std::vector<int>& sub, int d) {
+    long long best = -1;
+    int shape = 0;
+    for (int k : sub) {
+        const Level& V = it[k].c->lv[d];
+        if (V.N > best) {
+            best = V.N;
+            shape = V.shape;
+        }
     }
-    return g;
+    return shape;
 }
 
 // ---------------------------------------------------------------------------
-// V-cycle (Sec. 3.1): one group of at most MAX_SLOTS right-hand sides.
-//   u0   level-0 incoming iterate by rhs (nullptr: zero initial guess)
-//   f0   level-0 right-hand side, slot.in_off / slot.in_scale
-//   out0 level-0 result, slot.out_off; acc: out0 += result
-//   norm level-0 ||f - A u0||^2 partials per (local slot, tile), or nullptr
+// V-cycle pieces (Sec. 3.1)
 // ---------------------------------------------------------------------------
-mg_status vcycle(mg_ctx* c, int dir, const SlotTable& st, const cx<double>* u0, const cx<double>* f0,
-                 cx<double>* out0, bool acc, double* norm) {
-    const int L = c->L;
-    hipStream_t s = c->stream;
-    if (c->mixed && u0) return MG_E_STATE;
-    // algorithmic bytes per point: complex of the cycle precision, of the
-    // level-0 input/output (FP64) and the real k^2
-    const double ct = c->mixed ? 8.0 : 16.0, sk = c->mixed ? 4.0 : 8.0, c0b = 16.0;
-    const double ns = st.n;
-    for (int l = 0; l + 1 < L; ++l) {
-        const Level& A = c->lv[l];
-        const Level& B = c->lv[l + 1];
-        // read f, k^2 (and u), write the coarse right-hand side (and u1)
-        double by = ns * (A.N * ((l == 0 ? c0b : ct) + sk) + B.N * ct);
-        if (l == 0 && u0) by += ns * A.N * 2.0 * ct;
-        const int pi = prof_begin(c, l == 0 ? MG_K_SMOOTH_RESTRICT_FINE : MG_K_COARSE_LEVELS, by);
-        if (!c->mixed) {
-            mg::SmoothRestrictArgs<double, double> a{};
-            a.lv = view<double>(c, l, dir);
-            for (int k = 0; k < 3; ++k) a.nc[k] = k < c->dim ? B.n[k] : 1, a.ntiles[k] = A.ntiles[k];
-            a.Nc = B.N;
-            a.st = st;
-            a.u = l == 0 ? u0 : nullptr;
-            a.f = l == 0 ? f0 : (const cx<double>*)A.F;
-            a.f_by_slot = l != 0;
-            a.u1 = (l == 0 && u0) ? c->U1 : nullptr;
-            a.fc = (cx<double>*)B.F;
-            a.norm_part = (l == 0 && u0) ? norm : nullptr;
-            CK(mg::launch_smooth_restrict_f64(c->dim, !(l == 0 && u0), a, nullptr, s));
-        } else {
-            mg::SmoothRestrictArgs<float, double> a0{};
-            mg::SmoothRestrictArgs<float, float> ac{};
-            auto fill = [&](auto& a) {
-                a.lv = view<float>(c, l, dir);
-                for (int k = 0; k < 3; ++k) a.nc[k] = k < c->dim ? B.n[k] : 1, a.ntiles[k] = A.ntiles[k];
-                a.Nc = B.N;
-                a.st = st;
-                a.u = nullptr;
-                a.u1 = nullptr;
-                a.fc = (cx<float>*)B.F;
-                a.norm_part = nullptr;
-            };
-            fill(a0);
-            fill(ac);
-            a0.f = f0;
-            a0.f_by_slot = false;
-            ac.f = (const cx<float>*)A.F;
-            ac.f_by_slot = true;
-            CK(mg::launch_smooth_restrict_f32(c->dim, l == 0, a0, ac, nullptr, s));
+
+// K_A at depth d for the items that have a coarser level below d.  With norm
+// (level 0 with incoming iterates) ||f - A u||^2 of item k lands in
+// w->rtot_h[k] once the stream gets there.
+mg_status launch_ka(Run& R, int dir, const std::vector<Item>& it, const std::vector<L0>* l0, int d,
+                    bool norm) {
+    std::vector<int> who;
+    for (int k = 0; k < (int)it.size(); ++k)
+        if (d + 1 < it[k].c->L) who.push_back(k);
+    const bool zero = !(d == 0 && l0 && (*l0)[0].u);
+    return for_groups(who, [&](const std::vector<int>& sub, int gbase) -> mg_status {
+        const int shape = launch_shape(it, sub, d);
+        CycleArgs a{};
+        a.st.n = (int)sub.size();
+        int tiles = 0;
+        double by = 0.0;
+        const double ct = R.mixed ? 8.0 : 16.0, sk = R.mixed ? 4.0 : 8.0;
+        for (int q = 0; q < a.st.n; ++q) {
+            const Item& I = it[sub[q]];
+            mg_ctx* c = I.c;
+            CycleSlot& s = a.st.s[q];
+            s.lv = view_ptr(c, dir, d);
+            if (d == 0) {
+                const L0& z = (*l0)[sub[q]];
+                s.f = z.f;
+                s.fscale = z.fs;
+                s.u = z.u;
+                s.u1 = z.u ? (void*)(c->U1 + (size_t)I.rhs * c->lv[0].N) : nullptr;
+            } else {
+                s.f = lvec(c, c->lv[d].F, d, I.rhs);
+                s.fscale = 1.0;
+            }
+            s.c = lvec(c, c->lv[d + 1].F, d + 1, I.rhs);
+            s.tile0 = tiles;
+            int nt[3];
+            mg::tile_counts(R.dim, shape, c->lv[d].n, nt);
+            tiles += nt[0] * nt[1] * nt[2];
+            by += c->lv[d].N * ((d == 0 ? 16.0 : ct) + sk) + c->lv[d + 1].N * ct;
+            if (!zero) by += c->lv[0].N * 2.0 * ct;
         }
-        prof_end(c, pi);
-    }
-    {
-        const Level& C = c->lv[L - 1];
-        const int pi = prof_begin(c, MG_K_COARSEST_SOLVE, ns * C.N * 2.0 * ct);
-        if (!c->mixed)
-            CK(mg::launch_coarse_solve_f64(c->lu[dir], c->piv[dir], c->ncoarse, st, (const cx<double>*)C.F,
-                                           (cx<double>*)C.E, s));
-        else
-            CK(mg::launch_coarse_solve_f32(c->lu[dir], c->piv[dir], c->ncoarse, st, (const cx<float>*)C.F,
-                                           (cx<float>*)C.E, s));
-        prof_end(c, pi);
-    }
-    for (int l = L - 2; l >= 0; --l) {
-        const Level& A = c->lv[l];
-        const Level& B = c->lv[l + 1];
-        // read f, k^2, the coarse correction (and u1, and out when accumulating), write out
-        const double cf = l == 0 ? c0b : ct;
-        double by = ns * (A.N * (cf + sk + cf) + B.N * ct);
-        if (l == 0 && u0) by += ns * A.N * ct;
-        if (l == 0 && acc) by += ns * A.N * c0b;
-        const int pi = prof_begin(c, l == 0 ? MG_K_PROLONG_SMOOTH_FINE : MG_K_COARSE_LEVELS, by);
-        if (!c->mixed) {
-            mg::ProlongSmoothArgs<double, double, double> a{};
-            a.lv = view<double>(c, l, dir);
-            for (int k = 0; k < 3; ++k) a.nc[k] = k < c->dim ? B.n[k] : 1, a.ntiles[k] = A.ntiles[k];
-            a.Nc = B.N;
-            a.st = st;
-            a.u1 = (l == 0 && u0) ? c->U1 : nullptr;
-            a.f = l == 0 ? f0 : (const cx<double>*)A.F;
-            a.f_by_slot = l != 0;
-            a.ec = (const cx<double>*)B.E;
-            a.out = l == 0 ? out0 : (cx<double>*)A.E;
-            a.out_by_slot = l != 0;
-            CK(mg::launch_prolong_smooth_f64(c->dim, !(l == 0 && u0), l == 0 && acc, a, s));
-        } else {
-            mg::ProlongSmoothArgs<float, double, double> a0{};
-            mg::ProlongSmoothArgs<float, float, float> ac{};
-            auto fill = [&](auto& a) {
-                a.lv = view<float>(c, l, dir);
-                for (int k = 0; k < 3; ++k) a.nc[k] = k < c->dim ? B.n[k] : 1, a.ntiles[k] = A.ntiles[k];
-                a.Nc = B.N;
-                a.st = st;
-                a.u1 = nullptr;
-                a.ec = (const cx<float>*)B.E;
-            };
-            fill(a0);
-            fill(ac);
-            a0.f = f0;
-            a0.f_by_slot = false;
-            a0.out = out0;
-            a0.out_by_slot = false;
-            ac.f = (const cx<float>*)A.F;
-            ac.f_by_slot = true;
-            ac.out = (cx<float>*)A.E;
-            ac.out_by_slot = true;
-            CK(mg::launch_prolong_smooth_f32(c->dim, l == 0, acc, a0, ac, s));
+        a.st.ntiles = tiles;
+        a.norm_part = (norm && !zero) ? R.w->rpart : nullptr;
+        a.pstride = R.w->bstride;
+        const int pi = prof_begin(R, d == 0 ? MG_K_SMOOTH_RESTRICT_FINE : MG_K_COARSE_LEVELS, by);
+        CK(mg::launch_smooth_restrict(R.dim, R.mixed, d == 0, zero, shape, a, R.s));
+        prof_end(R, pi);
+        if (a.norm_part) {
+            ReduceArgs ra{};
+            ra.rpart = R.w->rpart;
+            ra.rout = R.w->rtot;
+            ra.bstride = R.w->bstride;
+            for (int q = 0; q < a.st.n; ++q) {
+                const int next = q + 1 < a.st.n ? a.st.s[q + 1].tile0 : tiles;
+                ra.cnt[q] = next - a.st.s[q].tile0;
+            }
+            const int pr = prof_begin(R, MG_K_REDUCE);
+            CK(mg::launch_reduce(ra, a.st.n, true, R.s));
+            prof_end(R, pr);
+            CK(hipMemcpyAsync(R.w->rtot_h + gbase, R.w->rtot, a.st.n * sizeof(double), hipMemcpyDeviceToHost,
+                              R.s));
         }
-        prof_end(c, pi);
+        return MG_OK;
+    });
+}
+
+// Coarsest solve for every item.
+mg_status launch_coarsest(Run& R, int dir, const std::vector<Item>& it) {
+    std::vector<int> all(it.size());
+    for (size_t k = 0; k < it.size(); ++k) all[k] = (int)k;
+    return for_groups(all, [&](const std::vector<int>& sub, int) -> mg_status {
+        CycleArgs a{};
+        a.st.n = (int)sub.size();
+        double by = 0.0;
+        for (int q = 0; q < a.st.n; ++q) {
+            const Item& I = it[sub[q]];
+            mg_ctx* c = I.c;
+            const int l = c->L - 1;
+            CycleSlot& s = a.st.s[q];
+            s.lv = view_ptr(c, dir, l);
+            s.f = lvec(c, c->lv[l].F, l, I.rhs);
+            s.out = lvec(c, c->lv[l].E, l, I.rhs);
+            by += 2.0 * c->lv[l].N * (R.mixed ? 8.0 : 16.0);
+        }
+        const int pi = prof_begin(R, MG_K_COARSEST_SOLVE, by);
+        CK(mg::launch_coarse_solve(R.mixed, a, R.s));
+        prof_end(R, pi);
+        return MG_OK;
+    });
+}
+
+// K_B at depth d for the items that have a coarser level below d.
+mg_status launch_kb(Run& R, int dir, const std::vector<Item>& it, const std::vector<L0>* l0, int d, bool acc) {
+    std::vector<int> who;
+    for (int k = 0; k < (int)it.size(); ++k)
+        if (d + 1 < it[k].c->L) who.push_back(k);
+    const bool zero = !(d == 0 && l0 && (*l0)[0].u);
+    return for_groups(who, [&](const std::vector<int>& sub, int) -> mg_status {
+        const int shape = launch_shape(it, sub, d);
+        CycleArgs a{};
+        a.st.n = (int)sub.size();
+        int tiles = 0;
+        double by = 0.0;
+        const double ct = R.mixed ? 8.0 : 16.0, sk = R.mixed ? 4.0 : 8.0;
+        for (int q = 0; q < a.st.n; ++q) {
+            const Item& I = it[sub[q]];
+            mg_ctx* c = I.c;
+            CycleSlot& s = a.st.s[q];
+            s.lv = view_ptr(c, dir, d);
+            if (d == 0) {
+                const L0& z = (*l0)[sub[q]];
+                s.f = z.f;
+                s.fscale = z.fs;
+                s.u1 = z.u ? (void*)(c->U1 + (size_t)I.rhs * c->lv[0].N) : nullptr;
+                s.out = z.out;
+            } else {
+                s.f = lvec(c, c->lv[d].F, d, I.rhs);
+                s.fscale = 1.0;
+                s.out = lvec(c, c->lv[d].E, d, I.rhs);
+            }
+            s.c = lvec(c, c->lv[d + 1].E, d + 1, I.rhs);
+            s.tile0 = tiles;
+            int nt[3];
+            mg::tile_counts(R.dim, shape, c->lv[d].n, nt);
+            tiles += nt[0] * nt[1] * nt[2];
+            const double cf = d == 0 ? 16.0 : ct;
+            by += c->lv[d].N * (cf + sk + cf) + c->lv[d + 1].N * ct;
+            if (!zero) by += c->lv[0].N * ct;
+            if (d == 0 && acc) by += c->lv[0].N * 16.0;
+        }
+        a.st.ntiles = tiles;
+        const int pi = prof_begin(R, d == 0 ? MG_K_PROLONG_SMOOTH_FINE : MG_K_COARSE_LEVELS, by);
+        CK(mg::launch_prolong_smooth(R.dim, R.mixed, d == 0, zero, d == 0 && acc, shape, a, R.s));
+        prof_end(R, pi);
+        return MG_OK;
+    });
+}
+
+// Levels >= 1 and the coarsest solve of one cycle: captured once per
+// (direction, item list) as a HIP graph and replayed; every pointer in it is
+// fixed per item (F_l and E_l by rhs).
+mg_status coarse_part(Run& R, int dir, const std::vector<Item>& it) {
+    int maxL = 0;
+    for (const Item& I : it) maxL = std::max(maxL, I.c->L);
+    auto record = [&](Run& Q) -> mg_status {
+        for (int d = 1; d + 1 < maxL; ++d) CKS(launch_ka(Q, dir, it, nullptr, d, false));
+        CKS(launch_coarsest(Q, dir, it));
+        for (int d = maxL - 2; d >= 1; --d) CKS(launch_kb(Q, dir, it, nullptr, d, false));
+        return MG_OK;
+    };
+    if (!R.gc) return record(R);
+    std::vector<uintptr_t> key;
+    key.push_back((uintptr_t)dir);
+    for (const Item& I : it) {
+        key.push_back((uintptr_t)I.c);
+        key.push_back((uintptr_t)I.rhs);
     }
-    return MG_OK;
-}
-
-// ||.||^2 of the partials rpart[local slot][nblocks] -> rtot_h[rhs] (async D2H).
-mg_status reduce_norms_to_host(mg_ctx* c, const SlotTable& st, int nblocks) {
-    const int pi = prof_begin(c, MG_K_REDUCE);
-    CK(mg::launch_reduce_real(c->rpart, nblocks, st.n, c->rtot, c->stream));
-    prof_end(c, pi);
-    // rtot[local] -> rtot_h[rhs]: copy contiguous block, scatter on the host later
-    CK(hipMemcpyAsync(c->rtot_h + mg::MAX_SLOTS * 0, c->rtot, st.n * sizeof(double), hipMemcpyDeviceToHost,
-                      c->stream));
-    return MG_OK;
-}
-
-// Per-rhs ||v||^2 of a vector indexed by rhs (synchronises).
-mg_status norms_by_rhs(mg_ctx* c, const std::vector<Slot>& slots, const cx<double>* x, std::vector<double>& out) {
-    const long long N = c->lv[0].N;
-    const int nb = mg::residual_blocks(N);
-    for (const SlotTable& st : groups(slots)) {
-        CK(mg::launch_norm(st, x, false, N, c->rpart, nb, c->stream));
-        CK(mg::launch_reduce_real(c->rpart, nb, st.n, c->rtot, c->stream));
-        CK(hipMemcpyAsync(c->rtot_h, c->rtot, st.n * sizeof(double), hipMemcpyDeviceToHost, c->stream));
-        CK(hipStreamSynchronize(c->stream));
-        for (int k = 0; k < st.n; ++k) out[st.s[k].rhs] = c->rtot_h[k];
+    auto f = R.gc->execs.find(key);
+    if (f == R.gc->execs.end()) {
+        if (!R.gc->capture) CK(hipStreamCreateWithFlags(&R.gc->capture, hipStreamNonBlocking));
+        Run Q = R;
+        Q.s = R.gc->capture;
+        Q.prof = nullptr;
+        CK(hipStreamBeginCapture(Q.s, hipStreamCaptureModeThreadLocal));
+        const mg_status st = record(Q);
+        hipGraph_t g = nullptr;
+        const hipError_t e = hipStreamEndCapture(Q.s, &g);
+        if (st != MG_OK) {
+            if (g) (void)hipGraphDestroy(g);
+            return st;
+        }
+        CK(e);
+        hipGraphExec_t ex = nullptr;
+        const hipError_t ei = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        CK(ei);
+        f = R.gc->execs.emplace(key, ex).first;
     }
+    double by = 0.0;   // algorithmic bytes of every level >= 1 kernel
+    if (R.prof && R.prof->on) {
+        const double ct = R.mixed ? 8.0 : 16.0, sk = R.mixed ? 4.0 : 8.0;
+        for (const Item& I : it)
+            for (int l = 1; l + 1 < I.c->L; ++l)
+                by += I.c->lv[l].N * (ct + sk) + I.c->lv[l + 1].N * ct +
+                      I.c->lv[l].N * (3 * ct + sk) + I.c->lv[l + 1].N * ct;
+    }
+    const int pi = prof_begin(R, MG_K_COARSE_LEVELS, by);
+    CK(hipGraphLaunch(f->second, R.s));
+    prof_end(R, pi);
     return MG_OK;
 }
 
-// y = f - A x (f == nullptr: y = A x) for the slots, y at slot.out_off, with
-// ||y||^2 per rhs into nrm (nullptr: skip; synchronises otherwise).
-mg_status residual(mg_ctx* c, int l, int dir, const std::vector<Slot>& slots, const cx<double>* x,
-                   const cx<double>* f, cx<double>* y, std::vector<double>* nrm) {
-    const long long N = c->lv[l].N;
-    const int nb = mg::residual_blocks(N);
-    for (const SlotTable& st : groups(slots)) {
-        mg::ResidualArgs a{};
-        a.lv = view<double>(c, l, dir);
-        a.st = st;
-        a.x = x;
-        a.f = f;
-        a.y = y;
-        a.norm_part = nrm ? c->rpart : nullptr;
-        a.nblocks = nb;
-        // read x, k^2 (and f), write y
-        const int pi = prof_begin(c, MG_K_RESIDUAL, (double)st.n * N * (16.0 + 8.0 + 16.0 + (f ? 16.0 : 0.0)));
-        CK(mg::launch_residual(c->dim, a, c->stream));
-        prof_end(c, pi);
+// One V(1,1) cycle for the items.  With norms (and incoming iterates),
+// ||f - A u||^2 of item k lands in w->rtot_h[k] once the stream gets there.
+mg_status vcycle(Run& R, int dir, const std::vector<Item>& it, const std::vector<L0>& l0, bool acc,
+                 bool norms) {
+    if (R.mixed && l0[0].u) return MG_E_STATE;
+    CKS(launch_ka(R, dir, it, &l0, 0, norms));
+    CKS(coarse_part(R, dir, it));
+    CKS(launch_kb(R, dir, it, &l0, 0, acc));
+    return MG_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Vector kernels over items
+// ---------------------------------------------------------------------------
+mg_status build_vec(Run& R, int dir, const std::vector<Item>& it, const std::vector<int>& sub,
+                    VecArgs& a, int* cnt) {
+    a.st.n = (int)sub.size();
+    int blocks = 0;
+    for (int q = 0; q < a.st.n; ++q) {
+        const Item& I = it[sub[q]];
+        VecSlot& s = a.st.s[q];
+        s.lv = I.c->views_d[dir];
+        s.block0 = blocks;
+        const int nb = mg::vec_blocks(I.c->lv[0].N);
+        if (nb > R.w->bstride) return MG_E_STATE;
+        cnt[q] = nb;
+        blocks += nb;
+    }
+    a.st.nblocks = blocks;
+    a.part = R.w->part;
+    a.rpart = R.w->rpart;
+    a.pstride = HSTRIDE;
+    a.bstride = R.w->bstride;
+    return MG_OK;
+}
+
+mg_status reduce_real(Run& R, int n, const int* cnt) {
+    ReduceArgs ra{};
+    ra.rpart = R.w->rpart;
+    ra.rout = R.w->rtot;
+    ra.bstride = R.w->bstride;
+    for (int q = 0; q < n; ++q) ra.cnt[q] = cnt[q];
+    const int pi = prof_begin(R, MG_K_REDUCE);
+    CK(mg::launch_reduce(ra, n, true, R.s));
+    prof_end(R, pi);
+    return MG_OK;
+}
+
+mg_status reduce_complex(Run& R, int n, const int* cnt, int nvals, int toff) {
+    ReduceArgs ra{};
+    ra.part = R.w->part;
+    ra.out = R.w->tot + toff;
+    ra.nvals = nvals;
+    ra.pstride = HSTRIDE;
+    ra.bstride = R.w->bstride;
+    ra.ostride = TOT;
+    for (int q = 0; q < n; ++q) ra.cnt[q] = cnt[q];
+    const int pi = prof_begin(R, MG_K_REDUCE);
+    CK(mg::launch_reduce(ra, n, false, R.s));
+    prof_end(R, pi);
+    return MG_OK;
+}
+
+// ||x_k||^2 of every item (x[k] a full-length level-0 vector), synchronising.
+mg_status norms(Run& R, const std::vector<Item>& it, const std::vector<const cx<double>*>& x,
+                std::vector<double>& out) {
+    std::vector<int> all(it.size());
+    for (size_t k = 0; k < it.size(); ++k) all[k] = (int)k;
+    CKS(for_groups(all, [&](const std::vector<int>& sub, int gbase) -> mg_status {
+        VecArgs a{};
+        int cnt[mg::MAX_SLOTS];
+        CKS(build_vec(R, 0, it, sub, a, cnt));
+        for (int q = 0; q < a.st.n; ++q) a.st.s[q].x = x[sub[q]];
+        CK(mg::launch_norm(a, R.s));
+        CKS(reduce_real(R, a.st.n, cnt));
+        CK(hipMemcpyAsync(R.w->rtot_h + gbase, R.w->rtot, a.st.n * sizeof(double), hipMemcpyDeviceToHost, R.s));
+        return MG_OK;
+    }));
+    CK(hipStreamSynchronize(R.s));
+    out.resize(it.size());
+    for (size_t k = 0; k < it.size(); ++k) out[k] = R.w->rtot_h[k];
+    return MG_OK;
+}
+
+// y_k = f_k - A x_k (f_k null: y_k = A x_k) on level 0 for the items in
+// `who`; with nrm, ||y_k||^2 into (*nrm)[k] (synchronising).
+mg_status residual(Run& R, int dir, const std::vector<Item>& it, const std::vector<int>& who,
+                   const std::vector<const cx<double>*>& x, const std::vector<const cx<double>*>& f,
+                   const std::vector<cx<double>*>& y, std::vector<double>* nrm) {
+    CKS(for_groups(who, [&](const std::vector<int>& sub, int gbase) -> mg_status {
+        VecArgs a{};
+        int cnt[mg::MAX_SLOTS];
+        CKS(build_vec(R, dir, it, sub, a, cnt));
+        double by = 0.0;
+        for (int q = 0; q < a.st.n; ++q) {
+            a.st.s[q].x = x[sub[q]];
+            a.st.s[q].f = f[sub[q]];
+            a.st.s[q].y = y[sub[q]];
+            by += it[sub[q]].c->lv[0].N * (40.0 + (f[sub[q]] ? 16.0 : 0.0));
+        }
+        if (!nrm) a.rpart = nullptr;
+        const int pi = prof_begin(R, MG_K_RESIDUAL, by);
+        CK(mg::launch_residual(R.dim, a, R.s));
+        prof_end(R, pi);
         if (nrm) {
-            CKS(reduce_norms_to_host(c, st, nb));
-            CK(hipStreamSynchronize(c->stream));
-            for (int k = 0; k < st.n; ++k) (*nrm)[st.s[k].rhs] = c->rtot_h[k];
+            CKS(reduce_real(R, a.st.n, cnt));
+            CK(hipMemcpyAsync(R.w->rtot_h + gbase, R.w->rtot, a.st.n * sizeof(double), hipMemcpyDeviceToHost,
+                              R.s));
         }
+        return MG_OK;
+    }));
+    if (nrm) {
+        CK(hipStreamSynchronize(R.s));
+        nrm->assign(it.size(), 0.0);
+        for (size_t g = 0; g < who.size(); ++g) (*nrm)[who[g]] = R.w->rtot_h[g];
     }
     return MG_OK;
 }
@@ -469,79 +661,80 @@ mg_status ensure_basis(mg_ctx* c, int restart) {
 // the incoming iterate is formed inside the first fused kernel of each cycle
 // (FP64) or by the FP64 residual of the refinement step (mixed).
 // ---------------------------------------------------------------------------
-mg_status solve_standalone(mg_ctx* c, int dir, double* u, const double* f, double rtol, int maxit,
-                           int* iters, double* hist) {
-    const long long N = c->lv[0].N;
-    cx<double>* U = (cx<double>*)u;
-    const cx<double>* F = (const cx<double>*)f;
-    std::vector<Slot> all(c->nrhs);
-    for (int r = 0; r < c->nrhs; ++r) {
-        all[r] = Slot{};
-        all[r].rhs = r;
-        all[r].buf = r;
-        all[r].in_off = (long long)r * N;
-        all[r].out_off = (long long)r * N;
-        all[r].in_scale = 1.0;
-    }
-    std::vector<double> nf(c->nrhs);
-    CKS(norms_by_rhs(c, all, F, nf));
-    std::vector<int> state(c->nrhs, 0);   // 0 running, 1 converged, 2 maxit, 3 diverged
-    std::vector<int> its(c->nrhs, 0);
-    std::vector<Slot> active;
-    for (int r = 0; r < c->nrhs; ++r) {
-        if (nf[r] == 0.0) {   // f = 0: the solution is 0
-            CK(mg::launch_fill_zero(U + (long long)r * N, N * sizeof(cx<double>), c->stream));
-            state[r] = 1;
-            if (hist) hist[(size_t)r * (maxit + 1)] = 0.0;
+mg_status solve_standalone(Run& R, int dir, const std::vector<Item>& it, const std::vector<cx<double>*>& U,
+                           const std::vector<const cx<double>*>& F, double rtol, int maxit, int* iters,
+                           double* hist) {
+    const int n = (int)it.size();
+    std::vector<double> nf;
+    CKS(norms(R, it, F, nf));
+    std::vector<int> state(n, 0);   // 0 running, 1 converged, 2 maxit, 3 diverged
+    std::vector<int> its(n, 0);
+    std::vector<int> active;
+    for (int k = 0; k < n; ++k) {
+        if (nf[k] == 0.0) {   // f = 0: the solution is 0
+            CK(mg::launch_fill_zero(U[k], it[k].c->lv[0].N * sizeof(cx<double>), R.s));
+            state[k] = 1;
+            if (hist) hist[(size_t)k * (maxit + 1)] = 0.0;
         } else {
-            active.push_back(all[r]);
+            active.push_back(k);
         }
     }
-    const int ntile0 = c->lv[0].ntiles[0] * c->lv[0].ntiles[1] * c->lv[0].ntiles[2];
-    for (int k = 0; k < maxit && !active.empty(); ++k) {
-        std::vector<double> rho(c->nrhs, 0.0);
-        for (const SlotTable& st : groups(active)) {
-            if (!c->mixed) {
-                CKS(vcycle(c, dir, st, U, F, U, false, c->rpart));
-                CKS(reduce_norms_to_host(c, st, ntile0));
-                CK(hipStreamSynchronize(c->stream));
-                for (int q = 0; q < st.n; ++q) rho[st.s[q].rhs] = c->rtot_h[q];
-            } else {
-                // iterative refinement form: r = f - A u (FP64), u += M r
-                std::vector<Slot> v(st.s, st.s + st.n);
-                for (Slot& x : v) x.out_off = (long long)x.buf * N;
-                std::vector<double> nr(c->nrhs);
-                CKS(residual(c, 0, dir, v, U, F, c->W, &nr));
-                for (int q = 0; q < st.n; ++q) rho[st.s[q].rhs] = nr[st.s[q].rhs];
-                SlotTable s2 = st;
-                for (int q = 0; q < s2.n; ++q) s2.s[q].in_off = (long long)s2.s[q].buf * N;
-                CKS(vcycle(c, dir, s2, nullptr, c->W, U, true, nullptr));
-            }
+    for (int cyc = 0; cyc < maxit && !active.empty(); ++cyc) {
+        std::vector<Item> sub;
+        std::vector<L0> l0;
+        for (int k : active) {
+            sub.push_back(it[k]);
+            mg_ctx* c = it[k].c;
+            if (!R.mixed)
+                l0.push_back(L0{F[k], 1.0, U[k], U[k]});
+            else
+                l0.push_back(L0{c->W + (size_t)it[k].rhs * c->lv[0].N, 1.0, nullptr, U[k]});
         }
-        std::vector<Slot> next;
-        for (const Slot& sl : active) {
-            const int r = sl.rhs;
-            const double ratio = std::sqrt(rho[r]) / std::sqrt(nf[r]);
-            if (hist) hist[(size_t)r * (maxit + 1) + k] = ratio;
-            its[r] = k;
+        std::vector<double> rho(sub.size(), 0.0);
+        if (!R.mixed) {
+            CKS(vcycle(R, dir, sub, l0, false, true));
+            CK(hipStreamSynchronize(R.s));
+            for (size_t q = 0; q < sub.size(); ++q) rho[q] = R.w->rtot_h[q];
+        } else {
+            // iterative refinement form: r = f - A u (FP64), u += M r
+            std::vector<int> who(sub.size());
+            std::vector<const cx<double>*> xs, fs;
+            std::vector<cx<double>*> ys;
+            for (size_t q = 0; q < sub.size(); ++q) {
+                who[q] = (int)q;
+                xs.push_back(U[active[q]]);
+                fs.push_back(F[active[q]]);
+                ys.push_back((cx<double>*)l0[q].f);
+            }
+            std::vector<double> nr;
+            CKS(residual(R, dir, sub, who, xs, fs, ys, &nr));
+            rho = nr;
+            CKS(vcycle(R, dir, sub, l0, true, false));
+        }
+        std::vector<int> next;
+        for (size_t q = 0; q < sub.size(); ++q) {
+            const int k = active[q];
+            const double ratio = std::sqrt(rho[q]) / std::sqrt(nf[k]);
+            if (hist) hist[(size_t)k * (maxit + 1) + cyc] = ratio;
+            its[k] = cyc;
             if (ratio <= rtol) {
-                state[r] = 1;
+                state[k] = 1;
             } else if (!std::isfinite(ratio) || ratio > DIVERGE) {
-                state[r] = 3;
+                state[k] = 3;
             } else {
-                its[r] = k + 1;
-                next.push_back(sl);
+                its[k] = cyc + 1;
+                next.push_back(k);
             }
         }
         active.swap(next);
     }
-    CK(hipStreamSynchronize(c->stream));
+    CK(hipStreamSynchronize(R.s));
     mg_status ret = MG_OK;
-    for (int r = 0; r < c->nrhs; ++r) {
-        if (state[r] == 0) state[r] = 2;
-        if (iters) iters[r] = its[r];
-        if (state[r] == 3) ret = MG_E_DIVERGED;
-        else if (state[r] == 2 && ret == MG_OK) ret = MG_NOT_CONVERGED;
+    for (int k = 0; k < n; ++k) {
+        if (state[k] == 0) state[k] = 2;
+        if (iters) iters[k] = its[k];
+        if (state[k] == 3) ret = MG_E_DIVERGED;
+        else if (state[k] == 2 && ret == MG_OK) ret = MG_NOT_CONVERGED;
     }
     return ret;
 }
@@ -557,7 +750,6 @@ struct GmresState {
     int j = 0;                  // basis vectors V_0..V_j exist
     int its = 0;
     int state = 0;              // 0 arnoldi, 1 converged, 2 maxit, 3 diverged
-    bool finish = false;        // restart cycle ends after this step
     double nf = 0.0;
     std::vector<cd> H;          // (m+1) x m, column-major
     std::vector<double> cs;
@@ -565,48 +757,48 @@ struct GmresState {
     std::vector<cd> g;
 };
 
-mg_status solve_gmres(mg_ctx* c, int dir, double* x, const double* f, double rtol, int maxit, int m,
-                      int* iters, double* hist) {
-    const long long N = c->lv[0].N;
-    cx<double>* X = (cx<double>*)x;
-    const cx<double>* F = (const cx<double>*)f;
-    CKS(ensure_basis(c, m));
-    const int vs = c->vstride;
-    std::vector<GmresState> gs(c->nrhs);
-    std::vector<Slot> all(c->nrhs);
-    for (int r = 0; r < c->nrhs; ++r) {
-        all[r] = Slot{};
-        all[r].rhs = r;
-        all[r].buf = r;
-        all[r].in_scale = 1.0;
-        gs[r].H.assign((size_t)(m + 1) * m, 0.0);
-        gs[r].cs.assign(m, 0.0);
-        gs[r].sn.assign(m, 0.0);
-        gs[r].g.assign(m + 1, 0.0);
-    }
-    std::vector<double> nf(c->nrhs);
-    CKS(norms_by_rhs(c, all, F, nf));
-    std::vector<int> hist_len(c->nrhs, 0);
-    auto push_hist = [&](int r, double v) {
-        if (hist && hist_len[r] <= maxit) hist[(size_t)r * (maxit + 1) + hist_len[r]] = v;
-        hist_len[r]++;
-    };
+cx<double>* basis(const Item& I, int i) {
+    mg_ctx* c = I.c;
+    return c->V + ((size_t)I.rhs * c->vstride + i) * c->lv[0].N;
+}
 
-    // (Re)start: r = f - A x into V_0, beta = ||r||; decide per rhs.
-    auto restart = [&](std::vector<int>& who) -> mg_status {
-        std::vector<Slot> sl;
-        for (int r : who) {
-            Slot s = all[r];
-            s.out_off = (long long)r * vs * N;
-            sl.push_back(s);
+mg_status solve_gmres(Run& R, int dir, const std::vector<Item>& it, const std::vector<cx<double>*>& X,
+                      const std::vector<const cx<double>*>& F, double rtol, int maxit, int m, int* iters,
+                      double* hist) {
+    const int n = (int)it.size();
+    for (const Item& I : it) CKS(ensure_basis(I.c, m));
+    std::vector<GmresState> gs(n);
+    for (int k = 0; k < n; ++k) {
+        gs[k].H.assign((size_t)(m + 1) * m, 0.0);
+        gs[k].cs.assign(m, 0.0);
+        gs[k].sn.assign(m, 0.0);
+        gs[k].g.assign(m + 1, 0.0);
+    }
+    std::vector<double> nf;
+    CKS(norms(R, it, F, nf));
+    std::vector<int> hist_len(n, 0);
+    auto push_hist = [&](int k, double v) {
+        if (hist && hist_len[k] <= maxit) hist[(size_t)k * (maxit + 1) + hist_len[k]] = v;
+        hist_len[k]++;
+    };
+    auto scale_h = [&](int k, int i) -> double& { return it[k].c->scale_h[(size_t)it[k].rhs * HSTRIDE + i]; };
+
+    // (Re)start: r = f - A x into V_0, beta = ||r||; decide per item.
+    auto restart = [&](const std::vector<int>& who) -> mg_status {
+        std::vector<const cx<double>*> xs(n), fs(n);
+        std::vector<cx<double>*> ys(n);
+        for (int k : who) {
+            xs[k] = X[k];
+            fs[k] = F[k];
+            ys[k] = basis(it[k], 0);
         }
-        std::vector<double> beta2(c->nrhs, 0.0);
-        CKS(residual(c, 0, dir, sl, X, F, c->V, &beta2));
-        for (int r : who) {
-            GmresState& G = gs[r];
-            const double beta = std::sqrt(beta2[r]);
+        std::vector<double> beta2;
+        CKS(residual(R, dir, it, who, xs, fs, ys, &beta2));
+        for (int k : who) {
+            GmresState& G = gs[k];
+            const double beta = std::sqrt(beta2[k]);
             const double ratio = beta / G.nf;
-            if (hist_len[r] == 0) push_hist(r, ratio);
+            if (hist_len[k] == 0) push_hist(k, ratio);
             if (ratio <= rtol) {
                 G.state = 1;
             } else if (!std::isfinite(ratio)) {
@@ -615,106 +807,107 @@ mg_status solve_gmres(mg_ctx* c, int dir, double* x, const double* f, double rto
                 G.state = 2;
             } else {
                 G.j = 0;
-                G.finish = false;
                 std::fill(G.g.begin(), G.g.end(), cd(0.0));
                 G.g[0] = beta;
-                c->scale_h[(size_t)r * HSTRIDE + 0] = 1.0 / beta;
+                scale_h(k, 0) = 1.0 / beta;
             }
         }
         return MG_OK;
     };
 
     std::vector<int> who;
-    for (int r = 0; r < c->nrhs; ++r) {
-        gs[r].nf = std::sqrt(nf[r]);
-        if (nf[r] == 0.0) {
-            CK(mg::launch_fill_zero(X + (long long)r * N, N * sizeof(cx<double>), c->stream));
-            gs[r].state = 1;
-            push_hist(r, 0.0);
+    for (int k = 0; k < n; ++k) {
+        gs[k].nf = std::sqrt(nf[k]);
+        if (nf[k] == 0.0) {
+            CK(mg::launch_fill_zero(X[k], it[k].c->lv[0].N * sizeof(cx<double>), R.s));
+            gs[k].state = 1;
+            push_hist(k, 0.0);
         } else {
-            who.push_back(r);
+            who.push_back(k);
         }
     }
     CKS(restart(who));
 
+    std::vector<mg_ctx*> ctxs;
+    for (const Item& I : it)
+        if (std::find(ctxs.begin(), ctxs.end(), I.c) == ctxs.end()) ctxs.push_back(I.c);
+
     for (;;) {
-        std::vector<Slot> act;
+        std::vector<int> act;
         int jmax = 0;
-        for (int r = 0; r < c->nrhs; ++r) {
-            if (gs[r].state != 0) continue;
-            Slot s = all[r];
-            s.j = gs[r].j;
-            s.in_off = ((long long)r * vs + gs[r].j) * N;
-            s.in_scale = c->scale_h[(size_t)r * HSTRIDE + gs[r].j];
-            s.out_off = (long long)r * N;
-            act.push_back(s);
-            jmax = std::max(jmax, gs[r].j + 1);
-        }
+        for (int k = 0; k < n; ++k)
+            if (gs[k].state == 0) {
+                act.push_back(k);
+                jmax = std::max(jmax, gs[k].j + 1);
+            }
         if (act.empty()) break;
-        // scales of every active basis to the device
-        CK(hipMemcpyAsync(c->scale_d, c->scale_h, (size_t)c->nrhs * HSTRIDE * sizeof(double),
-                          hipMemcpyHostToDevice, c->stream));
-        const int nb = mg::ortho_blocks(N);
-        int gbase = 0;
-        for (const SlotTable& st : groups(act)) {
-            // z = M v_j
-            CKS(vcycle(c, dir, st, nullptr, c->V, c->Z, false, nullptr));
-            mg::OrthoArgs o{};
-            o.lv = view<double>(c, 0, dir);
-            o.st = st;
-            o.N = N;
-            o.z = c->Z;
-            o.w = c->W;
-            o.Vb = c->V;
-            o.vstride = vs;
-            o.scale = c->scale_d;
-            o.sstride = HSTRIDE;
-            o.hstride = TOT;
-            o.part = c->part;
-            o.pstride = HSTRIDE;
-            o.nblocks = nb;
-            // basis vectors read per pass: sum over slots of (j + 1)
-            double nvsum = 0.0;
-            for (int q = 0; q < st.n; ++q) nvsum += st.s[q].j + 1;
-            const double vb = 16.0 * N;
-            // pass 1: w = A z, h1 = V^H w; reads z, k^2, V_0..V_j, writes w
-            int pi = prof_begin(c, MG_K_MATVEC_DOT, vb * (nvsum + 2.0 * st.n) + 8.0 * N * st.n);
-            CK(mg::launch_matvec_dot(c->dim, jmax, o, c->stream));
-            prof_end(c, pi);
-            pi = prof_begin(c, MG_K_REDUCE);
-            CK(mg::launch_reduce_complex(c->part, jmax, HSTRIDE, nb, st.n, c->tot, TOT, c->stream));
-            prof_end(c, pi);
-            // pass 2: w -= V h1, h2 = V^H w
-            o.hin = c->tot;
-            pi = prof_begin(c, MG_K_UPDATE_DOT, vb * (nvsum + 2.0 * st.n));
-            CK(mg::launch_update_dot(jmax, o, c->stream));
-            prof_end(c, pi);
-            pi = prof_begin(c, MG_K_REDUCE);
-            CK(mg::launch_reduce_complex(c->part, jmax, HSTRIDE, nb, st.n, c->tot + HSTRIDE, TOT, c->stream));
-            prof_end(c, pi);
-            // pass 3: V_{j+1} = w - V h2, ||V_{j+1}||^2
-            o.hin = c->tot + HSTRIDE;
-            pi = prof_begin(c, MG_K_UPDATE_NORM, vb * (nvsum + 2.0 * st.n));
-            CK(mg::launch_update_norm(jmax, o, c->stream));
-            prof_end(c, pi);
-            pi = prof_begin(c, MG_K_REDUCE);
-            CK(mg::launch_reduce_complex(c->part, 1, HSTRIDE, nb, st.n, c->tot + 2 * HSTRIDE, TOT, c->stream));
-            prof_end(c, pi);
-            CK(hipMemcpyAsync(c->tot_h + (size_t)gbase * TOT, c->tot, (size_t)st.n * TOT * sizeof(cx<double>),
-                              hipMemcpyDeviceToHost, c->stream));
-            gbase += st.n;
+        // scales of every basis to the device
+        for (mg_ctx* c : ctxs)
+            CK(hipMemcpyAsync(c->scale_d, c->scale_h, (size_t)c->nrhs * HSTRIDE * sizeof(double),
+                              hipMemcpyHostToDevice, R.s));
+        // z = M v_j for every active item
+        std::vector<Item> sub;
+        std::vector<L0> l0;
+        for (int k : act) {
+            sub.push_back(it[k]);
+            mg_ctx* c = it[k].c;
+            l0.push_back(L0{basis(it[k], gs[k].j), scale_h(k, gs[k].j), nullptr,
+                            c->Z + (size_t)it[k].rhs * c->lv[0].N});
         }
-        CK(hipStreamSynchronize(c->stream));
+        CKS(vcycle(R, dir, sub, l0, false, false));
+        std::vector<int> local(act.size());
+        for (size_t q = 0; q < act.size(); ++q) local[q] = (int)q;
+        CKS(for_groups(local, [&](const std::vector<int>& g, int gbase) -> mg_status {
+            VecArgs a{};
+            int cnt[mg::MAX_SLOTS];
+            CKS(build_vec(R, dir, sub, g, a, cnt));
+            double nvsum = 0.0, vb = 0.0;
+            for (int q = 0; q < a.st.n; ++q) {
+                const int k = act[g[q]];
+                mg_ctx* c = it[k].c;
+                VecSlot& s = a.st.s[q];
+                s.x = c->Z + (size_t)it[k].rhs * c->lv[0].N;
+                s.y = c->W + (size_t)it[k].rhs * c->lv[0].N;
+                s.V = basis(it[k], 0);
+                s.scale = c->scale_d + (size_t)it[k].rhs * HSTRIDE;
+                s.j = gs[k].j;
+                s.hin = R.w->tot + (size_t)q * TOT;
+                nvsum += 16.0 * c->lv[0].N * (gs[k].j + 1);
+                vb += 16.0 * c->lv[0].N;
+            }
+            // pass 1: w = A z, h1 = V^H w; reads z, k^2, V_0..V_j, writes w
+            int pi = prof_begin(R, MG_K_MATVEC_DOT, nvsum + 2.0 * vb + 0.5 * vb);
+            CK(mg::launch_matvec_dot(R.dim, jmax, a, R.s));
+            prof_end(R, pi);
+            CKS(reduce_complex(R, a.st.n, cnt, jmax, 0));
+            // pass 2: w -= V h1, h2 = V^H w
+            pi = prof_begin(R, MG_K_UPDATE_DOT, nvsum + 2.0 * vb);
+            CK(mg::launch_update_dot(jmax, a, R.s));
+            prof_end(R, pi);
+            CKS(reduce_complex(R, a.st.n, cnt, jmax, HSTRIDE));
+            // pass 3: V_{j+1} = w - V h2, ||V_{j+1}||^2
+            for (int q = 0; q < a.st.n; ++q) a.st.s[q].hin = R.w->tot + (size_t)q * TOT + HSTRIDE;
+            pi = prof_begin(R, MG_K_UPDATE_NORM, nvsum + 2.0 * vb);
+            CK(mg::launch_update_norm(jmax, a, R.s));
+            prof_end(R, pi);
+            CKS(reduce_real(R, a.st.n, cnt));
+            CK(hipMemcpyAsync(R.w->tot_h + (size_t)gbase * TOT, R.w->tot, (size_t)a.st.n * TOT * sizeof(cx<double>),
+                              hipMemcpyDeviceToHost, R.s));
+            CK(hipMemcpyAsync(R.w->rtot_h + gbase, R.w->rtot, a.st.n * sizeof(double), hipMemcpyDeviceToHost,
+                              R.s));
+            return MG_OK;
+        }));
+        CK(hipStreamSynchronize(R.s));
 
         std::vector<int> fin;
         for (size_t q = 0; q < act.size(); ++q) {
-            const int r = act[q].rhs;
-            GmresState& G = gs[r];
-            const cx<double>* T = c->tot_h + q * TOT;
+            const int k = act[q];
+            GmresState& G = gs[k];
+            const cx<double>* T = R.w->tot_h + q * TOT;
             const int j = G.j;
             cd* col = &G.H[(size_t)j * (m + 1)];
             for (int i = 0; i <= j; ++i) col[i] = cd(T[i].r, T[i].i) + cd(T[HSTRIDE + i].r, T[HSTRIDE + i].i);
-            const double hn = std::sqrt(std::max(0.0, T[2 * HSTRIDE].r));
+            const double hn = std::sqrt(std::max(0.0, R.w->rtot_h[q]));
             col[j + 1] = hn;
             for (int i = 0; i < j; ++i) {
                 const cd a = col[i], b = col[i + 1];
@@ -744,87 +937,115 @@ mg_status solve_gmres(mg_ctx* c, int dir, double* x, const double* f, double rto
             G.g[j] = cj * G.g[j];
             G.its++;
             const double est = std::abs(G.g[j + 1]) / G.nf;
-            push_hist(r, est);
+            push_hist(k, est);
             if (!std::isfinite(est)) {
                 G.state = 3;
                 continue;
             }
-            if (hn != 0.0) c->scale_h[(size_t)r * HSTRIDE + j + 1] = 1.0 / hn;
-            if (est <= rtol || G.its >= maxit || j + 1 == m || hn == 0.0) {
-                fin.push_back(r);
-            } else {
+            if (hn != 0.0) scale_h(k, j + 1) = 1.0 / hn;
+            if (est <= rtol || G.its >= maxit || j + 1 == m || hn == 0.0)
+                fin.push_back(k);
+            else
                 G.j = j + 1;
-            }
         }
         if (!fin.empty()) {
             // y = R^{-1} g, x += M (V y)
-            std::vector<Slot> fs;
-            for (int r : fin) {
-                GmresState& G = gs[r];
-                const int k = G.j + 1;
-                std::vector<cd> y(k);
-                for (int i = k - 1; i >= 0; --i) {
+            int jm = 0;
+            std::vector<Item> fs;
+            std::vector<L0> fl0;
+            for (int k : fin) {
+                GmresState& G = gs[k];
+                const int kk = G.j + 1;
+                std::vector<cd> y(kk);
+                for (int i = kk - 1; i >= 0; --i) {
                     cd s = G.g[i];
-                    for (int l = i + 1; l < k; ++l) s -= G.H[(size_t)l * (m + 1) + i] * y[l];
+                    for (int l = i + 1; l < kk; ++l) s -= G.H[(size_t)l * (m + 1) + i] * y[l];
                     y[i] = s / G.H[(size_t)i * (m + 1) + i];
                 }
-                for (int i = 0; i < k; ++i)
-                    c->coef_h[(size_t)r * HSTRIDE + i] = tocx(y[i] * c->scale_h[(size_t)r * HSTRIDE + i]);
-                Slot s = all[r];
-                s.j = G.j;
-                s.in_off = (long long)r * N;   // combine output W by buf (= r)
-                s.in_scale = 1.0;
-                s.out_off = (long long)r * N;
-                fs.push_back(s);
+                mg_ctx* c = it[k].c;
+                for (int i = 0; i < kk; ++i)
+                    c->coef_h[(size_t)it[k].rhs * HSTRIDE + i] = tocx(y[i] * scale_h(k, i));
+                jm = std::max(jm, kk);
+                fs.push_back(it[k]);
+                fl0.push_back(L0{c->W + (size_t)it[k].rhs * c->lv[0].N, 1.0, nullptr, X[k]});
             }
-            CK(hipMemcpyAsync(c->coef_d, c->coef_h, (size_t)c->nrhs * HSTRIDE * sizeof(cx<double>),
-                              hipMemcpyHostToDevice, c->stream));
-            int jm = 0;
-            for (int r : fin) jm = std::max(jm, gs[r].j + 1);
-            for (const SlotTable& st : groups(fs)) {
-                mg::CombineArgs cb{};
-                cb.st = st;
-                cb.N = N;
-                cb.Vb = c->V;
-                cb.vstride = vs;
-                cb.coef = c->coef_d;
-                cb.sstride = HSTRIDE;
-                cb.t = c->W;
-                double nvsum = 0.0;
-                for (int q = 0; q < st.n; ++q) nvsum += st.s[q].j + 1;
-                const int pi = prof_begin(c, MG_K_COMBINE, 16.0 * N * (nvsum + st.n));
-                CK(mg::launch_combine(jm, cb, c->stream));
-                prof_end(c, pi);
-                CKS(vcycle(c, dir, st, nullptr, c->W, X, true, nullptr));
-            }
+            for (mg_ctx* c : ctxs)
+                CK(hipMemcpyAsync(c->coef_d, c->coef_h, (size_t)c->nrhs * HSTRIDE * sizeof(cx<double>),
+                                  hipMemcpyHostToDevice, R.s));
+            std::vector<int> local2(fin.size());
+            for (size_t q = 0; q < fin.size(); ++q) local2[q] = (int)q;
+            CKS(for_groups(local2, [&](const std::vector<int>& g, int) -> mg_status {
+                VecArgs a{};
+                int cnt[mg::MAX_SLOTS];
+                CKS(build_vec(R, dir, fs, g, a, cnt));
+                double by = 0.0;
+                for (int q = 0; q < a.st.n; ++q) {
+                    const int k = fin[g[q]];
+                    mg_ctx* c = it[k].c;
+                    VecSlot& s = a.st.s[q];
+                    s.V = basis(it[k], 0);
+                    s.coef = c->coef_d + (size_t)it[k].rhs * HSTRIDE;
+                    s.y = c->W + (size_t)it[k].rhs * c->lv[0].N;
+                    s.j = gs[k].j;
+                    by += 16.0 * c->lv[0].N * (gs[k].j + 2);
+                }
+                const int pi = prof_begin(R, MG_K_COMBINE, by);
+                CK(mg::launch_combine(jm, a, R.s));
+                prof_end(R, pi);
+                return MG_OK;
+            }));
+            CKS(vcycle(R, dir, fs, fl0, true, false));
             CKS(restart(fin));
         }
     }
-    CK(hipStreamSynchronize(c->stream));
+    CK(hipStreamSynchronize(R.s));
     mg_status ret = MG_OK;
-    for (int r = 0; r < c->nrhs; ++r) {
-        if (iters) iters[r] = gs[r].its;
-        if (gs[r].state == 3) ret = MG_E_DIVERGED;
-        else if (gs[r].state == 2 && ret == MG_OK) ret = MG_NOT_CONVERGED;
+    for (int k = 0; k < n; ++k) {
+        if (iters) iters[k] = gs[k].its;
+        if (gs[k].state == 3) ret = MG_E_DIVERGED;
+        else if (gs[k].state == 2 && ret == MG_OK) ret = MG_NOT_CONVERGED;
     }
     return ret;
 }
 
-mg_status solve(mg_ctx* c, int dir, double* u, const double* f, int mode, double rtol, int maxit, int restart,
-                int* iters, double* hist) {
-    if (!c || !u || !f || maxit < 0 || !(rtol >= 0.0)) return MG_E_INVAL;
+mg_status solve_items(Run& R, int dir, const std::vector<Item>& it, const std::vector<cx<double>*>& U,
+                      const std::vector<const cx<double>*>& F, int mode, double rtol, int maxit, int restart,
+                      int* iters, double* hist) {
+    if (maxit < 0 || !(rtol >= 0.0)) return MG_E_INVAL;
     if (hist)
-        for (size_t i = 0; i < (size_t)c->nrhs * (maxit + 1); ++i) hist[i] = -1.0;
-    if (mode == MG_MODE_STANDALONE) return solve_standalone(c, dir, u, f, rtol, maxit, iters, hist);
+        for (size_t i = 0; i < it.size() * (size_t)(maxit + 1); ++i) hist[i] = -1.0;
+    if (mode == MG_MODE_STANDALONE) return solve_standalone(R, dir, it, U, F, rtol, maxit, iters, hist);
     if (mode == MG_MODE_GMRES) {
         if (restart < 1 || restart > MAX_RESTART) return MG_E_INVAL;
-        return solve_gmres(c, dir, u, f, rtol, maxit, restart, iters, hist);
+        return solve_gmres(R, dir, it, U, F, rtol, maxit, restart, iters, hist);
     }
     return MG_E_INVAL;
 }
 
+Run ctx_run(mg_ctx* c) { return Run{c->stream, &c->prof, &c->work, &c->graphs, c->dim, c->mixed}; }
+
+mg_status ctx_solve(mg_ctx* c, int dir, double* u, const double* f, int mode, double rtol, int maxit,
+                    int restart, int* iters, double* hist) {
+    if (!c || !u || !f) return MG_E_INVAL;
+    std::vector<Item> it;
+    std::vector<cx<double>*> U;
+    std::vector<const cx<double>*> F;
+    const long long N = c->lv[0].N;
+    for (int r = 0; r < c->nrhs; ++r) {
+        it.push_back(Item{c, r});
+        U.push_back((cx<double>*)u + (size_t)r * N);
+        F.push_back((const cx<double>*)f + (size_t)r * N);
+    }
+    Run R = ctx_run(c);
+    return solve_items(R, dir, it, U, F, mode, rtol, maxit, restart, iters, hist);
+}
+
+// ---------------------------------------------------------------------------
+// Set-up
+// ---------------------------------------------------------------------------
 void release(mg_ctx* c) {
     if (!c) return;
+    graphs_free(c->graphs);
     for (Level& L : c->lv) {
         for (int d = 0; d < 2; ++d) {
             dfree(L.coef_d[d]);
@@ -838,6 +1059,8 @@ void release(mg_ctx* c) {
     for (int d = 0; d < 2; ++d) {
         dfree(c->lu[d]);
         dfree(c->piv[d]);
+        dfree(c->views_d[d]);
+        dfree(c->views_f[d]);
     }
     dfree(c->U1);
     dfree(c->Z);
@@ -845,16 +1068,112 @@ void release(mg_ctx* c) {
     dfree(c->V);
     dfree(c->scale_d);
     dfree(c->coef_d);
-    dfree(c->part);
-    dfree(c->rpart);
-    dfree(c->tot);
-    dfree(c->rtot);
     hfree(c->scale_h);
     hfree(c->coef_h);
-    hfree(c->tot_h);
-    hfree(c->rtot_h);
+    work_free(c->work);
     for (hipEvent_t e : c->prof.pool) (void)hipEventDestroy(e);
     c->prof.pool.clear();
+}
+
+// Device descriptors of every level, both directions and precisions.
+mg_status upload_views(mg_ctx* c) {
+    const int d = c->dim;
+    for (int dir = 0; dir < 2; ++dir) {
+        std::vector<LevelView<double>> vd(c->L);
+        std::vector<LevelView<float>> vf(c->L);
+        for (int l = 0; l < c->L; ++l) {
+            const Level& V = c->lv[l];
+            LevelView<double>& a = vd[l];
+            LevelView<float>& b = vf[l];
+            a = LevelView<double>{};
+            b = LevelView<float>{};
+            for (int ax = 0; ax < 3; ++ax) {
+                const int aa = ax < d ? ax : 0;
+                long long o = 0;
+                for (int q = 0; q < aa; ++q) o += 3LL * V.n[q];
+                a.n[ax] = b.n[ax] = ax < d ? V.n[ax] : 1;
+                a.cm[ax] = V.coef_d[dir] + o;
+                a.c0[ax] = V.coef_d[dir] + o + V.n[aa];
+                a.cp[ax] = V.coef_d[dir] + o + 2LL * V.n[aa];
+                if (c->mixed) {
+                    b.cm[ax] = V.coef_f[dir] + o;
+                    b.c0[ax] = V.coef_f[dir] + o + V.n[aa];
+                    b.cp[ax] = V.coef_f[dir] + o + 2LL * V.n[aa];
+                }
+            }
+            a.N = b.N = V.N;
+            a.k2 = V.k2;
+            b.k2 = V.k2f;
+            const cd s = dir ? std::conj(V.sigma) : V.sigma;
+            a.sigma = tocx(s);
+            b.sigma = mg::mk((float)s.real(), (float)s.imag());
+            a.omega = mg::mk(c->p.omega[0], c->p.omega[1]);
+            b.omega = mg::mk((float)c->p.omega[0], (float)c->p.omega[1]);
+            if (l == c->L - 1) {
+                a.lu = b.lu = c->lu[dir];
+                a.piv = b.piv = c->piv[dir];
+            }
+        }
+        CKS(dalloc(&c->views_d[dir], vd.size() * sizeof(LevelView<double>)));
+        CK(hipMemcpy(c->views_d[dir], vd.data(), vd.size() * sizeof(LevelView<double>), hipMemcpyHostToDevice));
+        if (c->mixed) {
+            CKS(dalloc(&c->views_f[dir], vf.size() * sizeof(LevelView<float>)));
+            CK(hipMemcpy(c->views_f[dir], vf.data(), vf.size() * sizeof(LevelView<float>), hipMemcpyHostToDevice));
+        }
+    }
+    return MG_OK;
+}
+
+// Pick the tile shape of every large enough level by timing the two fused
+// kernels (zero-guess variants, all right-hand sides) for every shape.
+mg_status autotune(mg_ctx* c) {
+    std::vector<Item> it;
+    std::vector<L0> l0;
+    const long long N0 = c->lv[0].N;
+    if (N0 < AUTOTUNE_MIN_POINTS) return MG_OK;
+    CK(mg::launch_fill_zero(c->Z, (long long)c->nrhs * N0 * sizeof(cx<double>), c->stream));
+    for (int r = 0; r < c->nrhs; ++r) {
+        it.push_back(Item{c, r});
+        l0.push_back(L0{c->Z + (size_t)r * N0, 1.0, nullptr, c->W + (size_t)r * N0});
+    }
+    for (int l = 1; l < c->L; ++l) {
+        CK(mg::launch_fill_zero(c->lv[l].F, (long long)c->nrhs * c->lv[l].N * elem(c), c->stream));
+        CK(mg::launch_fill_zero(c->lv[l].E, (long long)c->nrhs * c->lv[l].N * elem(c), c->stream));
+    }
+    hipEvent_t e0, e1;
+    CK(hipEventCreate(&e0));
+    CK(hipEventCreate(&e1));
+    Run R = ctx_run(c);
+    R.prof = nullptr;
+    R.gc = nullptr;
+    mg_status st = MG_OK;
+    for (int l = 0; l + 1 < c->L && st == MG_OK; ++l) {
+        if (c->lv[l].N < AUTOTUNE_MIN_POINTS) break;
+        float best = 1e30f;
+        int best_shape = 0;
+        for (int shape = 0; shape < mg::NUM_TILE_SHAPES && st == MG_OK; ++shape) {
+            c->lv[l].shape = shape;
+            float tot = 0.0f;
+            for (int rep = 0; rep < 4 && st == MG_OK; ++rep) {
+                if (hipEventRecord(e0, c->stream) != hipSuccess) st = MG_E_DEVICE;
+                if (st == MG_OK) st = launch_ka(R, 0, it, &l0, l, false);
+                if (st == MG_OK) st = launch_kb(R, 0, it, &l0, l, false);
+                if (st == MG_OK && hipEventRecord(e1, c->stream) != hipSuccess) st = MG_E_DEVICE;
+                if (st == MG_OK && hipEventSynchronize(e1) != hipSuccess) st = MG_E_DEVICE;
+                float ms = 0.0f;
+                if (st == MG_OK && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) st = MG_E_DEVICE;
+                if (rep > 0) tot += ms;
+            }
+            if (tot < best) {
+                best = tot;
+                best_shape = shape;
+            }
+        }
+        c->lv[l].shape = best_shape;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return st;
 }
 
 mg_status setup(const mg_params* p, const double* k2_dev, void* stream, mg_ctx* c) {
@@ -893,7 +1212,6 @@ mg_status setup(const mg_params* p, const double* k2_dev, void* stream, mg_ctx* 
             if (l + 1 < L && V.n[a] % 2 == 0) return MG_E_INVAL;
         }
         V.N = (long long)V.n[0] * V.n[1] * V.n[2];
-        mg::tile_counts(d, c->mixed, V.n, V.ntiles);
     }
     c->ncoarse = (int)c->lv[L - 1].N;
     if (c->ncoarse > mg::MAX_COARSE) return MG_E_INVAL;
@@ -924,14 +1242,14 @@ mg_status setup(const mg_params* p, const double* k2_dev, void* stream, mg_ctx* 
                 hp[j] = j + 1 < na ? std::conj(cm[j + 1]) : cd(0.0);
                 h0[j] = std::conj(c0[j]);
             }
-            auto& F = V.coef_host[0];
-            F.insert(F.end(), cm.begin(), cm.end());
-            F.insert(F.end(), c0.begin(), c0.end());
-            F.insert(F.end(), cp.begin(), cp.end());
-            auto& H = V.coef_host[1];
-            H.insert(H.end(), hm.begin(), hm.end());
-            H.insert(H.end(), h0.begin(), h0.end());
-            H.insert(H.end(), hp.begin(), hp.end());
+            auto& Fw = V.coef_host[0];
+            Fw.insert(Fw.end(), cm.begin(), cm.end());
+            Fw.insert(Fw.end(), c0.begin(), c0.end());
+            Fw.insert(Fw.end(), cp.begin(), cp.end());
+            auto& Hw = V.coef_host[1];
+            Hw.insert(Hw.end(), hm.begin(), hm.end());
+            Hw.insert(Hw.end(), h0.begin(), h0.end());
+            Hw.insert(Hw.end(), hp.begin(), hp.end());
         }
         for (int dir = 0; dir < 2; ++dir) {
             const auto& src = V.coef_host[dir];
@@ -1001,9 +1319,10 @@ mg_status setup(const mg_params* p, const double* k2_dev, void* stream, mg_ctx* 
             CK(hipMemcpy(c->piv[dir], piv.data(), nc * sizeof(int), hipMemcpyHostToDevice));
         }
     }
+    CKS(upload_views(c));
 
     // work vectors
-    const size_t esz = c->mixed ? sizeof(cx<float>) : sizeof(cx<double>);
+    const size_t esz = elem(c);
     for (int l = 1; l < L; ++l) {
         CKS(dalloc(&c->lv[l].F, (size_t)c->nrhs * c->lv[l].N * esz));
         CKS(dalloc(&c->lv[l].E, (size_t)c->nrhs * c->lv[l].N * esz));
@@ -1012,19 +1331,19 @@ mg_status setup(const mg_params* p, const double* k2_dev, void* stream, mg_ctx* 
     if (!c->mixed) CKS(dalloc(&c->U1, vbytes));
     CKS(dalloc(&c->Z, vbytes));
     CKS(dalloc(&c->W, vbytes));
-    const int ntile0 = c->lv[0].ntiles[0] * c->lv[0].ntiles[1] * c->lv[0].ntiles[2];
-    c->part_blocks = std::max<long long>({(long long)ntile0, mg::residual_blocks(c->lv[0].N),
-                                          mg::ortho_blocks(c->lv[0].N)});
-    CKS(dalloc(&c->part, (size_t)mg::MAX_SLOTS * TOT * c->part_blocks * sizeof(cx<double>)));
-    CKS(dalloc(&c->rpart, (size_t)mg::MAX_SLOTS * c->part_blocks * sizeof(double)));
-    CKS(dalloc(&c->tot, (size_t)mg::MAX_SLOTS * TOT * sizeof(cx<double>)));
-    CKS(dalloc(&c->rtot, (size_t)mg::MAX_SLOTS * sizeof(double)));
+    int maxt = 0;
+    for (int shape = 0; shape < mg::NUM_TILE_SHAPES; ++shape) {
+        int nt[3];
+        mg::tile_counts(d, shape, c->lv[0].n, nt);
+        maxt = std::max(maxt, nt[0] * nt[1] * nt[2]);
+    }
+    CKS(work_alloc(c->work, c->nrhs, std::max(maxt, mg::vec_blocks(c->lv[0].N))));
     CKS(dalloc(&c->scale_d, (size_t)c->nrhs * HSTRIDE * sizeof(double)));
     CKS(dalloc(&c->coef_d, (size_t)c->nrhs * HSTRIDE * sizeof(cx<double>)));
     CKS(halloc(&c->scale_h, (size_t)c->nrhs * HSTRIDE * sizeof(double)));
     CKS(halloc(&c->coef_h, (size_t)c->nrhs * HSTRIDE * sizeof(cx<double>)));
-    CKS(halloc(&c->tot_h, (size_t)std::max(c->nrhs, mg::MAX_SLOTS) * TOT * sizeof(cx<double>)));
-    CKS(halloc(&c->rtot_h, (size_t)std::max(c->nrhs, mg::MAX_SLOTS) * sizeof(double)));
+    CK(hipStreamSynchronize(c->stream));
+    CKS(autotune(c));
     CK(hipStreamSynchronize(c->stream));
     return MG_OK;
 }
@@ -1080,70 +1399,150 @@ mg_status mg_setup(const mg_params* p, const double* k2_dev, void* stream, mg_ct
 mg_status mg_cycle(mg_ctx* c, double* u, const double* f, double* res_before) {
     if (!c || !u || !f) return MG_E_INVAL;
     const long long N = c->lv[0].N;
-    std::vector<Slot> all(c->nrhs);
+    std::vector<Item> it;
+    std::vector<L0> l0;
+    Run R = ctx_run(c);
     for (int r = 0; r < c->nrhs; ++r) {
-        all[r] = Slot{};
-        all[r].rhs = r;
-        all[r].buf = r;
-        all[r].in_off = (long long)r * N;
-        all[r].out_off = (long long)r * N;
-        all[r].in_scale = 1.0;
+        it.push_back(Item{c, r});
+        cx<double>* ur = (cx<double>*)u + (size_t)r * N;
+        const cx<double>* fr = (const cx<double>*)f + (size_t)r * N;
+        if (!c->mixed)
+            l0.push_back(L0{fr, 1.0, ur, ur});
+        else
+            l0.push_back(L0{c->W + (size_t)r * N, 1.0, nullptr, ur});
     }
-    cx<double>* U = (cx<double>*)u;
-    const cx<double>* F = (const cx<double>*)f;
-    const int ntile0 = c->lv[0].ntiles[0] * c->lv[0].ntiles[1] * c->lv[0].ntiles[2];
-    for (const SlotTable& st : groups(all)) {
-        if (!c->mixed) {
-            CKS(vcycle(c, 0, st, U, F, U, false, res_before ? c->rpart : nullptr));
-            if (res_before) {
-                CKS(reduce_norms_to_host(c, st, ntile0));
-                CK(hipStreamSynchronize(c->stream));
-                for (int q = 0; q < st.n; ++q) res_before[st.s[q].rhs] = std::sqrt(c->rtot_h[q]);
-            }
-        } else {
-            std::vector<Slot> v(st.s, st.s + st.n);
-            for (Slot& x : v) x.out_off = (long long)x.buf * N;
-            std::vector<double> nr(c->nrhs);
-            CKS(residual(c, 0, 0, v, U, F, c->W, res_before ? &nr : nullptr));
-            if (res_before)
-                for (int q = 0; q < st.n; ++q) res_before[st.s[q].rhs] = std::sqrt(nr[st.s[q].rhs]);
-            SlotTable s2 = st;
-            for (int q = 0; q < s2.n; ++q) s2.s[q].in_off = (long long)s2.s[q].buf * N;
-            CKS(vcycle(c, 0, s2, nullptr, c->W, U, true, nullptr));
+    if (!c->mixed) {
+        CKS(vcycle(R, 0, it, l0, false, res_before != nullptr));
+        if (res_before) {
+            CK(hipStreamSynchronize(c->stream));
+            for (int r = 0; r < c->nrhs; ++r) res_before[r] = std::sqrt(c->work.rtot_h[r]);
         }
+    } else {
+        std::vector<int> who(c->nrhs);
+        std::vector<const cx<double>*> xs, fs;
+        std::vector<cx<double>*> ys;
+        for (int r = 0; r < c->nrhs; ++r) {
+            who[r] = r;
+            xs.push_back((const cx<double>*)u + (size_t)r * N);
+            fs.push_back((const cx<double>*)f + (size_t)r * N);
+            ys.push_back(c->W + (size_t)r * N);
+        }
+        std::vector<double> nr;
+        CKS(residual(R, 0, it, who, xs, fs, ys, res_before ? &nr : nullptr));
+        if (res_before)
+            for (int r = 0; r < c->nrhs; ++r) res_before[r] = std::sqrt(nr[r]);
+        CKS(vcycle(R, 0, it, l0, true, false));
     }
     return MG_OK;
 }
 
 mg_status mg_solve(mg_ctx* c, double* u, const double* f, int mode, double rtol, int maxit, int restart,
                    int* iters, double* hist) {
-    return solve(c, 0, u, f, mode, rtol, maxit, restart, iters, hist);
+    return ctx_solve(c, 0, u, f, mode, rtol, maxit, restart, iters, hist);
 }
 
 mg_status mg_solve_adjoint(mg_ctx* c, double* lam, const double* g, int mode, double rtol, int maxit,
                            int restart, int* iters, double* hist) {
-    return solve(c, 1, lam, g, mode, rtol, maxit, restart, iters, hist);
+    return ctx_solve(c, 1, lam, g, mode, rtol, maxit, restart, iters, hist);
 }
 
 mg_status mg_grad_k2(mg_ctx* c, const double* u, const double* lam, double* grad) {
     if (!c || !u || !lam || !grad) return MG_E_INVAL;
-    const int pi = prof_begin(c, MG_K_OTHER, (double)c->lv[0].N * (32.0 * c->nrhs + 16.0));
+    Run R = ctx_run(c);
+    const int pi = prof_begin(R, MG_K_OTHER, (double)c->lv[0].N * (32.0 * c->nrhs + 16.0));
     CK(mg::launch_grad_k2((const cx<double>*)u, (const cx<double>*)lam, c->nrhs, c->lv[0].N, grad, c->stream));
-    prof_end(c, pi);
+    prof_end(R, pi);
     return MG_OK;
 }
 
 mg_status mg_apply(mg_ctx* c, int level, int adjoint, const double* x, double* y) {
     if (!c || !x || !y || level < 0 || level >= c->L) return MG_E_INVAL;
     const long long N = c->lv[level].N;
-    std::vector<Slot> all(c->nrhs);
-    for (int r = 0; r < c->nrhs; ++r) {
-        all[r] = Slot{};
-        all[r].rhs = r;
-        all[r].buf = r;
-        all[r].out_off = (long long)r * N;
+    const int dir = adjoint ? 1 : 0;
+    for (int r0 = 0; r0 < c->nrhs; r0 += mg::MAX_SLOTS) {
+        VecArgs a{};
+        a.st.n = std::min(mg::MAX_SLOTS, c->nrhs - r0);
+        int blocks = 0;
+        for (int q = 0; q < a.st.n; ++q) {
+            VecSlot& s = a.st.s[q];
+            s.lv = c->views_d[dir] + level;
+            s.x = (const cx<double>*)x + (size_t)(r0 + q) * N;
+            s.y = (cx<double>*)y + (size_t)(r0 + q) * N;
+            s.block0 = blocks;
+            blocks += mg::vec_blocks(N);
+        }
+        a.st.nblocks = blocks;
+        a.bstride = c->work.bstride;
+        CK(mg::launch_residual(c->dim, a, c->stream));
     }
-    return residual(c, level, adjoint ? 1 : 0, all, (const cx<double>*)x, nullptr, (cx<double>*)y, nullptr);
+    return MG_OK;
+}
+
+int mg_tile_shape(mg_ctx* c, int level, int shape) {
+    if (!c || level < 0 || level >= c->L) return MG_E_INVAL;
+    if (shape >= mg::NUM_TILE_SHAPES) return MG_E_INVAL;
+    if (shape >= 0) {
+        if (hipStreamSynchronize(c->stream) != hipSuccess) return MG_E_DEVICE;
+        c->lv[level].shape = shape;
+        graphs_free(c->graphs);   // captured coarse parts hold the old shapes
+    }
+    return c->lv[level].shape;
+}
+
+mg_status mg_batch_create(mg_ctx* const* ctxs, int count, mg_batch** out) {
+    if (!out) return MG_E_INVAL;
+    *out = nullptr;
+    if (!ctxs || count < 1) return MG_E_INVAL;
+    int items = 0, bstride = 0;
+    for (int i = 0; i < count; ++i) {
+        const mg_ctx* c = ctxs[i];
+        if (!c || c->dim != ctxs[0]->dim || c->mixed != ctxs[0]->mixed || c->stream != ctxs[0]->stream)
+            return MG_E_INVAL;
+        for (int j = 0; j < i; ++j)
+            if (ctxs[j] == c) return MG_E_INVAL;
+        items += c->nrhs;
+        bstride = std::max(bstride, c->work.bstride);
+    }
+    mg_batch* b = new (std::nothrow) mg_batch();
+    if (!b) return MG_E_NOMEM;
+    b->ctxs.assign(ctxs, ctxs + count);
+    const mg_status st = work_alloc(b->work, items, bstride);
+    if (st != MG_OK) {
+        work_free(b->work);
+        delete b;
+        return st;
+    }
+    *out = b;
+    return MG_OK;
+}
+
+mg_status mg_batch_solve(mg_batch* b, double* const* u, const double* const* f, int mode, double rtol,
+                         int maxit, int restart, int* iters, double* hist) {
+    if (!b || !u || !f) return MG_E_INVAL;
+    std::vector<Item> it;
+    std::vector<cx<double>*> U;
+    std::vector<const cx<double>*> F;
+    for (size_t i = 0; i < b->ctxs.size(); ++i) {
+        mg_ctx* c = b->ctxs[i];
+        if (!u[i] || !f[i]) return MG_E_INVAL;
+        const long long N = c->lv[0].N;
+        for (int r = 0; r < c->nrhs; ++r) {
+            it.push_back(Item{c, r});
+            U.push_back((cx<double>*)u[i] + (size_t)r * N);
+            F.push_back((const cx<double>*)f[i] + (size_t)r * N);
+        }
+    }
+    mg_ctx* c0 = b->ctxs[0];
+    Run R{c0->stream, &c0->prof, &b->work, &b->graphs, c0->dim, c0->mixed};
+    return solve_items(R, 0, it, U, F, mode, rtol, maxit, restart, iters, hist);
+}
+
+void mg_batch_destroy(mg_batch* b) {
+    if (!b) return;
+    if (!b->ctxs.empty()) (void)hipStreamSynchronize(b->ctxs[0]->stream);
+    graphs_free(b->graphs);
+    work_free(b->work);
+    delete b;
 }
 
 int mg_num_levels(const mg_ctx* c) { return c ? c->L : 0; }
@@ -1192,7 +1591,7 @@ mg_status mg_profile_read(mg_ctx* c, int which, double* total_ms, long long* cou
 
 void mg_destroy(mg_ctx* c) {
     if (!c) return;
-    if (c->stream || true) (void)hipStreamSynchronize(c->stream);
+    (void)hipStreamSynchronize(c->stream);
     release(c);
     delete c;
 }

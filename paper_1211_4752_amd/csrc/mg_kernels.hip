@@ -62,6 +62,21 @@ __device__ __forceinline__ double block_sum(double v, double* sm) {
     return t;
 }
 
+// Slot of logical workgroup pid: the last slot whose first tile is <= pid
+// (slots are listed in increasing first-tile order).
+template <typename S>
+__device__ __forceinline__ int find_slot(const S* s, int n, int pid) {
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (s[mid].tile0 <= pid)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
+
 template <int D, typename T>
 __device__ __forceinline__ cx<T> diag_at(const LevelView<T>& L, int gx, int gy, int gz, T k2) {
     cx<T> d = L.c0[0][gx] + L.c0[1][gy];
@@ -76,7 +91,7 @@ __device__ __forceinline__ cx<T> diag_at(const LevelView<T>& L, int gx, int gy, 
 // the tile origin: u on [-2, T+2], u1 on [-1, T+1], r on [0, T].
 // ---------------------------------------------------------------------------
 template <int D, typename T, typename TF, bool ZERO, int TX, int TY, int TZ>
-__global__ void __launch_bounds__(NT) k_smooth_restrict(const SmoothRestrictArgs<T, TF> a) {
+__global__ void __launch_bounds__(NT) k_smooth_restrict(const CycleArgs a) {
     constexpr int TZE = (D == 3) ? TZ : 1;
     constexpr int UX = TX + 5, UY = TY + 5, UZ = (D == 3) ? TZ + 5 : 1;
     constexpr int VX = TX + 3, VY = TY + 3, VZ = (D == 3) ? TZ + 3 : 1;
@@ -90,24 +105,25 @@ __global__ void __launch_bounds__(NT) k_smooth_restrict(const SmoothRestrictArgs
     __shared__ cx<T> s1[NV];    // u1
     __shared__ double sred[NT / 64];
 
-    const LevelView<T>& L = a.lv;
-    const int nx = L.n[0], ny = L.n[1], nz = L.n[2];
-    const int ntile = a.ntiles[0] * a.ntiles[1] * a.ntiles[2];
     const int pid = xcd_remap(blockIdx.x, gridDim.x);
-    const int slot = pid / ntile;
-    int t = pid - slot * ntile;
-    const int tile = t;
-    const int tx = t % a.ntiles[0];
-    t /= a.ntiles[0];
-    const int ty = t % a.ntiles[1];
-    const int tz = t / a.ntiles[1];
+    const int slot = find_slot(a.st.s, a.st.n, pid);
+    const CycleSlot& sl = a.st.s[slot];
+    const int tile = pid - sl.tile0;
+    const LevelView<T>* Lp = static_cast<const LevelView<T>*>(sl.lv);
+    const LevelView<T> L = *Lp;
+    const int nx = L.n[0], ny = L.n[1], nz = L.n[2];
+    const int ntx = (nx + TX - 1) / TX, nty = (ny + TY - 1) / TY;
+    const int tx = tile % ntx;
+    const int rest = tile / ntx;
+    const int ty = rest % nty;
+    const int tz = rest / nty;
     const int x0 = tx * TX, y0 = ty * TY, z0 = tz * TZE;
-    const Slot sl = a.st.s[slot];
-    const cx<TF>* f = a.f + (a.f_by_slot ? (long long)sl.buf * L.N : sl.in_off);
-    const T fs = a.f_by_slot ? T(1) : (T)sl.in_scale;
+    const cx<TF>* f = static_cast<const cx<TF>*>(sl.f);
+    const T fs = (T)sl.fscale;
+    cx<T>* u1p = static_cast<cx<T>*>(sl.u1);
 
     if constexpr (!ZERO) {
-        const cx<T>* u = a.u + (long long)sl.rhs * L.N;
+        const cx<T>* u = static_cast<const cx<T>*>(sl.u);
         for (int idx = threadIdx.x; idx < NU; idx += NT) {
             const int lx = idx % UX;
             const int rr = idx / UX;
@@ -149,7 +165,7 @@ __global__ void __launch_bounds__(NT) k_smooth_restrict(const SmoothRestrictArgs
                 const bool own = lx >= 1 && lx <= TX && ly >= 1 && ly <= TY && (D == 2 || (lz >= 1 && lz <= TZ));
                 if (own) {
                     nrm += (double)abs2(res);
-                    if (a.u1) a.u1[(long long)sl.buf * L.N + g] = u1;
+                    if (u1p) u1p[g] = u1;
                 }
             }
         }
@@ -179,7 +195,8 @@ __global__ void __launch_bounds__(NT) k_smooth_restrict(const SmoothRestrictArgs
     }
     __syncthreads();
 
-    const int ncx = a.nc[0], ncy = a.nc[1], ncz = a.nc[2];
+    const int ncx = Lp[1].n[0], ncy = Lp[1].n[1], ncz = Lp[1].n[2];
+    cx<T>* fc = static_cast<cx<T>*>(sl.c);
     for (int idx = threadIdx.x; idx < CX * CY * CZ; idx += NT) {
         const int cxl = idx % CX;
         const int rr = idx / CX;
@@ -204,14 +221,14 @@ __global__ void __launch_bounds__(NT) k_smooth_restrict(const SmoothRestrictArgs
                     }
                 }
             }
-            a.fc[(long long)sl.buf * a.Nc + ((long long)Cz * ncy + Cy) * ncx + Cx] = acc;
+            fc[((long long)Cz * ncy + Cy) * ncx + Cx] = acc;
         }
     }
 
     if constexpr (!ZERO) {
         if (a.norm_part) {
             const double s = block_sum(nrm, sred);
-            if (threadIdx.x == 0) a.norm_part[(long long)slot * ntile + tile] = s;
+            if (threadIdx.x == 0) a.norm_part[(long long)slot * a.pstride + tile] = s;
         }
     }
 }
@@ -238,7 +255,7 @@ __device__ __forceinline__ void interp_1d(int g, int cs, int& i0, int& i1, T& w0
 }
 
 template <int D, typename T, typename TF, typename TO, bool ZERO, bool ACC, int TX, int TY, int TZ>
-__global__ void __launch_bounds__(NT) k_prolong_smooth(const ProlongSmoothArgs<T, TF, TO> a) {
+__global__ void __launch_bounds__(NT) k_prolong_smooth(const CycleArgs a) {
     constexpr int TZE = (D == 3) ? TZ : 1;
     constexpr int EX = TX / 2 + 2, EY = TY / 2 + 2, EZ = (D == 3) ? TZ / 2 + 2 : 1;
     constexpr int WX = TX + 2, WY = TY + 2, WZ = (D == 3) ? TZ + 2 : 1;
@@ -247,22 +264,24 @@ __global__ void __launch_bounds__(NT) k_prolong_smooth(const ProlongSmoothArgs<T
     __shared__ cx<T> se[NE];
     __shared__ cx<T> s2[NW];
 
-    const LevelView<T>& L = a.lv;
-    const int nx = L.n[0], ny = L.n[1], nz = L.n[2];
-    const int ncx = a.nc[0], ncy = a.nc[1], ncz = a.nc[2];
-    const int ntile = a.ntiles[0] * a.ntiles[1] * a.ntiles[2];
     const int pid = xcd_remap(blockIdx.x, gridDim.x);
-    const int slot = pid / ntile;
-    int t = pid - slot * ntile;
-    const int tx = t % a.ntiles[0];
-    t /= a.ntiles[0];
-    const int ty = t % a.ntiles[1];
-    const int tz = t / a.ntiles[1];
+    const int slot = find_slot(a.st.s, a.st.n, pid);
+    const CycleSlot& sl = a.st.s[slot];
+    const int tile = pid - sl.tile0;
+    const LevelView<T>* Lp = static_cast<const LevelView<T>*>(sl.lv);
+    const LevelView<T> L = *Lp;
+    const int nx = L.n[0], ny = L.n[1], nz = L.n[2];
+    const int ncx = Lp[1].n[0], ncy = Lp[1].n[1], ncz = Lp[1].n[2];
+    const int ntx = (nx + TX - 1) / TX, nty = (ny + TY - 1) / TY;
+    const int tx = tile % ntx;
+    const int rest = tile / ntx;
+    const int ty = rest % nty;
+    const int tz = rest / nty;
     const int x0 = tx * TX, y0 = ty * TY, z0 = tz * TZE;
-    const Slot sl = a.st.s[slot];
-    const cx<TF>* f = a.f + (a.f_by_slot ? (long long)sl.buf * L.N : sl.in_off);
-    const T fs = a.f_by_slot ? T(1) : (T)sl.in_scale;
-    const cx<T>* ec = a.ec + (long long)sl.buf * a.Nc;
+    const cx<TF>* f = static_cast<const cx<TF>*>(sl.f);
+    const T fs = (T)sl.fscale;
+    const cx<T>* ec = static_cast<const cx<T>*>(sl.c);
+    const cx<T>* u1in = static_cast<const cx<T>*>(sl.u1);
     const int cxs = x0 / 2 - 1, cys = y0 / 2 - 1, czs = (D == 3) ? z0 / 2 - 1 : 0;
 
     for (int idx = threadIdx.x; idx < NE; idx += NT) {
@@ -293,7 +312,7 @@ __global__ void __launch_bounds__(NT) k_prolong_smooth(const ProlongSmoothArgs<T
                 const cx<T> fv = fs * cvt<T>(f[g]);
                 u1 = cdiv(L.omega * fv, diag_at<D>(L, gx, gy, gz, L.k2[g]));
             } else {
-                u1 = a.u1[(long long)sl.buf * L.N + g];
+                u1 = u1in[g];
             }
             int ix0, ix1, iy0, iy1;
             T wx0, wx1, wy0, wy1;
@@ -320,7 +339,7 @@ __global__ void __launch_bounds__(NT) k_prolong_smooth(const ProlongSmoothArgs<T
     }
     __syncthreads();
 
-    cx<TO>* out = a.out + (a.out_by_slot ? (long long)sl.buf * L.N : sl.out_off);
+    cx<TO>* out = static_cast<cx<TO>*>(sl.out);
     for (int idx = threadIdx.x; idx < TX * TY * TZE; idx += NT) {
         const int lx = idx % TX;
         const int rr = idx / TX;
@@ -349,15 +368,21 @@ __global__ void __launch_bounds__(NT) k_prolong_smooth(const ProlongSmoothArgs<T
 
 // ---------------------------------------------------------------------------
 // Coarsest level: LU forward/back substitution, one workgroup per slot, in
-// FP64 whatever the cycle precision.  lu: row-major n x n, unit-lower L below
-// the diagonal, U on and above; piv: row interchanges in elimination order.
+// FP64 whatever the cycle precision.  The slot's level descriptor holds the
+// row-major LU factors (unit-lower L below the diagonal, U on and above) and
+// the row interchanges in elimination order; f: slot.f, e: slot.out.
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ void __launch_bounds__(NT) k_coarse_solve(const cx<double>* lu, const int* piv, int n,
-                                                      const SlotTable st, const cx<T>* f, cx<T>* e) {
+__global__ void __launch_bounds__(NT) k_coarse_solve(const CycleArgs a) {
     __shared__ cx<double> b[MAX_COARSE];
-    const long long base = (long long)st.s[blockIdx.x].buf * n;
-    for (int i = threadIdx.x; i < n; i += NT) b[i] = cvt<double>(f[base + i]);
+    const CycleSlot& sl = a.st.s[blockIdx.x];
+    const LevelView<T>* Lp = static_cast<const LevelView<T>*>(sl.lv);
+    const int n = (int)Lp->N;
+    const cx<double>* lu = Lp->lu;
+    const int* piv = Lp->piv;
+    const cx<T>* f = static_cast<const cx<T>*>(sl.f);
+    cx<T>* e = static_cast<cx<T>*>(sl.out);
+    for (int i = threadIdx.x; i < n; i += NT) b[i] = cvt<double>(f[i]);
     __syncthreads();
     if (threadIdx.x == 0) {
         for (int i = 0; i < n; ++i) {
@@ -382,12 +407,12 @@ __global__ void __launch_bounds__(NT) k_coarse_solve(const cx<double>* lu, const
         for (int i = threadIdx.x; i < k; i += NT) b[i] = b[i] - lu[(long long)i * n + k] * bk;
         __syncthreads();
     }
-    for (int i = threadIdx.x; i < n; i += NT) e[base + i] = cvt<T>(b[i]);
+    for (int i = threadIdx.x; i < n; i += NT) e[i] = cvt<T>(b[i]);
 }
 
 // ---------------------------------------------------------------------------
-// Residual / operator application, one point per thread, contiguous chunk
-// per workgroup.
+// Vector kernels: one point per thread, a contiguous chunk of the slot's
+// vector per workgroup.
 // ---------------------------------------------------------------------------
 template <int D>
 __device__ __forceinline__ cx<double> apply_at(const LevelView<double>& L, const cx<double>* x, int p,
@@ -406,6 +431,29 @@ __device__ __forceinline__ cx<double> apply_at(const LevelView<double>& L, const
     return ax;
 }
 
+// Slot, workgroup within the slot and its point range [lo, hi).
+struct VecPos {
+    int slot, b, nb, lo, hi;
+};
+
+__device__ __forceinline__ VecPos vec_pos(const VecSlots& st) {
+    VecPos q;
+    const int pid = xcd_remap(blockIdx.x, gridDim.x);
+    int lo = 0, hi = st.n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (st.s[mid].block0 <= pid)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    q.slot = lo;
+    q.b = pid - st.s[lo].block0;
+    q.nb = (lo + 1 < st.n ? st.s[lo + 1].block0 : st.nblocks) - st.s[lo].block0;
+    q.lo = q.hi = 0;
+    return q;
+}
+
 __device__ __forceinline__ void chunk_range(long long N, int nblocks, int b, int& lo, int& hi) {
     const long long per = (N + nblocks - 1) / nblocks;
     long long l = per * b, h = l + per;
@@ -415,49 +463,43 @@ __device__ __forceinline__ void chunk_range(long long N, int nblocks, int b, int
     hi = (int)h;
 }
 
+// y = f - A x (f null: y = A x); ||y||^2 partials in rpart.
 template <int D>
-__global__ void __launch_bounds__(NT) k_residual(const ResidualArgs a) {
+__global__ void __launch_bounds__(NT) k_residual(const VecArgs a) {
     __shared__ double sred[NT / 64];
-    const LevelView<double>& L = a.lv;
-    const int slot = blockIdx.y;
-    const Slot sl = a.st.s[slot];
-    const long long N = L.N;
-    const cx<double>* x = a.x + (long long)sl.rhs * N;
-    const cx<double>* f = a.f ? a.f + (long long)sl.rhs * N : nullptr;
-    cx<double>* y = a.y + sl.out_off;
-    const int b = xcd_remap(blockIdx.x, gridDim.x);
-    int lo, hi;
-    chunk_range(N, gridDim.x, b, lo, hi);
+    VecPos q = vec_pos(a.st);
+    const VecSlot& sl = a.st.s[q.slot];
+    const LevelView<double> L = *static_cast<const LevelView<double>*>(sl.lv);
+    chunk_range(L.N, q.nb, q.b, q.lo, q.hi);
     double nrm = 0.0;
     const int nx = L.n[0], ny = L.n[1];
-    for (int p = lo + (int)threadIdx.x; p < hi; p += NT) {
+    for (int p = q.lo + (int)threadIdx.x; p < q.hi; p += NT) {
         const int gx = p % nx;
         const int rr = p / nx;
         const int gy = rr % ny;
         const int gz = rr / ny;
-        cx<double> v = apply_at<D>(L, x, p, gx, gy, gz);
-        if (f) v = f[p] - v;
-        y[p] = v;
+        cx<double> v = apply_at<D>(L, sl.x, p, gx, gy, gz);
+        if (sl.f) v = sl.f[p] - v;
+        sl.y[p] = v;
         nrm += abs2(v);
     }
-    if (a.norm_part) {
+    if (a.rpart) {
         const double s = block_sum(nrm, sred);
-        if (threadIdx.x == 0) a.norm_part[(long long)slot * gridDim.x + b] = s;
+        if (threadIdx.x == 0) a.rpart[(long long)q.slot * a.bstride + q.b] = s;
     }
 }
 
-__global__ void __launch_bounds__(NT) k_norm(const SlotTable st, const cx<double>* x, bool by_buf,
-                                             long long N, double* part) {
+// ||x||^2 partials.
+__global__ void __launch_bounds__(NT) k_norm(const VecArgs a) {
     __shared__ double sred[NT / 64];
-    const int slot = blockIdx.y;
-    const Slot sl = st.s[slot];
-    const cx<double>* v = x + (by_buf ? (long long)sl.buf : (long long)sl.rhs) * N;
-    int lo, hi;
-    chunk_range(N, gridDim.x, blockIdx.x, lo, hi);
+    VecPos q = vec_pos(a.st);
+    const VecSlot& sl = a.st.s[q.slot];
+    const long long N = static_cast<const LevelView<double>*>(sl.lv)->N;
+    chunk_range(N, q.nb, q.b, q.lo, q.hi);
     double nrm = 0.0;
-    for (int p = lo + (int)threadIdx.x; p < hi; p += NT) nrm += abs2(v[p]);
+    for (int p = q.lo + (int)threadIdx.x; p < q.hi; p += NT) nrm += abs2(sl.x[p]);
     const double s = block_sum(nrm, sred);
-    if (threadIdx.x == 0) part[(long long)slot * gridDim.x + blockIdx.x] = s;
+    if (threadIdx.x == 0) a.rpart[(long long)q.slot * a.bstride + q.b] = s;
 }
 
 // ---------------------------------------------------------------------------
@@ -466,8 +508,8 @@ __global__ void __launch_bounds__(NT) k_norm(const SlotTable st, const cx<double
 // ---------------------------------------------------------------------------
 template <int MAXJ>
 __device__ __forceinline__ void block_sum_vec(cx<double> (&acc)[MAXJ], int nv, cx<double>* sm,
-                                              cx<double>* dst, int nblocks, int b) {
-    // sm: (NT/64) * MAXJ complex
+                                              cx<double>* dst, long long bstride, int b) {
+    // sm: (NT/64) * MAXJ complex; dst[i * bstride + b] for i < nv
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
 #pragma unroll
@@ -483,29 +525,28 @@ __device__ __forceinline__ void block_sum_vec(cx<double> (&acc)[MAXJ], int nv, c
         cx<double> s = mk(0.0, 0.0);
 #pragma unroll
         for (int w = 0; w < NT / 64; ++w) s = s + sm[w * MAXJ + threadIdx.x];
-        dst[(long long)threadIdx.x * nblocks + b] = s;
+        dst[(long long)threadIdx.x * bstride + b] = s;
     }
 }
 
+// w = A z, h_i = <v_i, w>.
 template <int D, int MAXJ>
-__global__ void __launch_bounds__(NT) k_matvec_dot(const OrthoArgs a) {
+__global__ void __launch_bounds__(NT) k_matvec_dot(const VecArgs a) {
     __shared__ cx<double> sm[(NT / 64) * MAXJ];
-    const LevelView<double>& L = a.lv;
-    const int slot = blockIdx.y;
-    const Slot sl = a.st.s[slot];
+    VecPos q = vec_pos(a.st);
+    const VecSlot& sl = a.st.s[q.slot];
+    const LevelView<double> L = *static_cast<const LevelView<double>*>(sl.lv);
+    const long long N = L.N;
     const int nv = sl.j + 1;
-    const long long N = a.N;
-    const cx<double>* z = a.z + (long long)sl.buf * N;
-    cx<double>* w = a.w + (long long)sl.buf * N;
-    const cx<double>* V = a.Vb + (long long)sl.rhs * a.vstride * N;
-    const int b = xcd_remap(blockIdx.x, gridDim.x);
-    int lo, hi;
-    chunk_range(N, gridDim.x, b, lo, hi);
+    const cx<double>* z = sl.x;
+    cx<double>* w = sl.y;
+    const cx<double>* V = sl.V;
+    chunk_range(N, q.nb, q.b, q.lo, q.hi);
     cx<double> acc[MAXJ];
 #pragma unroll
     for (int i = 0; i < MAXJ; ++i) acc[i] = mk(0.0, 0.0);
     const int nx = L.n[0], ny = L.n[1];
-    for (int p = lo + (int)threadIdx.x; p < hi; p += NT) {
+    for (int p = q.lo + (int)threadIdx.x; p < q.hi; p += NT) {
         const int gx = p % nx;
         const int rr = p / nx;
         const int gy = rr % ny;
@@ -516,34 +557,30 @@ __global__ void __launch_bounds__(NT) k_matvec_dot(const OrthoArgs a) {
         for (int i = 0; i < MAXJ; ++i)
             if (i < nv) acc[i] = acc[i] + cmulc(V[(long long)i * N + p], wv);
     }
-    const double* sc = a.scale + (long long)sl.rhs * a.sstride;
 #pragma unroll
     for (int i = 0; i < MAXJ; ++i)
-        if (i < nv) acc[i] = sc[i] * acc[i];
-    block_sum_vec<MAXJ>(acc, nv, sm, a.part + (long long)slot * a.pstride * a.nblocks, a.nblocks, b);
+        if (i < nv) acc[i] = sl.scale[i] * acc[i];
+    block_sum_vec<MAXJ>(acc, nv, sm, a.part + (long long)q.slot * a.pstride * a.bstride, a.bstride, q.b);
 }
 
+// w -= sum_i h_i v_i, then h2_i = <v_i, w>.
 template <int MAXJ>
-__global__ void __launch_bounds__(NT) k_update_dot(const OrthoArgs a) {
+__global__ void __launch_bounds__(NT) k_update_dot(const VecArgs a) {
     __shared__ cx<double> sm[(NT / 64) * MAXJ];
-    const int slot = blockIdx.y;
-    const Slot sl = a.st.s[slot];
+    VecPos q = vec_pos(a.st);
+    const VecSlot& sl = a.st.s[q.slot];
+    const long long N = static_cast<const LevelView<double>*>(sl.lv)->N;
     const int nv = sl.j + 1;
-    const long long N = a.N;
-    cx<double>* w = a.w + (long long)sl.buf * N;
-    const cx<double>* V = a.Vb + (long long)sl.rhs * a.vstride * N;
-    const double* sc = a.scale + (long long)sl.rhs * a.sstride;
-    const cx<double>* h = a.hin + (long long)slot * a.hstride;
+    cx<double>* w = sl.y;
+    const cx<double>* V = sl.V;
     cx<double> coef[MAXJ];
 #pragma unroll
-    for (int i = 0; i < MAXJ; ++i) coef[i] = (i < nv) ? sc[i] * h[i] : mk(0.0, 0.0);
-    const int b = xcd_remap(blockIdx.x, gridDim.x);
-    int lo, hi;
-    chunk_range(N, gridDim.x, b, lo, hi);
+    for (int i = 0; i < MAXJ; ++i) coef[i] = (i < nv) ? sl.scale[i] * sl.hin[i] : mk(0.0, 0.0);
+    chunk_range(N, q.nb, q.b, q.lo, q.hi);
     cx<double> acc[MAXJ];
 #pragma unroll
     for (int i = 0; i < MAXJ; ++i) acc[i] = mk(0.0, 0.0);
-    for (int p = lo + (int)threadIdx.x; p < hi; p += NT) {
+    for (int p = q.lo + (int)threadIdx.x; p < q.hi; p += NT) {
         cx<double> vv[MAXJ];
 #pragma unroll
         for (int i = 0; i < MAXJ; ++i) vv[i] = (i < nv) ? V[(long long)i * N + p] : mk(0.0, 0.0);
@@ -556,30 +593,27 @@ __global__ void __launch_bounds__(NT) k_update_dot(const OrthoArgs a) {
     }
 #pragma unroll
     for (int i = 0; i < MAXJ; ++i)
-        if (i < nv) acc[i] = sc[i] * acc[i];
-    block_sum_vec<MAXJ>(acc, nv, sm, a.part + (long long)slot * a.pstride * a.nblocks, a.nblocks, b);
+        if (i < nv) acc[i] = sl.scale[i] * acc[i];
+    block_sum_vec<MAXJ>(acc, nv, sm, a.part + (long long)q.slot * a.pstride * a.bstride, a.bstride, q.b);
 }
 
+// V_{j+1} = w - sum_i h_i v_i, ||V_{j+1}||^2 partials.
 template <int MAXJ>
-__global__ void __launch_bounds__(NT) k_update_norm(const OrthoArgs a) {
+__global__ void __launch_bounds__(NT) k_update_norm(const VecArgs a) {
     __shared__ double sred[NT / 64];
-    const int slot = blockIdx.y;
-    const Slot sl = a.st.s[slot];
+    VecPos q = vec_pos(a.st);
+    const VecSlot& sl = a.st.s[q.slot];
+    const long long N = static_cast<const LevelView<double>*>(sl.lv)->N;
     const int nv = sl.j + 1;
-    const long long N = a.N;
-    const cx<double>* w = a.w + (long long)sl.buf * N;
-    cx<double>* V = a.Vb + (long long)sl.rhs * a.vstride * N;
-    const double* sc = a.scale + (long long)sl.rhs * a.sstride;
-    const cx<double>* h = a.hin + (long long)slot * a.hstride;
+    const cx<double>* w = sl.y;
+    cx<double>* V = sl.V;
     cx<double> coef[MAXJ];
 #pragma unroll
-    for (int i = 0; i < MAXJ; ++i) coef[i] = (i < nv) ? sc[i] * h[i] : mk(0.0, 0.0);
-    const int b = xcd_remap(blockIdx.x, gridDim.x);
-    int lo, hi;
-    chunk_range(N, gridDim.x, b, lo, hi);
+    for (int i = 0; i < MAXJ; ++i) coef[i] = (i < nv) ? sl.scale[i] * sl.hin[i] : mk(0.0, 0.0);
+    chunk_range(N, q.nb, q.b, q.lo, q.hi);
     cx<double>* vout = V + (long long)nv * N;
     double nrm = 0.0;
-    for (int p = lo + (int)threadIdx.x; p < hi; p += NT) {
+    for (int p = q.lo + (int)threadIdx.x; p < q.hi; p += NT) {
         cx<double> wv = w[p];
 #pragma unroll
         for (int i = 0; i < MAXJ; ++i)
@@ -588,24 +622,23 @@ __global__ void __launch_bounds__(NT) k_update_norm(const OrthoArgs a) {
         nrm += abs2(wv);
     }
     const double s = block_sum(nrm, sred);
-    if (threadIdx.x == 0) a.part[(long long)slot * a.pstride * a.nblocks + b] = mk(s, 0.0);
+    if (threadIdx.x == 0) a.rpart[(long long)q.slot * a.bstride + q.b] = s;
 }
 
+// t = sum_i coef_i V_i.
 template <int MAXJ>
-__global__ void __launch_bounds__(NT) k_combine(const CombineArgs a) {
-    const int slot = blockIdx.y;
-    const Slot sl = a.st.s[slot];
+__global__ void __launch_bounds__(NT) k_combine(const VecArgs a) {
+    VecPos q = vec_pos(a.st);
+    const VecSlot& sl = a.st.s[q.slot];
+    const long long N = static_cast<const LevelView<double>*>(sl.lv)->N;
     const int nv = sl.j + 1;
-    const long long N = a.N;
-    const cx<double>* V = a.Vb + (long long)sl.rhs * a.vstride * N;
-    const cx<double>* c = a.coef + (long long)sl.rhs * a.sstride;
+    const cx<double>* V = sl.V;
     cx<double> coef[MAXJ];
 #pragma unroll
-    for (int i = 0; i < MAXJ; ++i) coef[i] = (i < nv) ? c[i] : mk(0.0, 0.0);
-    cx<double>* t = a.t + (long long)sl.buf * N;
-    int lo, hi;
-    chunk_range(N, gridDim.x, xcd_remap(blockIdx.x, gridDim.x), lo, hi);
-    for (int p = lo + (int)threadIdx.x; p < hi; p += NT) {
+    for (int i = 0; i < MAXJ; ++i) coef[i] = (i < nv) ? sl.coef[i] : mk(0.0, 0.0);
+    cx<double>* t = sl.y;
+    chunk_range(N, q.nb, q.b, q.lo, q.hi);
+    for (int p = q.lo + (int)threadIdx.x; p < q.hi; p += NT) {
         cx<double> s = mk(0.0, 0.0);
 #pragma unroll
         for (int i = 0; i < MAXJ; ++i)
@@ -617,29 +650,30 @@ __global__ void __launch_bounds__(NT) k_combine(const CombineArgs a) {
 // ---------------------------------------------------------------------------
 // Second reduction stage, fixed order.
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(NT) k_reduce_complex(const cx<double>* part, int vstride, int nblocks,
-                                                       cx<double>* out, int ostride) {
+__global__ void __launch_bounds__(NT) k_reduce_complex(const ReduceArgs a) {
     __shared__ double sr[NT / 64], si[NT / 64];
     const int v = blockIdx.x, slot = blockIdx.y;
-    const cx<double>* p = part + ((long long)slot * vstride + v) * nblocks;
+    const cx<double>* p = a.part + ((long long)slot * a.pstride + v) * a.bstride;
+    const int cnt = a.cnt[slot];
     double r = 0.0, im = 0.0;
-    for (int b = threadIdx.x; b < nblocks; b += NT) {
+    for (int b = threadIdx.x; b < cnt; b += NT) {
         r += p[b].r;
         im += p[b].i;
     }
     r = block_sum(r, sr);
     im = block_sum(im, si);
-    if (threadIdx.x == 0) out[(long long)slot * ostride + v] = mk(r, im);
+    if (threadIdx.x == 0) a.out[(long long)slot * a.ostride + v] = mk(r, im);
 }
 
-__global__ void __launch_bounds__(NT) k_reduce_real(const double* part, int nblocks, double* out) {
+__global__ void __launch_bounds__(NT) k_reduce_real(const ReduceArgs a) {
     __shared__ double sr[NT / 64];
-    const int slot = blockIdx.x;
-    const double* p = part + (long long)slot * nblocks;
+    const int slot = blockIdx.y;
+    const double* p = a.rpart + (long long)slot * a.bstride;
+    const int cnt = a.cnt[slot];
     double r = 0.0;
-    for (int b = threadIdx.x; b < nblocks; b += NT) r += p[b];
+    for (int b = threadIdx.x; b < cnt; b += NT) r += p[b];
     r = block_sum(r, sr);
-    if (threadIdx.x == 0) out[slot] = r;
+    if (threadIdx.x == 0) a.rout[slot] = r;
 }
 
 // ---------------------------------------------------------------------------
@@ -685,129 +719,126 @@ __global__ void k_fill_zero(uint4* p, long long n16) {
 // Launchers
 // ---------------------------------------------------------------------------
 namespace {
-// tile shapes (x, y, z) of the fused kernels
-constexpr int T2X = 64, T2Y = 16;
-constexpr int T3X = 16, T3Y = 8, T3Z = 4;
+// tile shapes (x, y, z) of the fused kernels; LDS per workgroup stays under
+// 64 KB for the complex-double iterate variant
+constexpr int SHAPES_2D[NUM_TILE_SHAPES][2] = {{64, 16}, {64, 8}, {128, 8}};
+constexpr int SHAPES_3D[NUM_TILE_SHAPES][3] = {{16, 8, 4}, {32, 4, 2}, {16, 4, 4}};
 
 inline int cdivi(int a, int b) { return (a + b - 1) / b; }
 }  // namespace
 
-void tile_counts(int dim, bool /*f32*/, const int n[3], int ntiles[3]) {
+void tile_shape(int dim, int shape, int t[3]) {
+    if (shape < 0 || shape >= NUM_TILE_SHAPES) shape = 0;
     if (dim == 2) {
-        ntiles[0] = cdivi(n[0], T2X);
-        ntiles[1] = cdivi(n[1], T2Y);
-        ntiles[2] = 1;
+        t[0] = SHAPES_2D[shape][0];
+        t[1] = SHAPES_2D[shape][1];
+        t[2] = 1;
     } else {
-        ntiles[0] = cdivi(n[0], T3X);
-        ntiles[1] = cdivi(n[1], T3Y);
-        ntiles[2] = cdivi(n[2], T3Z);
+        t[0] = SHAPES_3D[shape][0];
+        t[1] = SHAPES_3D[shape][1];
+        t[2] = SHAPES_3D[shape][2];
     }
 }
 
-template <int D, typename T, typename TF, bool ZERO>
-static hipError_t sr_launch(const SmoothRestrictArgs<T, TF>& a, int* nb, hipStream_t s) {
-    const int ntile = a.ntiles[0] * a.ntiles[1] * a.ntiles[2];
-    if (nb) *nb = ntile;
-    dim3 grid(ntile * a.st.n);
-    if (D == 2)
-        hipLaunchKernelGGL((k_smooth_restrict<2, T, TF, ZERO, T2X, T2Y, 1>), grid, dim3(NT), 0, s, a);
-    else
-        hipLaunchKernelGGL((k_smooth_restrict<3, T, TF, ZERO, T3X, T3Y, T3Z>), grid, dim3(NT), 0, s, a);
-    return hipGetLastError();
+void tile_counts(int dim, int shape, const int n[3], int ntiles[3]) {
+    int t[3];
+    tile_shape(dim, shape, t);
+    ntiles[0] = cdivi(n[0], t[0]);
+    ntiles[1] = cdivi(n[1], t[1]);
+    ntiles[2] = dim == 3 ? cdivi(n[2], t[2]) : 1;
 }
 
-template <int D, typename T, typename TF, typename TO, bool ZERO, bool ACC>
-static hipError_t ps_launch(const ProlongSmoothArgs<T, TF, TO>& a, hipStream_t s) {
-    const int ntile = a.ntiles[0] * a.ntiles[1] * a.ntiles[2];
-    dim3 grid(ntile * a.st.n);
-    if (D == 2)
-        hipLaunchKernelGGL((k_prolong_smooth<2, T, TF, TO, ZERO, ACC, T2X, T2Y, 1>), grid, dim3(NT), 0, s, a);
-    else
-        hipLaunchKernelGGL((k_prolong_smooth<3, T, TF, TO, ZERO, ACC, T3X, T3Y, T3Z>), grid, dim3(NT), 0, s,
-                           a);
-    return hipGetLastError();
-}
-
-hipError_t launch_smooth_restrict_f64(int dim, bool zero, const SmoothRestrictArgs<double, double>& a,
-                                      int* nb, hipStream_t s) {
-    if (dim == 2) return zero ? sr_launch<2, double, double, true>(a, nb, s) : sr_launch<2, double, double, false>(a, nb, s);
-    return zero ? sr_launch<3, double, double, true>(a, nb, s) : sr_launch<3, double, double, false>(a, nb, s);
-}
-
-hipError_t launch_smooth_restrict_f32(int dim, bool level0, const SmoothRestrictArgs<float, double>& a0,
-                                      const SmoothRestrictArgs<float, float>& ac, int* nb, hipStream_t s) {
-    if (dim == 2) return level0 ? sr_launch<2, float, double, true>(a0, nb, s) : sr_launch<2, float, float, true>(ac, nb, s);
-    return level0 ? sr_launch<3, float, double, true>(a0, nb, s) : sr_launch<3, float, float, true>(ac, nb, s);
-}
-
-hipError_t launch_prolong_smooth_f64(int dim, bool zero, bool acc,
-                                     const ProlongSmoothArgs<double, double, double>& a, hipStream_t s) {
-    if (dim == 2) {
-        if (zero) return acc ? ps_launch<2, double, double, double, true, true>(a, s)
-                             : ps_launch<2, double, double, double, true, false>(a, s);
-        return acc ? ps_launch<2, double, double, double, false, true>(a, s)
-                   : ps_launch<2, double, double, double, false, false>(a, s);
+// dispatch over (dim, shape) of a fused kernel template K<D, TX, TY, TZ>
+#define MG_SHAPE_SWITCH(LAUNCH)                                                    \
+    if (dim == 2) {                                                                \
+        switch (shape) {                                                           \
+            case 1: LAUNCH(2, 64, 8, 1); break;                                    \
+            case 2: LAUNCH(2, 128, 8, 1); break;                                   \
+            default: LAUNCH(2, 64, 16, 1); break;                                  \
+        }                                                                          \
+    } else {                                                                       \
+        switch (shape) {                                                           \
+            case 1: LAUNCH(3, 32, 4, 2); break;                                    \
+            case 2: LAUNCH(3, 16, 4, 4); break;                                    \
+            default: LAUNCH(3, 16, 8, 4); break;                                   \
+        }                                                                          \
     }
-    if (zero) return acc ? ps_launch<3, double, double, double, true, true>(a, s)
-                         : ps_launch<3, double, double, double, true, false>(a, s);
-    return acc ? ps_launch<3, double, double, double, false, true>(a, s)
-               : ps_launch<3, double, double, double, false, false>(a, s);
+
+template <typename T, typename TF, bool ZERO>
+static hipError_t sr_launch(int dim, int shape, const CycleArgs& a, hipStream_t s) {
+    dim3 grid(a.st.ntiles);
+#define SR(D, X, Y, Z) hipLaunchKernelGGL((k_smooth_restrict<D, T, TF, ZERO, X, Y, Z>), grid, dim3(NT), 0, s, a);
+    MG_SHAPE_SWITCH(SR)
+#undef SR
+    return hipGetLastError();
 }
 
-hipError_t launch_prolong_smooth_f32(int dim, bool level0, bool acc,
-                                     const ProlongSmoothArgs<float, double, double>& a0,
-                                     const ProlongSmoothArgs<float, float, float>& ac, hipStream_t s) {
-    if (dim == 2) {
-        if (!level0) return ps_launch<2, float, float, float, true, false>(ac, s);
-        return acc ? ps_launch<2, float, double, double, true, true>(a0, s)
-                   : ps_launch<2, float, double, double, true, false>(a0, s);
+template <typename T, typename TF, typename TO, bool ZERO, bool ACC>
+static hipError_t ps_launch(int dim, int shape, const CycleArgs& a, hipStream_t s) {
+    dim3 grid(a.st.ntiles);
+#define PS(D, X, Y, Z) \
+    hipLaunchKernelGGL((k_prolong_smooth<D, T, TF, TO, ZERO, ACC, X, Y, Z>), grid, dim3(NT), 0, s, a);
+    MG_SHAPE_SWITCH(PS)
+#undef PS
+    return hipGetLastError();
+}
+
+hipError_t launch_smooth_restrict(int dim, bool f32, bool level0, bool zero, int shape, const CycleArgs& a,
+                                  hipStream_t s) {
+    if (a.st.n <= 0) return hipSuccess;
+    if (!f32) {
+        return zero ? sr_launch<double, double, true>(dim, shape, a, s)
+                    : sr_launch<double, double, false>(dim, shape, a, s);
     }
-    if (!level0) return ps_launch<3, float, float, float, true, false>(ac, s);
-    return acc ? ps_launch<3, float, double, double, true, true>(a0, s)
-               : ps_launch<3, float, double, double, true, false>(a0, s);
+    if (!zero) return hipErrorInvalidValue;   // the complex64 cycle always starts from zero
+    return level0 ? sr_launch<float, double, true>(dim, shape, a, s) : sr_launch<float, float, true>(dim, shape, a, s);
 }
 
-hipError_t launch_coarse_solve_f64(const cx<double>* lu, const int* piv, int n, const SlotTable& st,
-                                   const cx<double>* f, cx<double>* e, hipStream_t s) {
-    hipLaunchKernelGGL((k_coarse_solve<double>), dim3(st.n), dim3(NT), 0, s, lu, piv, n,
-                       st, f, e);
-    return hipGetLastError();
+hipError_t launch_prolong_smooth(int dim, bool f32, bool level0, bool zero, bool acc, int shape,
+                                 const CycleArgs& a, hipStream_t s) {
+    if (a.st.n <= 0) return hipSuccess;
+    if (!f32) {
+        if (zero)
+            return acc ? ps_launch<double, double, double, true, true>(dim, shape, a, s)
+                       : ps_launch<double, double, double, true, false>(dim, shape, a, s);
+        return acc ? ps_launch<double, double, double, false, true>(dim, shape, a, s)
+                   : ps_launch<double, double, double, false, false>(dim, shape, a, s);
+    }
+    if (!zero) return hipErrorInvalidValue;
+    if (!level0) return ps_launch<float, float, float, true, false>(dim, shape, a, s);
+    return acc ? ps_launch<float, double, double, true, true>(dim, shape, a, s)
+               : ps_launch<float, double, double, true, false>(dim, shape, a, s);
 }
 
-hipError_t launch_coarse_solve_f32(const cx<double>* lu, const int* piv, int n, const SlotTable& st,
-                                   const cx<float>* f, cx<float>* e, hipStream_t s) {
-    hipLaunchKernelGGL((k_coarse_solve<float>), dim3(st.n), dim3(NT), 0, s, lu, piv, n,
-                       st, f, e);
-    return hipGetLastError();
-}
-
-int residual_blocks(long long N) {
-    long long b = (N + NT * 4 - 1) / (NT * 4);
-    if (b > 1024) b = 1024;
-    if (b < 1) b = 1;
-    return (int)b;
-}
-
-hipError_t launch_residual(int dim, const ResidualArgs& a, hipStream_t s) {
-    dim3 grid(a.nblocks, a.st.n);
-    if (dim == 2)
-        hipLaunchKernelGGL((k_residual<2>), grid, dim3(NT), 0, s, a);
+hipError_t launch_coarse_solve(bool f32, const CycleArgs& a, hipStream_t s) {
+    if (a.st.n <= 0) return hipSuccess;
+    if (f32)
+        hipLaunchKernelGGL((k_coarse_solve<float>), dim3(a.st.n), dim3(NT), 0, s, a);
     else
-        hipLaunchKernelGGL((k_residual<3>), grid, dim3(NT), 0, s, a);
+        hipLaunchKernelGGL((k_coarse_solve<double>), dim3(a.st.n), dim3(NT), 0, s, a);
     return hipGetLastError();
 }
 
-hipError_t launch_norm(const SlotTable& st, const cx<double>* x, bool by_buf, long long N, double* part,
-                       int nblocks, hipStream_t s) {
-    hipLaunchKernelGGL(k_norm, dim3(nblocks, st.n), dim3(NT), 0, s, st, x, by_buf, N, part);
-    return hipGetLastError();
-}
-
-int ortho_blocks(long long N) {
+int vec_blocks(long long N) {
     long long b = (N + NT * 8 - 1) / (NT * 8);
     if (b > 1024) b = 1024;
     if (b < 1) b = 1;
     return (int)b;
+}
+
+hipError_t launch_residual(int dim, const VecArgs& a, hipStream_t s) {
+    if (a.st.n <= 0) return hipSuccess;
+    if (dim == 2)
+        hipLaunchKernelGGL((k_residual<2>), dim3(a.st.nblocks), dim3(NT), 0, s, a);
+    else
+        hipLaunchKernelGGL((k_residual<3>), dim3(a.st.nblocks), dim3(NT), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_norm(const VecArgs& a, hipStream_t s) {
+    if (a.st.n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_norm, dim3(a.st.nblocks), dim3(NT), 0, s, a);
+    return hipGetLastError();
 }
 
 static int jbucket(int jmax) {
@@ -815,17 +846,18 @@ static int jbucket(int jmax) {
 }
 
 // MAXJ buckets of the GMRES pass kernels (registers scale with MAXJ)
-#define MG_JSWITCH(CASE) \
-    switch (jbucket(jmax)) { \
-        case 4: CASE(4) break; \
-        case 8: CASE(8) break; \
+#define MG_JSWITCH(CASE)         \
+    switch (jbucket(jmax)) {     \
+        case 4: CASE(4) break;   \
+        case 8: CASE(8) break;   \
         case 16: CASE(16) break; \
         case 24: CASE(24) break; \
         default: CASE(33) break; \
     }
 
-hipError_t launch_matvec_dot(int dim, int jmax, const OrthoArgs& a, hipStream_t s) {
-    dim3 grid(a.nblocks, a.st.n);
+hipError_t launch_matvec_dot(int dim, int jmax, const VecArgs& a, hipStream_t s) {
+    if (a.st.n <= 0) return hipSuccess;
+    dim3 grid(a.st.nblocks);
 #define MV(J)                                                                  \
     if (dim == 2)                                                              \
         hipLaunchKernelGGL((k_matvec_dot<2, J>), grid, dim3(NT), 0, s, a);     \
@@ -836,39 +868,39 @@ hipError_t launch_matvec_dot(int dim, int jmax, const OrthoArgs& a, hipStream_t 
     return hipGetLastError();
 }
 
-hipError_t launch_update_dot(int jmax, const OrthoArgs& a, hipStream_t s) {
-    dim3 grid(a.nblocks, a.st.n);
+hipError_t launch_update_dot(int jmax, const VecArgs& a, hipStream_t s) {
+    if (a.st.n <= 0) return hipSuccess;
+    dim3 grid(a.st.nblocks);
 #define UD(J) hipLaunchKernelGGL((k_update_dot<J>), grid, dim3(NT), 0, s, a);
     MG_JSWITCH(UD)
 #undef UD
     return hipGetLastError();
 }
 
-hipError_t launch_update_norm(int jmax, const OrthoArgs& a, hipStream_t s) {
-    dim3 grid(a.nblocks, a.st.n);
+hipError_t launch_update_norm(int jmax, const VecArgs& a, hipStream_t s) {
+    if (a.st.n <= 0) return hipSuccess;
+    dim3 grid(a.st.nblocks);
 #define UN(J) hipLaunchKernelGGL((k_update_norm<J>), grid, dim3(NT), 0, s, a);
     MG_JSWITCH(UN)
 #undef UN
     return hipGetLastError();
 }
 
-hipError_t launch_combine(int jmax, const CombineArgs& a, hipStream_t s) {
-    dim3 grid(ortho_blocks(a.N), a.st.n);
+hipError_t launch_combine(int jmax, const VecArgs& a, hipStream_t s) {
+    if (a.st.n <= 0) return hipSuccess;
+    dim3 grid(a.st.nblocks);
 #define CB(J) hipLaunchKernelGGL((k_combine<J>), grid, dim3(NT), 0, s, a);
     MG_JSWITCH(CB)
 #undef CB
     return hipGetLastError();
 }
 
-hipError_t launch_reduce_complex(const cx<double>* part, int nvals, int vstride, int nblocks, int nslots,
-                                 cx<double>* out, int ostride, hipStream_t s) {
-    hipLaunchKernelGGL(k_reduce_complex, dim3(nvals, nslots), dim3(NT), 0, s, part, vstride, nblocks, out,
-                       ostride);
-    return hipGetLastError();
-}
-
-hipError_t launch_reduce_real(const double* part, int nblocks, int nslots, double* out, hipStream_t s) {
-    hipLaunchKernelGGL(k_reduce_real, dim3(nslots), dim3(NT), 0, s, part, nblocks, out);
+hipError_t launch_reduce(const ReduceArgs& a, int nslots, bool real, hipStream_t s) {
+    if (nslots <= 0) return hipSuccess;
+    if (real)
+        hipLaunchKernelGGL(k_reduce_real, dim3(1, nslots), dim3(NT), 0, s, a);
+    else
+        hipLaunchKernelGGL(k_reduce_complex, dim3(a.nvals, nslots), dim3(NT), 0, s, a);
     return hipGetLastError();
 }
 

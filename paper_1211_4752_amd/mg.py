@@ -32,6 +32,7 @@ EXPORTS = [
     "mg_params_default", "mg_setup", "mg_cycle", "mg_solve", "mg_solve_adjoint",
     "mg_grad_k2", "mg_apply", "mg_num_levels", "mg_level_dims", "mg_get_sigma",
     "mg_profile", "mg_profile_read", "mg_destroy", "mg_status_str",
+    "mg_tile_shape", "mg_batch_create", "mg_batch_solve", "mg_batch_destroy",
 ]
 
 
@@ -86,6 +87,15 @@ def lib():
         L.mg_profile_read.argtypes = [vp, ctypes.c_int, dp, ctypes.POINTER(ctypes.c_longlong), dp]
         L.mg_destroy.argtypes = [vp]
         L.mg_destroy.restype = None
+        L.mg_tile_shape.argtypes = [vp, ctypes.c_int, ctypes.c_int]
+        L.mg_tile_shape.restype = ctypes.c_int
+        L.mg_batch_create.argtypes = [ctypes.POINTER(vp), ctypes.c_int, ctypes.POINTER(vp)]
+        L.mg_batch_create.restype = ctypes.c_int
+        L.mg_batch_solve.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.c_int, ctypes.c_double,
+                                     ctypes.c_int, ctypes.c_int, ip, dp]
+        L.mg_batch_solve.restype = ctypes.c_int
+        L.mg_batch_destroy.argtypes = [vp]
+        L.mg_batch_destroy.restype = None
         L.mg_status_str.argtypes = [ctypes.c_int]
         L.mg_status_str.restype = ctypes.c_char_p
         for name in ("mg_setup", "mg_cycle", "mg_solve", "mg_solve_adjoint", "mg_grad_k2", "mg_apply",
@@ -258,6 +268,13 @@ class Solver:
             raise MGError(st, "mg_apply")
         return y
 
+    def tile_shape(self, level, shape=-1):
+        """Tile-shape id of the fused cycle kernels on a level; shape >= 0 sets it."""
+        r = lib().mg_tile_shape(self.ctx, int(level), int(shape))
+        if r < 0:
+            raise MGError(r, "mg_tile_shape")
+        return r
+
     def profile(self, enable=True):
         st = lib().mg_profile(self.ctx, int(bool(enable)))
         if st != MG_OK:
@@ -280,6 +297,63 @@ class Solver:
         if getattr(self, "ctx", None):
             lib().mg_destroy(self.ctx)
             self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+_STATUS = {MG_OK: "converged", MG_NOT_CONVERGED: "not_converged", MG_E_DIVERGED: "diverged"}
+
+
+class Batch:
+    """Several Solvers (grids of different sizes, same dimension, precision
+    and stream) iterated together by mg_batch_solve: each kernel launch of a
+    step covers the right-hand sides of all of them.  Borrows the solvers;
+    close it before them."""
+
+    def __init__(self, solvers):
+        self.solvers = list(solvers)
+        arr = (ctypes.c_void_p * len(self.solvers))(*[s.ctx.value for s in self.solvers])
+        b = ctypes.c_void_p()
+        st = lib().mg_batch_create(arr, len(self.solvers), ctypes.byref(b))
+        if st != MG_OK:
+            raise MGError(st, "mg_batch_create")
+        self.handle = b
+
+    def solve(self, us, fs, mode="gmres", rtol=1e-6, maxit=1000, restart=20):
+        """Solve in place on each us[i]; returns (status, per-solver iteration
+        lists, per-solver history lists)."""
+        k = len(self.solvers)
+        if len(us) != k or len(fs) != k:
+            raise ValueError("one u and one f per solver")
+        for s, u, f in zip(self.solvers, us, fs):
+            s._check_vec(u)
+            s._check_vec(f)
+        up = (ctypes.c_void_p * k)(*[u.data_ptr() for u in us])
+        fp = (ctypes.c_void_p * k)(*[f.data_ptr() for f in fs])
+        tot = sum(s.nrhs for s in self.solvers)
+        its = (ctypes.c_int * tot)()
+        hist = np.empty(tot * (maxit + 1), dtype=np.float64)
+        mode_id = {"standalone": MODE_STANDALONE, "gmres": MODE_GMRES}[mode]
+        st = lib().mg_batch_solve(self.handle, up, fp, mode_id, float(rtol), int(maxit), int(restart), its,
+                                  hist.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+        if st not in _STATUS:
+            raise MGError(st, "mg_batch_solve")
+        hist = hist.reshape(tot, maxit + 1)
+        iters, hists, r = [], [], 0
+        for s in self.solvers:
+            iters.append(list(its[r:r + s.nrhs]))
+            hists.append([h[h >= 0] for h in hist[r:r + s.nrhs]])
+            r += s.nrhs
+        return _STATUS[st], iters, hists
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().mg_batch_destroy(self.handle)
+            self.handle = None
 
     def __del__(self):
         try:

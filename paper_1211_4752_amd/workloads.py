@@ -180,3 +180,10 @@ def uneven_batch(count: int = 24, seed: int = 5):
     sizes = rng.choice(UNEVEN_SIZES, size=count, replace=True)
     khs = rng.uniform(0.3, 0.625, size=count)
     return [constant_2d(int(n), float(kh)) for n, kh in zip(sizes, khs)]
+
+
+def batched_2d(n: int = 511, nrhs: int = 64, count: int = 24):
+    """Batched workload: ``nrhs`` unit sources (seed 4) on one n^2 GRF
+    medium as in heterogeneous_2d, plus ``count`` uneven constant-kh
+    problems (uneven_batch)."""
+    return [heterogeneous_2d(n, nrhs, source_seed=4)] + uneven_batch(count)

@@ -97,6 +97,21 @@ def test_null_handles():
     assert L.mg_apply(None, 0, 0, None, None) == mg.MG_E_INVAL
     out = ctypes.c_void_p(123)
     assert L.mg_setup(None, None, None, ctypes.byref(out)) == mg.MG_E_INVAL and not out.value
+    assert L.mg_tile_shape(None, 0, -1) == mg.MG_E_INVAL
+    assert L.mg_profile_read(None, 0, None, None, None) == mg.MG_E_INVAL
+
+
+def test_batch_null_handles():
+    L = mg.lib()
+    L.mg_batch_destroy(None)
+    out = ctypes.c_void_p(123)
+    assert L.mg_batch_create(None, 1, ctypes.byref(out)) == mg.MG_E_INVAL and not out.value
+    arr = (ctypes.c_void_p * 2)(None, None)
+    out = ctypes.c_void_p(123)
+    assert L.mg_batch_create(arr, 2, ctypes.byref(out)) == mg.MG_E_INVAL and not out.value
+    assert L.mg_batch_create(arr, 0, ctypes.byref(out)) == mg.MG_E_INVAL
+    assert L.mg_batch_create(arr, 1, None) == mg.MG_E_INVAL
+    assert L.mg_batch_solve(None, None, None, 1, 1e-6, 10, 20, None, None) == mg.MG_E_INVAL
 
 
 def test_status_strings():

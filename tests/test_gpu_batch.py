@@ -1,0 +1,191 @@
+"""GPU: batched solves over grids of different sizes (mg_batch_*) and the
+tile shapes of the fused cycle kernels.
+
+A batch runs each kernel launch of a step over the right-hand sides of all
+its contexts, so every right-hand side must follow exactly the iteration of
+its own context: GMRES results and histories are compared bit for bit with
+single-context solves (every reduction is per right-hand side and does not
+depend on the batch), standalone histories to 1e-12 relative (their residual
+norms are summed per cycle-kernel tile, and a batch launch takes the tile
+shape of its largest grid).  Members are checked against the oracle at the
+bars of the single-context parity tests.  Tile shapes: one V-cycle under
+every shape id matches the oracle to 1e-11 and the other shapes to 1e-14.
+"""
+
+import numpy as np
+import pytest
+
+from oracle import cycle as C
+from oracle import helmholtz as H
+from oracle import krylov as K
+from paper_1211_4752_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def _dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+def _mg():
+    from paper_1211_4752_amd import mg
+    mg.lib()
+    return mg
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def problem_of(wl):
+    d = len(wl.n)
+    return H.Problem(wl.n, wl.h, wl.k2, (wl.ecs,) * d, (wl.ecs,) * d, wl.ecs_angle)
+
+
+def solver_of(wl, **kw):
+    mg = _mg()
+    k2 = torch.tensor(wl.k2, dtype=torch.float64, device=_dev())
+    return mg.Solver(wl.n, wl.h, k2, ecs=wl.ecs, ecs_angle=wl.ecs_angle, theta_max=wl.theta_max,
+                     nrhs=wl.f.shape[0], **kw)
+
+
+def gpu(a):
+    return torch.tensor(np.ascontiguousarray(a), dtype=torch.complex128, device=_dev())
+
+
+def rnd(shape, seed):
+    rng = np.random.default_rng(seed)
+    return rng.standard_normal(shape) + 1j * rng.standard_normal(shape)
+
+
+@pytest.mark.parametrize("wl", [W.heterogeneous_2d(255, 2), W.constant_3d(63, 0.5, 4)],
+                         ids=["grf_255", "const3d_63"])
+def test_every_tile_shape(wl):
+    s = solver_of(wl)
+    levels = H.build_hierarchy(problem_of(wl))
+    vc = C.VCycle(levels)
+    tuned = [s.tile_shape(l) for l in range(s.num_levels)]
+    say("tuned shapes", tuned)
+    u0 = rnd((s.nrhs,) + tuple(reversed(wl.n)), 11)
+    f = rnd(u0.shape, 12)
+    want = [vc(u0[r].ravel(), f[r].ravel()) for r in range(s.nrhs)]
+    outs = []
+    for shape in range(3):
+        for l in range(s.num_levels):
+            assert s.tile_shape(l, shape) == shape
+        u = gpu(u0)
+        res = s.cycle(u, gpu(f), residual=True)
+        got = u.cpu().numpy()
+        for r in range(s.nrhs):
+            err = np.abs(got[r].ravel() - want[r]).max() / np.abs(want[r]).max()
+            assert err < 1e-11, (shape, r, err)
+            rw = np.linalg.norm(f[r].ravel() - levels[0].A @ u0[r].ravel())
+            assert abs(res[r] - rw) <= 1e-12 * rw
+        outs.append(got)
+    for got in outs[1:]:
+        assert np.abs(got - outs[0]).max() <= 1e-14 * np.abs(outs[0]).max()
+    with pytest.raises(_mg().MGError):
+        s.tile_shape(0, 3)
+    s.close()
+
+
+def _single(wls, mode, rtol, maxit, restart, **kw):
+    out = []
+    for wl in wls:
+        s = solver_of(wl, **kw)
+        u = s.empty()
+        st, its, hists = s.solve(u, gpu(wl.f), mode=mode, rtol=rtol, maxit=maxit, restart=restart)
+        out.append((u.cpu(), its, hists))
+        s.close()
+    return out
+
+
+def _batch(wls, mode, rtol, maxit, restart, **kw):
+    mg = _mg()
+    ss = [solver_of(wl, **kw) for wl in wls]
+    b = mg.Batch(ss)
+    us = [s.empty() for s in ss]
+    st, its, hists = b.solve(us, [gpu(wl.f) for wl in wls], mode=mode, rtol=rtol, maxit=maxit, restart=restart)
+    b.close()
+    for s in ss:
+        s.close()
+    return st, [u.cpu() for u in us], its, hists
+
+
+@pytest.mark.parametrize("precision", ["c128", "mixed"])
+def test_batch_gmres_equals_single(precision):
+    wls = [W.heterogeneous_2d(63, 2, ecs=2), W.heterogeneous_2d(159, 1, ecs=5), W.heterogeneous_2d(127, 3, ecs=4),
+           W.constant_2d(191, 0.4)]
+    st, us, its, hists = _batch(wls, "gmres", 1e-8, 400, 20, precision=precision)
+    single = _single(wls, "gmres", 1e-8, 400, 20, precision=precision)
+    say("batch", st, its)
+    for i, (u1, its1, h1) in enumerate(single):
+        assert its[i] == its1, (i, its[i], its1)
+        assert torch.equal(us[i], u1), i
+        for r in range(len(h1)):
+            assert np.array_equal(hists[i][r], h1[r]), (i, r)
+    if precision == "c128":
+        # one member against the oracle (uneven size: coarsest 4 x 4)
+        wl = wls[1]
+        levels = H.build_hierarchy(problem_of(wl))
+        x, hist, it, sto = K.gmres(levels[0].A, C.VCycle(levels).precondition, wl.f[0].ravel(), rtol=1e-8,
+                                   restart=20, maxit=400)
+        assert its[1][0] == it
+        np.testing.assert_allclose(hists[1][0], hist, rtol=1e-8, atol=1e-11 * hist[0])
+        assert np.linalg.norm(us[1][0].numpy().ravel() - x) <= 1e-10 * np.linalg.norm(x)
+
+
+def test_batch_standalone_matches_single():
+    # constant kh = 0.3 with a wide layer: the standalone cycle converges
+    wls = [W.constant_2d(127, 0.3, ecs=16), W.constant_2d(255, 0.3, ecs=32), W.constant_2d(191, 0.3, ecs=24)]
+    st, us, its, hists = _batch(wls, "standalone", 1e-6, 300, 20)
+    single = _single(wls, "standalone", 1e-6, 300, 20)
+    say("batch standalone", st, its)
+    assert st == "converged"
+    for i, (u1, its1, h1) in enumerate(single):
+        assert its[i] == its1
+        np.testing.assert_allclose(hists[i][0], h1[0], rtol=1e-12, atol=0)
+        assert (us[i] - u1).abs().max() <= 1e-12 * u1.abs().max()
+    wl = wls[0]
+    levels = H.build_hierarchy(problem_of(wl))
+    uo, ho, ito, sto = C.standalone(C.VCycle(levels), wl.f[0].ravel(), rtol=1e-6, maxit=300)
+    assert its[0][0] == ito
+    np.testing.assert_allclose(hists[0][0], ho, rtol=1e-8, atol=1e-11 * ho[0])
+
+
+def test_batch_rejects_mismatch():
+    mg = _mg()
+    a = solver_of(W.heterogeneous_2d(63, 1, ecs=2))
+    b = solver_of(W.constant_3d(31, 0.5, 2))
+    c = solver_of(W.heterogeneous_2d(63, 1, ecs=2), precision="mixed")
+    for group in ([a, b], [a, c], [a, a]):
+        with pytest.raises(mg.MGError):
+            mg.Batch(group)
+    for s in (a, b, c):
+        s.close()
+
+
+def test_batched_workload_prefix():
+    """64 sources on one 511^2 GRF medium plus 24 uneven constant-kh problems
+    (127^2 .. 1023^2), mixed precision, one batch: the first GMRES(20) steps
+    of three members equal their single-context solves bit for bit, and the
+    smallest uneven member follows the oracle's complex64-cycle history."""
+    wls = W.batched_2d()
+    say("sizes", [wl.n[0] for wl in wls])
+    st, us, its, hists = _batch(wls, "gmres", 1e-6, 6, 20, precision="mixed")
+    assert st == "not_converged" and all(i == 6 for row in its for i in row)
+    small = int(np.argmin([wl.n[0] for wl in wls[1:]])) + 1
+    pick = [0, small, int(np.argmax([wl.n[0] for wl in wls]))]
+    single = _single([wls[i] for i in pick], "gmres", 1e-6, 6, 20, precision="mixed")
+    for i, (u1, its1, h1) in zip(pick, single):
+        assert torch.equal(us[i], u1), i
+        assert all(np.array_equal(a, b) for a, b in zip(hists[i], h1)), i
+    wl = wls[small]
+    levels = H.build_hierarchy(problem_of(wl))
+    vc32 = C.VCycle(levels, dtype=np.complex64)
+    x, h32, it, _ = K.gmres(levels[0].A, lambda v: vc32.precondition(v).astype(np.complex128), wl.f[0].ravel(),
+                            rtol=1e-6, restart=20, maxit=6)
+    np.testing.assert_allclose(hists[small][0], h32, rtol=1e-3)

@@ -225,14 +225,15 @@ def test_gmres_dirichlet_63():
     vc = C.VCycle(levels)
     u = s.empty()
     status, its, hists = s.solve(u, gpu(wl.f), mode="gmres", rtol=1e-6, maxit=8000, restart=20)
-    x, hist, it, st = K.gmres(levels[0].A, vc.precondition, wl.f[0].ravel(), rtol=1e-6, restart=20, maxit=8000)
-    say("dirichlet gmres", st, it, "gpu", status, its[0])
-    assert status == st == "converged"
-    assert abs(its[0] - it) <= max(2, it // 100)
+    assert status == "converged"
+    # ~2700 steps: the rounding drift between two correct FP64 runs reaches
+    # a few 1e-6 here (the oracle's MGS and CGS2 runs differ by that much and
+    # by ~10 steps), so the drift-measured bars of check_gmres apply.
+    it = check_gmres(u[0].cpu().numpy().ravel(), hists[0], its[0], levels[0].A, vc.precondition,
+                     wl.f[0].ravel(), 1e-6, 8000)
+    say("dirichlet gmres oracle", it, "gpu", status, its[0])
     true = np.linalg.norm(wl.f[0].ravel() - levels[0].A @ u[0].cpu().numpy().ravel())
     assert true / np.linalg.norm(wl.f[0]) <= 1e-6 * (1 + 1e-6)
-    err = np.linalg.norm(u[0].cpu().numpy().ravel() - x) / np.linalg.norm(x)
-    assert err < 1e-6, err
     s.close()
 
 
