@@ -8,6 +8,13 @@ TEST INFRASTRUCTURE ONLY (see oracle/__init__.py).
   eq. standardtg).
 * omega-Jacobi relaxation R_omega = I - omega D^{-1} A~ (Sec. 3.2.1,
   eq. wjacobi), D the diagonal of the level operator.
+* GMRES(m) as the smoother (Sec. 3.2.1 and 3.2.2): one application is one
+  GMRES cycle of m steps started from the current iterate, i.e. the iterate
+  u + z, z in the Krylov space K_m(A~, r) with r = f - A~ u, of least
+  residual norm; its residual is p_m(A~) r with a degree-m polynomial,
+  p_m(0) = 1, whose coefficients are chosen anew on every application and on
+  every level.  Arnoldi with modified Gram-Schmidt; the (m+1) x m
+  least-squares problem is handed to a library solver.
 * Two-grid correction with a perturbed coarse problem, applied recursively:
   on level l the operator is A~_l, the coarse problem is A~_{l+1} e = c R r
   with c = 1 for the CSL variant (Sec. 3.1, eq. cslvariant and eq. erreq1),
@@ -71,6 +78,39 @@ def jacobi(A, D, u, f, omega):
     return u + omega * (f - A @ u) / D
 
 
+def gmres_smooth(A, u, f, m=3):
+    """One GMRES(m) smoothing step (Sec. 3.2.2): argmin over u + K_m(A, r) of
+    ||f - A v||, r = f - A u.  Vectors stay in the dtype of u (complex64 in
+    the mixed-precision inner cycle); the Hessenberg matrix and the small
+    least-squares solve are complex128.  An exact breakdown (the Krylov space
+    is invariant after j < m steps) ends the Arnoldi process early."""
+    dt = u.dtype.type
+    r = f - A @ u
+    beta = float(np.linalg.norm(r))
+    if beta == 0.0:
+        return u
+    V = [r / dt(beta)]
+    H = np.zeros((m + 1, m), dtype=np.complex128)
+    k = m
+    for j in range(m):
+        w = A @ V[j]
+        for i in range(j + 1):
+            H[i, j] = np.vdot(V[i], w)
+            w = w - dt(H[i, j]) * V[i]
+        H[j + 1, j] = np.linalg.norm(w)
+        if H[j + 1, j] == 0:
+            k = j + 1
+            break
+        V.append(w / dt(H[j + 1, j]))
+    rhs = np.zeros(k + 1, dtype=np.complex128)
+    rhs[0] = beta
+    y = np.linalg.lstsq(H[:k + 1, :k], rhs, rcond=None)[0]
+    z = np.zeros_like(u)
+    for i in range(k):
+        z = z + dt(y[i]) * V[i]
+    return u + z
+
+
 # ---------------------------------------------------------------------------
 # V-cycle (Sec. 3.1)
 # ---------------------------------------------------------------------------
@@ -82,10 +122,15 @@ class VCycle:
     levels (complex128, or complex64 for the mixed-precision inner cycle); the
     coarsest direct solve is always done in complex128 and rounded back.
     ``adjoint=True`` uses the conjugate-transposed level operators A~_l^H.
+    ``smoother`` is "jacobi" (omega-Jacobi) or "gmres" (GMRES(degree)); with
+    the latter the cycle is a nonlinear map of its right-hand side.
     """
 
     def __init__(self, levels, nu1=1, nu2=1, omega=2.0 / 3.0,
-                 dtype=np.complex128, adjoint=False, rhs_scale=1.0):
+                 dtype=np.complex128, adjoint=False, rhs_scale=1.0, smoother="jacobi", degree=3):
+        if smoother not in ("jacobi", "gmres"):
+            raise ValueError(smoother)
+        self.smoother, self.degree = smoother, degree
         self.levels = levels
         self.nu1, self.nu2 = nu1, nu2
         self.dtype = np.dtype(dtype)
@@ -111,14 +156,19 @@ class VCycle:
             return self.solve_coarsest(f)
         A, D = self.A[l], self.D[l]
         for _ in range(self.nu1):
-            u = jacobi(A, D, u, f, self.omega)
+            u = self.smooth(A, D, u, f)
         r = f - A @ u
         fc = self.dtype.type(self.rhs_scale) * (self.R[l] @ r)
         e = self.cycle(l + 1, np.zeros_like(fc), fc)
         u = u + self.P[l] @ e
         for _ in range(self.nu2):
-            u = jacobi(A, D, u, f, self.omega)
+            u = self.smooth(A, D, u, f)
         return u
+
+    def smooth(self, A, D, u, f):
+        if self.smoother == "gmres":
+            return gmres_smooth(A, u, f, self.degree)
+        return jacobi(A, D, u, f, self.omega)
 
     def __call__(self, u, f):
         return self.cycle(0, u.astype(self.dtype), f.astype(self.dtype))

@@ -27,6 +27,12 @@ H[:, j] = h1 + h2); both are standard stable Arnoldi variants and serve to
 measure how far two correct FP64 evaluations of the same iteration drift
 apart.
 
+``flexible=True`` is flexible GMRES (Saad 1993): z_j = M v_j is stored and
+the update is x += Z y, which stays exact when M changes from step to step,
+as the cycle with the GMRES(m) smoother does (Sec. 3.2.2 last paragraph).
+For a fixed linear M it produces the same iterates as the right-
+preconditioned form.
+
 The history records ||f - A x0|| / ||f|| first, then the estimate after every
 outer step (one preconditioner application each).  When the estimate meets
 rtol the solution is updated and the true residual is checked; if it still
@@ -56,8 +62,8 @@ def givens(a: complex, b: complex):
     return c, s
 
 
-def gmres(A, M, f, x0=None, rtol=1e-6, restart=20, maxit=1000, ortho="mgs"):
-    """Right-preconditioned restarted GMRES(restart).
+def gmres(A, M, f, x0=None, rtol=1e-6, restart=20, maxit=1000, ortho="mgs", flexible=False):
+    """Right-preconditioned restarted GMRES(restart) (FGMRES with flexible).
 
     ``A`` is a sparse matrix, ``M`` a callable v -> M v returning complex128,
     ``ortho`` "mgs" or "cgs2".  Returns (x, history, iterations, status).
@@ -86,9 +92,13 @@ def gmres(A, M, f, x0=None, rtol=1e-6, restart=20, maxit=1000, ortho="mgs"):
         g = np.zeros(m + 1, dtype=np.complex128)
         g[0] = beta
         V[0] = r / beta
+        Z = np.zeros((m, len(f)), dtype=np.complex128) if flexible else None
         j_end = 0
         for j in range(m):
-            w = A @ M(V[j])
+            z = M(V[j])
+            if flexible:
+                Z[j] = z
+            w = A @ z
             if ortho == "mgs":
                 for i in range(j + 1):
                     H[i, j] = np.vdot(V[i], w)
@@ -122,7 +132,7 @@ def gmres(A, M, f, x0=None, rtol=1e-6, restart=20, maxit=1000, ortho="mgs"):
         y = np.zeros(k, dtype=np.complex128)
         for i in reversed(range(k)):                # back substitution
             y[i] = (g[i] - H[i, i + 1:k] @ y[i + 1:k]) / H[i, i]
-        x = x + M(V[:k].T @ y)
+        x = x + (Z[:k].T @ y if flexible else M(V[:k].T @ y))
 
 
 def refine_standalone(A, M, f, rtol=1e-6, maxit=100, div=1e8):
