@@ -65,8 +65,21 @@ enum mg_precision {
 
 enum mg_mode {
     MG_MODE_STANDALONE = 0, /* repeated V-cycles (Sec. 4.1, LVL-MG)          */
-    MG_MODE_GMRES = 1       /* restarted GMRES(restart), right-preconditioned
-                               by one V-cycle from a zero guess per step     */
+    MG_MODE_GMRES = 1,      /* restarted GMRES(restart), right-preconditioned
+                               by one V-cycle from a zero guess per step;
+                               flexible (as MG_MODE_FGMRES) when the smoother
+                               is GMRES(3), whose cycle is nonlinear         */
+    MG_MODE_FGMRES = 2      /* restarted flexible GMRES (Sec. 3.2.2: the
+                               preconditioner may change per step): stores
+                               z_j = M v_j, x += Z y                         */
+};
+
+enum mg_smoother {
+    MG_SMOOTH_JACOBI = 0,   /* omega-Jacobi, weight omega (Sec. 3.2.1)       */
+    MG_SMOOTH_GMRES3 = 1    /* one GMRES(3) cycle per smoothing step
+                               (Sec. 3.2.2): the iterate of least residual in
+                               u + K_3(A~_l, r), coefficients recomputed on
+                               every level and application                 */
 };
 
 typedef struct mg_params {
@@ -86,6 +99,7 @@ typedef struct mg_params {
     double omega[2];        /* complex Jacobi weight (re, im)                */
     int precision;          /* enum mg_precision                             */
     int nrhs;               /* right-hand sides handled by every call (>= 1) */
+    int smoother;           /* enum mg_smoother                              */
 } mg_params;
 
 typedef struct mg_ctx mg_ctx;
@@ -185,9 +199,11 @@ mg_status mg_get_sigma(const mg_ctx *c, double *sigma);
  * class `which` (enum mg_kernel_class) since then, synchronising the stream.
  * Any of the three out-pointers may be NULL. */
 enum mg_kernel_class {
-    MG_K_SMOOTH_RESTRICT_FINE = 0,  /* pre-smooth + residual + restriction, level 0 */
-    MG_K_PROLONG_SMOOTH_FINE = 1,   /* prolongation + correction + post-smooth, level 0 */
-    MG_K_COARSE_LEVELS = 2,         /* the same two kernels on levels >= 1 */
+    MG_K_SMOOTH_RESTRICT_FINE = 0,  /* pre-smooth + residual + restriction, level 0
+                                       (GMRES(3): the pass applying the polynomial) */
+    MG_K_PROLONG_SMOOTH_FINE = 1,   /* prolongation + correction + post-smooth, level 0
+                                       (GMRES(3): prolongation + residual, final apply) */
+    MG_K_COARSE_LEVELS = 2,         /* every cycle kernel on levels >= 1 */
     MG_K_COARSEST_SOLVE = 3,
     MG_K_RESIDUAL = 4,
     MG_K_MATVEC_DOT = 5,            /* GMRES: w = A z fused with <v_i, w> */
@@ -196,7 +212,9 @@ enum mg_kernel_class {
     MG_K_REDUCE = 8,
     MG_K_COMBINE = 9,               /* GMRES: t = V y */
     MG_K_OTHER = 10,
-    MG_K_NUM_CLASSES = 11
+    MG_K_SMOOTH_POWER_FINE = 11,    /* GMRES(3) smoother, level 0: q_i = (A/s) q_{i-1} */
+    MG_K_SMOOTH_GRAM_FINE = 12,     /* GMRES(3) smoother, level 0: Gram partials of q_0..q_3 */
+    MG_K_NUM_CLASSES = 13
 };
 mg_status mg_profile(mg_ctx *c, int enable);
 mg_status mg_profile_read(mg_ctx *c, int which, double *total_ms,

@@ -73,6 +73,18 @@ struct LevelView {
     const int* piv;            //   and row interchanges
     cx<T> sigma;               // shift multiplying k^2
     cx<T> omega;               // Jacobi weight
+    T sinv;                    // 1 / s, s the scale of the smoother's power basis
+};
+
+// Work vectors of the GMRES(3) smoother for one right-hand side on one level,
+// in compute precision, device resident.  With r the residual of the iterate
+// being smoothed, q0 = r, q1 = (A/s) q0, q2 = (A/s) q1 (q3 = (A/s) q2 is
+// only ever formed on the fly).
+struct SmoothBufs {
+    void* q[3];
+    void* u1;                  // iterate after pre-smoothing
+    void* u2;                  // iterate after the coarse-grid correction
+    cx<double>* coef;          // [2][4]: c1, c2, c3, (||r||^2, 0) for pre (0) and post (1)
 };
 
 // A slot of the two fused cycle kernels and of the coarsest solve.
@@ -86,6 +98,7 @@ struct CycleSlot {
     double fscale;        // f is multiplied by this
     int tile0;            // first logical tile of this slot in the launch
     int pad_;
+    const SmoothBufs* sb; // GMRES(3) smoother buffers of this slot's rhs on the launch level
 };
 
 struct CycleSlots {
@@ -143,8 +156,44 @@ struct ReduceArgs {
     int cnt[MAX_SLOTS];
 };
 
+// A slot of the pointwise passes of the GMRES(3) smoother.
+struct SmSlot {
+    const void* lv;             // LevelView<T>* of the slot's level
+    const SmoothBufs* sb;
+    const void* f;              // non-null: q0 = fscale f (complex double on level 0, else T)
+    void* out;                  // apply pass: result (complex double on level 0, else T)
+    double fscale;
+    int block0;                 // first workgroup of this slot in the launch
+    int pad_;
+};
+
+struct SmSlots {
+    int n;
+    int nblocks;
+    SmSlot s[MAX_SLOTS];
+};
+
+// Pointwise smoother passes; Gram partials at part[(slot * pstride + v) *
+// bstride + b], v < 10 (G00 G11 G22 G33 G01 G02 G03 G12 G13 G23, G_ij =
+// sum conj(q_i) q_j).
+struct SmArgs {
+    SmSlots st;
+    cx<double>* part;
+    int pstride;
+    int bstride;
+};
+
+// Gram reduction and coefficient solve: per slot, sum cnt[slot] partials in
+// a fixed order and write c1, c2, c3, (G00, 0) to coef[slot][0..3].
+struct SmCoefArgs {
+    const cx<double>* part;
+    int pstride, bstride;
+    int cnt[MAX_SLOTS];
+    cx<double>* coef[MAX_SLOTS];
+};
+
 // ---------------------------------------------------------------------------
-// Launchers (defined in mg_kernels.hip).  All return hipError_t of the launch.
+// Launchers (defined in mg_kernels.hip and mg_smooth.hip).  All return hipError_t of the launch.
 // Tile shape of the fused kernels: a shape id (chosen per level by timing).
 // ---------------------------------------------------------------------------
 constexpr int NUM_TILE_SHAPES = 3;
@@ -164,8 +213,18 @@ hipError_t launch_norm(const VecArgs& a, hipStream_t s);
 hipError_t launch_matvec_dot(int dim, int jmax, const VecArgs& a, hipStream_t s);
 hipError_t launch_update_dot(int jmax, const VecArgs& a, hipStream_t s);
 hipError_t launch_update_norm(int jmax, const VecArgs& a, hipStream_t s);
-hipError_t launch_combine(int jmax, const VecArgs& a, hipStream_t s);
+hipError_t launch_combine(int jmax, bool accumulate, const VecArgs& a, hipStream_t s);
 hipError_t launch_reduce(const ReduceArgs& a, int nslots, bool real, hipStream_t s);
+
+// GMRES(3) smoother passes (mg_smooth.hip).  level0: f is complex double.
+constexpr int NUM_GRAM = 10;
+hipError_t launch_sm_power(int dim, bool f32, bool level0, int stage, const SmArgs& a, hipStream_t s);
+hipError_t launch_sm_gram(int dim, bool f32, bool level0, const SmArgs& a, hipStream_t s);
+hipError_t launch_sm_coef(bool f32, const SmCoefArgs& a, int nslots, hipStream_t s);
+hipError_t launch_sm_apply_restrict(int dim, bool f32, bool level0, bool nonzero, int shape, const CycleArgs& a,
+                                    hipStream_t s);
+hipError_t launch_sm_prolong_resid(int dim, bool f32, bool level0, int shape, const CycleArgs& a, hipStream_t s);
+hipError_t launch_sm_apply_out(bool f32, bool level0, bool accumulate, const SmArgs& a, hipStream_t s);
 
 hipError_t launch_inject_k2(int dim, const double* fine, const int nf[3], double* coarse, const int nc[3],
                             hipStream_t s);

@@ -124,6 +124,9 @@ struct Level {
     float* k2f = nullptr;
     void* F = nullptr;            // right-hand sides on levels >= 1, by rhs
     void* E = nullptr;            // corrections on levels >= 1, by rhs
+    void* Q[3] = {nullptr, nullptr, nullptr};   // GMRES(3) smoother: q0, q1, q2 by rhs
+    void* SU1 = nullptr;          //   u1 by rhs
+    void* SU2 = nullptr;          //   u2 by rhs
 };
 
 struct Prof {
@@ -174,6 +177,13 @@ struct mg_ctx {
     // GMRES basis, by rhs: V + (rhs * vstride + i) * N0
     cx<double>* V = nullptr;
     int vstride = 0;
+    // FGMRES: z_i = M v_i, by rhs: Zb + (rhs * zstride + i) * N0
+    cx<double>* Zb = nullptr;
+    int zstride = 0;
+    // GMRES(3) smoother
+    bool gsmooth = false;
+    mg::SmoothBufs* sb_d = nullptr;   // [rhs * L + l]
+    cx<double>* gcoef = nullptr;      // [(rhs * L + l) * 8]
     double* scale_d = nullptr;     // [rhs * HSTRIDE + i]
     double* scale_h = nullptr;     // pinned
     cx<double>* coef_d = nullptr;  // [rhs * HSTRIDE + i]
@@ -473,6 +483,216 @@ mg_status launch_kb(Run& R, int dir, const std::vector<Item>& it, const std::vec
     });
 }
 
+// ---------------------------------------------------------------------------
+// GMRES(3) smoothing (Sec. 3.2.2): pre-smoothing at depth d ends in the
+// restriction of its residual, post-smoothing starts from u1 + P e.
+// ---------------------------------------------------------------------------
+mg_status build_vec(Run& R, int dir, const std::vector<Item>& it, const std::vector<int>& sub, VecArgs& a,
+                    int* cnt);
+mg_status reduce_real(Run& R, int n, const int* cnt);
+
+const mg::SmoothBufs* sbuf(const mg_ctx* c, int l, int rhs) { return c->sb_d + (size_t)rhs * c->L + l; }
+cx<double>* gcoef_of(const mg_ctx* c, int l, int rhs, int phase) {
+    return c->gcoef + ((size_t)rhs * c->L + l) * 8 + 4 * phase;
+}
+
+// Powers, Gram partials and coefficients of one smoothing step for the slots
+// of sa (q0 given by slot.f or the q0 buffer).
+mg_status smooth_coef(Run& R, int d, int phase, const std::vector<Item>& it, const std::vector<int>& sub,
+                      mg::SmArgs& sa, bool q0f) {
+    const bool fine = d == 0;
+    const double ct = R.mixed ? 8.0 : 16.0, sk = R.mixed ? 4.0 : 8.0;
+    double n = 0.0;
+    for (int k : sub) n += (double)it[k].c->lv[d].N;
+    const double q0b = (fine && q0f) ? 16.0 : ct;
+    for (int stage = 1; stage <= 2; ++stage) {
+        const double by = n * ((stage == 1 ? q0b : ct) + sk + ct);
+        const int pi = prof_begin(R, fine ? MG_K_SMOOTH_POWER_FINE : MG_K_COARSE_LEVELS, by);
+        CK(mg::launch_sm_power(R.dim, R.mixed, fine, stage, sa, R.s));
+        prof_end(R, pi);
+    }
+    int pi = prof_begin(R, fine ? MG_K_SMOOTH_GRAM_FINE : MG_K_COARSE_LEVELS, n * (q0b + 2.0 * ct + sk));
+    CK(mg::launch_sm_gram(R.dim, R.mixed, fine, sa, R.s));
+    prof_end(R, pi);
+    mg::SmCoefArgs ca{};
+    ca.part = R.w->part;
+    ca.pstride = HSTRIDE;
+    ca.bstride = R.w->bstride;
+    for (int q = 0; q < sa.st.n; ++q) {
+        const Item& I = it[sub[q]];
+        ca.cnt[q] = mg::vec_blocks(I.c->lv[d].N);
+        ca.coef[q] = gcoef_of(I.c, d, I.rhs, phase);
+    }
+    pi = prof_begin(R, fine ? MG_K_REDUCE : MG_K_COARSE_LEVELS);
+    CK(mg::launch_sm_coef(R.mixed, ca, sa.st.n, R.s));
+    prof_end(R, pi);
+    return MG_OK;
+}
+
+mg_status build_sm(Run& R, int dir, int d, const std::vector<Item>& it, const std::vector<int>& sub,
+                   mg::SmArgs& sa) {
+    sa.st.n = (int)sub.size();
+    int blocks = 0;
+    for (int q = 0; q < sa.st.n; ++q) {
+        const Item& I = it[sub[q]];
+        mg::SmSlot& s = sa.st.s[q];
+        s.lv = view_ptr(I.c, dir, d);
+        s.sb = sbuf(I.c, d, I.rhs);
+        s.block0 = blocks;
+        const int nb = mg::vec_blocks(I.c->lv[d].N);
+        if (nb > R.w->bstride) return MG_E_STATE;
+        blocks += nb;
+    }
+    sa.st.nblocks = blocks;
+    sa.part = R.w->part;
+    sa.pstride = HSTRIDE;
+    sa.bstride = R.w->bstride;
+    return MG_OK;
+}
+
+// Pre-smoothing at depth d and restriction of its residual to depth d + 1.
+// Level 0 with incoming iterates (FP64 only): q0 = f - A u by the FP64
+// residual kernel, whose ||q0||^2 of item k lands in w->rtot_h[k] when norm.
+mg_status launch_pre_g(Run& R, int dir, const std::vector<Item>& it, const std::vector<L0>* l0, int d, bool norm) {
+    std::vector<int> who;
+    for (int k = 0; k < (int)it.size(); ++k)
+        if (d + 1 < it[k].c->L) who.push_back(k);
+    const bool nz = d == 0 && l0 && (*l0)[0].u;
+    if (nz && R.mixed) return MG_E_STATE;
+    return for_groups(who, [&](const std::vector<int>& sub, int gbase) -> mg_status {
+        if (nz) {
+            VecArgs a{};
+            int cnt[mg::MAX_SLOTS];
+            CKS(build_vec(R, dir, it, sub, a, cnt));
+            double by = 0.0;
+            for (int q = 0; q < a.st.n; ++q) {
+                const Item& I = it[sub[q]];
+                const L0& z = (*l0)[sub[q]];
+                if (z.fs != 1.0) return MG_E_STATE;
+                a.st.s[q].x = z.u;
+                a.st.s[q].f = (const cx<double>*)z.f;
+                a.st.s[q].y = (cx<double>*)lvec(I.c, I.c->lv[0].Q[0], 0, I.rhs);
+                by += I.c->lv[0].N * 56.0;
+            }
+            if (!norm) a.rpart = nullptr;
+            const int pi = prof_begin(R, MG_K_RESIDUAL, by);
+            CK(mg::launch_residual(R.dim, a, R.s));
+            prof_end(R, pi);
+            if (norm) {
+                CKS(reduce_real(R, a.st.n, cnt));
+                CK(hipMemcpyAsync(R.w->rtot_h + gbase, R.w->rtot, a.st.n * sizeof(double), hipMemcpyDeviceToHost,
+                                  R.s));
+            }
+        }
+        mg::SmArgs sa{};
+        CKS(build_sm(R, dir, d, it, sub, sa));
+        for (int q = 0; q < sa.st.n; ++q) {
+            const Item& I = it[sub[q]];
+            mg::SmSlot& s = sa.st.s[q];
+            if (nz) {
+                s.f = nullptr;
+                s.fscale = 1.0;
+            } else if (d == 0) {
+                s.f = (*l0)[sub[q]].f;
+                s.fscale = (*l0)[sub[q]].fs;
+            } else {
+                s.f = lvec(I.c, I.c->lv[d].F, d, I.rhs);
+                s.fscale = 1.0;
+            }
+        }
+        CKS(smooth_coef(R, d, 0, it, sub, sa, !nz));
+        const int shape = launch_shape(it, sub, d);
+        CycleArgs a{};
+        a.st.n = sa.st.n;
+        int tiles = 0;
+        double by = 0.0;
+        const double ct = R.mixed ? 8.0 : 16.0, sk = R.mixed ? 4.0 : 8.0;
+        for (int q = 0; q < a.st.n; ++q) {
+            const Item& I = it[sub[q]];
+            mg_ctx* c = I.c;
+            CycleSlot& s = a.st.s[q];
+            s.lv = sa.st.s[q].lv;
+            s.f = sa.st.s[q].f;
+            s.fscale = sa.st.s[q].fscale;
+            s.u = nz ? (const void*)(*l0)[sub[q]].u : nullptr;
+            s.c = lvec(c, c->lv[d + 1].F, d + 1, I.rhs);
+            s.sb = sbuf(c, d, I.rhs);
+            s.tile0 = tiles;
+            int nt[3];
+            mg::tile_counts(R.dim, shape, c->lv[d].n, nt);
+            tiles += nt[0] * nt[1] * nt[2];
+            const double q0b = (d == 0 && !nz) ? 16.0 : ct;
+            by += c->lv[d].N * (q0b + 3.0 * ct + sk + (nz ? 16.0 : 0.0)) + c->lv[d + 1].N * ct;
+        }
+        a.st.ntiles = tiles;
+        const int pi = prof_begin(R, d == 0 ? MG_K_SMOOTH_RESTRICT_FINE : MG_K_COARSE_LEVELS, by);
+        CK(mg::launch_sm_apply_restrict(R.dim, R.mixed, d == 0, nz, shape, a, R.s));
+        prof_end(R, pi);
+        return MG_OK;
+    });
+}
+
+// Coarse-grid correction and post-smoothing at depth d.
+mg_status launch_post_g(Run& R, int dir, const std::vector<Item>& it, const std::vector<L0>* l0, int d, bool acc) {
+    std::vector<int> who;
+    for (int k = 0; k < (int)it.size(); ++k)
+        if (d + 1 < it[k].c->L) who.push_back(k);
+    return for_groups(who, [&](const std::vector<int>& sub, int) -> mg_status {
+        const int shape = launch_shape(it, sub, d);
+        const double ct = R.mixed ? 8.0 : 16.0, sk = R.mixed ? 4.0 : 8.0;
+        CycleArgs a{};
+        a.st.n = (int)sub.size();
+        int tiles = 0;
+        double by = 0.0;
+        for (int q = 0; q < a.st.n; ++q) {
+            const Item& I = it[sub[q]];
+            mg_ctx* c = I.c;
+            CycleSlot& s = a.st.s[q];
+            s.lv = view_ptr(c, dir, d);
+            if (d == 0) {
+                s.f = (*l0)[sub[q]].f;
+                s.fscale = (*l0)[sub[q]].fs;
+            } else {
+                s.f = lvec(c, c->lv[d].F, d, I.rhs);
+                s.fscale = 1.0;
+            }
+            s.c = lvec(c, c->lv[d + 1].E, d + 1, I.rhs);
+            s.sb = sbuf(c, d, I.rhs);
+            s.tile0 = tiles;
+            int nt[3];
+            mg::tile_counts(R.dim, shape, c->lv[d].n, nt);
+            tiles += nt[0] * nt[1] * nt[2];
+            by += c->lv[d].N * (ct + (d == 0 ? 16.0 : ct) + sk + 2.0 * ct) + c->lv[d + 1].N * ct;
+        }
+        a.st.ntiles = tiles;
+        int pi = prof_begin(R, d == 0 ? MG_K_PROLONG_SMOOTH_FINE : MG_K_COARSE_LEVELS, by);
+        CK(mg::launch_sm_prolong_resid(R.dim, R.mixed, d == 0, shape, a, R.s));
+        prof_end(R, pi);
+        mg::SmArgs sa{};
+        CKS(build_sm(R, dir, d, it, sub, sa));
+        CKS(smooth_coef(R, d, 1, it, sub, sa, false));
+        by = 0.0;
+        for (int q = 0; q < sa.st.n; ++q) {
+            const Item& I = it[sub[q]];
+            mg_ctx* c = I.c;
+            sa.st.s[q].out = d == 0 ? (void*)(*l0)[sub[q]].out : lvec(c, c->lv[d].E, d, I.rhs);
+            by += c->lv[d].N * (4.0 * ct + (d == 0 ? 16.0 : ct) + (d == 0 && acc ? 16.0 : 0.0));
+        }
+        pi = prof_begin(R, d == 0 ? MG_K_PROLONG_SMOOTH_FINE : MG_K_COARSE_LEVELS, by);
+        CK(mg::launch_sm_apply_out(R.mixed, d == 0, d == 0 && acc, sa, R.s));
+        prof_end(R, pi);
+        return MG_OK;
+    });
+}
+
+// The descending / ascending halves of one level's cycle work.
+mg_status cycle_down(Run& R, int dir, const std::vector<Item>& it, const std::vector<L0>* l0, int d, bool norm) {
+    return it[0].c->gsmooth ? launch_pre_g(R, dir, it, l0, d, norm) : launch_ka(R, dir, it, l0, d, norm);
+}
+mg_status cycle_up(Run& R, int dir, const std::vector<Item>& it, const std::vector<L0>* l0, int d, bool acc) {
+    return it[0].c->gsmooth ? launch_post_g(R, dir, it, l0, d, acc) : launch_kb(R, dir, it, l0, d, acc);
+}
+
 // Levels >= 1 and the coarsest solve of one cycle: captured once per
 // (direction, item list) as a HIP graph and replayed; every pointer in it is
 // fixed per item (F_l and E_l by rhs).
@@ -480,9 +700,9 @@ mg_status coarse_part(Run& R, int dir, const std::vector<Item>& it) {
     int maxL = 0;
     for (const Item& I : it) maxL = std::max(maxL, I.c->L);
     auto record = [&](Run& Q) -> mg_status {
-        for (int d = 1; d + 1 < maxL; ++d) CKS(launch_ka(Q, dir, it, nullptr, d, false));
+        for (int d = 1; d + 1 < maxL; ++d) CKS(cycle_down(Q, dir, it, nullptr, d, false));
         CKS(launch_coarsest(Q, dir, it));
-        for (int d = maxL - 2; d >= 1; --d) CKS(launch_kb(Q, dir, it, nullptr, d, false));
+        for (int d = maxL - 2; d >= 1; --d) CKS(cycle_up(Q, dir, it, nullptr, d, false));
         return MG_OK;
     };
     if (!R.gc) return record(R);
@@ -517,9 +737,13 @@ mg_status coarse_part(Run& R, int dir, const std::vector<Item>& it) {
     if (R.prof && R.prof->on) {
         const double ct = R.mixed ? 8.0 : 16.0, sk = R.mixed ? 4.0 : 8.0;
         for (const Item& I : it)
-            for (int l = 1; l + 1 < I.c->L; ++l)
-                by += I.c->lv[l].N * (ct + sk) + I.c->lv[l + 1].N * ct +
-                      I.c->lv[l].N * (3 * ct + sk) + I.c->lv[l + 1].N * ct;
+            for (int l = 1; l + 1 < I.c->L; ++l) {
+                if (I.c->gsmooth)   // powers, Gram, apply passes of both smoothing steps
+                    by += I.c->lv[l].N * (27 * ct + 8 * sk) + 2 * I.c->lv[l + 1].N * ct;
+                else
+                    by += I.c->lv[l].N * (ct + sk) + I.c->lv[l + 1].N * ct +
+                          I.c->lv[l].N * (3 * ct + sk) + I.c->lv[l + 1].N * ct;
+            }
     }
     const int pi = prof_begin(R, MG_K_COARSE_LEVELS, by);
     CK(hipGraphLaunch(f->second, R.s));
@@ -532,9 +756,9 @@ mg_status coarse_part(Run& R, int dir, const std::vector<Item>& it) {
 mg_status vcycle(Run& R, int dir, const std::vector<Item>& it, const std::vector<L0>& l0, bool acc,
                  bool norms) {
     if (R.mixed && l0[0].u) return MG_E_STATE;
-    CKS(launch_ka(R, dir, it, &l0, 0, norms));
+    CKS(cycle_down(R, dir, it, &l0, 0, norms));
     CKS(coarse_part(R, dir, it));
-    CKS(launch_kb(R, dir, it, &l0, 0, acc));
+    CKS(cycle_up(R, dir, it, &l0, 0, acc));
     return MG_OK;
 }
 
@@ -646,13 +870,21 @@ mg_status residual(Run& R, int dir, const std::vector<Item>& it, const std::vect
     return MG_OK;
 }
 
-mg_status ensure_basis(mg_ctx* c, int restart) {
-    if (c->V && c->vstride >= restart + 1) return MG_OK;
-    dfree(c->V);
-    c->vstride = 0;
-    const size_t bytes = (size_t)c->nrhs * (restart + 1) * c->lv[0].N * sizeof(cx<double>);
-    CKS(dalloc(&c->V, bytes));
-    c->vstride = restart + 1;
+mg_status ensure_basis(mg_ctx* c, int restart, bool flexible) {
+    if (!c->V || c->vstride < restart + 1) {
+        dfree(c->V);
+        c->vstride = 0;
+        const size_t bytes = (size_t)c->nrhs * (restart + 1) * c->lv[0].N * sizeof(cx<double>);
+        CKS(dalloc(&c->V, bytes));
+        c->vstride = restart + 1;
+    }
+    if (flexible && (!c->Zb || c->zstride < restart)) {
+        dfree(c->Zb);
+        c->zstride = 0;
+        const size_t bytes = (size_t)c->nrhs * restart * c->lv[0].N * sizeof(cx<double>);
+        CKS(dalloc(&c->Zb, bytes));
+        c->zstride = restart;
+    }
     return MG_OK;
 }
 
@@ -744,7 +976,8 @@ mg_status solve_standalone(Run& R, int dir, const std::vector<Item>& it, const s
 // zero guess per outer step).  Arnoldi by classical Gram-Schmidt with one
 // re-orthogonalisation pass; Hessenberg least squares by complex Givens
 // rotations on the host; x += M (V y) at the end of each restart cycle (the
-// cycle is a fixed linear map).
+// cycle is a fixed linear map).  Flexible GMRES (Sec. 3.2.2, for the
+// nonlinear GMRES(3)-smoothed cycle) keeps z_j = M v_j and adds Z y.
 // ---------------------------------------------------------------------------
 struct GmresState {
     int j = 0;                  // basis vectors V_0..V_j exist
@@ -761,12 +994,16 @@ cx<double>* basis(const Item& I, int i) {
     mg_ctx* c = I.c;
     return c->V + ((size_t)I.rhs * c->vstride + i) * c->lv[0].N;
 }
+cx<double>* zbasis(const Item& I, int i) {
+    mg_ctx* c = I.c;
+    return c->Zb + ((size_t)I.rhs * c->zstride + i) * c->lv[0].N;
+}
 
 mg_status solve_gmres(Run& R, int dir, const std::vector<Item>& it, const std::vector<cx<double>*>& X,
-                      const std::vector<const cx<double>*>& F, double rtol, int maxit, int m, int* iters,
-                      double* hist) {
+                      const std::vector<const cx<double>*>& F, double rtol, int maxit, int m, bool flexible,
+                      int* iters, double* hist) {
     const int n = (int)it.size();
-    for (const Item& I : it) CKS(ensure_basis(I.c, m));
+    for (const Item& I : it) CKS(ensure_basis(I.c, m, flexible));
     std::vector<GmresState> gs(n);
     for (int k = 0; k < n; ++k) {
         gs[k].H.assign((size_t)(m + 1) * m, 0.0);
@@ -852,7 +1089,7 @@ mg_status solve_gmres(Run& R, int dir, const std::vector<Item>& it, const std::v
             sub.push_back(it[k]);
             mg_ctx* c = it[k].c;
             l0.push_back(L0{basis(it[k], gs[k].j), scale_h(k, gs[k].j), nullptr,
-                            c->Z + (size_t)it[k].rhs * c->lv[0].N});
+                            flexible ? zbasis(it[k], gs[k].j) : c->Z + (size_t)it[k].rhs * c->lv[0].N});
         }
         CKS(vcycle(R, dir, sub, l0, false, false));
         std::vector<int> local(act.size());
@@ -866,7 +1103,7 @@ mg_status solve_gmres(Run& R, int dir, const std::vector<Item>& it, const std::v
                 const int k = act[g[q]];
                 mg_ctx* c = it[k].c;
                 VecSlot& s = a.st.s[q];
-                s.x = c->Z + (size_t)it[k].rhs * c->lv[0].N;
+                s.x = flexible ? zbasis(it[k], gs[k].j) : c->Z + (size_t)it[k].rhs * c->lv[0].N;
                 s.y = c->W + (size_t)it[k].rhs * c->lv[0].N;
                 s.V = basis(it[k], 0);
                 s.scale = c->scale_d + (size_t)it[k].rhs * HSTRIDE;
@@ -949,7 +1186,7 @@ mg_status solve_gmres(Run& R, int dir, const std::vector<Item>& it, const std::v
                 G.j = j + 1;
         }
         if (!fin.empty()) {
-            // y = R^{-1} g, x += M (V y)
+            // y = R^{-1} g, x += M (V y) (flexible: x += Z y)
             int jm = 0;
             std::vector<Item> fs;
             std::vector<L0> fl0;
@@ -964,7 +1201,7 @@ mg_status solve_gmres(Run& R, int dir, const std::vector<Item>& it, const std::v
                 }
                 mg_ctx* c = it[k].c;
                 for (int i = 0; i < kk; ++i)
-                    c->coef_h[(size_t)it[k].rhs * HSTRIDE + i] = tocx(y[i] * scale_h(k, i));
+                    c->coef_h[(size_t)it[k].rhs * HSTRIDE + i] = tocx(flexible ? y[i] : y[i] * scale_h(k, i));
                 jm = std::max(jm, kk);
                 fs.push_back(it[k]);
                 fl0.push_back(L0{c->W + (size_t)it[k].rhs * c->lv[0].N, 1.0, nullptr, X[k]});
@@ -983,18 +1220,18 @@ mg_status solve_gmres(Run& R, int dir, const std::vector<Item>& it, const std::v
                     const int k = fin[g[q]];
                     mg_ctx* c = it[k].c;
                     VecSlot& s = a.st.s[q];
-                    s.V = basis(it[k], 0);
+                    s.V = flexible ? zbasis(it[k], 0) : basis(it[k], 0);
                     s.coef = c->coef_d + (size_t)it[k].rhs * HSTRIDE;
-                    s.y = c->W + (size_t)it[k].rhs * c->lv[0].N;
+                    s.y = flexible ? X[k] : c->W + (size_t)it[k].rhs * c->lv[0].N;
                     s.j = gs[k].j;
-                    by += 16.0 * c->lv[0].N * (gs[k].j + 2);
+                    by += 16.0 * c->lv[0].N * (gs[k].j + 2 + (flexible ? 1 : 0));
                 }
                 const int pi = prof_begin(R, MG_K_COMBINE, by);
-                CK(mg::launch_combine(jm, a, R.s));
+                CK(mg::launch_combine(jm, flexible, a, R.s));
                 prof_end(R, pi);
                 return MG_OK;
             }));
-            CKS(vcycle(R, dir, fs, fl0, true, false));
+            if (!flexible) CKS(vcycle(R, dir, fs, fl0, true, false));
             CKS(restart(fin));
         }
     }
@@ -1015,9 +1252,10 @@ mg_status solve_items(Run& R, int dir, const std::vector<Item>& it, const std::v
     if (hist)
         for (size_t i = 0; i < it.size() * (size_t)(maxit + 1); ++i) hist[i] = -1.0;
     if (mode == MG_MODE_STANDALONE) return solve_standalone(R, dir, it, U, F, rtol, maxit, iters, hist);
-    if (mode == MG_MODE_GMRES) {
+    if (mode == MG_MODE_GMRES || mode == MG_MODE_FGMRES) {
         if (restart < 1 || restart > MAX_RESTART) return MG_E_INVAL;
-        return solve_gmres(R, dir, it, U, F, rtol, maxit, restart, iters, hist);
+        const bool flexible = mode == MG_MODE_FGMRES || it[0].c->gsmooth;
+        return solve_gmres(R, dir, it, U, F, rtol, maxit, restart, flexible, iters, hist);
     }
     return MG_E_INVAL;
 }
@@ -1055,7 +1293,13 @@ void release(mg_ctx* c) {
         dfree(L.k2f);
         dfree(L.F);
         dfree(L.E);
+        for (int i = 0; i < 3; ++i) dfree(L.Q[i]);
+        dfree(L.SU1);
+        dfree(L.SU2);
     }
+    dfree(c->sb_d);
+    dfree(c->gcoef);
+    dfree(c->Zb);
     for (int d = 0; d < 2; ++d) {
         dfree(c->lu[d]);
         dfree(c->piv[d]);
@@ -1109,6 +1353,10 @@ mg_status upload_views(mg_ctx* c) {
             b.sigma = mg::mk((float)s.real(), (float)s.imag());
             a.omega = mg::mk(c->p.omega[0], c->p.omega[1]);
             b.omega = mg::mk((float)c->p.omega[0], (float)c->p.omega[1]);
+            double sc = 0.0;   // bound of the Laplacian part: sum over axes of 4 / h^2
+            for (int ax = 0; ax < d; ++ax) sc += 4.0 / (V.h[ax] * V.h[ax]);
+            a.sinv = 1.0 / sc;
+            b.sinv = (float)(1.0 / sc);
             if (l == c->L - 1) {
                 a.lu = b.lu = c->lu[dir];
                 a.piv = b.piv = c->piv[dir];
@@ -1156,8 +1404,8 @@ mg_status autotune(mg_ctx* c) {
             float tot = 0.0f;
             for (int rep = 0; rep < 4 && st == MG_OK; ++rep) {
                 if (hipEventRecord(e0, c->stream) != hipSuccess) st = MG_E_DEVICE;
-                if (st == MG_OK) st = launch_ka(R, 0, it, &l0, l, false);
-                if (st == MG_OK) st = launch_kb(R, 0, it, &l0, l, false);
+                if (st == MG_OK) st = cycle_down(R, 0, it, &l0, l, false);
+                if (st == MG_OK) st = cycle_up(R, 0, it, &l0, l, false);
                 if (st == MG_OK && hipEventRecord(e1, c->stream) != hipSuccess) st = MG_E_DEVICE;
                 if (st == MG_OK && hipEventSynchronize(e1) != hipSuccess) st = MG_E_DEVICE;
                 float ms = 0.0f;
@@ -1327,6 +1575,27 @@ mg_status setup(const mg_params* p, const double* k2_dev, void* stream, mg_ctx* 
         CKS(dalloc(&c->lv[l].F, (size_t)c->nrhs * c->lv[l].N * esz));
         CKS(dalloc(&c->lv[l].E, (size_t)c->nrhs * c->lv[l].N * esz));
     }
+    c->gsmooth = p->smoother == MG_SMOOTH_GMRES3;
+    if (c->gsmooth) {
+        std::vector<mg::SmoothBufs> sb((size_t)c->nrhs * L);
+        CKS(dalloc(&c->gcoef, (size_t)c->nrhs * L * 8 * sizeof(cx<double>)));
+        for (int l = 0; l < L; ++l) {
+            Level& V = c->lv[l];
+            const size_t bytes = (size_t)c->nrhs * V.N * esz;
+            for (int i = 0; i < 3; ++i) CKS(dalloc(&V.Q[i], bytes));
+            CKS(dalloc(&V.SU1, bytes));
+            CKS(dalloc(&V.SU2, bytes));
+            for (int r = 0; r < c->nrhs; ++r) {
+                mg::SmoothBufs& b = sb[(size_t)r * L + l];
+                for (int i = 0; i < 3; ++i) b.q[i] = lvec(c, V.Q[i], l, r);
+                b.u1 = lvec(c, V.SU1, l, r);
+                b.u2 = lvec(c, V.SU2, l, r);
+                b.coef = c->gcoef + ((size_t)r * L + l) * 8;
+            }
+        }
+        CKS(dalloc(&c->sb_d, sb.size() * sizeof(mg::SmoothBufs)));
+        CK(hipMemcpy(c->sb_d, sb.data(), sb.size() * sizeof(mg::SmoothBufs), hipMemcpyHostToDevice));
+    }
     const size_t vbytes = (size_t)c->nrhs * c->lv[0].N * sizeof(cx<double>);
     if (!c->mixed) CKS(dalloc(&c->U1, vbytes));
     CKS(dalloc(&c->Z, vbytes));
@@ -1376,6 +1645,7 @@ mg_status mg_setup(const mg_params* p, const double* k2_dev, void* stream, mg_ct
     if (p->ndim != 2 && p->ndim != 3) return MG_E_INVAL;
     if (p->nrhs < 1 || p->nu1 != 1 || p->nu2 != 1) return MG_E_INVAL;
     if (p->precision != MG_PREC_C128 && p->precision != MG_PREC_MIXED) return MG_E_INVAL;
+    if (p->smoother != MG_SMOOTH_JACOBI && p->smoother != MG_SMOOTH_GMRES3) return MG_E_INVAL;
     for (int a = 0; a < p->ndim; ++a) {
         if (p->n[a] < 3 || !(p->h[a] > 0.0)) return MG_E_INVAL;
         if (p->ecs_lo[a] < 0 || p->ecs_hi[a] < 0 || p->ecs_lo[a] + p->ecs_hi[a] > p->n[a] + 1) return MG_E_INVAL;
@@ -1496,7 +1766,8 @@ mg_status mg_batch_create(mg_ctx* const* ctxs, int count, mg_batch** out) {
     int items = 0, bstride = 0;
     for (int i = 0; i < count; ++i) {
         const mg_ctx* c = ctxs[i];
-        if (!c || c->dim != ctxs[0]->dim || c->mixed != ctxs[0]->mixed || c->stream != ctxs[0]->stream)
+        if (!c || c->dim != ctxs[0]->dim || c->mixed != ctxs[0]->mixed || c->stream != ctxs[0]->stream ||
+            c->gsmooth != ctxs[0]->gsmooth)
             return MG_E_INVAL;
         for (int j = 0; j < i; ++j)
             if (ctxs[j] == c) return MG_E_INVAL;

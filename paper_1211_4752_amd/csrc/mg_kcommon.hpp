@@ -1,0 +1,153 @@
+// Device helpers shared by the kernel translation units (gfx950, wave64).
+#pragma once
+
+#include "mg_device.hpp"
+
+// dispatch over (dim, shape) of a fused kernel template K<D, TX, TY, TZ>
+#define MG_SHAPE_SWITCH(LAUNCH)                                                    \
+    if (dim == 2) {                                                                \
+        switch (shape) {                                                           \
+            case 1: LAUNCH(2, 64, 8, 1); break;                                    \
+            case 2: LAUNCH(2, 128, 8, 1); break;                                   \
+            default: LAUNCH(2, 64, 16, 1); break;                                  \
+        }                                                                          \
+    } else {                                                                       \
+        switch (shape) {                                                           \
+            case 1: LAUNCH(3, 32, 4, 2); break;                                    \
+            case 2: LAUNCH(3, 16, 4, 4); break;                                    \
+            default: LAUNCH(3, 16, 8, 4); break;                                   \
+        }                                                                          \
+    }
+
+
+namespace mg {
+namespace kc {
+
+constexpr int NT = 256;      // threads per workgroup (4 wave64)
+constexpr int NXCD = 8;      // MI355X: 8 XCDs, workgroups dealt round-robin
+
+// Map the hardware workgroup id to a logical tile id such that each XCD gets
+// one contiguous range of tiles (neighbouring tiles share halos in its L2).
+__device__ __forceinline__ int xcd_remap(int pid, int num) {
+    const int xcd = pid % NXCD;
+    const int local = pid / NXCD;
+    const int per = num / NXCD;
+    const int extra = num % NXCD;
+    return xcd * per + (xcd < extra ? xcd : extra) + local;
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Deterministic workgroup sum; the result is valid in thread 0.  sm holds
+// NT/64 doubles.  Must be reached by every thread of the workgroup.
+__device__ __forceinline__ double block_sum(double v, double* sm) {
+    v = wave_sum(v);
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) sm[wave] = v;
+    __syncthreads();
+    double t = 0.0;
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int w = 0; w < NT / 64; ++w) t += sm[w];
+    }
+    return t;
+}
+
+// Slot of logical workgroup pid: the last slot whose first tile is <= pid
+// (slots are listed in increasing first-tile order).
+template <typename S>
+__device__ __forceinline__ int find_slot(const S* s, int n, int pid) {
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (s[mid].tile0 <= pid)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
+
+template <int D, typename T>
+__device__ __forceinline__ cx<T> diag_at(const LevelView<T>& L, int gx, int gy, int gz, T k2) {
+    cx<T> d = L.c0[0][gx] + L.c0[1][gy];
+    if constexpr (D == 3) d = d + L.c0[2][gz];
+    return d - k2 * L.sigma;
+}
+
+template <typename T>
+__device__ __forceinline__ void interp_1d(int g, int cs, int& i0, int& i1, T& w0, T& w1) {
+    if (g & 1) {
+        i0 = (g - 1) / 2 - cs;
+        i1 = i0;
+        w0 = T(1);
+        w1 = T(0);
+    } else {
+        const int J = g / 2;
+        i0 = J - 1 - cs;
+        i1 = J - cs;
+        w0 = T(0.5);
+        w1 = T(0.5);
+    }
+}
+
+// Slot, workgroup within the slot and its point range [lo, hi).
+struct VecPos {
+    int slot, b, nb, lo, hi;
+};
+
+__device__ __forceinline__ VecPos vec_pos(const VecSlots& st) {
+    VecPos q;
+    const int pid = xcd_remap(blockIdx.x, gridDim.x);
+    int lo = 0, hi = st.n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (st.s[mid].block0 <= pid)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    q.slot = lo;
+    q.b = pid - st.s[lo].block0;
+    q.nb = (lo + 1 < st.n ? st.s[lo + 1].block0 : st.nblocks) - st.s[lo].block0;
+    q.lo = q.hi = 0;
+    return q;
+}
+
+__device__ __forceinline__ void chunk_range(long long N, int nblocks, int b, int& lo, int& hi) {
+    const long long per = (N + nblocks - 1) / nblocks;
+    long long l = per * b, h = l + per;
+    if (l > N) l = N;
+    if (h > N) h = N;
+    lo = (int)l;
+    hi = (int)h;
+}
+
+
+// 3-point-per-axis stencil of the level operator at point p of x, x scaled by
+// xs and converted to the compute precision T.
+template <int D, typename T, typename TX>
+__device__ __forceinline__ cx<T> stencil_at(const LevelView<T>& L, const cx<TX>* x, T xs, long long p, int gx,
+                                            int gy, int gz) {
+    const int nx = L.n[0], ny = L.n[1], nz = L.n[2];
+    cx<T> ax = diag_at<D>(L, gx, gy, gz, L.k2[p]) * cvt<T>(x[p]);
+    if (gx > 0) ax = ax + L.cm[0][gx] * cvt<T>(x[p - 1]);
+    if (gx < nx - 1) ax = ax + L.cp[0][gx] * cvt<T>(x[p + 1]);
+    if (gy > 0) ax = ax + L.cm[1][gy] * cvt<T>(x[p - nx]);
+    if (gy < ny - 1) ax = ax + L.cp[1][gy] * cvt<T>(x[p + nx]);
+    if constexpr (D == 3) {
+        const long long sz = (long long)nx * ny;
+        if (gz > 0) ax = ax + L.cm[2][gz] * cvt<T>(x[p - sz]);
+        if (gz < nz - 1) ax = ax + L.cp[2][gz] * cvt<T>(x[p + sz]);
+    }
+    return xs * ax;
+}
+
+}  // namespace kc
+}  // namespace mg

@@ -20,69 +20,13 @@
 // Level operator (Sec. 3.1, eq. cslvariant): A~ u = sum_axes (cm u_- + c0 u +
 // cp u_+) - sigma k^2 u, zero Dirichlet ghosts; D = sum_axes c0 - sigma k^2.
 
-#include "mg_device.hpp"
+#include "mg_kcommon.hpp"
 
 namespace mg {
 
+using namespace kc;
+
 namespace {
-
-constexpr int NT = 256;      // threads per workgroup (4 wave64)
-constexpr int NXCD = 8;      // MI355X: 8 XCDs, workgroups dealt round-robin
-
-// Map the hardware workgroup id to a logical tile id such that each XCD gets
-// one contiguous range of tiles (neighbouring tiles share halos in its L2).
-__device__ __forceinline__ int xcd_remap(int pid, int num) {
-    const int xcd = pid % NXCD;
-    const int local = pid / NXCD;
-    const int per = num / NXCD;
-    const int extra = num % NXCD;
-    return xcd * per + (xcd < extra ? xcd : extra) + local;
-}
-
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
-}
-
-// Deterministic workgroup sum; the result is valid in thread 0.  sm holds
-// NT/64 doubles.  Must be reached by every thread of the workgroup.
-__device__ __forceinline__ double block_sum(double v, double* sm) {
-    v = wave_sum(v);
-    const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
-    __syncthreads();
-    if (lane == 0) sm[wave] = v;
-    __syncthreads();
-    double t = 0.0;
-    if (threadIdx.x == 0) {
-#pragma unroll
-        for (int w = 0; w < NT / 64; ++w) t += sm[w];
-    }
-    return t;
-}
-
-// Slot of logical workgroup pid: the last slot whose first tile is <= pid
-// (slots are listed in increasing first-tile order).
-template <typename S>
-__device__ __forceinline__ int find_slot(const S* s, int n, int pid) {
-    int lo = 0, hi = n - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (s[mid].tile0 <= pid)
-            lo = mid;
-        else
-            hi = mid - 1;
-    }
-    return lo;
-}
-
-template <int D, typename T>
-__device__ __forceinline__ cx<T> diag_at(const LevelView<T>& L, int gx, int gy, int gz, T k2) {
-    cx<T> d = L.c0[0][gx] + L.c0[1][gy];
-    if constexpr (D == 3) d = d + L.c0[2][gz];
-    return d - k2 * L.sigma;
-}
 
 // ---------------------------------------------------------------------------
 // Fused pre-smooth + residual + full weighting.
@@ -238,22 +182,6 @@ __global__ void __launch_bounds__(NT) k_smooth_restrict(const CycleArgs a) {
 // LDS: coarse correction on [x0/2 - 1, x0/2 + TX/2], corrected iterate u2 on
 // fine [-1, T] relative to the tile.
 // ---------------------------------------------------------------------------
-template <typename T>
-__device__ __forceinline__ void interp_1d(int g, int cs, int& i0, int& i1, T& w0, T& w1) {
-    if (g & 1) {
-        i0 = (g - 1) / 2 - cs;
-        i1 = i0;
-        w0 = T(1);
-        w1 = T(0);
-    } else {
-        const int J = g / 2;
-        i0 = J - 1 - cs;
-        i1 = J - cs;
-        w0 = T(0.5);
-        w1 = T(0.5);
-    }
-}
-
 template <int D, typename T, typename TF, typename TO, bool ZERO, bool ACC, int TX, int TY, int TZ>
 __global__ void __launch_bounds__(NT) k_prolong_smooth(const CycleArgs a) {
     constexpr int TZE = (D == 3) ? TZ : 1;
@@ -431,38 +359,6 @@ __device__ __forceinline__ cx<double> apply_at(const LevelView<double>& L, const
     return ax;
 }
 
-// Slot, workgroup within the slot and its point range [lo, hi).
-struct VecPos {
-    int slot, b, nb, lo, hi;
-};
-
-__device__ __forceinline__ VecPos vec_pos(const VecSlots& st) {
-    VecPos q;
-    const int pid = xcd_remap(blockIdx.x, gridDim.x);
-    int lo = 0, hi = st.n - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (st.s[mid].block0 <= pid)
-            lo = mid;
-        else
-            hi = mid - 1;
-    }
-    q.slot = lo;
-    q.b = pid - st.s[lo].block0;
-    q.nb = (lo + 1 < st.n ? st.s[lo + 1].block0 : st.nblocks) - st.s[lo].block0;
-    q.lo = q.hi = 0;
-    return q;
-}
-
-__device__ __forceinline__ void chunk_range(long long N, int nblocks, int b, int& lo, int& hi) {
-    const long long per = (N + nblocks - 1) / nblocks;
-    long long l = per * b, h = l + per;
-    if (l > N) l = N;
-    if (h > N) h = N;
-    lo = (int)l;
-    hi = (int)h;
-}
-
 // y = f - A x (f null: y = A x); ||y||^2 partials in rpart.
 template <int D>
 __global__ void __launch_bounds__(NT) k_residual(const VecArgs a) {
@@ -625,8 +521,8 @@ __global__ void __launch_bounds__(NT) k_update_norm(const VecArgs a) {
     if (threadIdx.x == 0) a.rpart[(long long)q.slot * a.bstride + q.b] = s;
 }
 
-// t = sum_i coef_i V_i.
-template <int MAXJ>
+// t = sum_i coef_i V_i (ACC: t += ...).
+template <int MAXJ, bool ACC>
 __global__ void __launch_bounds__(NT) k_combine(const VecArgs a) {
     VecPos q = vec_pos(a.st);
     const VecSlot& sl = a.st.s[q.slot];
@@ -643,7 +539,10 @@ __global__ void __launch_bounds__(NT) k_combine(const VecArgs a) {
 #pragma unroll
         for (int i = 0; i < MAXJ; ++i)
             if (i < nv) s = s + coef[i] * V[(long long)i * N + p];
-        t[p] = s;
+        if constexpr (ACC)
+            t[p] = t[p] + s;
+        else
+            t[p] = s;
     }
 }
 
@@ -747,22 +646,6 @@ void tile_counts(int dim, int shape, const int n[3], int ntiles[3]) {
     ntiles[1] = cdivi(n[1], t[1]);
     ntiles[2] = dim == 3 ? cdivi(n[2], t[2]) : 1;
 }
-
-// dispatch over (dim, shape) of a fused kernel template K<D, TX, TY, TZ>
-#define MG_SHAPE_SWITCH(LAUNCH)                                                    \
-    if (dim == 2) {                                                                \
-        switch (shape) {                                                           \
-            case 1: LAUNCH(2, 64, 8, 1); break;                                    \
-            case 2: LAUNCH(2, 128, 8, 1); break;                                   \
-            default: LAUNCH(2, 64, 16, 1); break;                                  \
-        }                                                                          \
-    } else {                                                                       \
-        switch (shape) {                                                           \
-            case 1: LAUNCH(3, 32, 4, 2); break;                                    \
-            case 2: LAUNCH(3, 16, 4, 4); break;                                    \
-            default: LAUNCH(3, 16, 8, 4); break;                                   \
-        }                                                                          \
-    }
 
 template <typename T, typename TF, bool ZERO>
 static hipError_t sr_launch(int dim, int shape, const CycleArgs& a, hipStream_t s) {
@@ -886,10 +769,14 @@ hipError_t launch_update_norm(int jmax, const VecArgs& a, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_combine(int jmax, const VecArgs& a, hipStream_t s) {
+hipError_t launch_combine(int jmax, bool accumulate, const VecArgs& a, hipStream_t s) {
     if (a.st.n <= 0) return hipSuccess;
     dim3 grid(a.st.nblocks);
-#define CB(J) hipLaunchKernelGGL((k_combine<J>), grid, dim3(NT), 0, s, a);
+#define CB(J)                                                                \
+    if (accumulate)                                                          \
+        hipLaunchKernelGGL((k_combine<J, true>), grid, dim3(NT), 0, s, a);   \
+    else                                                                     \
+        hipLaunchKernelGGL((k_combine<J, false>), grid, dim3(NT), 0, s, a);
     MG_JSWITCH(CB)
 #undef CB
     return hipGetLastError();

@@ -1,0 +1,589 @@
+// gfx950 kernels of the GMRES(3) smoother (Sec. 3.2.2): one application on
+// a level replaces the iterate u by the u + z, z in K_3(A, r), r = f - A u,
+// of least residual norm.
+//
+// The paper obtains the minimiser with GMRES (Arnoldi).  Here it is computed
+// from the Gram matrix of the scaled power basis q_i = (A/s)^i r, i = 0..3,
+// which needs one global reduction per application instead of one per
+// Arnoldi step:
+//     minimise || q0 + c1 q1 + c2 q2 + c3 q3 ||   over (c1, c2, c3)
+//     u_new = u - (c1 q0 + c2 q1 + c3 q2) / s,   r_new = q0 + sum_i c_i q_i,
+// the 3 x 3 normal equations solved by Cholesky after symmetric diagonal
+// scaling (an exact breakdown of the Krylov space lowers the degree).  s is
+// a bound of the Laplacian part of A (sum over axes of 4 / h^2) and only
+// keeps the powers in range.  Passes per application:
+//   k_sm_power  x2   q1 = (A/s) q0, q2 = (A/s) q1          (pointwise stencil)
+//   k_sm_gram        q3 on the fly, Gram partials of q0..q3
+//   k_sm_coef        fixed-order reduction, 3 x 3 solve, coefficients on device
+//   pre-smoothing:   k_sm_apply_restrict: u1 and r_new (q3 on an LDS tile),
+//                    full-weighting restriction of r_new to the next level
+//   post-smoothing:  k_sm_prolong_resid (before the passes above): u2 = u1 +
+//                    P e and q0 = f - A u2 through an LDS tile; k_sm_apply_out
+//                    (after them): the smoothed iterate.
+// Every reduction is deterministic (fixed trees, fixed order).
+
+#include "mg_kcommon.hpp"
+
+namespace mg {
+
+using namespace kc;
+
+namespace {
+
+struct SmPos {
+    int slot, b, nb;
+};
+
+__device__ __forceinline__ SmPos sm_pos(const SmSlots& st) {
+    SmPos q;
+    const int pid = xcd_remap(blockIdx.x, gridDim.x);
+    int lo = 0, hi = st.n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (st.s[mid].block0 <= pid)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    q.slot = lo;
+    q.b = pid - st.s[lo].block0;
+    q.nb = (lo + 1 < st.n ? st.s[lo + 1].block0 : st.nblocks) - st.s[lo].block0;
+    return q;
+}
+
+__device__ __forceinline__ void grid_pos(long long p, int nx, int ny, int& gx, int& gy, int& gz) {
+    gx = (int)(p % nx);
+    const long long rr = p / nx;
+    gy = (int)(rr % ny);
+    gz = (int)(rr / ny);
+}
+
+// q0 at p: fscale f (f typed TQ) or the q0 buffer.
+template <typename T, typename TQ>
+__device__ __forceinline__ cx<T> load_q0(const SmSlot& sl, const SmoothBufs& B, long long p) {
+    if (sl.f) return (T)sl.fscale * cvt<T>(static_cast<const cx<TQ>*>(sl.f)[p]);
+    return static_cast<const cx<T>*>(B.q[0])[p];
+}
+
+// q_stage = (A/s) q_{stage-1}.
+template <int D, typename T, typename TQ>
+__global__ void __launch_bounds__(NT) k_sm_power(const SmArgs a, int stage) {
+    const SmPos q = sm_pos(a.st);
+    const SmSlot& sl = a.st.s[q.slot];
+    const LevelView<T> L = *static_cast<const LevelView<T>*>(sl.lv);
+    const SmoothBufs B = *sl.sb;
+    int lo, hi;
+    chunk_range(L.N, q.nb, q.b, lo, hi);
+    cx<T>* y = static_cast<cx<T>*>(B.q[stage]);
+    const int nx = L.n[0], ny = L.n[1];
+    const bool from_f = stage == 1 && sl.f;
+    for (int p = lo + (int)threadIdx.x; p < hi; p += NT) {
+        int gx, gy, gz;
+        grid_pos(p, nx, ny, gx, gy, gz);
+        cx<T> ax;
+        if (from_f)
+            ax = stencil_at<D, T, TQ>(L, static_cast<const cx<TQ>*>(sl.f), (T)sl.fscale, p, gx, gy, gz);
+        else
+            ax = stencil_at<D, T, T>(L, static_cast<const cx<T>*>(B.q[stage - 1]), T(1), p, gx, gy, gz);
+        y[p] = L.sinv * ax;
+    }
+}
+
+// Gram partials of q0..q3, accumulated in FP64.
+template <int D, typename T, typename TQ>
+__global__ void __launch_bounds__(NT) k_sm_gram(const SmArgs a) {
+    __shared__ cx<double> sm[(NT / 64) * NUM_GRAM];
+    const SmPos q = sm_pos(a.st);
+    const SmSlot& sl = a.st.s[q.slot];
+    const LevelView<T> L = *static_cast<const LevelView<T>*>(sl.lv);
+    const SmoothBufs B = *sl.sb;
+    int lo, hi;
+    chunk_range(L.N, q.nb, q.b, lo, hi);
+    const cx<T>* q1p = static_cast<const cx<T>*>(B.q[1]);
+    const cx<T>* q2p = static_cast<const cx<T>*>(B.q[2]);
+    const int nx = L.n[0], ny = L.n[1];
+    cx<double> g[NUM_GRAM];
+#pragma unroll
+    for (int v = 0; v < NUM_GRAM; ++v) g[v] = mk(0.0, 0.0);
+    for (int p = lo + (int)threadIdx.x; p < hi; p += NT) {
+        int gx, gy, gz;
+        grid_pos(p, nx, ny, gx, gy, gz);
+        const cx<double> v0 = cvt<double>(load_q0<T, TQ>(sl, B, p));
+        const cx<double> v1 = cvt<double>(q1p[p]);
+        const cx<double> v2 = cvt<double>(q2p[p]);
+        const cx<double> v3 = cvt<double>(L.sinv * stencil_at<D, T, T>(L, q2p, T(1), p, gx, gy, gz));
+        g[0].r += abs2(v0);
+        g[1].r += abs2(v1);
+        g[2].r += abs2(v2);
+        g[3].r += abs2(v3);
+        g[4] = g[4] + cmulc(v0, v1);
+        g[5] = g[5] + cmulc(v0, v2);
+        g[6] = g[6] + cmulc(v0, v3);
+        g[7] = g[7] + cmulc(v1, v2);
+        g[8] = g[8] + cmulc(v1, v3);
+        g[9] = g[9] + cmulc(v2, v3);
+    }
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int v = 0; v < NUM_GRAM; ++v) {
+        const double r = wave_sum(g[v].r);
+        const double i = wave_sum(g[v].i);
+        if (lane == 0) sm[wave * NUM_GRAM + v] = mk(r, i);
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < NUM_GRAM) {
+        cx<double> s = mk(0.0, 0.0);
+#pragma unroll
+        for (int w = 0; w < NT / 64; ++w) s = s + sm[w * NUM_GRAM + threadIdx.x];
+        a.part[((long long)q.slot * a.pstride + threadIdx.x) * a.bstride + q.b] = s;
+    }
+}
+
+__device__ __forceinline__ cx<double> conjd(cx<double> z) { return mk(z.r, -z.i); }
+
+// Coefficients of the least-squares residual polynomial from the Gram matrix.
+// brk: relative pivot below which the Krylov space counts as exhausted.
+__device__ void solve_coef(const cx<double>* G, double brk, cx<double>* out) {
+    const double g00 = G[0].r;
+    out[0] = out[1] = out[2] = mk(0.0, 0.0);
+    out[3] = mk(g00, 0.0);
+    if (!(g00 > 0.0) || !(G[1].r > 0.0)) return;
+    const double d0 = sqrt(g00), d1 = sqrt(G[1].r), d2 = sqrt(G[2].r), d3 = sqrt(G[3].r);
+    // right-hand side b_i = -G_i0 / (d_i d0), G_i0 = conj(G_0i)
+    const cx<double> b1 = (-1.0 / (d1 * d0)) * conjd(G[4]);
+    int deg = 1;
+    cx<double> L21 = mk(0.0, 0.0), L31 = mk(0.0, 0.0), L32 = mk(0.0, 0.0);
+    double L22 = 0.0, L33 = 0.0;
+    cx<double> b2 = mk(0.0, 0.0), b3 = mk(0.0, 0.0);
+    if (d2 > 0.0) {
+        L21 = (1.0 / (d1 * d2)) * conjd(G[7]);
+        const double p2 = 1.0 - abs2(L21);
+        if (p2 > brk) {
+            deg = 2;
+            L22 = sqrt(p2);
+            b2 = (-1.0 / (d2 * d0)) * conjd(G[5]);
+            if (d3 > 0.0) {
+                L31 = (1.0 / (d1 * d3)) * conjd(G[8]);
+                const cx<double> S32 = (1.0 / (d2 * d3)) * conjd(G[9]);
+                L32 = (1.0 / L22) * (S32 - L31 * conjd(L21));
+                const double p3 = 1.0 - abs2(L31) - abs2(L32);
+                if (p3 > brk) {
+                    deg = 3;
+                    L33 = sqrt(p3);
+                    b3 = (-1.0 / (d3 * d0)) * conjd(G[6]);
+                }
+            }
+        }
+    }
+    // L y = b, L^H x = y
+    cx<double> x1, x2 = mk(0.0, 0.0), x3 = mk(0.0, 0.0);
+    const cx<double> y1 = b1;
+    if (deg == 1) {
+        x1 = y1;
+    } else {
+        const cx<double> y2 = (1.0 / L22) * (b2 - L21 * y1);
+        if (deg == 3) {
+            const cx<double> y3 = (1.0 / L33) * (b3 - L31 * y1 - L32 * y2);
+            x3 = (1.0 / L33) * y3;
+        }
+        x2 = (1.0 / L22) * (y2 - conjd(L32) * x3);
+        x1 = y1 - conjd(L21) * x2 - conjd(L31) * x3;
+    }
+    out[0] = (d0 / d1) * x1;
+    out[1] = deg >= 2 ? (d0 / d2) * x2 : mk(0.0, 0.0);
+    out[2] = deg == 3 ? (d0 / d3) * x3 : mk(0.0, 0.0);
+}
+
+// One workgroup per slot: fixed-order sums of the Gram partials, then solve.
+__global__ void __launch_bounds__(NT) k_sm_coef(const SmCoefArgs a, double brk) {
+    __shared__ cx<double> sm[(NT / 64) * NUM_GRAM];
+    __shared__ cx<double> G[NUM_GRAM];
+    const int slot = blockIdx.x;
+    const int cnt = a.cnt[slot];
+    cx<double> g[NUM_GRAM];
+#pragma unroll
+    for (int v = 0; v < NUM_GRAM; ++v) g[v] = mk(0.0, 0.0);
+    const cx<double>* base = a.part + (long long)slot * a.pstride * a.bstride;
+    for (int b = threadIdx.x; b < cnt; b += NT) {
+#pragma unroll
+        for (int v = 0; v < NUM_GRAM; ++v) g[v] = g[v] + base[(long long)v * a.bstride + b];
+    }
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int v = 0; v < NUM_GRAM; ++v) {
+        const double r = wave_sum(g[v].r);
+        const double i = wave_sum(g[v].i);
+        if (lane == 0) sm[wave * NUM_GRAM + v] = mk(r, i);
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < NUM_GRAM) {
+        cx<double> s = mk(0.0, 0.0);
+#pragma unroll
+        for (int w = 0; w < NT / 64; ++w) s = s + sm[w * NUM_GRAM + threadIdx.x];
+        G[threadIdx.x] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) solve_coef(G, brk, a.coef[slot]);
+}
+
+template <typename T>
+__device__ __forceinline__ void load_coef(const cx<double>* c, cx<T>& c1, cx<T>& c2, cx<T>& c3) {
+    c1 = cvt<T>(c[0]);
+    c2 = cvt<T>(c[1]);
+    c3 = cvt<T>(c[2]);
+}
+
+// Tile position of a fused kernel's workgroup.
+template <int D, int TX, int TY, int TZ>
+__device__ __forceinline__ void tile_origin(int tile, int nx, int ny, int& x0, int& y0, int& z0) {
+    const int ntx = (nx + TX - 1) / TX, nty = (ny + TY - 1) / TY;
+    const int tx = tile % ntx;
+    const int rest = tile / ntx;
+    x0 = tx * TX;
+    y0 = (rest % nty) * TY;
+    z0 = (D == 3) ? (rest / nty) * TZ : 0;
+}
+
+// ---------------------------------------------------------------------------
+// Pre-smoothing end: u1 = u - (c1 q0 + c2 q1 + c3 q2)/s on the tile, r1 =
+// q0 + c1 q1 + c2 q2 + c3 q3 on [0, T] (q3 from q2 staged on [-1, T+1]), and
+// the full-weighting restriction of r1 to the coarse points owned by the tile.
+// Slot fields: f (q0 = fscale f; null: q0 buffer), u (incoming iterate when
+// NZ), c (coarse right-hand side out), sb.
+// ---------------------------------------------------------------------------
+template <int D, typename T, typename TQ, bool NZ, int TX, int TY, int TZ>
+__global__ void __launch_bounds__(NT) k_sm_apply_restrict(const CycleArgs a) {
+    constexpr int TZE = (D == 3) ? TZ : 1;
+    constexpr int QX = TX + 3, QY = TY + 3, QZ = (D == 3) ? TZ + 3 : 1;
+    constexpr int RX = TX + 1, RY = TY + 1, RZ = (D == 3) ? TZ + 1 : 1;
+    constexpr int NQ = QX * QY * QZ, NR = RX * RY * RZ;
+    constexpr int CX = TX / 2, CY = TY / 2, CZ = (D == 3) ? TZ / 2 : 1;
+    static_assert(TX % 2 == 0 && TY % 2 == 0 && (D == 2 || TZ % 2 == 0), "even tiles");
+
+    __shared__ cx<T> sq[NQ];
+    __shared__ cx<T> sr[NR];
+
+    const int pid = xcd_remap(blockIdx.x, gridDim.x);
+    const int slot = find_slot(a.st.s, a.st.n, pid);
+    const CycleSlot& sl = a.st.s[slot];
+    const LevelView<T>* Lp = static_cast<const LevelView<T>*>(sl.lv);
+    const LevelView<T> L = *Lp;
+    const SmoothBufs B = *sl.sb;
+    const int nx = L.n[0], ny = L.n[1], nz = L.n[2];
+    int x0, y0, z0;
+    tile_origin<D, TX, TY, TZE>(pid - sl.tile0, nx, ny, x0, y0, z0);
+    const cx<T>* q1p = static_cast<const cx<T>*>(B.q[1]);
+    const cx<T>* q2p = static_cast<const cx<T>*>(B.q[2]);
+    const cx<T>* q0p = static_cast<const cx<T>*>(B.q[0]);
+    const cx<TQ>* f = static_cast<const cx<TQ>*>(sl.f);
+    const T fs = (T)sl.fscale;
+    cx<T> c1, c2, c3;
+    load_coef<T>(B.coef, c1, c2, c3);
+
+    for (int idx = threadIdx.x; idx < NQ; idx += NT) {
+        const int lx = idx % QX;
+        const int rr = idx / QX;
+        const int ly = rr % QY;
+        const int lz = rr / QY;
+        const int gx = x0 - 1 + lx, gy = y0 - 1 + ly;
+        const int gz = (D == 3) ? z0 - 1 + lz : 0;
+        cx<T> v = mk<T>(0, 0);
+        if (gx >= 0 && gx < nx && gy >= 0 && gy < ny && (D == 2 || (gz >= 0 && gz < nz)))
+            v = q2p[((long long)gz * ny + gy) * nx + gx];
+        sq[idx] = v;
+    }
+    __syncthreads();
+
+    cx<T>* u1p = static_cast<cx<T>*>(B.u1);
+    const cx<T>* up = static_cast<const cx<T>*>(sl.u);
+    for (int idx = threadIdx.x; idx < NR; idx += NT) {
+        const int lx = idx % RX;
+        const int rr = idx / RX;
+        const int ly = rr % RY;
+        const int lz = rr / RY;
+        const int gx = x0 + lx, gy = y0 + ly;
+        const int gz = (D == 3) ? z0 + lz : 0;
+        cx<T> r = mk<T>(0, 0);
+        if (gx < nx && gy < ny && (D == 2 || gz < nz)) {
+            const long long g = ((long long)gz * ny + gy) * nx + gx;
+            const cx<T> q0 = f ? fs * cvt<T>(f[g]) : q0p[g];
+            const cx<T> q1 = q1p[g];
+            const int c = ((D == 3 ? lz + 1 : 0) * QY + (ly + 1)) * QX + (lx + 1);
+            const cx<T> q2 = sq[c];
+            cx<T> aq = diag_at<D>(L, gx, gy, gz, L.k2[g]) * q2 + L.cm[0][gx] * sq[c - 1] +
+                       L.cp[0][gx] * sq[c + 1] + L.cm[1][gy] * sq[c - QX] + L.cp[1][gy] * sq[c + QX];
+            if constexpr (D == 3) aq = aq + L.cm[2][gz] * sq[c - QX * QY] + L.cp[2][gz] * sq[c + QX * QY];
+            const cx<T> q3 = L.sinv * aq;
+            r = q0 + c1 * q1 + c2 * q2 + c3 * q3;
+            const bool own = lx < TX && ly < TY && (D == 2 || lz < TZ);
+            if (own) {
+                cx<T> u = L.sinv * (c1 * q0 + c2 * q1 + c3 * q2);
+                if constexpr (NZ) u = up[g] - u;
+                else u = mk<T>(0, 0) - u;
+                u1p[g] = u;
+            }
+        }
+        sr[idx] = r;
+    }
+    __syncthreads();
+
+    const int ncx = Lp[1].n[0], ncy = Lp[1].n[1], ncz = Lp[1].n[2];
+    cx<T>* fc = static_cast<cx<T>*>(sl.c);
+    for (int idx = threadIdx.x; idx < CX * CY * CZ; idx += NT) {
+        const int cxl = idx % CX;
+        const int rr = idx / CX;
+        const int cyl = rr % CY;
+        const int czl = rr / CY;
+        const int Cx = x0 / 2 + cxl, Cy = y0 / 2 + cyl;
+        const int Cz = (D == 3) ? z0 / 2 + czl : 0;
+        if (Cx < ncx && Cy < ncy && (D == 2 || Cz < ncz)) {
+            cx<T> acc = mk<T>(0, 0);
+#pragma unroll
+            for (int oz = (D == 3 ? -1 : 0); oz <= (D == 3 ? 1 : 0); ++oz) {
+                const int zz = (D == 3) ? 2 * czl + 1 + oz : 0;
+                const T wz = (D == 3) ? (oz == 0 ? T(0.5) : T(0.25)) : T(1);
+#pragma unroll
+                for (int oy = -1; oy <= 1; ++oy) {
+                    const T wy = wz * (oy == 0 ? T(0.5) : T(0.25));
+                    const int row = (zz * RY + 2 * cyl + 1 + oy) * RX + 2 * cxl + 1;
+#pragma unroll
+                    for (int ox = -1; ox <= 1; ++ox) {
+                        const T w = wy * (ox == 0 ? T(0.5) : T(0.25));
+                        acc = acc + w * sr[row + ox];
+                    }
+                }
+            }
+            fc[((long long)Cz * ncy + Cy) * ncx + Cx] = acc;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Post-smoothing start: u2 = u1 + P e through an LDS tile (e on the coarse
+// points around the tile, u2 on [-1, T]); writes u2 and q0 = fscale f - A u2
+// on the tile.  Slot fields: f, fscale, c (coarse correction e), sb.
+// ---------------------------------------------------------------------------
+template <int D, typename T, typename TF, int TX, int TY, int TZ>
+__global__ void __launch_bounds__(NT) k_sm_prolong_resid(const CycleArgs a) {
+    constexpr int TZE = (D == 3) ? TZ : 1;
+    constexpr int EX = TX / 2 + 2, EY = TY / 2 + 2, EZ = (D == 3) ? TZ / 2 + 2 : 1;
+    constexpr int WX = TX + 2, WY = TY + 2, WZ = (D == 3) ? TZ + 2 : 1;
+    constexpr int NE = EX * EY * EZ, NW = WX * WY * WZ;
+
+    __shared__ cx<T> se[NE];
+    __shared__ cx<T> s2[NW];
+
+    const int pid = xcd_remap(blockIdx.x, gridDim.x);
+    const int slot = find_slot(a.st.s, a.st.n, pid);
+    const CycleSlot& sl = a.st.s[slot];
+    const LevelView<T>* Lp = static_cast<const LevelView<T>*>(sl.lv);
+    const LevelView<T> L = *Lp;
+    const SmoothBufs B = *sl.sb;
+    const int nx = L.n[0], ny = L.n[1], nz = L.n[2];
+    const int ncx = Lp[1].n[0], ncy = Lp[1].n[1], ncz = Lp[1].n[2];
+    int x0, y0, z0;
+    tile_origin<D, TX, TY, TZE>(pid - sl.tile0, nx, ny, x0, y0, z0);
+    const cx<TF>* f = static_cast<const cx<TF>*>(sl.f);
+    const T fs = (T)sl.fscale;
+    const cx<T>* ec = static_cast<const cx<T>*>(sl.c);
+    const cx<T>* u1p = static_cast<const cx<T>*>(B.u1);
+    const int cxs = x0 / 2 - 1, cys = y0 / 2 - 1, czs = (D == 3) ? z0 / 2 - 1 : 0;
+
+    for (int idx = threadIdx.x; idx < NE; idx += NT) {
+        const int lx = idx % EX;
+        const int rr = idx / EX;
+        const int ly = rr % EY;
+        const int lz = rr / EY;
+        const int Cx = cxs + lx, Cy = cys + ly, Cz = czs + lz;
+        cx<T> v = mk<T>(0, 0);
+        if (Cx >= 0 && Cx < ncx && Cy >= 0 && Cy < ncy && (D == 2 || (Cz >= 0 && Cz < ncz)))
+            v = ec[((long long)Cz * ncy + Cy) * ncx + Cx];
+        se[idx] = v;
+    }
+    __syncthreads();
+
+    for (int idx = threadIdx.x; idx < NW; idx += NT) {
+        const int lx = idx % WX;
+        const int rr = idx / WX;
+        const int ly = rr % WY;
+        const int lz = rr / WY;
+        const int gx = x0 - 1 + lx, gy = y0 - 1 + ly;
+        const int gz = (D == 3) ? z0 - 1 + lz : 0;
+        cx<T> u2 = mk<T>(0, 0);
+        if (gx >= 0 && gx < nx && gy >= 0 && gy < ny && (D == 2 || (gz >= 0 && gz < nz))) {
+            const long long g = ((long long)gz * ny + gy) * nx + gx;
+            int ix0, ix1, iy0, iy1;
+            T wx0, wx1, wy0, wy1;
+            interp_1d<T>(gx, cxs, ix0, ix1, wx0, wx1);
+            interp_1d<T>(gy, cys, iy0, iy1, wy0, wy1);
+            cx<T> pe;
+            if constexpr (D == 2) {
+                pe = (wy0 * wx0) * se[iy0 * EX + ix0] + (wy0 * wx1) * se[iy0 * EX + ix1] +
+                     (wy1 * wx0) * se[iy1 * EX + ix0] + (wy1 * wx1) * se[iy1 * EX + ix1];
+            } else {
+                int iz0, iz1;
+                T wz0, wz1;
+                interp_1d<T>(gz, czs, iz0, iz1, wz0, wz1);
+                const int p00 = (iz0 * EY + iy0) * EX, p01 = (iz0 * EY + iy1) * EX;
+                const int p10 = (iz1 * EY + iy0) * EX, p11 = (iz1 * EY + iy1) * EX;
+                pe = (wz0 * wy0 * wx0) * se[p00 + ix0] + (wz0 * wy0 * wx1) * se[p00 + ix1] +
+                     (wz0 * wy1 * wx0) * se[p01 + ix0] + (wz0 * wy1 * wx1) * se[p01 + ix1] +
+                     (wz1 * wy0 * wx0) * se[p10 + ix0] + (wz1 * wy0 * wx1) * se[p10 + ix1] +
+                     (wz1 * wy1 * wx0) * se[p11 + ix0] + (wz1 * wy1 * wx1) * se[p11 + ix1];
+            }
+            u2 = u1p[g] + pe;
+        }
+        s2[idx] = u2;
+    }
+    __syncthreads();
+
+    cx<T>* u2p = static_cast<cx<T>*>(B.u2);
+    cx<T>* q0p = static_cast<cx<T>*>(B.q[0]);
+    for (int idx = threadIdx.x; idx < TX * TY * TZE; idx += NT) {
+        const int lx = idx % TX;
+        const int rr = idx / TX;
+        const int ly = rr % TY;
+        const int lz = rr / TY;
+        const int gx = x0 + lx, gy = y0 + ly;
+        const int gz = (D == 3) ? z0 + lz : 0;
+        if (gx < nx && gy < ny && (D == 2 || gz < nz)) {
+            const long long g = ((long long)gz * ny + gy) * nx + gx;
+            const int c = ((D == 3 ? lz + 1 : 0) * WY + (ly + 1)) * WX + (lx + 1);
+            const cx<T> u2c = s2[c];
+            cx<T> au = diag_at<D>(L, gx, gy, gz, L.k2[g]) * u2c + L.cm[0][gx] * s2[c - 1] +
+                       L.cp[0][gx] * s2[c + 1] + L.cm[1][gy] * s2[c - WX] + L.cp[1][gy] * s2[c + WX];
+            if constexpr (D == 3) au = au + L.cm[2][gz] * s2[c - WX * WY] + L.cp[2][gz] * s2[c + WX * WY];
+            u2p[g] = u2c;
+            q0p[g] = fs * cvt<T>(f[g]) - au;
+        }
+    }
+}
+
+// Post-smoothing end: out = u2 - (c1 q0 + c2 q1 + c3 q2)/s (or out +=).
+template <typename T, typename TO, bool ACC>
+__global__ void __launch_bounds__(NT) k_sm_apply_out(const SmArgs a) {
+    const SmPos q = sm_pos(a.st);
+    const SmSlot& sl = a.st.s[q.slot];
+    const LevelView<T> L = *static_cast<const LevelView<T>*>(sl.lv);
+    const SmoothBufs B = *sl.sb;
+    int lo, hi;
+    chunk_range(L.N, q.nb, q.b, lo, hi);
+    cx<T> c1, c2, c3;
+    load_coef<T>(B.coef + 4, c1, c2, c3);
+    const cx<T>* q0p = static_cast<const cx<T>*>(B.q[0]);
+    const cx<T>* q1p = static_cast<const cx<T>*>(B.q[1]);
+    const cx<T>* q2p = static_cast<const cx<T>*>(B.q[2]);
+    const cx<T>* u2p = static_cast<const cx<T>*>(B.u2);
+    cx<TO>* out = static_cast<cx<TO>*>(sl.out);
+    for (int p = lo + (int)threadIdx.x; p < hi; p += NT) {
+        const cx<T> v = u2p[p] - L.sinv * (c1 * q0p[p] + c2 * q1p[p] + c3 * q2p[p]);
+        if constexpr (ACC)
+            out[p] = out[p] + cvt<TO>(v);
+        else
+            out[p] = cvt<TO>(v);
+    }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+hipError_t launch_sm_power(int dim, bool f32, bool level0, int stage, const SmArgs& a, hipStream_t s) {
+    if (a.st.n <= 0) return hipSuccess;
+    if (stage != 1 && stage != 2) return hipErrorInvalidValue;
+    dim3 grid(a.st.nblocks);
+#define PW(D, T, TQ) hipLaunchKernelGGL((k_sm_power<D, T, TQ>), grid, dim3(NT), 0, s, a, stage)
+    if (dim == 2) {
+        if (!f32) PW(2, double, double);
+        else if (level0) PW(2, float, double);
+        else PW(2, float, float);
+    } else {
+        if (!f32) PW(3, double, double);
+        else if (level0) PW(3, float, double);
+        else PW(3, float, float);
+    }
+#undef PW
+    return hipGetLastError();
+}
+
+hipError_t launch_sm_gram(int dim, bool f32, bool level0, const SmArgs& a, hipStream_t s) {
+    if (a.st.n <= 0) return hipSuccess;
+    dim3 grid(a.st.nblocks);
+#define GR(D, T, TQ) hipLaunchKernelGGL((k_sm_gram<D, T, TQ>), grid, dim3(NT), 0, s, a)
+    if (dim == 2) {
+        if (!f32) GR(2, double, double);
+        else if (level0) GR(2, float, double);
+        else GR(2, float, float);
+    } else {
+        if (!f32) GR(3, double, double);
+        else if (level0) GR(3, float, double);
+        else GR(3, float, float);
+    }
+#undef GR
+    return hipGetLastError();
+}
+
+hipError_t launch_sm_coef(bool f32, const SmCoefArgs& a, int nslots, hipStream_t s) {
+    if (nslots <= 0) return hipSuccess;
+    // an exhausted Krylov space shows as a relative Cholesky pivot at the
+    // rounding level of the vectors' precision
+    const double brk = f32 ? 1e-5 : 1e-13;
+    hipLaunchKernelGGL(k_sm_coef, dim3(nslots), dim3(NT), 0, s, a, brk);
+    return hipGetLastError();
+}
+
+template <typename T, typename TQ, bool NZ>
+static hipError_t ar_launch(int dim, int shape, const CycleArgs& a, hipStream_t s) {
+    dim3 grid(a.st.ntiles);
+#define AR(D, X, Y, Z) hipLaunchKernelGGL((k_sm_apply_restrict<D, T, TQ, NZ, X, Y, Z>), grid, dim3(NT), 0, s, a);
+    MG_SHAPE_SWITCH(AR)
+#undef AR
+    return hipGetLastError();
+}
+
+hipError_t launch_sm_apply_restrict(int dim, bool f32, bool level0, bool nonzero, int shape, const CycleArgs& a,
+                                    hipStream_t s) {
+    if (a.st.n <= 0) return hipSuccess;
+    if (!f32)
+        return nonzero ? ar_launch<double, double, true>(dim, shape, a, s)
+                       : ar_launch<double, double, false>(dim, shape, a, s);
+    if (nonzero) return hipErrorInvalidValue;   // the complex64 cycle always starts from zero
+    return level0 ? ar_launch<float, double, false>(dim, shape, a, s) : ar_launch<float, float, false>(dim, shape, a, s);
+}
+
+template <typename T, typename TF>
+static hipError_t pr_launch(int dim, int shape, const CycleArgs& a, hipStream_t s) {
+    dim3 grid(a.st.ntiles);
+#define PR(D, X, Y, Z) hipLaunchKernelGGL((k_sm_prolong_resid<D, T, TF, X, Y, Z>), grid, dim3(NT), 0, s, a);
+    MG_SHAPE_SWITCH(PR)
+#undef PR
+    return hipGetLastError();
+}
+
+hipError_t launch_sm_prolong_resid(int dim, bool f32, bool level0, int shape, const CycleArgs& a, hipStream_t s) {
+    if (a.st.n <= 0) return hipSuccess;
+    if (!f32) return pr_launch<double, double>(dim, shape, a, s);
+    return level0 ? pr_launch<float, double>(dim, shape, a, s) : pr_launch<float, float>(dim, shape, a, s);
+}
+
+hipError_t launch_sm_apply_out(bool f32, bool level0, bool accumulate, const SmArgs& a, hipStream_t s) {
+    if (a.st.n <= 0) return hipSuccess;
+    dim3 grid(a.st.nblocks);
+#define AO(T, TO, ACC) hipLaunchKernelGGL((k_sm_apply_out<T, TO, ACC>), grid, dim3(NT), 0, s, a)
+    if (!f32) {
+        if (accumulate) AO(double, double, true);
+        else AO(double, double, false);
+    } else if (level0) {
+        if (accumulate) AO(float, double, true);
+        else AO(float, double, false);
+    } else {
+        AO(float, float, false);
+    }
+#undef AO
+    return hipGetLastError();
+}
+
+}  // namespace mg

@@ -21,10 +21,13 @@ LIB_PATH = os.path.join(_PKG, "libmg.so")
 MG_OK, MG_NOT_CONVERGED = 0, 1
 MG_E_INVAL, MG_E_NOMEM, MG_E_DEVICE, MG_E_DIVERGED, MG_E_STATE = -1, -2, -3, -4, -5
 PREC_C128, PREC_MIXED = 0, 1
-MODE_STANDALONE, MODE_GMRES = 0, 1
+MODE_STANDALONE, MODE_GMRES, MODE_FGMRES = 0, 1, 2
+SMOOTH_JACOBI, SMOOTH_GMRES3 = 0, 1
+MODES = {"standalone": MODE_STANDALONE, "gmres": MODE_GMRES, "fgmres": MODE_FGMRES}
 KERNEL_CLASSES = [
     "smooth_restrict_fine", "prolong_smooth_fine", "coarse_levels", "coarsest_solve",
     "residual", "matvec_dot", "update_dot", "update_norm", "reduce", "combine", "other",
+    "smooth_power_fine", "smooth_gram_fine",
 ]
 
 # every symbol include/mg.h declares
@@ -52,6 +55,7 @@ class Params(ctypes.Structure):
         ("omega", ctypes.c_double * 2),
         ("precision", ctypes.c_int),
         ("nrhs", ctypes.c_int),
+        ("smoother", ctypes.c_int),
     ]
 
 
@@ -123,12 +127,14 @@ class Solver:
     per axis); k2: float64 device tensor shaped like the grid (slowest axis
     first); ecs: cells of the absorbing layer, an int for all sides or
     (lo, hi) tuples per axis; sigma: per-level complex shifts (None: default
-    schedule with theta_max); precision: "c128" or "mixed".
+    schedule with theta_max); precision: "c128" or "mixed"; smoother:
+    "jacobi" (omega-Jacobi) or "gmres3" (one GMRES(3) cycle per smoothing
+    step; GMRES mode then runs flexible GMRES).
     """
 
     def __init__(self, n, h, k2, *, ecs=0, ecs_angle=math.pi / 4, sigma=None,
                  theta_max=math.pi / 6, omega=2.0 / 3.0, precision="c128", nrhs=1,
-                 nlevels=0, stream=None):
+                 nlevels=0, stream=None, smoother="jacobi"):
         import torch
         self.torch = torch
         self.n = tuple(int(v) for v in n)
@@ -153,6 +159,8 @@ class Solver:
         p.precision = {"c128": PREC_C128, "mixed": PREC_MIXED}[precision]
         p.nrhs = int(nrhs)
         p.nlevels = int(nlevels)
+        p.smoother = {"jacobi": SMOOTH_JACOBI, "gmres3": SMOOTH_GMRES3}[smoother]
+        self.smoother = smoother
         self._sigma_buf = None
         if sigma is not None:
             s = np.asarray(sigma, dtype=np.complex128)
@@ -234,7 +242,7 @@ class Solver:
         self._check_vec(f)
         its = (ctypes.c_int * self.nrhs)()
         hist = np.empty(self.nrhs * (maxit + 1), dtype=np.float64)
-        mode_id = {"standalone": MODE_STANDALONE, "gmres": MODE_GMRES}[mode]
+        mode_id = MODES[mode]
         st = fn(self.ctx, _ptr(u), _ptr(f), mode_id, float(rtol), int(maxit), int(restart), its,
                 hist.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
         if st not in (MG_OK, MG_NOT_CONVERGED, MG_E_DIVERGED):
@@ -337,7 +345,7 @@ class Batch:
         tot = sum(s.nrhs for s in self.solvers)
         its = (ctypes.c_int * tot)()
         hist = np.empty(tot * (maxit + 1), dtype=np.float64)
-        mode_id = {"standalone": MODE_STANDALONE, "gmres": MODE_GMRES}[mode]
+        mode_id = MODES[mode]
         st = lib().mg_batch_solve(self.handle, up, fp, mode_id, float(rtol), int(maxit), int(restart), its,
                                   hist.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
         if st not in _STATUS:
