@@ -225,6 +225,13 @@ hipError_t launch_sm_apply_restrict(int dim, bool f32, bool level0, bool nonzero
                                     hipStream_t s);
 hipError_t launch_sm_prolong_resid(int dim, bool f32, bool level0, int shape, const CycleArgs& a, hipStream_t s);
 hipError_t launch_sm_apply_out(bool f32, bool level0, bool accumulate, const SmArgs& a, hipStream_t s);
+// Fused 2D passes (mg_smooth2d.hip): Gram partials per tile at
+// part[(slot * pstride + v) * bstride + tile].
+hipError_t launch_sm2_gram(bool f32, bool level0, bool post, int shape, const CycleArgs& a, cx<double>* part,
+                           int pstride, int bstride, hipStream_t s);
+hipError_t launch_sm2_apply_restrict(bool f32, bool level0, bool nonzero, int shape, const CycleArgs& a,
+                                     hipStream_t s);
+hipError_t launch_sm2_apply_out(bool f32, bool level0, bool accumulate, int shape, const CycleArgs& a, hipStream_t s);
 
 hipError_t launch_inject_k2(int dim, const double* fine, const int nf[3], double* coarse, const int nc[3],
                             hipStream_t s);

@@ -550,6 +550,115 @@ mg_status build_sm(Run& R, int dir, int d, const std::vector<Item>& it, const st
     return MG_OK;
 }
 
+// 2D: the fused tile passes of mg_smooth2d.hip.  Slots carry f (q0 source;
+// null: the q0 buffer), u (incoming iterate, NZ), c (coarse rhs out for the
+// pre-smoothing step, coarse correction in for the post-smoothing step), out.
+mg_status coef_from_tiles(Run& R, int d, int phase, const std::vector<Item>& it, const std::vector<int>& sub,
+                          const CycleArgs& a) {
+    mg::SmCoefArgs ca{};
+    ca.part = R.w->part;
+    ca.pstride = HSTRIDE;
+    ca.bstride = R.w->bstride;
+    for (int q = 0; q < a.st.n; ++q) {
+        const Item& I = it[sub[q]];
+        const int next = q + 1 < a.st.n ? a.st.s[q + 1].tile0 : a.st.ntiles;
+        ca.cnt[q] = next - a.st.s[q].tile0;
+        ca.coef[q] = gcoef_of(I.c, d, I.rhs, phase);
+    }
+    const int pi = prof_begin(R, d == 0 ? MG_K_REDUCE : MG_K_COARSE_LEVELS);
+    CK(mg::launch_sm_coef(R.mixed, ca, a.st.n, R.s));
+    prof_end(R, pi);
+    return MG_OK;
+}
+
+mg_status pre_fused_2d(Run& R, int dir, const std::vector<Item>& it, const std::vector<L0>* l0, int d, bool nz,
+                       const std::vector<int>& sub) {
+    const int shape = launch_shape(it, sub, d);
+    const double ct = R.mixed ? 8.0 : 16.0, sk = R.mixed ? 4.0 : 8.0;
+    CycleArgs a{};
+    a.st.n = (int)sub.size();
+    int tiles = 0;
+    double bg = 0.0, ba = 0.0;
+    for (int q = 0; q < a.st.n; ++q) {
+        const Item& I = it[sub[q]];
+        mg_ctx* c = I.c;
+        CycleSlot& s = a.st.s[q];
+        s.lv = view_ptr(c, dir, d);
+        if (nz) {
+            s.f = nullptr;
+            s.fscale = 1.0;
+            s.u = (*l0)[sub[q]].u;
+        } else if (d == 0) {
+            s.f = (*l0)[sub[q]].f;
+            s.fscale = (*l0)[sub[q]].fs;
+        } else {
+            s.f = lvec(c, c->lv[d].F, d, I.rhs);
+            s.fscale = 1.0;
+        }
+        s.c = lvec(c, c->lv[d + 1].F, d + 1, I.rhs);
+        s.sb = sbuf(c, d, I.rhs);
+        s.tile0 = tiles;
+        int nt[3];
+        mg::tile_counts(2, shape, c->lv[d].n, nt);
+        tiles += nt[0] * nt[1];
+        const double q0b = (d == 0 && !nz) ? 16.0 : ct;
+        bg += c->lv[d].N * (q0b + sk);
+        ba += c->lv[d].N * (q0b + sk + ct + (nz ? 16.0 : 0.0)) + c->lv[d + 1].N * ct;
+    }
+    a.st.ntiles = tiles;
+    int pi = prof_begin(R, d == 0 ? MG_K_SMOOTH_GRAM_FINE : MG_K_COARSE_LEVELS, bg);
+    CK(mg::launch_sm2_gram(R.mixed, d == 0, false, shape, a, R.w->part, HSTRIDE, R.w->bstride, R.s));
+    prof_end(R, pi);
+    CKS(coef_from_tiles(R, d, 0, it, sub, a));
+    pi = prof_begin(R, d == 0 ? MG_K_SMOOTH_RESTRICT_FINE : MG_K_COARSE_LEVELS, ba);
+    CK(mg::launch_sm2_apply_restrict(R.mixed, d == 0, nz, shape, a, R.s));
+    prof_end(R, pi);
+    return MG_OK;
+}
+
+mg_status post_fused_2d(Run& R, int dir, const std::vector<Item>& it, const std::vector<L0>* l0, int d, bool acc,
+                        const std::vector<int>& sub) {
+    const int shape = launch_shape(it, sub, d);
+    const double ct = R.mixed ? 8.0 : 16.0, sk = R.mixed ? 4.0 : 8.0;
+    CycleArgs a{};
+    a.st.n = (int)sub.size();
+    int tiles = 0;
+    double bg = 0.0, ba = 0.0;
+    for (int q = 0; q < a.st.n; ++q) {
+        const Item& I = it[sub[q]];
+        mg_ctx* c = I.c;
+        CycleSlot& s = a.st.s[q];
+        s.lv = view_ptr(c, dir, d);
+        if (d == 0) {
+            s.f = (*l0)[sub[q]].f;
+            s.fscale = (*l0)[sub[q]].fs;
+            s.out = (*l0)[sub[q]].out;
+        } else {
+            s.f = lvec(c, c->lv[d].F, d, I.rhs);
+            s.fscale = 1.0;
+            s.out = lvec(c, c->lv[d].E, d, I.rhs);
+        }
+        s.c = lvec(c, c->lv[d + 1].E, d + 1, I.rhs);
+        s.sb = sbuf(c, d, I.rhs);
+        s.tile0 = tiles;
+        int nt[3];
+        mg::tile_counts(2, shape, c->lv[d].n, nt);
+        tiles += nt[0] * nt[1];
+        const double fb = d == 0 ? 16.0 : ct;
+        bg += c->lv[d].N * (ct + fb + sk) + c->lv[d + 1].N * ct;
+        ba += c->lv[d].N * (ct + fb + sk + fb + (d == 0 && acc ? 16.0 : 0.0)) + c->lv[d + 1].N * ct;
+    }
+    a.st.ntiles = tiles;
+    int pi = prof_begin(R, d == 0 ? MG_K_SMOOTH_GRAM_FINE : MG_K_COARSE_LEVELS, bg);
+    CK(mg::launch_sm2_gram(R.mixed, d == 0, true, shape, a, R.w->part, HSTRIDE, R.w->bstride, R.s));
+    prof_end(R, pi);
+    CKS(coef_from_tiles(R, d, 1, it, sub, a));
+    pi = prof_begin(R, d == 0 ? MG_K_PROLONG_SMOOTH_FINE : MG_K_COARSE_LEVELS, ba);
+    CK(mg::launch_sm2_apply_out(R.mixed, d == 0, d == 0 && acc, shape, a, R.s));
+    prof_end(R, pi);
+    return MG_OK;
+}
+
 // Pre-smoothing at depth d and restriction of its residual to depth d + 1.
 // Level 0 with incoming iterates (FP64 only): q0 = f - A u by the FP64
 // residual kernel, whose ||q0||^2 of item k lands in w->rtot_h[k] when norm.
@@ -584,6 +693,7 @@ mg_status launch_pre_g(Run& R, int dir, const std::vector<Item>& it, const std::
                                   R.s));
             }
         }
+        if (R.dim == 2) return pre_fused_2d(R, dir, it, l0, d, nz, sub);
         mg::SmArgs sa{};
         CKS(build_sm(R, dir, d, it, sub, sa));
         for (int q = 0; q < sa.st.n; ++q) {
@@ -638,6 +748,7 @@ mg_status launch_post_g(Run& R, int dir, const std::vector<Item>& it, const std:
     for (int k = 0; k < (int)it.size(); ++k)
         if (d + 1 < it[k].c->L) who.push_back(k);
     return for_groups(who, [&](const std::vector<int>& sub, int) -> mg_status {
+        if (R.dim == 2) return post_fused_2d(R, dir, it, l0, d, acc, sub);
         const int shape = launch_shape(it, sub, d);
         const double ct = R.mixed ? 8.0 : 16.0, sk = R.mixed ? 4.0 : 8.0;
         CycleArgs a{};
@@ -738,7 +849,9 @@ mg_status coarse_part(Run& R, int dir, const std::vector<Item>& it) {
         const double ct = R.mixed ? 8.0 : 16.0, sk = R.mixed ? 4.0 : 8.0;
         for (const Item& I : it)
             for (int l = 1; l + 1 < I.c->L; ++l) {
-                if (I.c->gsmooth)   // powers, Gram, apply passes of both smoothing steps
+                if (I.c->gsmooth && I.c->dim == 2)   // fused Gram and apply passes of both steps
+                    by += I.c->lv[l].N * (8 * ct + 4 * sk) + 3 * I.c->lv[l + 1].N * ct;
+                else if (I.c->gsmooth)   // powers, Gram, apply passes of both smoothing steps
                     by += I.c->lv[l].N * (27 * ct + 8 * sk) + 2 * I.c->lv[l + 1].N * ct;
                 else
                     by += I.c->lv[l].N * (ct + sk) + I.c->lv[l + 1].N * ct +
@@ -1582,14 +1695,16 @@ mg_status setup(const mg_params* p, const double* k2_dev, void* stream, mg_ctx* 
         for (int l = 0; l < L; ++l) {
             Level& V = c->lv[l];
             const size_t bytes = (size_t)c->nrhs * V.N * esz;
-            for (int i = 0; i < 3; ++i) CKS(dalloc(&V.Q[i], bytes));
+            // the fused 2D passes keep only u1 (and q0 of an incoming iterate)
+            for (int i = 0; i < 3; ++i)
+                if (d == 3 || (i == 0 && l == 0)) CKS(dalloc(&V.Q[i], bytes));
             CKS(dalloc(&V.SU1, bytes));
-            CKS(dalloc(&V.SU2, bytes));
+            if (d == 3) CKS(dalloc(&V.SU2, bytes));
             for (int r = 0; r < c->nrhs; ++r) {
                 mg::SmoothBufs& b = sb[(size_t)r * L + l];
-                for (int i = 0; i < 3; ++i) b.q[i] = lvec(c, V.Q[i], l, r);
+                for (int i = 0; i < 3; ++i) b.q[i] = V.Q[i] ? lvec(c, V.Q[i], l, r) : nullptr;
                 b.u1 = lvec(c, V.SU1, l, r);
-                b.u2 = lvec(c, V.SU2, l, r);
+                b.u2 = V.SU2 ? lvec(c, V.SU2, l, r) : nullptr;
                 b.coef = c->gcoef + ((size_t)r * L + l) * 8;
             }
         }

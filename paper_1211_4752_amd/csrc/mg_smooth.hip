@@ -51,11 +51,12 @@ __device__ __forceinline__ SmPos sm_pos(const SmSlots& st) {
     return q;
 }
 
-__device__ __forceinline__ void grid_pos(long long p, int nx, int ny, int& gx, int& gy, int& gz) {
-    gx = (int)(p % nx);
-    const long long rr = p / nx;
-    gy = (int)(rr % ny);
-    gz = (int)(rr / ny);
+// 32-bit index arithmetic: a level has fewer than 2^31 points.
+__device__ __forceinline__ void grid_pos(int p, int nx, int ny, int& gx, int& gy, int& gz) {
+    gx = p % nx;
+    const int rr = p / nx;
+    gy = rr % ny;
+    gz = rr / ny;
 }
 
 // q0 at p: fscale f (f typed TQ) or the q0 buffer.
