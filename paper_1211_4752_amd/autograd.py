@@ -24,8 +24,10 @@ from . import mg
 class HelmholtzSolve(torch.autograd.Function):
     """u = HelmholtzSolve.apply(k2, f, opts) with opts a dict:
 
-    n, h, ecs, ecs_angle, theta_max, omega, mode ("gmres" | "standalone"),
-    rtol, maxit, restart, adjoint_rtol (defaults to rtol).
+    n, h, ecs, ecs_angle, theta_max, omega, smoother ("gmres3" | "jacobi",
+    default "gmres3", the paper's smoother), precision ("c128" | "mixed"),
+    mode ("gmres" | "standalone"), rtol, maxit, restart, adjoint_rtol
+    (defaults to rtol).
     k2: float64 device tensor shaped like the grid; f: complex128 device
     tensor (nrhs, *grid).  A solve that does not reach rtol raises.
     """
@@ -37,7 +39,8 @@ class HelmholtzSolve(torch.autograd.Function):
         s = mg.Solver(opts["n"], opts["h"], k2, ecs=opts.get("ecs", 0),
                       ecs_angle=opts.get("ecs_angle", math.pi / 4),
                       theta_max=opts.get("theta_max", math.pi / 6), omega=opts.get("omega", 2.0 / 3.0),
-                      nrhs=f.shape[0])
+                      nrhs=f.shape[0], smoother=opts.get("smoother", "gmres3"),
+                      precision=opts.get("precision", "c128"))
         u = s.empty()
         st, its, _ = s.solve(u, f, mode=opts.get("mode", "gmres"), rtol=opts.get("rtol", 1e-10),
                              maxit=opts.get("maxit", 20000), restart=opts.get("restart", 20))

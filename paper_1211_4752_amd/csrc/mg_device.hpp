@@ -85,7 +85,28 @@ struct SmoothBufs {
     void* u1;                  // iterate after pre-smoothing
     void* u2;                  // iterate after the coarse-grid correction
     cx<double>* coef;          // [2][4]: c1, c2, c3, (||r||^2, 0) for pre (0) and post (1)
+    void* f;                   // the level's right-hand side (levels >= 1)
+    void* e;                   // the level's correction (levels >= 1)
 };
+
+// The coarse tail: one workgroup per slot runs the cycle from level lt
+// (rhs in sb[0].f, zero guess) down to the coarsest and back, leaving the
+// correction in sb[0].e.  lv and sb point at level lt; both tables are
+// contiguous by level.
+struct TailSlot {
+    const void* lv;
+    const SmoothBufs* sb;
+    int nlev;                  // levels lt .. coarsest
+    int pad_;
+};
+
+struct TailArgs {
+    int n;
+    int gmres;                 // smoother: 0 omega-Jacobi, 1 GMRES(3)
+    double brk;                // relative Cholesky pivot of an exhausted Krylov space
+    TailSlot s[MAX_SLOTS];
+};
+constexpr int TAIL_POINTS = 4096;   // levels of at most this many points go to the tail
 
 // A slot of the two fused cycle kernels and of the coarsest solve.
 struct CycleSlot {
@@ -204,7 +225,6 @@ hipError_t launch_smooth_restrict(int dim, bool f32, bool level0, bool zero, int
                                   hipStream_t s);
 hipError_t launch_prolong_smooth(int dim, bool f32, bool level0, bool zero, bool accumulate, int shape,
                                  const CycleArgs& a, hipStream_t s);
-hipError_t launch_coarse_solve(bool f32, const CycleArgs& a, hipStream_t s);
 
 // number of workgroups a vector kernel uses for N points
 int vec_blocks(long long N);
@@ -225,13 +245,17 @@ hipError_t launch_sm_apply_restrict(int dim, bool f32, bool level0, bool nonzero
                                     hipStream_t s);
 hipError_t launch_sm_prolong_resid(int dim, bool f32, bool level0, int shape, const CycleArgs& a, hipStream_t s);
 hipError_t launch_sm_apply_out(bool f32, bool level0, bool accumulate, const SmArgs& a, hipStream_t s);
-// Fused 2D passes (mg_smooth2d.hip): Gram partials per tile at
+// 2D passes as row-marching wavefronts (mg_march2d.hip): a tile is a strip
+// of 56 columns by 16, 32 or 64 rows (shape id); Gram partials per strip at
 // part[(slot * pstride + v) * bstride + tile].
+void march_counts(int shape, const int n[3], int ntiles[3]);
 hipError_t launch_sm2_gram(bool f32, bool level0, bool post, int shape, const CycleArgs& a, cx<double>* part,
                            int pstride, int bstride, hipStream_t s);
 hipError_t launch_sm2_apply_restrict(bool f32, bool level0, bool nonzero, int shape, const CycleArgs& a,
                                      hipStream_t s);
 hipError_t launch_sm2_apply_out(bool f32, bool level0, bool accumulate, int shape, const CycleArgs& a, hipStream_t s);
+
+hipError_t launch_tail(int dim, bool f32, const TailArgs& a, hipStream_t s);
 
 hipError_t launch_inject_k2(int dim, const double* fine, const int nf[3], double* coarse, const int nc[3],
                             hipStream_t s);

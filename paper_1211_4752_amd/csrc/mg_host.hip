@@ -182,6 +182,7 @@ struct mg_ctx {
     int zstride = 0;
     // GMRES(3) smoother
     bool gsmooth = false;
+    int lt = 1;                       // first level of the coarse tail (levels lt..L-1 in one launch)
     mg::SmoothBufs* sb_d = nullptr;   // [rhs * L + l]
     cx<double>* gcoef = nullptr;      // [(rhs * L + l) * 8]
     double* scale_d = nullptr;     // [rhs * HSTRIDE + i]
@@ -354,7 +355,7 @@ mg_status launch_ka(Run& R, int dir, const std::vector<Item>& it, const std::vec
                     bool norm) {
     std::vector<int> who;
     for (int k = 0; k < (int)it.size(); ++k)
-        if (d + 1 < it[k].c->L) who.push_back(k);
+        if (d < it[k].c->lt) who.push_back(k);
     const bool zero = !(d == 0 && l0 && (*l0)[0].u);
     return for_groups(who, [&](const std::vector<int>& sub, int gbase) -> mg_status {
         const int shape = launch_shape(it, sub, d);
@@ -411,26 +412,30 @@ mg_status launch_ka(Run& R, int dir, const std::vector<Item>& it, const std::vec
     });
 }
 
-// Coarsest solve for every item.
-mg_status launch_coarsest(Run& R, int dir, const std::vector<Item>& it) {
+const mg::SmoothBufs* sbuf(const mg_ctx* c, int l, int rhs);
+
+// The coarse tail of every item (levels lt..L-1 and the coarsest solve),
+// one workgroup per item: its correction lands in E_lt.
+mg_status launch_tail_items(Run& R, int dir, const std::vector<Item>& it) {
     std::vector<int> all(it.size());
     for (size_t k = 0; k < it.size(); ++k) all[k] = (int)k;
     return for_groups(all, [&](const std::vector<int>& sub, int) -> mg_status {
-        CycleArgs a{};
-        a.st.n = (int)sub.size();
+        mg::TailArgs a{};
+        a.n = (int)sub.size();
+        a.gmres = it[sub[0]].c->gsmooth ? 1 : 0;
+        a.brk = R.mixed ? 1e-5 : 1e-13;
         double by = 0.0;
-        for (int q = 0; q < a.st.n; ++q) {
+        for (int q = 0; q < a.n; ++q) {
             const Item& I = it[sub[q]];
             mg_ctx* c = I.c;
-            const int l = c->L - 1;
-            CycleSlot& s = a.st.s[q];
-            s.lv = view_ptr(c, dir, l);
-            s.f = lvec(c, c->lv[l].F, l, I.rhs);
-            s.out = lvec(c, c->lv[l].E, l, I.rhs);
-            by += 2.0 * c->lv[l].N * (R.mixed ? 8.0 : 16.0);
+            mg::TailSlot& s = a.s[q];
+            s.lv = view_ptr(c, dir, c->lt);
+            s.sb = sbuf(c, c->lt, I.rhs);
+            s.nlev = c->L - c->lt;
+            for (int l = c->lt; l < c->L; ++l) by += 2.0 * c->lv[l].N * (R.mixed ? 8.0 : 16.0);
         }
         const int pi = prof_begin(R, MG_K_COARSEST_SOLVE, by);
-        CK(mg::launch_coarse_solve(R.mixed, a, R.s));
+        CK(mg::launch_tail(R.dim, R.mixed, a, R.s));
         prof_end(R, pi);
         return MG_OK;
     });
@@ -440,7 +445,7 @@ mg_status launch_coarsest(Run& R, int dir, const std::vector<Item>& it) {
 mg_status launch_kb(Run& R, int dir, const std::vector<Item>& it, const std::vector<L0>* l0, int d, bool acc) {
     std::vector<int> who;
     for (int k = 0; k < (int)it.size(); ++k)
-        if (d + 1 < it[k].c->L) who.push_back(k);
+        if (d < it[k].c->lt) who.push_back(k);
     const bool zero = !(d == 0 && l0 && (*l0)[0].u);
     return for_groups(who, [&](const std::vector<int>& sub, int) -> mg_status {
         const int shape = launch_shape(it, sub, d);
@@ -599,7 +604,7 @@ mg_status pre_fused_2d(Run& R, int dir, const std::vector<Item>& it, const std::
         s.sb = sbuf(c, d, I.rhs);
         s.tile0 = tiles;
         int nt[3];
-        mg::tile_counts(2, shape, c->lv[d].n, nt);
+        mg::march_counts(shape, c->lv[d].n, nt);
         tiles += nt[0] * nt[1];
         const double q0b = (d == 0 && !nz) ? 16.0 : ct;
         bg += c->lv[d].N * (q0b + sk);
@@ -642,7 +647,7 @@ mg_status post_fused_2d(Run& R, int dir, const std::vector<Item>& it, const std:
         s.sb = sbuf(c, d, I.rhs);
         s.tile0 = tiles;
         int nt[3];
-        mg::tile_counts(2, shape, c->lv[d].n, nt);
+        mg::march_counts(shape, c->lv[d].n, nt);
         tiles += nt[0] * nt[1];
         const double fb = d == 0 ? 16.0 : ct;
         bg += c->lv[d].N * (ct + fb + sk) + c->lv[d + 1].N * ct;
@@ -665,7 +670,7 @@ mg_status post_fused_2d(Run& R, int dir, const std::vector<Item>& it, const std:
 mg_status launch_pre_g(Run& R, int dir, const std::vector<Item>& it, const std::vector<L0>* l0, int d, bool norm) {
     std::vector<int> who;
     for (int k = 0; k < (int)it.size(); ++k)
-        if (d + 1 < it[k].c->L) who.push_back(k);
+        if (d < it[k].c->lt) who.push_back(k);
     const bool nz = d == 0 && l0 && (*l0)[0].u;
     if (nz && R.mixed) return MG_E_STATE;
     return for_groups(who, [&](const std::vector<int>& sub, int gbase) -> mg_status {
@@ -746,7 +751,7 @@ mg_status launch_pre_g(Run& R, int dir, const std::vector<Item>& it, const std::
 mg_status launch_post_g(Run& R, int dir, const std::vector<Item>& it, const std::vector<L0>* l0, int d, bool acc) {
     std::vector<int> who;
     for (int k = 0; k < (int)it.size(); ++k)
-        if (d + 1 < it[k].c->L) who.push_back(k);
+        if (d < it[k].c->lt) who.push_back(k);
     return for_groups(who, [&](const std::vector<int>& sub, int) -> mg_status {
         if (R.dim == 2) return post_fused_2d(R, dir, it, l0, d, acc, sub);
         const int shape = launch_shape(it, sub, d);
@@ -808,12 +813,12 @@ mg_status cycle_up(Run& R, int dir, const std::vector<Item>& it, const std::vect
 // (direction, item list) as a HIP graph and replayed; every pointer in it is
 // fixed per item (F_l and E_l by rhs).
 mg_status coarse_part(Run& R, int dir, const std::vector<Item>& it) {
-    int maxL = 0;
-    for (const Item& I : it) maxL = std::max(maxL, I.c->L);
+    int maxT = 0;
+    for (const Item& I : it) maxT = std::max(maxT, I.c->lt);
     auto record = [&](Run& Q) -> mg_status {
-        for (int d = 1; d + 1 < maxL; ++d) CKS(cycle_down(Q, dir, it, nullptr, d, false));
-        CKS(launch_coarsest(Q, dir, it));
-        for (int d = maxL - 2; d >= 1; --d) CKS(cycle_up(Q, dir, it, nullptr, d, false));
+        for (int d = 1; d < maxT; ++d) CKS(cycle_down(Q, dir, it, nullptr, d, false));
+        CKS(launch_tail_items(Q, dir, it));
+        for (int d = maxT - 1; d >= 1; --d) CKS(cycle_up(Q, dir, it, nullptr, d, false));
         return MG_OK;
     };
     if (!R.gc) return record(R);
@@ -848,7 +853,7 @@ mg_status coarse_part(Run& R, int dir, const std::vector<Item>& it) {
     if (R.prof && R.prof->on) {
         const double ct = R.mixed ? 8.0 : 16.0, sk = R.mixed ? 4.0 : 8.0;
         for (const Item& I : it)
-            for (int l = 1; l + 1 < I.c->L; ++l) {
+            for (int l = 1; l < I.c->lt; ++l) {
                 if (I.c->gsmooth && I.c->dim == 2)   // fused Gram and apply passes of both steps
                     by += I.c->lv[l].N * (8 * ct + 4 * sk) + 3 * I.c->lv[l + 1].N * ct;
                 else if (I.c->gsmooth)   // powers, Gram, apply passes of both smoothing steps
@@ -1689,23 +1694,34 @@ mg_status setup(const mg_params* p, const double* k2_dev, void* stream, mg_ctx* 
         CKS(dalloc(&c->lv[l].E, (size_t)c->nrhs * c->lv[l].N * esz));
     }
     c->gsmooth = p->smoother == MG_SMOOTH_GMRES3;
-    if (c->gsmooth) {
+    // coarse tail: from the first level >= 1 with at most TAIL_POINTS points
+    c->lt = L - 1;
+    for (int l = 1; l < L; ++l)
+        if (c->lv[l].N <= mg::TAIL_POINTS) {
+            c->lt = l;
+            break;
+        }
+    {
         std::vector<mg::SmoothBufs> sb((size_t)c->nrhs * L);
         CKS(dalloc(&c->gcoef, (size_t)c->nrhs * L * 8 * sizeof(cx<double>)));
         for (int l = 0; l < L; ++l) {
             Level& V = c->lv[l];
             const size_t bytes = (size_t)c->nrhs * V.N * esz;
-            // the fused 2D passes keep only u1 (and q0 of an incoming iterate)
+            const bool tail = l >= c->lt;
+            // the 2D GMRES(3) passes keep only u1 (and q0 of an incoming
+            // iterate); the 3D passes and the tail use q0..q2 and u1
             for (int i = 0; i < 3; ++i)
-                if (d == 3 || (i == 0 && l == 0)) CKS(dalloc(&V.Q[i], bytes));
-            CKS(dalloc(&V.SU1, bytes));
-            if (d == 3) CKS(dalloc(&V.SU2, bytes));
+                if (tail || (c->gsmooth && (d == 3 || (i == 0 && l == 0)))) CKS(dalloc(&V.Q[i], bytes));
+            if (tail || c->gsmooth) CKS(dalloc(&V.SU1, bytes));
+            if (c->gsmooth && d == 3 && !tail) CKS(dalloc(&V.SU2, bytes));
             for (int r = 0; r < c->nrhs; ++r) {
                 mg::SmoothBufs& b = sb[(size_t)r * L + l];
                 for (int i = 0; i < 3; ++i) b.q[i] = V.Q[i] ? lvec(c, V.Q[i], l, r) : nullptr;
-                b.u1 = lvec(c, V.SU1, l, r);
+                b.u1 = V.SU1 ? lvec(c, V.SU1, l, r) : nullptr;
                 b.u2 = V.SU2 ? lvec(c, V.SU2, l, r) : nullptr;
                 b.coef = c->gcoef + ((size_t)r * L + l) * 8;
+                b.f = l > 0 ? lvec(c, V.F, l, r) : nullptr;
+                b.e = l > 0 ? lvec(c, V.E, l, r) : nullptr;
             }
         }
         CKS(dalloc(&c->sb_d, sb.size() * sizeof(mg::SmoothBufs)));
@@ -1720,6 +1736,10 @@ mg_status setup(const mg_params* p, const double* k2_dev, void* stream, mg_ctx* 
         int nt[3];
         mg::tile_counts(d, shape, c->lv[0].n, nt);
         maxt = std::max(maxt, nt[0] * nt[1] * nt[2]);
+        if (d == 2) {
+            mg::march_counts(shape, c->lv[0].n, nt);
+            maxt = std::max(maxt, nt[0] * nt[1]);
+        }
     }
     CKS(work_alloc(c->work, c->nrhs, std::max(maxt, mg::vec_blocks(c->lv[0].N))));
     CKS(dalloc(&c->scale_d, (size_t)c->nrhs * HSTRIDE * sizeof(double)));

@@ -149,5 +149,60 @@ __device__ __forceinline__ cx<T> stencil_at(const LevelView<T>& L, const cx<TX>*
     return xs * ax;
 }
 
+__device__ __forceinline__ cx<double> conjd(cx<double> z) { return mk(z.r, -z.i); }
+
+// Coefficients of the least-squares residual polynomial from the Gram matrix.
+// brk: relative pivot below which the Krylov space counts as exhausted.
+__device__ inline void solve_coef(const cx<double>* G, double brk, cx<double>* out) {
+    const double g00 = G[0].r;
+    out[0] = out[1] = out[2] = mk(0.0, 0.0);
+    out[3] = mk(g00, 0.0);
+    if (!(g00 > 0.0) || !(G[1].r > 0.0)) return;
+    const double d0 = sqrt(g00), d1 = sqrt(G[1].r), d2 = sqrt(G[2].r), d3 = sqrt(G[3].r);
+    // right-hand side b_i = -G_i0 / (d_i d0), G_i0 = conj(G_0i)
+    const cx<double> b1 = (-1.0 / (d1 * d0)) * conjd(G[4]);
+    int deg = 1;
+    cx<double> L21 = mk(0.0, 0.0), L31 = mk(0.0, 0.0), L32 = mk(0.0, 0.0);
+    double L22 = 0.0, L33 = 0.0;
+    cx<double> b2 = mk(0.0, 0.0), b3 = mk(0.0, 0.0);
+    if (d2 > 0.0) {
+        L21 = (1.0 / (d1 * d2)) * conjd(G[7]);
+        const double p2 = 1.0 - abs2(L21);
+        if (p2 > brk) {
+            deg = 2;
+            L22 = sqrt(p2);
+            b2 = (-1.0 / (d2 * d0)) * conjd(G[5]);
+            if (d3 > 0.0) {
+                L31 = (1.0 / (d1 * d3)) * conjd(G[8]);
+                const cx<double> S32 = (1.0 / (d2 * d3)) * conjd(G[9]);
+                L32 = (1.0 / L22) * (S32 - L31 * conjd(L21));
+                const double p3 = 1.0 - abs2(L31) - abs2(L32);
+                if (p3 > brk) {
+                    deg = 3;
+                    L33 = sqrt(p3);
+                    b3 = (-1.0 / (d3 * d0)) * conjd(G[6]);
+                }
+            }
+        }
+    }
+    // L y = b, L^H x = y
+    cx<double> x1, x2 = mk(0.0, 0.0), x3 = mk(0.0, 0.0);
+    const cx<double> y1 = b1;
+    if (deg == 1) {
+        x1 = y1;
+    } else {
+        const cx<double> y2 = (1.0 / L22) * (b2 - L21 * y1);
+        if (deg == 3) {
+            const cx<double> y3 = (1.0 / L33) * (b3 - L31 * y1 - L32 * y2);
+            x3 = (1.0 / L33) * y3;
+        }
+        x2 = (1.0 / L22) * (y2 - conjd(L32) * x3);
+        x1 = y1 - conjd(L21) * x2 - conjd(L31) * x3;
+    }
+    out[0] = (d0 / d1) * x1;
+    out[1] = deg >= 2 ? (d0 / d2) * x2 : mk(0.0, 0.0);
+    out[2] = deg == 3 ? (d0 / d3) * x3 : mk(0.0, 0.0);
+}
+
 }  // namespace kc
 }  // namespace mg

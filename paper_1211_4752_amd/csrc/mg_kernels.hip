@@ -295,50 +295,6 @@ __global__ void __launch_bounds__(NT) k_prolong_smooth(const CycleArgs a) {
 }
 
 // ---------------------------------------------------------------------------
-// Coarsest level: LU forward/back substitution, one workgroup per slot, in
-// FP64 whatever the cycle precision.  The slot's level descriptor holds the
-// row-major LU factors (unit-lower L below the diagonal, U on and above) and
-// the row interchanges in elimination order; f: slot.f, e: slot.out.
-// ---------------------------------------------------------------------------
-template <typename T>
-__global__ void __launch_bounds__(NT) k_coarse_solve(const CycleArgs a) {
-    __shared__ cx<double> b[MAX_COARSE];
-    const CycleSlot& sl = a.st.s[blockIdx.x];
-    const LevelView<T>* Lp = static_cast<const LevelView<T>*>(sl.lv);
-    const int n = (int)Lp->N;
-    const cx<double>* lu = Lp->lu;
-    const int* piv = Lp->piv;
-    const cx<T>* f = static_cast<const cx<T>*>(sl.f);
-    cx<T>* e = static_cast<cx<T>*>(sl.out);
-    for (int i = threadIdx.x; i < n; i += NT) b[i] = cvt<double>(f[i]);
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        for (int i = 0; i < n; ++i) {
-            const int p = piv[i];
-            if (p != i) {
-                const cx<double> tmp = b[i];
-                b[i] = b[p];
-                b[p] = tmp;
-            }
-        }
-    }
-    __syncthreads();
-    for (int k = 0; k < n; ++k) {
-        const cx<double> bk = b[k];
-        for (int i = k + 1 + threadIdx.x; i < n; i += NT) b[i] = b[i] - lu[(long long)i * n + k] * bk;
-        __syncthreads();
-    }
-    for (int k = n - 1; k >= 0; --k) {
-        if (threadIdx.x == 0) b[k] = cdiv(b[k], lu[(long long)k * n + k]);
-        __syncthreads();
-        const cx<double> bk = b[k];
-        for (int i = threadIdx.x; i < k; i += NT) b[i] = b[i] - lu[(long long)i * n + k] * bk;
-        __syncthreads();
-    }
-    for (int i = threadIdx.x; i < n; i += NT) e[i] = cvt<T>(b[i]);
-}
-
-// ---------------------------------------------------------------------------
 // Vector kernels: one point per thread, a contiguous chunk of the slot's
 // vector per workgroup.
 // ---------------------------------------------------------------------------
@@ -691,15 +647,6 @@ hipError_t launch_prolong_smooth(int dim, bool f32, bool level0, bool zero, bool
     if (!level0) return ps_launch<float, float, float, true, false>(dim, shape, a, s);
     return acc ? ps_launch<float, double, double, true, true>(dim, shape, a, s)
                : ps_launch<float, double, double, true, false>(dim, shape, a, s);
-}
-
-hipError_t launch_coarse_solve(bool f32, const CycleArgs& a, hipStream_t s) {
-    if (a.st.n <= 0) return hipSuccess;
-    if (f32)
-        hipLaunchKernelGGL((k_coarse_solve<float>), dim3(a.st.n), dim3(NT), 0, s, a);
-    else
-        hipLaunchKernelGGL((k_coarse_solve<double>), dim3(a.st.n), dim3(NT), 0, s, a);
-    return hipGetLastError();
 }
 
 int vec_blocks(long long N) {
