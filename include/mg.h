@@ -161,10 +161,12 @@ mg_status mg_grad_k2(mg_ctx *c, const double *u_dev, const double *lam_dev,
 mg_status mg_apply(mg_ctx *c, int level, int adjoint, const double *x_dev,
                    double *y_dev);
 
-/* Tile shape of the two fused cycle kernels on one level (the shape ids are
- * 64x16, 64x8, 128x8 in 2D and 16x8x4, 32x4x2, 16x4x4 in 3D).  mg_setup
- * picks one per level by timing every shape on the level's own arrays
- * (levels of at least 16384 points; smaller levels use shape 0).
+/* Tile shape of the cycle kernels on one level.  Shape ids 0, 1, 2 are
+ * 64x16, 64x8, 128x8 (2D) and 16x8x4, 32x4x2, 16x4x4 (3D) for the
+ * omega-Jacobi kernels, and strips of 56 columns by 32, 16, 8 rows for the
+ * 2D GMRES(3) kernels.  mg_setup picks one per level by timing every shape
+ * on the level's own arrays (levels of at least 4096 points above the coarse
+ * tail; other levels use shape 0).
  * shape >= 0 sets it, shape < 0 only queries; returns the shape in force or
  * a negative mg_status. */
 int mg_tile_shape(mg_ctx *c, int level, int shape);

@@ -246,7 +246,7 @@ hipError_t launch_sm_apply_restrict(int dim, bool f32, bool level0, bool nonzero
 hipError_t launch_sm_prolong_resid(int dim, bool f32, bool level0, int shape, const CycleArgs& a, hipStream_t s);
 hipError_t launch_sm_apply_out(bool f32, bool level0, bool accumulate, const SmArgs& a, hipStream_t s);
 // 2D passes as row-marching wavefronts (mg_march2d.hip): a tile is a strip
-// of 56 columns by 16, 32 or 64 rows (shape id); Gram partials per strip at
+// of 56 columns by 32, 16 or 8 rows (shape id 0, 1, 2); Gram partials per strip at
 // part[(slot * pstride + v) * bstride + tile].
 void march_counts(int shape, const int n[3], int ntiles[3]);
 hipError_t launch_sm2_gram(bool f32, bool level0, bool post, int shape, const CycleArgs& a, cx<double>* part,

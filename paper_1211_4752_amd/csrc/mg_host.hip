@@ -36,7 +36,7 @@ constexpr int MAX_RESTART = 32;
 constexpr int HSTRIDE = MAX_RESTART + 1;     // per-slot stride of one set of dot results
 constexpr int TOT = 2 * HSTRIDE;             // per-slot totals: H1 | H2
 constexpr double DIVERGE = 1e8;
-constexpr long long AUTOTUNE_MIN_POINTS = 16384;
+constexpr long long AUTOTUNE_MIN_POINTS = 4096;
 
 #define CK(expr)                                        \
     do {                                                \
@@ -1513,7 +1513,7 @@ mg_status autotune(mg_ctx* c) {
     R.prof = nullptr;
     R.gc = nullptr;
     mg_status st = MG_OK;
-    for (int l = 0; l + 1 < c->L && st == MG_OK; ++l) {
+    for (int l = 0; l < c->lt && st == MG_OK; ++l) {
         if (c->lv[l].N < AUTOTUNE_MIN_POINTS) break;
         float best = 1e30f;
         int best_shape = 0;

@@ -323,11 +323,12 @@ __global__ void __launch_bounds__(MW) k_mg_gram(const CycleArgs a, cx<double>* p
             cur = nxt;
         }
     }
+    cx<double>* P = part + (long long)slot * pstride * bstride;
 #pragma unroll
     for (int v = 0; v < NUM_GRAM; ++v) {
         const double r = wave_sum(g[v].r);
         const double i = wave_sum(g[v].i);
-        if (threadIdx.x == 0) part[((long long)slot * pstride + v) * bstride + tile] = mk(r, i);
+        if (threadIdx.x == 0) P[(long long)v * bstride + tile] = mk(r, i);
     }
 }
 
@@ -505,7 +506,7 @@ __global__ void __launch_bounds__(MW) k_mg_apply_out(const CycleArgs a) {
 // Geometry and launchers
 // ---------------------------------------------------------------------------
 namespace {
-constexpr int MARCH_TY[NUM_TILE_SHAPES] = {32, 64, 16};
+constexpr int MARCH_TY[NUM_TILE_SHAPES] = {32, 16, 8};
 }
 
 void march_counts(int shape, const int n[3], int nt[3]) {
@@ -517,8 +518,8 @@ void march_counts(int shape, const int n[3], int nt[3]) {
 
 #define MG_MARCH_SWITCH(LAUNCH)         \
     switch (shape) {                    \
-        case 1: LAUNCH(64); break;      \
-        case 2: LAUNCH(16); break;      \
+        case 1: LAUNCH(16); break;      \
+        case 2: LAUNCH(8); break;       \
         default: LAUNCH(32); break;     \
     }
 

@@ -16,6 +16,24 @@ using namespace kc;
 namespace {
 
 constexpr int NTT = 512;
+constexpr int PPT = TAIL_POINTS / NTT;   // points per thread on a tail level
+
+// out[p] = fn(p) for the level's points: every value first, then every store,
+// so that the loads of all of a thread's points are in flight together.
+template <typename T, typename F>
+__device__ __forceinline__ void map_store(int N, cx<T>* out, F fn) {
+    cx<T> v[PPT];
+#pragma unroll
+    for (int i = 0; i < PPT; ++i) {
+        const int p = threadIdx.x + i * NTT;
+        v[i] = p < N ? fn(p) : mk<T>(0, 0);
+    }
+#pragma unroll
+    for (int i = 0; i < PPT; ++i) {
+        const int p = threadIdx.x + i * NTT;
+        if (p < N) out[p] = v[i];
+    }
+}
 
 template <int D>
 __device__ __forceinline__ void pos3(int p, int nx, int ny, int& gx, int& gy, int& gz) {
@@ -102,7 +120,10 @@ __device__ void tail_gram(const LevelView<T>& L, const cx<T>* q0, const cx<T>* q
     cx<double> g[NUM_GRAM];
 #pragma unroll
     for (int v = 0; v < NUM_GRAM; ++v) g[v] = mk(0.0, 0.0);
-    for (int p = threadIdx.x; p < N; p += NTT) {
+#pragma unroll
+    for (int i = 0; i < PPT; ++i) {
+        const int p = threadIdx.x + i * NTT;
+        if (p >= N) continue;
         int gx, gy, gz;
         pos3<D>(p, nx, ny, gx, gy, gz);
         const cx<double> v0 = cvt<double>(q0[p]), v1 = cvt<double>(q1[p]), v2 = cvt<double>(q2[p]);
@@ -154,51 +175,65 @@ __global__ void __launch_bounds__(NTT) k_tail(const TailArgs a) {
         cx<T>* q1 = static_cast<cx<T>*>(B.q[1]);
         if constexpr (GM) {
             cx<T>* q2 = static_cast<cx<T>*>(B.q[2]);
-            for (int p = threadIdx.x; p < N; p += NTT) {
+            map_store<T>(N, q1, [&](int p) {
                 int gx, gy, gz;
                 pos3<D>(p, nx, ny, gx, gy, gz);
-                q1[p] = L.sinv * stencil_at<D, T, T>(L, f, T(1), p, gx, gy, gz);
-            }
+                return L.sinv * stencil_at<D, T, T>(L, f, T(1), p, gx, gy, gz);
+            });
             __syncthreads();
-            for (int p = threadIdx.x; p < N; p += NTT) {
+            map_store<T>(N, q2, [&](int p) {
                 int gx, gy, gz;
                 pos3<D>(p, nx, ny, gx, gy, gz);
-                q2[p] = L.sinv * stencil_at<D, T, T>(L, q1, T(1), p, gx, gy, gz);
-            }
+                return L.sinv * stencil_at<D, T, T>(L, q1, T(1), p, gx, gy, gz);
+            });
             __syncthreads();
             tail_gram<D, T>(L, f, q1, q2, a.brk, sred, sc);
             const cx<T> c1 = cvt<T>(sc[0]), c2 = cvt<T>(sc[1]), c3 = cvt<T>(sc[2]);
             // u1 and the new residual (into q1, pointwise in place)
-            for (int p = threadIdx.x; p < N; p += NTT) {
-                int gx, gy, gz;
-                pos3<D>(p, nx, ny, gx, gy, gz);
-                const cx<T> q0 = f[p], v1 = q1[p], v2 = q2[p];
-                const cx<T> v3 = L.sinv * stencil_at<D, T, T>(L, q2, T(1), p, gx, gy, gz);
-                u1[p] = mk<T>(0, 0) - L.sinv * (c1 * q0 + c2 * v1 + c3 * v2);
-                q1[p] = q0 + c1 * v1 + c2 * v2 + c3 * v3;
+            cx<T> ru[PPT], rr[PPT];
+#pragma unroll
+            for (int i = 0; i < PPT; ++i) {
+                const int p = threadIdx.x + i * NTT;
+                ru[i] = rr[i] = mk<T>(0, 0);
+                if (p < N) {
+                    int gx, gy, gz;
+                    pos3<D>(p, nx, ny, gx, gy, gz);
+                    const cx<T> q0 = f[p], v1 = q1[p], v2 = q2[p];
+                    const cx<T> v3 = L.sinv * stencil_at<D, T, T>(L, q2, T(1), p, gx, gy, gz);
+                    ru[i] = mk<T>(0, 0) - L.sinv * (c1 * q0 + c2 * v1 + c3 * v2);
+                    rr[i] = q0 + c1 * v1 + c2 * v2 + c3 * v3;
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < PPT; ++i) {
+                const int p = threadIdx.x + i * NTT;
+                if (p < N) {
+                    u1[p] = ru[i];
+                    q1[p] = rr[i];
+                }
             }
         } else {
-            for (int p = threadIdx.x; p < N; p += NTT) {
+            map_store<T>(N, u1, [&](int p) {
                 int gx, gy, gz;
                 pos3<D>(p, nx, ny, gx, gy, gz);
-                u1[p] = cdiv(L.omega * f[p], diag_at<D>(L, gx, gy, gz, L.k2[p]));
-            }
+                return cdiv(L.omega * f[p], diag_at<D>(L, gx, gy, gz, L.k2[p]));
+            });
             __syncthreads();
-            for (int p = threadIdx.x; p < N; p += NTT) {
+            map_store<T>(N, q1, [&](int p) {
                 int gx, gy, gz;
                 pos3<D>(p, nx, ny, gx, gy, gz);
-                q1[p] = f[p] - stencil_at<D, T, T>(L, u1, T(1), p, gx, gy, gz);
-            }
+                return f[p] - stencil_at<D, T, T>(L, u1, T(1), p, gx, gy, gz);
+            });
         }
         __syncthreads();
         const LevelView<T> Lc = Lv[k + 1];
         cx<T>* fc = static_cast<cx<T>*>(SB[k + 1].f);
         const int Nc = (int)Lc.N;
-        for (int p = threadIdx.x; p < Nc; p += NTT) {
+        map_store<T>(Nc, fc, [&](int p) {
             int cx_, cy, cz;
             pos3<D>(p, Lc.n[0], Lc.n[1], cx_, cy, cz);
-            fc[p] = restrict_at<D, T>(L, q1, cx_, cy, cz);
-        }
+            return restrict_at<D, T>(L, q1, cx_, cy, cz);
+        });
         __syncthreads();
     }
 
@@ -248,45 +283,44 @@ __global__ void __launch_bounds__(NTT) k_tail(const TailArgs a) {
         cx<T>* u = static_cast<cx<T>*>(B.u1);   // u2 = u1 + P e, in place
         cx<T>* e = static_cast<cx<T>*>(B.e);
         const cx<T>* ec = static_cast<const cx<T>*>(SB[k + 1].e);
-        for (int p = threadIdx.x; p < N; p += NTT) {
+        map_store<T>(N, u, [&](int p) {
             int gx, gy, gz;
             pos3<D>(p, nx, ny, gx, gy, gz);
-            u[p] = u[p] + prolong_at<D, T>(Lc, ec, gx, gy, gz);
-        }
+            return u[p] + prolong_at<D, T>(Lc, ec, gx, gy, gz);
+        });
         __syncthreads();
         if constexpr (GM) {
             cx<T>* q0 = static_cast<cx<T>*>(B.q[0]);
             cx<T>* q1 = static_cast<cx<T>*>(B.q[1]);
             cx<T>* q2 = static_cast<cx<T>*>(B.q[2]);
-            for (int p = threadIdx.x; p < N; p += NTT) {
+            map_store<T>(N, q0, [&](int p) {
                 int gx, gy, gz;
                 pos3<D>(p, nx, ny, gx, gy, gz);
-                q0[p] = f[p] - stencil_at<D, T, T>(L, u, T(1), p, gx, gy, gz);
-            }
+                return f[p] - stencil_at<D, T, T>(L, u, T(1), p, gx, gy, gz);
+            });
             __syncthreads();
-            for (int p = threadIdx.x; p < N; p += NTT) {
+            map_store<T>(N, q1, [&](int p) {
                 int gx, gy, gz;
                 pos3<D>(p, nx, ny, gx, gy, gz);
-                q1[p] = L.sinv * stencil_at<D, T, T>(L, q0, T(1), p, gx, gy, gz);
-            }
+                return L.sinv * stencil_at<D, T, T>(L, q0, T(1), p, gx, gy, gz);
+            });
             __syncthreads();
-            for (int p = threadIdx.x; p < N; p += NTT) {
+            map_store<T>(N, q2, [&](int p) {
                 int gx, gy, gz;
                 pos3<D>(p, nx, ny, gx, gy, gz);
-                q2[p] = L.sinv * stencil_at<D, T, T>(L, q1, T(1), p, gx, gy, gz);
-            }
+                return L.sinv * stencil_at<D, T, T>(L, q1, T(1), p, gx, gy, gz);
+            });
             __syncthreads();
             tail_gram<D, T>(L, q0, q1, q2, a.brk, sred, sc);
             const cx<T> c1 = cvt<T>(sc[0]), c2 = cvt<T>(sc[1]), c3 = cvt<T>(sc[2]);
-            for (int p = threadIdx.x; p < N; p += NTT)
-                e[p] = u[p] - L.sinv * (c1 * q0[p] + c2 * q1[p] + c3 * q2[p]);
+            map_store<T>(N, e, [&](int p) { return u[p] - L.sinv * (c1 * q0[p] + c2 * q1[p] + c3 * q2[p]); });
         } else {
-            for (int p = threadIdx.x; p < N; p += NTT) {
+            map_store<T>(N, e, [&](int p) {
                 int gx, gy, gz;
                 pos3<D>(p, nx, ny, gx, gy, gz);
                 const cx<T> r = f[p] - stencil_at<D, T, T>(L, u, T(1), p, gx, gy, gz);
-                e[p] = u[p] + cdiv(L.omega * r, diag_at<D>(L, gx, gy, gz, L.k2[p]));
-            }
+                return u[p] + cdiv(L.omega * r, diag_at<D>(L, gx, gy, gz, L.k2[p]));
+            });
         }
         __syncthreads();
     }
