@@ -167,8 +167,10 @@ __device__ __forceinline__ void gram_add(cx<double>* g, cx<T> a0, cx<T> a1, cx<T
     g[9] = g[9] + cmulc(v2, v3);
 }
 
-// One row of a pass's inputs at this lane, loaded one step ahead of its use
-// so that the loads of row t + 1 are in flight while row t is computed.
+// One row of a pass's inputs at this lane, loaded ahead of its use (two rows
+// in the Gram passes, one in the apply passes, where the extra registers
+// would cost occupancy) so that the loads are in flight while row t is
+// computed.
 template <typename T, typename TQ>
 struct RowIn {
     cx<T> u;                 // u1 (post-smoothing) or the incoming iterate
@@ -250,10 +252,11 @@ __global__ void __launch_bounds__(MW) k_mg_gram(const CycleArgs a, cx<double>* p
         cx<T> d3 = Z, d4 = Z, d5 = Z;
         cx<T> fprev = Z;
         T k0 = 0, k1 = 0, kk2 = 0, k3 = 0, k4 = 0;   // k^2 at rows t..t-4
-        RowIn<T, TQ> cur, nxt;
+        RowIn<T, TQ> cur, n1, n2;
         load_row<T, TQ, true, false>(cur, L, Lc, c, ix, u1, e, sl.f, y0 - 4);
+        load_row<T, TQ, true, false>(n1, L, Lc, c, ix, u1, e, sl.f, y0 - 3);
         for (int t = y0 - 4; t < yend + 4; ++t) {
-            load_row<T, TQ, true, false>(nxt, L, Lc, c, ix, u1, e, sl.f, t + 1);
+            load_row<T, TQ, true, false>(n2, L, Lc, c, ix, u1, e, sl.f, t + 2);
             a2 = a1;
             a1 = a0;
             a0 = u2_of(cur, ix);
@@ -280,7 +283,8 @@ __global__ void __launch_bounds__(MW) k_mg_gram(const CycleArgs a, cx<double>* p
             v = row_apply<T>(L, c, d5, d4, d3, t - 4, k4);
             const int yr = t - 4;
             if (c.own && yr >= y0 && yr < yend) gram_add<T>(g, b4, c4, d4, L.sinv * v);
-            cur = nxt;
+            cur = n1;
+            n1 = n2;
         }
     } else {
         // q0 rows t..t-3; q1 rows t-1..t-3; q2 rows t-2..t-4
@@ -291,7 +295,7 @@ __global__ void __launch_bounds__(MW) k_mg_gram(const CycleArgs a, cx<double>* p
         cx<T> b1 = Z, b2 = Z, b3 = Z;
         cx<T> c2 = Z, c3 = Z, c4 = Z;
         T k0 = 0, k1 = 0, kk2 = 0, k3 = 0;
-        RowIn<T, TQ> cur, nxt;
+        RowIn<T, TQ> cur, n1, n2;
         auto ld = [&](RowIn<T, TQ>& r, int y) {
             if (q0buf)
                 load_row<T, TQ, false, true>(r, L, Lc, c, ix, nullptr, nullptr, src, y);
@@ -299,8 +303,9 @@ __global__ void __launch_bounds__(MW) k_mg_gram(const CycleArgs a, cx<double>* p
                 load_row<T, TQ, false, false>(r, L, Lc, c, ix, nullptr, nullptr, src, y);
         };
         ld(cur, y0 - 3);
+        ld(n1, y0 - 2);
         for (int t = y0 - 3; t < yend + 3; ++t) {
-            ld(nxt, t + 1);
+            ld(n2, t + 2);
             a3 = a2;
             a2 = a1;
             a1 = a0;
@@ -320,7 +325,8 @@ __global__ void __launch_bounds__(MW) k_mg_gram(const CycleArgs a, cx<double>* p
             v = row_apply<T>(L, c, c4, c3, c2, t - 3, k3);
             const int yr = t - 3;
             if (c.own && yr >= y0 && yr < yend) gram_add<T>(g, a3, b3, c3, L.sinv * v);
-            cur = nxt;
+            cur = n1;
+            n1 = n2;
         }
     }
     cx<double>* P = part + (long long)slot * pstride * bstride;
@@ -374,7 +380,7 @@ __global__ void __launch_bounds__(MW) k_mg_apply_restrict(const CycleArgs a) {
     cx<T> r3 = Z, r4 = Z, r5 = Z;   // r1 at rows t-3, t-4, t-5
     cx<T> w0 = Z, w1 = Z, w2 = Z, w3 = Z;   // incoming iterate at rows t..t-3 (NZ)
     T k0 = 0, k1 = 0, kk2 = 0, k3 = 0;
-    RowIn<T, TQ> cur, nxt;
+    RowIn<T, TQ> cur, n1;
     auto ld = [&](RowIn<T, TQ>& r, int y) {
         if (q0buf)
             load_row<T, TQ, false, true>(r, L, Lc, c, ix, NZ ? up : nullptr, nullptr, src, y);
@@ -383,7 +389,7 @@ __global__ void __launch_bounds__(MW) k_mg_apply_restrict(const CycleArgs a) {
     };
     ld(cur, y0 - 3);
     for (int t = y0 - 3; t <= yend + 3; ++t) {
-        ld(nxt, t + 1);
+        ld(n1, t + 1);
         a3 = a2;
         a2 = a1;
         a1 = a0;
@@ -426,7 +432,7 @@ __global__ void __launch_bounds__(MW) k_mg_apply_restrict(const CycleArgs a) {
             const int C = (yc - 1) / 2, Cx = (c.gx - 1) / 2;
             fc[(long long)C * ncx + Cx] = T(0.25) * vl + T(0.5) * vv + T(0.25) * vr;
         }
-        cur = nxt;
+        cur = n1;
     }
 }
 
@@ -463,10 +469,10 @@ __global__ void __launch_bounds__(MW) k_mg_apply_out(const CycleArgs a) {
     cx<T> c2 = Z, c3 = Z, c4 = Z;
     cx<T> fprev = Z;
     T k0 = 0, k1 = 0, kk2 = 0, k3 = 0;
-    RowIn<T, TF> cur, nxt;
+    RowIn<T, TF> cur, n1;
     load_row<T, TF, true, false>(cur, L, Lc, c, ix, u1, e, sl.f, y0 - 3);
     for (int t = y0 - 3; t < yend + 3; ++t) {
-        load_row<T, TF, true, false>(nxt, L, Lc, c, ix, u1, e, sl.f, t + 1);
+        load_row<T, TF, true, false>(n1, L, Lc, c, ix, u1, e, sl.f, t + 1);
         a3 = a2;
         a2 = a1;
         a1 = a0;
@@ -496,7 +502,7 @@ __global__ void __launch_bounds__(MW) k_mg_apply_out(const CycleArgs a) {
             else
                 out[gi] = cvt<TO>(w);
         }
-        cur = nxt;
+        cur = n1;
     }
 }
 

@@ -1,6 +1,6 @@
 // The coarse tail of the V-cycle (Sec. 3.1) in one launch: every level of at
 // most TAIL_POINTS points, the coarsest direct solve and the way back up, one
-// 512-thread workgroup per right-hand side, passes separated by workgroup
+// 1024-thread workgroup per right-hand side, passes separated by workgroup
 // barriers.  On these levels a pass is a few points per thread, so the cost
 // of a cycle there is set by dependent steps, not bytes: one launch replaces
 // about six per level.  Smoothing is omega-Jacobi (Sec. 3.2.1) or one GMRES(3)
@@ -15,7 +15,7 @@ using namespace kc;
 
 namespace {
 
-constexpr int NTT = 512;
+constexpr int NTT = 1024;
 constexpr int PPT = TAIL_POINTS / NTT;   // points per thread on a tail level
 
 // out[p] = fn(p) for the level's points: every value first, then every store,
