@@ -262,6 +262,16 @@ def main():
                                        "last_ratio": [float(h[-1]) for h in hists]}
         log("omega-jacobi:", st, its)
         sj.close()
+        # comparator of Table 3 (MG-FGMRES): the cycle on -Delta - (1 + 0.5 i) k^2
+        # on every level, preconditioning the unshifted problem
+        L = s.num_levels
+        sc = mg.Solver(wl.n, wl.h, k2, ecs=wl.ecs, ecs_angle=wl.ecs_angle, sigma=[1 + 0.5j] * L, nrhs=NRHS,
+                       smoother=SMOOTHER)
+        st, its, hists, dtc = timed(sc, u, "gmres", 2000)
+        extra["fixed_shift_csl"] = {"sigma": "1+0.5i on every level", "status": st, "gmres_steps": its,
+                                    "seconds": round(dtc, 3), "Mdof_per_s": round(dofs / dtc / 1e6, 3)}
+        log("fixed-shift comparator:", st, its)
+        sc.close()
         extra["batched"] = batched(mg, W, torch, dev)
     s.close()
 

@@ -93,7 +93,15 @@ typedef struct mg_params {
     int ecs_hi[3];          /* ECS cells at the high end of each axis        */
     double ecs_angle;       /* rotation phi of the ECS contour (radians)     */
     const double *sigma;    /* host, 2 * nlevels doubles (re, im) of sigma_l,
-                               sigma[0] must be 1; NULL = default schedule   */
+                               the shifts of the cycle's level operators;
+                               NULL = default schedule (sigma_0 = 1).
+                               sigma_0 != 1 makes the cycle a fixed-shift
+                               preconditioner (the CSL-preconditioned
+                               comparator of Sec. 2.2 / Table 3 with sigma_l =
+                               1 + i beta on every level): residuals and
+                               Krylov steps keep the problem's operator
+                               (sigma = 1); standalone mode and mg_cycle then
+                               iterate u <- u + M (f - A u)                  */
     double theta_max;       /* default schedule sigma_l = exp(i l theta_max/L) */
     int nu1, nu2;           /* smoothing sweeps; this build supports 1, 1    */
     double omega[2];        /* complex Jacobi weight (re, im)                */
@@ -114,7 +122,7 @@ void mg_params_default(mg_params *p);
  * conjugate transpose.  k2_dev: n_x n_y n_z doubles on the device, copied
  * (the caller may free it after the call returns).  stream: a hipStream_t
  * (NULL = the null stream).  Errors: MG_E_INVAL for inconsistent dimensions,
- * sigma[0] != 1, unsupported nu1/nu2, nrhs < 1 or a coarsest level above
+ * unsupported nu1/nu2, nrhs < 1 or a coarsest level above
  * 1024 unknowns; MG_E_NOMEM; MG_E_DEVICE.  *out is NULL on error. */
 mg_status mg_setup(const mg_params *p, const double *k2_dev, void *stream,
                    mg_ctx **out);

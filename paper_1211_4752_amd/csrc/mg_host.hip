@@ -169,6 +169,8 @@ struct mg_ctx {
     cx<double>* lu[2] = {nullptr, nullptr};
     int* piv[2] = {nullptr, nullptr};
     LevelView<double>* views_d[2] = {nullptr, nullptr};   // device, one per level
+    LevelView<double>* outer_d[2] = {nullptr, nullptr};   // the unshifted level-0 operator (sigma = 1)
+    bool shifted0 = false;            // the cycle's level-0 shift differs from 1 (fixed-shift preconditioner)
     LevelView<float>* views_f[2] = {nullptr, nullptr};
     // level-0 work vectors, by rhs
     cx<double>* U1 = nullptr;
@@ -890,7 +892,7 @@ mg_status build_vec(Run& R, int dir, const std::vector<Item>& it, const std::vec
     for (int q = 0; q < a.st.n; ++q) {
         const Item& I = it[sub[q]];
         VecSlot& s = a.st.s[q];
-        s.lv = I.c->views_d[dir];
+        s.lv = I.c->outer_d[dir];
         s.block0 = blocks;
         const int nb = mg::vec_blocks(I.c->lv[0].N);
         if (nb > R.w->bstride) return MG_E_STATE;
@@ -1035,13 +1037,13 @@ mg_status solve_standalone(Run& R, int dir, const std::vector<Item>& it, const s
         for (int k : active) {
             sub.push_back(it[k]);
             mg_ctx* c = it[k].c;
-            if (!R.mixed)
+            if (!R.mixed && !c->shifted0)
                 l0.push_back(L0{F[k], 1.0, U[k], U[k]});
             else
                 l0.push_back(L0{c->W + (size_t)it[k].rhs * c->lv[0].N, 1.0, nullptr, U[k]});
         }
         std::vector<double> rho(sub.size(), 0.0);
-        if (!R.mixed) {
+        if (!R.mixed && !it[0].c->shifted0) {
             CKS(vcycle(R, dir, sub, l0, false, true));
             CK(hipStreamSynchronize(R.s));
             for (size_t q = 0; q < sub.size(); ++q) rho[q] = R.w->rtot_h[q];
@@ -1422,6 +1424,7 @@ void release(mg_ctx* c) {
         dfree(c->lu[d]);
         dfree(c->piv[d]);
         dfree(c->views_d[d]);
+        dfree(c->outer_d[d]);
         dfree(c->views_f[d]);
     }
     dfree(c->U1);
@@ -1482,6 +1485,12 @@ mg_status upload_views(mg_ctx* c) {
         }
         CKS(dalloc(&c->views_d[dir], vd.size() * sizeof(LevelView<double>)));
         CK(hipMemcpy(c->views_d[dir], vd.data(), vd.size() * sizeof(LevelView<double>), hipMemcpyHostToDevice));
+        LevelView<double> outer = vd[0];   // residuals and Krylov steps: the problem's own operator
+        outer.sigma = mg::mk(1.0, 0.0);
+        outer.lu = nullptr;
+        outer.piv = nullptr;
+        CKS(dalloc(&c->outer_d[dir], sizeof(LevelView<double>)));
+        CK(hipMemcpy(c->outer_d[dir], &outer, sizeof(LevelView<double>), hipMemcpyHostToDevice));
         if (c->mixed) {
             CKS(dalloc(&c->views_f[dir], vf.size() * sizeof(LevelView<float>)));
             CK(hipMemcpy(c->views_f[dir], vf.data(), vf.size() * sizeof(LevelView<float>), hipMemcpyHostToDevice));
@@ -1589,7 +1598,9 @@ mg_status setup(const mg_params* p, const double* k2_dev, void* stream, mg_ctx* 
         else
             c->lv[l].sigma = std::polar(1.0, l * p->theta_max / L);
     }
-    if (c->lv[0].sigma != cd(1.0, 0.0)) return MG_E_INVAL;
+    // sigma_0 != 1: a fixed-shift (comparator) preconditioner; the outer
+    // operator stays -Delta - k^2
+    c->shifted0 = c->lv[0].sigma != cd(1.0, 0.0);
 
     // coefficients of every level, forward and conjugate transpose
     for (int l = 0; l < L; ++l) {
@@ -1811,12 +1822,12 @@ mg_status mg_cycle(mg_ctx* c, double* u, const double* f, double* res_before) {
         it.push_back(Item{c, r});
         cx<double>* ur = (cx<double>*)u + (size_t)r * N;
         const cx<double>* fr = (const cx<double>*)f + (size_t)r * N;
-        if (!c->mixed)
+        if (!c->mixed && !c->shifted0)
             l0.push_back(L0{fr, 1.0, ur, ur});
         else
             l0.push_back(L0{c->W + (size_t)r * N, 1.0, nullptr, ur});
     }
-    if (!c->mixed) {
+    if (!c->mixed && !c->shifted0) {
         CKS(vcycle(R, 0, it, l0, false, res_before != nullptr));
         if (res_before) {
             CK(hipStreamSynchronize(c->stream));
@@ -1902,7 +1913,7 @@ mg_status mg_batch_create(mg_ctx* const* ctxs, int count, mg_batch** out) {
     for (int i = 0; i < count; ++i) {
         const mg_ctx* c = ctxs[i];
         if (!c || c->dim != ctxs[0]->dim || c->mixed != ctxs[0]->mixed || c->stream != ctxs[0]->stream ||
-            c->gsmooth != ctxs[0]->gsmooth)
+            c->gsmooth != ctxs[0]->gsmooth || c->shifted0 != ctxs[0]->shifted0)
             return MG_E_INVAL;
         for (int j = 0; j < i; ++j)
             if (ctxs[j] == c) return MG_E_INVAL;

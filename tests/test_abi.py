@@ -80,14 +80,6 @@ def test_setup_rejects_bad_dimensions():
     assert _setup(_params(), k2=0)[0] == mg.MG_E_INVAL
 
 
-def test_setup_rejects_shift_on_finest_level():
-    import numpy as np
-    sig = np.array([1.0, 0.1, 1.0, 0.0] + [1.0, 0.0] * 3)   # sigma_0 = 1 + 0.1i
-    p = _params()
-    p.sigma = sig.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
-    assert _setup(p)[0] == mg.MG_E_INVAL
-
-
 def test_null_handles():
     L = mg.lib()
     L.mg_destroy(None)
