@@ -139,6 +139,30 @@ def batched(mg, W, torch, dev):
             "max_steps": max(max(r) for r in its), "precision": "mixed"}
 
 
+# Table 5 of the paper: standalone level-dependent V(1,1) cycles with GMRES(3)
+# smoothing, constant k = 30 on n = 128 points, rtol 1e-7, d-theta = theta_max / 7.
+TABLE5_THETA_OVER_PI = [1 / 15, 1 / 12, 1 / 10, 1 / 8, 1 / 6, 1 / 5, 1 / 4]
+TABLE5_CYCLES = [27, 25, 23, 22, 22, 25, 28]
+
+
+def theta_sweep(mg, W, torch, dev):
+    """The theta_max sweep on the same k h and number of levels (255^2 grid,
+    64-cell layers inside it around the 128-point physical region)."""
+    wl = W.constant_2d(255, 30.0 / 128, ecs=64)
+    k2 = torch.tensor(wl.k2, dtype=torch.float64, device=dev)
+    f = torch.tensor(wl.f, dtype=torch.complex128, device=dev)
+    cycles = []
+    for tm in TABLE5_THETA_OVER_PI:
+        s = mg.Solver(wl.n, wl.h, k2, ecs=64, theta_max=tm * math.pi, nrhs=1, smoother=SMOOTHER)
+        u = s.empty()
+        st, its, _ = s.solve(u, f, mode="standalone", rtol=1e-7, maxit=200)
+        cycles.append(its[0] if st == "converged" else None)
+        s.close()
+    log("theta sweep:", cycles)
+    return {"theta_max_over_pi": [round(t, 4) for t in TABLE5_THETA_OVER_PI], "gpu_cycles": cycles,
+            "paper_cycles": TABLE5_CYCLES, "grid": "255x255, ECS 64, kh 30/128, 7 levels"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -273,6 +297,7 @@ def main():
         log("fixed-shift comparator:", st, its)
         sc.close()
         extra["batched"] = batched(mg, W, torch, dev)
+        extra["theta_sweep_table5"] = theta_sweep(mg, W, torch, dev)
     s.close()
 
     cpu = None
