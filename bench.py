@@ -163,6 +163,43 @@ def theta_sweep(mg, W, torch, dev):
             "paper_cycles": TABLE5_CYCLES, "grid": "255x255, ECS 64, kh 30/128, 7 levels"}
 
 
+# LVL-MG rows of Tables 6, 7 and 8 (Sec. 4.2 wedge in 2D and 3D, Sec. 4.3
+# ionization): standalone V(1,1) cycles with GMRES(3) smoothing, rtol 1e-7.
+TABLE6_CYCLES = [30, 47, 72, 83, 101]
+TABLE7_CYCLES = [38, 46, 50, 58, 71]
+TABLE8_CYCLES = [44, 83, 208, 149, 289]
+
+
+def paper_models(mg, W, torch, dev):
+    """Every case of the three tables on the paper's physical grids (plus
+    layers of a quarter of the x cell count outside the physical region)."""
+    rows = {}
+    cases = ([("wedge_2d_table6", W.wedge_2d(fz, c), p) for (fz, c), p in zip(W.WEDGE_2D_TABLE6, TABLE6_CYCLES)]
+             + [("wedge_3d_table7", W.wedge_3d(fz), p) for fz, p in zip(W.WEDGE_3D_TABLE7, TABLE7_CYCLES)]
+             + [("ionization_table8", W.ionization_2d(k0, c), p)
+                for (k0, c), p in zip(W.IONIZATION_TABLE8, TABLE8_CYCLES)])
+    for table, wl, paper in cases:
+        k2 = torch.tensor(wl.k2, dtype=torch.float64, device=dev)
+        f = torch.tensor(wl.f, dtype=torch.complex128, device=dev)
+        s = mg.Solver(wl.n, wl.h, k2, ecs=(wl.ecs_lo, wl.ecs_hi), ecs_angle=wl.ecs_angle,
+                      theta_max=wl.theta_max, nrhs=1, smoother=SMOOTHER)
+        u = s.empty()
+        s.solve(u, f, mode="standalone", rtol=1e-7, maxit=2)
+        u.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st, its, _ = s.solve(u, f, mode="standalone", rtol=1e-7, maxit=1000)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        nlev = s.num_levels
+        s.close()
+        rows.setdefault(table, []).append({"case": wl.name, "grid": "x".join(map(str, wl.n)),
+                                           "levels": nlev, "status": st, "gpu_cycles": its[0],
+                                           "paper_cycles": paper, "seconds": round(dt, 4)})
+        log("%s: %s %d cycles (paper %d), %.3f s" % (wl.name, st, its[0], paper, dt))
+    return rows
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -298,6 +335,7 @@ def main():
         sc.close()
         extra["batched"] = batched(mg, W, torch, dev)
         extra["theta_sweep_table5"] = theta_sweep(mg, W, torch, dev)
+        extra["paper_models"] = paper_models(mg, W, torch, dev)
     s.close()
 
     cpu = None

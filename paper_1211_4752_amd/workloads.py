@@ -126,10 +126,23 @@ class Workload:
     ecs: int              # complex-scaled cells on every side (0 = Dirichlet)
     ecs_angle: float = math.pi / 4
     theta_max: float = math.pi / 6
+    spacing: tuple | None = None   # grid spacing per axis (None: 1/(n+1))
+    sides: tuple | None = None     # ((lo per axis), (hi per axis)) ECS cells,
+                                   # overriding ``ecs`` when set
 
     @property
     def h(self):
+        if self.spacing is not None:
+            return tuple(self.spacing)
         return tuple(1.0 / (m + 1) for m in self.n)
+
+    @property
+    def ecs_lo(self):
+        return tuple(self.sides[0]) if self.sides else (self.ecs,) * len(self.n)
+
+    @property
+    def ecs_hi(self):
+        return tuple(self.sides[1]) if self.sides else (self.ecs,) * len(self.n)
 
     @property
     def dofs(self) -> int:
@@ -187,3 +200,95 @@ def batched_2d(n: int = 511, nrhs: int = 64, count: int = 24):
     medium as in heterogeneous_2d, plus ``count`` uneven constant-kh
     problems (uneven_batch)."""
     return [heterogeneous_2d(n, nrhs, source_seed=4)] + uneven_batch(count)
+
+
+
+# ---------------------------------------------------------------------------
+# Analytic models of Sec. 4.2 and 4.3
+# ---------------------------------------------------------------------------
+#
+# The grid holds the physical region plus the complex-scaled layers, as for
+# the unit-square workloads.  The paper gives the physical grid (its n_x x
+# n_y cells over Omega) but not the layers, so the physical spacing is kept
+# and layers are added outside Omega: a quarter of the x cell count on every
+# outgoing side, which makes every axis m 2^q - 1 interior points with
+# m in {3, 5}.  Coefficients inside a layer are the model's own formula
+# evaluated at the layer node's real coordinate (the wedge clamps the
+# coordinate into Omega first: its velocity is only defined there).
+
+WEDGE_X, WEDGE_Y = 600.0, 1000.0
+
+
+def wedge_velocity(x, y):
+    """Piecewise-constant velocity c(x, y) of the wedge model (Sec. 4.2):
+    2000 below the line y = x/6 + 400, 1500 between it and y = 800 - x/3,
+    3000 above."""
+    x = np.asarray(x, dtype=np.float64)
+    y = np.asarray(y, dtype=np.float64)
+    return np.where(y < x / 6.0 + 400.0, 2000.0,
+                    np.where(y < -x / 3.0 + 800.0, 1500.0, 3000.0))
+
+
+def _axis(cells: int, layer_lo: int, layer_hi: int, length: float):
+    """Interior-node count, spacing and the physical coordinate of every
+    interior node of an axis of ``cells`` physical cells over (0, length)
+    with ``layer_lo`` / ``layer_hi`` extra cells outside it."""
+    h = length / cells
+    n = cells + layer_lo + layer_hi - 1
+    x = (np.arange(n) + 1 - layer_lo) * h
+    return n, h, x
+
+
+def wedge_2d(f_hz: float, cells_x: int) -> Workload:
+    """2D wedge model (Sec. 4.2, Table 6): Omega = (0,600) x (0,1000) on
+    cells_x x 2 cells_x physical cells, k^2 = (2 pi f / c)^2, unit point
+    source at (300, 0), ECS layers of cells_x / 4 cells on all four sides."""
+    L = cells_x // 4
+    nx, hx, x = _axis(cells_x, L, L, WEDGE_X)
+    ny, hy, y = _axis(2 * cells_x, L, L, WEDGE_Y)
+    X, Y = np.meshgrid(np.clip(x, 0, WEDGE_X), np.clip(y, 0, WEDGE_Y))
+    k2 = (2.0 * math.pi * f_hz / wedge_velocity(X, Y)) ** 2
+    src = (int(round(300.0 / hx)) + L - 1, L - 1)       # node at (300, 0)
+    return Workload("wedge_2d_%dhz_%dx%d" % (round(f_hz), cells_x, 2 * cells_x), (nx, ny), k2,
+                    point_sources((nx, ny), [src]), ecs=L, spacing=(hx, hy),
+                    sides=((L, L), (L, L)))
+
+
+def wedge_3d(f_hz: float, cells_x: int = 64) -> Workload:
+    """3D wedge model (Sec. 4.2, Table 7): the third axis z repeats the x
+    axis (0, 600) and the velocity does not depend on z; unit source at
+    (300, 0, 300); layers of cells_x / 4 cells on all six sides."""
+    L = cells_x // 4
+    nx, hx, x = _axis(cells_x, L, L, WEDGE_X)
+    ny, hy, y = _axis(2 * cells_x, L, L, WEDGE_Y)
+    X, Y = np.meshgrid(np.clip(x, 0, WEDGE_X), np.clip(y, 0, WEDGE_Y))
+    k2_xy = (2.0 * math.pi * f_hz / wedge_velocity(X, Y)) ** 2
+    k2 = np.ascontiguousarray(np.broadcast_to(k2_xy, (nx, ny, nx)))
+    c = int(round(300.0 / hx)) + L - 1
+    return Workload("wedge_3d_%dhz_%dx%dx%d" % (round(f_hz), cells_x, 2 * cells_x, cells_x),
+                    (nx, ny, nx), k2, point_sources((nx, ny, nx), [(c, L - 1, c)]), ecs=L,
+                    spacing=(hx, hy, hx), sides=((L,) * 3, (L,) * 3))
+
+
+IONIZATION_R = 50.0
+
+
+def ionization_2d(k0: float, cells: int) -> Workload:
+    """Quantum-mechanical ionization model (Sec. 4.3, Table 8): Omega =
+    (0, 50)^2 on cells^2 physical cells, k^2(x, y) = exp(-x^2) + exp(-y^2)
+    + k0^2, right-hand side chi = exp(-(x^2 + y^2)) at the nodes, u = 0 on
+    x = 0 and y = 0 (no layer there), ECS layers of cells / 4 cells beyond
+    x = 50 and y = 50."""
+    L = cells // 4
+    n, h, x = _axis(cells, 0, L, IONIZATION_R)
+    X, Y = np.meshgrid(x, x)
+    k2 = np.exp(-X * X) + np.exp(-Y * Y) + float(k0) ** 2
+    f = np.exp(-(X * X + Y * Y)).astype(np.complex128)[None]
+    return Workload("ionization_2d_k%g_%d" % (k0, cells), (n, n), k2, f, ecs=L,
+                    spacing=(h, h), sides=((0, 0), (L, L)))
+
+
+# (f, physical cells in x) of Table 6, f of Table 7 and (k0, cells) of Table 8
+WEDGE_2D_TABLE6 = [(10, 64), (20, 128), (30, 128), (40, 256), (50, 256)]
+WEDGE_3D_TABLE7 = [12, 14, 16, 18, 20]
+IONIZATION_TABLE8 = [(1, 128), (2, 256), (3, 256), (4, 512), (5, 512)]

@@ -141,6 +141,52 @@ def test_ecs_outgoing_wave_1d(kh):
     assert abs(u[2]) < 2 * decay * abs(u[j0])
 
 
+@pytest.mark.parametrize("kh", [0.5, 0.25])
+def test_ecs_one_sided_outgoing_wave_1d(kh):
+    """Dirichlet wall at x = 0 (no layer there), ECS layer at the far end:
+    by the image method the discrete solution in the physical region is
+    C (e^{i kappa h |m - m0|} - e^{i kappa h (m + m0)}), m the node number
+    counted from the wall, which vanishes at the wall and is outgoing beyond
+    the source."""
+    n, ecs = 255, 32
+    h = 1.0 / (n + 1)
+    k = kh / h
+    A = H.operator(H.Problem((n,), (h,), np.full(n, k * k), (0,), (ecs,), math.pi / 4))
+    j0 = 60
+    f = np.zeros(n, complex)
+    f[j0] = 1.0
+    u = spla.spsolve(A.tocsc(), f)
+    kap_h = math.acos(1 - kh * kh / 2)
+    C = 1j * h * h / (2 * math.sin(kap_h))
+    m, m0 = np.arange(n) + 1, j0 + 1
+    g = C * (np.exp(1j * kap_h * np.abs(m - m0)) - np.exp(1j * kap_h * (m + m0)))
+    phys = m < n + 1 - ecs
+    # the layer's O((kh)^2) reflection, relative to the amplitude 2 |C| of
+    # the two-wave solution
+    err = np.abs(u[phys] - g[phys]).max() / (2 * abs(C))
+    assert err < 0.2 * kh * kh
+    # the same problem with a wrong (mirror-free) Green's function is far off
+    g_free = C * np.exp(1j * kap_h * np.abs(m - m0))
+    assert np.abs(u[phys] - g_free[phys]).max() / abs(C) > 0.5
+
+
+def test_anisotropic_rectangular_eigenpairs():
+    """Per-axis sizes and spacings (the wedge and ionization grids): on
+    n_x x n_y points with spacings h_x != h_y, tensor sine modes are
+    eigenvectors with eigenvalue sum_a (4/h_a^2) sin^2(l_a pi / 2(n_a+1))
+    - sigma k^2."""
+    n, h = (11, 23), (0.3, 0.17)
+    k2, sigma = 40.0, np.exp(0.2j)
+    A = H.operator(H.Problem(n, h, np.full((n[1], n[0]), k2)), sigma)
+    for lx, ly in [(1, 1), (3, 17), (11, 2), (6, 23)]:
+        wx = np.sin(lx * np.arange(1, n[0] + 1) * math.pi / (n[0] + 1))
+        wy = np.sin(ly * np.arange(1, n[1] + 1) * math.pi / (n[1] + 1))
+        w = np.multiply.outer(wy, wx).ravel()
+        lam = (4 / h[0] ** 2 * math.sin(lx * math.pi / (2 * (n[0] + 1))) ** 2
+               + 4 / h[1] ** 2 * math.sin(ly * math.pi / (2 * (n[1] + 1))) ** 2 - sigma * k2)
+        np.testing.assert_allclose(A @ w, lam * w, rtol=0, atol=1e-12 * abs(lam) + 1e-10)
+
+
 def test_printed_dtheta_values():
     """Tables 1, 2 and 5 print d-theta = theta_max / p, p the number of levels
     of an n = 2^p interval grid coarsened down to one point."""
