@@ -168,17 +168,25 @@ def theta_sweep(mg, W, torch, dev):
 TABLE6_CYCLES = [30, 47, 72, 83, 101]
 TABLE7_CYCLES = [38, 46, 50, 58, 71]
 TABLE8_CYCLES = [44, 83, 208, 149, 289]
+# MG-FGMRES(10) rows: fixed-shift CSG cycles preconditioning FGMRES(10)
+TABLE6_FGMRES10 = [32, 58, 85, 107, 133]
+TABLE7_FGMRES10 = [35, 40, 47, 55, 62]
+TABLE8_FGMRES10 = [66, 140, 245, 250, 393]
 
 
 def paper_models(mg, W, torch, dev):
     """Every case of the three tables on the paper's physical grids (plus
-    layers of a quarter of the x cell count outside the physical region)."""
+    layers of a quarter of the x cell count outside the physical region):
+    LVL-MG, and the MG-FGMRES(10) comparator (sigma = 1 + 0.5 i on every
+    level, FGMRES restarted every 10 steps)."""
     rows = {}
-    cases = ([("wedge_2d_table6", W.wedge_2d(fz, c), p) for (fz, c), p in zip(W.WEDGE_2D_TABLE6, TABLE6_CYCLES)]
-             + [("wedge_3d_table7", W.wedge_3d(fz), p) for fz, p in zip(W.WEDGE_3D_TABLE7, TABLE7_CYCLES)]
-             + [("ionization_table8", W.ionization_2d(k0, c), p)
-                for (k0, c), p in zip(W.IONIZATION_TABLE8, TABLE8_CYCLES)])
-    for table, wl, paper in cases:
+    cases = ([("wedge_2d_table6", W.wedge_2d(fz, c), p, q)
+              for (fz, c), p, q in zip(W.WEDGE_2D_TABLE6, TABLE6_CYCLES, TABLE6_FGMRES10)]
+             + [("wedge_3d_table7", W.wedge_3d(fz), p, q)
+                for fz, p, q in zip(W.WEDGE_3D_TABLE7, TABLE7_CYCLES, TABLE7_FGMRES10)]
+             + [("ionization_table8", W.ionization_2d(k0, c), p, q)
+                for (k0, c), p, q in zip(W.IONIZATION_TABLE8, TABLE8_CYCLES, TABLE8_FGMRES10)])
+    for table, wl, paper, paper_fg in cases:
         k2 = torch.tensor(wl.k2, dtype=torch.float64, device=dev)
         f = torch.tensor(wl.f, dtype=torch.complex128, device=dev)
         s = mg.Solver(wl.n, wl.h, k2, ecs=(wl.ecs_lo, wl.ecs_hi), ecs_angle=wl.ecs_angle,
@@ -193,10 +201,22 @@ def paper_models(mg, W, torch, dev):
         dt = time.perf_counter() - t0
         nlev = s.num_levels
         s.close()
+        sc = mg.Solver(wl.n, wl.h, k2, ecs=(wl.ecs_lo, wl.ecs_hi), ecs_angle=wl.ecs_angle,
+                       sigma=[1 + 0.5j] * nlev, nrhs=1, smoother=SMOOTHER)
+        u.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        stc, itc, _ = sc.solve(u, f, mode="gmres", rtol=1e-7, maxit=2000, restart=10)
+        torch.cuda.synchronize()
+        dtc = time.perf_counter() - t0
+        sc.close()
         rows.setdefault(table, []).append({"case": wl.name, "grid": "x".join(map(str, wl.n)),
                                            "levels": nlev, "status": st, "gpu_cycles": its[0],
-                                           "paper_cycles": paper, "seconds": round(dt, 4)})
-        log("%s: %s %d cycles (paper %d), %.3f s" % (wl.name, st, its[0], paper, dt))
+                                           "paper_cycles": paper, "seconds": round(dt, 4),
+                                           "mg_fgmres10": {"status": stc, "gpu_steps": itc[0],
+                                                           "paper_steps": paper_fg, "seconds": round(dtc, 4)}})
+        log("%s: LVL-MG %s %d cycles (paper %d), %.3f s; MG-FGMRES(10) %s %d (paper %d), %.3f s"
+            % (wl.name, st, its[0], paper, dt, stc, itc[0], paper_fg, dtc))
     return rows
 
 

@@ -26,6 +26,7 @@ from oracle import cycle as C
 from oracle import helmholtz as H
 from paper_1211_4752_amd import workloads as W
 from test_gpu_parity import HIST_FLOOR, _compare_hist, diverge_index, drift, perturbed
+from test_gpu_smoother import check_fgmres
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -34,10 +35,10 @@ GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "paper_models.json")
 RTOL, MAXIT = 1e-7, 400
 
 
-def _paper(kind, key):
+def _paper(kind, key, row="lvl_mg"):
     t = json.load(open(GOLDEN))[kind]
     keys = t["f_hz"] if "f_hz" in t else t["k0"]
-    return t["lvl_mg"][keys.index(key)]
+    return t[row][keys.index(key)]
 
 
 CASES = {
@@ -89,3 +90,33 @@ def test_model_standalone(name):
     # the converged iterate meets the tolerance for the problem's operator
     A = levels[0].A
     assert np.linalg.norm(f0 - A @ got) <= 1.01 * RTOL * np.linalg.norm(f0)
+
+
+@pytest.mark.parametrize("name", ["wedge2d_10hz", "ionization_k1"])
+def test_model_fixed_shift_fgmres10(name):
+    """The comparator rows MG-FGMRES(10) of Tables 6 and 8: the cycle on
+    -Delta - (1 + 0.5 i) k^2 on every level preconditioning FGMRES(10) on the
+    unshifted problem, against the oracle's flexible GMRES(10)."""
+    from paper_1211_4752_amd import mg
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    print("case", name, "fixed shift FGMRES(10)", flush=True)
+    make, (table, key) = CASES[name]
+    wl = make()
+    prob = H.Problem(wl.n, wl.h, wl.k2, wl.ecs_lo, wl.ecs_hi, wl.ecs_angle)
+    L = H.auto_levels(prob.n)
+    sig = np.full(L, 1 + 0.5j)
+    levels = H.build_hierarchy(prob, sigma=sig)
+    k2 = torch.tensor(wl.k2, dtype=torch.float64, device="cuda:0")
+    s = mg.Solver(wl.n, wl.h, k2, ecs=(wl.ecs_lo, wl.ecs_hi), ecs_angle=wl.ecs_angle, sigma=sig,
+                  nrhs=1, smoother="gmres3")
+    u = s.empty()
+    f = torch.tensor(wl.f, dtype=torch.complex128, device="cuda:0")
+    st, its, hists = s.solve(u, f, mode="gmres", rtol=RTOL, maxit=MAXIT, restart=10)
+    s.close()
+    assert st == "converged"
+    vc = C.VCycle(levels, smoother="gmres")
+    it = check_fgmres(u[0].cpu().numpy().ravel(), hists[0], its[0], H.operator(prob), vc.precondition,
+                      wl.f[0].ravel(), RTOL, MAXIT, restart=10)
+    print("%s MG-FGMRES(10): paper %d, gpu %d, oracle %d"
+          % (name, _paper(table, key, "mg_fgmres10"), its[0], it), flush=True)
