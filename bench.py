@@ -48,7 +48,8 @@ MAXIT = 5000           # outer steps per solve before it is reported as not conv
 JACOBI_MAXIT = 2000    # capped omega-Jacobi GMRES(20) run reported in "extra"
 SMOOTHER = "gmres3"
 FINE_CLASSES = ["smooth_restrict_fine", "prolong_smooth_fine", "residual", "matvec_dot",
-                "update_dot", "update_norm", "combine", "smooth_power_fine", "smooth_gram_fine"]
+                "update_dot", "update_norm", "combine", "smooth_power_fine", "smooth_gram_fine",
+                "smooth_gram_post_fine"]
 
 
 def log(*a):

@@ -223,8 +223,10 @@ enum mg_kernel_class {
     MG_K_COMBINE = 9,               /* GMRES: t = V y */
     MG_K_OTHER = 10,
     MG_K_SMOOTH_POWER_FINE = 11,    /* GMRES(3) smoother, level 0: q_i = (A/s) q_{i-1} */
-    MG_K_SMOOTH_GRAM_FINE = 12,     /* GMRES(3) smoother, level 0: Gram partials of q_0..q_3 */
-    MG_K_NUM_CLASSES = 13
+    MG_K_SMOOTH_GRAM_FINE = 12,     /* GMRES(3) smoother, level 0, pre-smoothing: Gram
+                                       partials of q_0..q_3                          */
+    MG_K_SMOOTH_GRAM_POST_FINE = 13,/* the same after the coarse-grid correction     */
+    MG_K_NUM_CLASSES = 14
 };
 mg_status mg_profile(mg_ctx *c, int enable);
 mg_status mg_profile_read(mg_ctx *c, int which, double *total_ms,

@@ -227,7 +227,9 @@ hipError_t launch_prolong_smooth(int dim, bool f32, bool level0, bool zero, bool
                                  const CycleArgs& a, hipStream_t s);
 
 // number of workgroups a vector kernel uses for N points
-int vec_blocks(long long N);
+// Workgroups per slot of a vector launch over N points: about per points
+// per thread, between 1 and 1024.
+int vec_blocks(long long N, int per = 8);
 hipError_t launch_residual(int dim, const VecArgs& a, hipStream_t s);
 hipError_t launch_norm(const VecArgs& a, hipStream_t s);
 hipError_t launch_matvec_dot(int dim, int jmax, const VecArgs& a, hipStream_t s);

@@ -37,6 +37,8 @@ constexpr int HSTRIDE = MAX_RESTART + 1;     // per-slot stride of one set of do
 constexpr int TOT = 2 * HSTRIDE;             // per-slot totals: H1 | H2
 constexpr double DIVERGE = 1e8;
 constexpr long long AUTOTUNE_MIN_POINTS = 4096;
+constexpr int VEC_PER_DOT = 64;    // points per thread, Arnoldi dot passes
+constexpr int VEC_PER_NORM = 16;   // points per thread, Arnoldi norm pass
 
 #define CK(expr)                                        \
     do {                                                \
@@ -518,7 +520,8 @@ mg_status smooth_coef(Run& R, int d, int phase, const std::vector<Item>& it, con
         CK(mg::launch_sm_power(R.dim, R.mixed, fine, stage, sa, R.s));
         prof_end(R, pi);
     }
-    int pi = prof_begin(R, fine ? MG_K_SMOOTH_GRAM_FINE : MG_K_COARSE_LEVELS, n * (q0b + 2.0 * ct + sk));
+    const int gcls = phase ? MG_K_SMOOTH_GRAM_POST_FINE : MG_K_SMOOTH_GRAM_FINE;
+    int pi = prof_begin(R, fine ? gcls : MG_K_COARSE_LEVELS, n * (q0b + 2.0 * ct + sk));
     CK(mg::launch_sm_gram(R.dim, R.mixed, fine, sa, R.s));
     prof_end(R, pi);
     mg::SmCoefArgs ca{};
@@ -656,7 +659,7 @@ mg_status post_fused_2d(Run& R, int dir, const std::vector<Item>& it, const std:
         ba += c->lv[d].N * (ct + fb + sk + fb + (d == 0 && acc ? 16.0 : 0.0)) + c->lv[d + 1].N * ct;
     }
     a.st.ntiles = tiles;
-    int pi = prof_begin(R, d == 0 ? MG_K_SMOOTH_GRAM_FINE : MG_K_COARSE_LEVELS, bg);
+    int pi = prof_begin(R, d == 0 ? MG_K_SMOOTH_GRAM_POST_FINE : MG_K_COARSE_LEVELS, bg);
     CK(mg::launch_sm2_gram(R.mixed, d == 0, true, shape, a, R.w->part, HSTRIDE, R.w->bstride, R.s));
     prof_end(R, pi);
     CKS(coef_from_tiles(R, d, 1, it, sub, a));
@@ -1232,7 +1235,23 @@ mg_status solve_gmres(Run& R, int dir, const std::vector<Item>& it, const std::v
                 nvsum += 16.0 * c->lv[0].N * (gs[k].j + 1);
                 vb += 16.0 * c->lv[0].N;
             }
+            // Workgroups per pass: the two dot passes hold up to 2 (j+1)
+            // complex values per thread and run at 2 waves per SIMD, so one
+            // round of 64-point-per-thread workgroups fills the chip for the
+            // 8-rhs batch; the lighter norm pass wants more, smaller ones.
+            // The split depends on N only, so a batched solve reduces in the
+            // same order as a single one.
+            auto split = [&](int per) {
+                int blocks = 0;
+                for (int q = 0; q < a.st.n; ++q) {
+                    cnt[q] = mg::vec_blocks(it[act[g[q]]].c->lv[0].N, per);
+                    a.st.s[q].block0 = blocks;
+                    blocks += cnt[q];
+                }
+                a.st.nblocks = blocks;
+            };
             // pass 1: w = A z, h1 = V^H w; reads z, k^2, V_0..V_j, writes w
+            split(VEC_PER_DOT);
             int pi = prof_begin(R, MG_K_MATVEC_DOT, nvsum + 2.0 * vb + 0.5 * vb);
             CK(mg::launch_matvec_dot(R.dim, jmax, a, R.s));
             prof_end(R, pi);
@@ -1243,6 +1262,7 @@ mg_status solve_gmres(Run& R, int dir, const std::vector<Item>& it, const std::v
             prof_end(R, pi);
             CKS(reduce_complex(R, a.st.n, cnt, jmax, HSTRIDE));
             // pass 3: V_{j+1} = w - V h2, ||V_{j+1}||^2
+            split(VEC_PER_NORM);
             for (int q = 0; q < a.st.n; ++q) a.st.s[q].hin = R.w->tot + (size_t)q * TOT + HSTRIDE;
             pi = prof_begin(R, MG_K_UPDATE_NORM, nvsum + 2.0 * vb);
             CK(mg::launch_update_norm(jmax, a, R.s));

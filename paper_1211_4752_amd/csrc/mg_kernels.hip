@@ -398,16 +398,26 @@ __global__ void __launch_bounds__(NT) k_matvec_dot(const VecArgs a) {
 #pragma unroll
     for (int i = 0; i < MAXJ; ++i) acc[i] = mk(0.0, 0.0);
     const int nx = L.n[0], ny = L.n[1];
-    for (int p = q.lo + (int)threadIdx.x; p < q.hi; p += NT) {
-        const int gx = p % nx;
-        const int rr = p / nx;
-        const int gy = rr % ny;
-        const int gz = rr / ny;
+    // grid coordinates of p, carried forward by NT points per iteration
+    int p = q.lo + (int)threadIdx.x;
+    int gx = p % nx, gy = (p / nx) % ny, gz = p / nx / ny;
+    for (; p < q.hi; p += NT) {
+        // the basis loads do not depend on the stencil: issue them first
+        cx<double> vv[MAXJ];
+#pragma unroll
+        for (int i = 0; i < MAXJ; ++i) vv[i] = (i < nv) ? V[(long long)i * N + p] : mk(0.0, 0.0);
         const cx<double> wv = apply_at<D>(L, z, p, gx, gy, gz);
         w[p] = wv;
 #pragma unroll
-        for (int i = 0; i < MAXJ; ++i)
-            if (i < nv) acc[i] = acc[i] + cmulc(V[(long long)i * N + p], wv);
+        for (int i = 0; i < MAXJ; ++i) acc[i] = acc[i] + cmulc(vv[i], wv);
+        gx += NT;
+        while (gx >= nx) {
+            gx -= nx;
+            if (++gy == ny) {
+                gy = 0;
+                ++gz;
+            }
+        }
     }
 #pragma unroll
     for (int i = 0; i < MAXJ; ++i)
@@ -649,8 +659,8 @@ hipError_t launch_prolong_smooth(int dim, bool f32, bool level0, bool zero, bool
                : ps_launch<float, double, double, true, false>(dim, shape, a, s);
 }
 
-int vec_blocks(long long N) {
-    long long b = (N + NT * 8 - 1) / (NT * 8);
+int vec_blocks(long long N, int per) {
+    long long b = (N + (long long)NT * per - 1) / ((long long)NT * per);
     if (b > 1024) b = 1024;
     if (b < 1) b = 1;
     return (int)b;

@@ -27,7 +27,7 @@ MODES = {"standalone": MODE_STANDALONE, "gmres": MODE_GMRES, "fgmres": MODE_FGMR
 KERNEL_CLASSES = [
     "smooth_restrict_fine", "prolong_smooth_fine", "coarse_levels", "coarsest_solve",
     "residual", "matvec_dot", "update_dot", "update_norm", "reduce", "combine", "other",
-    "smooth_power_fine", "smooth_gram_fine",
+    "smooth_power_fine", "smooth_gram_fine", "smooth_gram_post_fine",
 ]
 
 # every symbol include/mg.h declares
