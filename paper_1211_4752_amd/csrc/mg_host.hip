@@ -1235,9 +1235,9 @@ mg_status solve_gmres(Run& R, int dir, const std::vector<Item>& it, const std::v
                 nvsum += 16.0 * c->lv[0].N * (gs[k].j + 1);
                 vb += 16.0 * c->lv[0].N;
             }
-            // Workgroups per pass: the two dot passes hold up to 2 (j+1)
-            // complex values per thread and run at 2 waves per SIMD, so one
-            // round of 64-point-per-thread workgroups fills the chip for the
+            // Workgroups per pass: the two dot passes hold 2 (j+1) complex
+            // values per thread and run at 1-2 waves per SIMD, so a round or
+            // two of 64-point-per-thread workgroups fills the chip for the
             // 8-rhs batch; the lighter norm pass wants more, smaller ones.
             // The split depends on N only, so a batched solve reduces in the
             // same order as a single one.
