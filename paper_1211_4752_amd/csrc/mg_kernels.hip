@@ -476,10 +476,12 @@ __global__ void __launch_bounds__(NT) k_update_norm(const VecArgs a) {
     cx<double>* vout = V + (long long)nv * N;
     double nrm = 0.0;
     for (int p = q.lo + (int)threadIdx.x; p < q.hi; p += NT) {
+        cx<double> vv[MAXJ];
+#pragma unroll
+        for (int i = 0; i < MAXJ; ++i) vv[i] = (i < nv) ? V[(long long)i * N + p] : mk(0.0, 0.0);
         cx<double> wv = w[p];
 #pragma unroll
-        for (int i = 0; i < MAXJ; ++i)
-            if (i < nv) wv = wv - coef[i] * V[(long long)i * N + p];
+        for (int i = 0; i < MAXJ; ++i) wv = wv - coef[i] * vv[i];
         vout[p] = wv;
         nrm += abs2(wv);
     }
