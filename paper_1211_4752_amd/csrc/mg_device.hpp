@@ -230,6 +230,10 @@ hipError_t launch_prolong_smooth(int dim, bool f32, bool level0, bool zero, bool
 // Workgroups per slot of a vector launch over N points: about per points
 // per thread, between 1 and 1024.
 int vec_blocks(long long N, int per = 8);
+// Workgroups per slot of the matvec-dot pass on an n[0] x n[1] (x n[2]) grid:
+// 2D: column blocks of NT times row strips of about per rows; 3D: as
+// vec_blocks.
+int mv_blocks(int dim, const int n[3], int per);
 hipError_t launch_residual(int dim, const VecArgs& a, hipStream_t s);
 hipError_t launch_norm(const VecArgs& a, hipStream_t s);
 hipError_t launch_matvec_dot(int dim, int jmax, const VecArgs& a, hipStream_t s);

@@ -1241,28 +1241,32 @@ mg_status solve_gmres(Run& R, int dir, const std::vector<Item>& it, const std::v
             // 8-rhs batch; the lighter norm pass wants more, smaller ones.
             // The split depends on N only, so a batched solve reduces in the
             // same order as a single one.
-            auto split = [&](int per) {
+            auto split = [&](int per, bool mv) -> mg_status {
                 int blocks = 0;
                 for (int q = 0; q < a.st.n; ++q) {
-                    cnt[q] = mg::vec_blocks(it[act[g[q]]].c->lv[0].N, per);
+                    const Level& l0 = it[act[g[q]]].c->lv[0];
+                    cnt[q] = mv ? mg::mv_blocks(R.dim, l0.n, per) : mg::vec_blocks(l0.N, per);
+                    if (cnt[q] > R.w->bstride) return MG_E_STATE;
                     a.st.s[q].block0 = blocks;
                     blocks += cnt[q];
                 }
                 a.st.nblocks = blocks;
+                return MG_OK;
             };
             // pass 1: w = A z, h1 = V^H w; reads z, k^2, V_0..V_j, writes w
-            split(VEC_PER_DOT);
+            CKS(split(VEC_PER_DOT, true));
             int pi = prof_begin(R, MG_K_MATVEC_DOT, nvsum + 2.0 * vb + 0.5 * vb);
             CK(mg::launch_matvec_dot(R.dim, jmax, a, R.s));
             prof_end(R, pi);
             CKS(reduce_complex(R, a.st.n, cnt, jmax, 0));
             // pass 2: w -= V h1, h2 = V^H w
+            CKS(split(VEC_PER_DOT, false));
             pi = prof_begin(R, MG_K_UPDATE_DOT, nvsum + 2.0 * vb);
             CK(mg::launch_update_dot(jmax, a, R.s));
             prof_end(R, pi);
             CKS(reduce_complex(R, a.st.n, cnt, jmax, HSTRIDE));
             // pass 3: V_{j+1} = w - V h2, ||V_{j+1}||^2
-            split(VEC_PER_NORM);
+            CKS(split(VEC_PER_NORM, false));
             for (int q = 0; q < a.st.n; ++q) a.st.s[q].hin = R.w->tot + (size_t)q * TOT + HSTRIDE;
             pi = prof_begin(R, MG_K_UPDATE_NORM, nvsum + 2.0 * vb);
             CK(mg::launch_update_norm(jmax, a, R.s));
@@ -1772,6 +1776,7 @@ mg_status setup(const mg_params* p, const double* k2_dev, void* stream, mg_ctx* 
             maxt = std::max(maxt, nt[0] * nt[1]);
         }
     }
+    maxt = std::max(maxt, mg::mv_blocks(c->dim, c->lv[0].n, VEC_PER_DOT));
     CKS(work_alloc(c->work, c->nrhs, std::max(maxt, mg::vec_blocks(c->lv[0].N))));
     CKS(dalloc(&c->scale_d, (size_t)c->nrhs * HSTRIDE * sizeof(double)));
     CKS(dalloc(&c->coef_d, (size_t)c->nrhs * HSTRIDE * sizeof(cx<double>)));

@@ -398,6 +398,47 @@ __global__ void __launch_bounds__(NT) k_matvec_dot(const VecArgs a) {
 #pragma unroll
     for (int i = 0; i < MAXJ; ++i) acc[i] = mk(0.0, 0.0);
     const int nx = L.n[0], ny = L.n[1];
+    if constexpr (D == 2) {
+        // Column marching: workgroup b owns NT consecutive columns of a strip
+        // of rows (b = row strip * ncb + column block); each thread walks
+        // down its column keeping the rows above, at and below in registers,
+        // so every z value is fetched once.  The host sizes the launch with
+        // mv_blocks(), i.e. nb = ncb * (number of row strips).
+        const int ncb = (nx + NT - 1) / NT;
+        const int nrs = q.nb / ncb;
+        const int rows = (ny + nrs - 1) / nrs;
+        const int gx = (q.b % ncb) * NT + (int)threadIdx.x;
+        const int y0 = (q.b / ncb) * rows;
+        const int y1 = y0 + rows < ny ? y0 + rows : ny;
+        if (gx < nx && y0 < y1) {
+            const cx<double> zero = mk(0.0, 0.0);
+            cx<double> zm = y0 > 0 ? z[(y0 - 1) * nx + gx] : zero;
+            cx<double> zc = z[y0 * nx + gx];
+            for (int gy = y0; gy < y1; ++gy) {
+                const int p = gy * nx + gx;
+                cx<double> vv[MAXJ];
+#pragma unroll
+                for (int i = 0; i < MAXJ; ++i) vv[i] = (i < nv) ? V[(long long)i * N + p] : zero;
+                const cx<double> zp = gy + 1 < ny ? z[p + nx] : zero;
+                // same terms in the same order as apply_at<2>
+                cx<double> wv = diag_at<2>(L, gx, gy, 0, L.k2[p]) * zc;
+                if (gx > 0) wv = wv + L.cm[0][gx] * z[p - 1];
+                if (gx < nx - 1) wv = wv + L.cp[0][gx] * z[p + 1];
+                if (gy > 0) wv = wv + L.cm[1][gy] * zm;
+                if (gy < ny - 1) wv = wv + L.cp[1][gy] * zp;
+                w[p] = wv;
+#pragma unroll
+                for (int i = 0; i < MAXJ; ++i) acc[i] = acc[i] + cmulc(vv[i], wv);
+                zm = zc;
+                zc = zp;
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < MAXJ; ++i)
+            if (i < nv) acc[i] = sl.scale[i] * acc[i];
+        block_sum_vec<MAXJ>(acc, nv, sm, a.part + (long long)q.slot * a.pstride * a.bstride, a.bstride, q.b);
+        return;
+    }
     // grid coordinates of p, carried forward by NT points per iteration
     int p = q.lo + (int)threadIdx.x;
     int gx = p % nx, gy = (p / nx) % ny, gz = p / nx / ny;
@@ -659,6 +700,12 @@ hipError_t launch_prolong_smooth(int dim, bool f32, bool level0, bool zero, bool
     if (!level0) return ps_launch<float, float, float, true, false>(dim, shape, a, s);
     return acc ? ps_launch<float, double, double, true, true>(dim, shape, a, s)
                : ps_launch<float, double, double, true, false>(dim, shape, a, s);
+}
+
+int mv_blocks(int dim, const int n[3], int per) {
+    if (dim != 2) return vec_blocks((long long)n[0] * n[1] * n[2], per);
+    const int ncb = (n[0] + NT - 1) / NT;
+    return ncb * ((n[1] + per - 1) / per);
 }
 
 int vec_blocks(long long N, int per) {
