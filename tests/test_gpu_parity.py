@@ -389,3 +389,28 @@ def test_full_size_cycle_and_gmres_prefix():
     x, hist, it, st = K.gmres(levels[0].A, vc.precondition, wl.f[3].ravel(), rtol=1e-6, restart=20, maxit=12)
     _compare_hist(hists[3], hist, 1e-8)
     s.close()
+
+
+def test_matvec_column_blocks_ragged():
+    """The 2D Arnoldi matvec pass splits the grid into 256-column blocks and
+    row strips: on 287 x 143 the second column block holds 31 columns and
+    the three strips 48, 48 and 47 rows.  GMRES with the omega-Jacobi cycle
+    against the oracle on that grid (anisotropic spacing, ECS layers)."""
+    s_mod = _mg()
+    n, h = (287, 143), (1.0 / 288, 1.0 / 144)
+    k2 = np.full((n[1], n[0]), 400.0)
+    rng = np.random.default_rng(11)
+    f = rng.standard_normal((1, n[1], n[0])) + 1j * rng.standard_normal((1, n[1], n[0]))
+    prob = H.Problem(n, h, k2, (8, 4), (8, 4), math.pi / 4)
+    s = s_mod.Solver(n, h, torch.tensor(k2, dtype=torch.float64, device=_dev()), ecs=((8, 4), (8, 4)),
+                     nrhs=1, smoother="jacobi")
+    say("matvec column blocks", n, "levels", s.num_levels)
+    u = s.empty()
+    status, its, hists = s.solve(u, gpu(f), mode="gmres", rtol=1e-7, maxit=400, restart=20)
+    s.close()
+    assert status == "converged"
+    vc = C.VCycle(H.build_hierarchy(prob))
+    A = H.operator(prob)
+    got = u.cpu().numpy()
+    it = check_gmres(got[0].ravel(), hists[0], its[0], A, vc.precondition, f[0].ravel(), 1e-7, 400)
+    say("matvec column blocks: gpu", its[0], "oracle", it)
