@@ -5,8 +5,12 @@
 // is one right-hand side of one problem (grid); it carries a pointer to the
 // device-resident descriptor of its level (LevelView) and the pointers of the
 // vectors it reads and writes, so one launch can serve right-hand sides of
-// grids of different sizes.  Slot lists are passed by value in the kernel
-// arguments.
+// grids of different sizes.  Slot tables live in device memory (any number of
+// slots per launch); the kernel arguments carry their address.  A slot may
+// carry a gate: a device flag that, when zero, makes the slot's workgroups
+// return at once, so that one recorded sequence of launches (replayed as a
+// HIP graph) serves right-hand sides whose iterations stop at different
+// steps.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -54,8 +58,11 @@ __host__ __device__ __forceinline__ cx<T> cdiv(cx<T> a, cx<T> d) {
 }
 
 // Limits.
-constexpr int MAX_SLOTS = 32;      // slots per launch
 constexpr int MAX_COARSE = 1024;   // unknowns of the coarsest direct solve
+constexpr int MAX_RESTART = 32;    // GMRES restart length
+constexpr int HSTRIDE = MAX_RESTART + 1;   // reduction values per slot
+
+__host__ __device__ __forceinline__ bool gated_off(const int* g) { return g && *g == 0; }
 
 // One level of one problem, in compute precision T, resident in device
 // memory.  The descriptors of a problem's levels are contiguous, finest
@@ -98,13 +105,14 @@ struct TailSlot {
     const SmoothBufs* sb;
     int nlev;                  // levels lt .. coarsest
     int pad_;
+    const int* gate;
 };
 
 struct TailArgs {
     int n;
     int gmres;                 // smoother: 0 omega-Jacobi, 1 GMRES(3)
     double brk;                // relative Cholesky pivot of an exhausted Krylov space
-    TailSlot s[MAX_SLOTS];
+    const TailSlot* s;         // device table of n slots
 };
 constexpr int TAIL_POINTS = 4096;   // levels of at most this many points go to the tail
 
@@ -116,17 +124,24 @@ struct CycleSlot {
     void* u1;             // smoothed iterate buffer (standalone level 0) or null
     void* c;              // K_A: coarse right-hand side out; K_B: coarse correction in
     void* out;            // K_B: result; coarsest solve: correction out
-    double fscale;        // f is multiplied by this
+    double fscale;        // f is multiplied by this (unless fsp is set)
     int tile0;            // first logical tile of this slot in the launch
     int pad_;
     const SmoothBufs* sb; // GMRES(3) smoother buffers of this slot's rhs on the launch level
+    const double* fsp;    // device scale of f, overrides fscale when set
+    const int* gate;      // slot skipped when *gate == 0
 };
 
 struct CycleSlots {
     int n;
     int ntiles;           // total logical tiles of the launch
-    CycleSlot s[MAX_SLOTS];
+    const CycleSlot* s;   // device table of n slots, increasing tile0
 };
+
+template <typename S>
+__host__ __device__ __forceinline__ double fscale_of(const S& s) {
+    return s.fsp ? *s.fsp : s.fscale;
+}
 
 // Fused cycle kernels: slots, plus ||f - A u||^2 partials of the incoming
 // iterate (standalone level 0) at norm_part[slot * pstride + tile].
@@ -145,15 +160,17 @@ struct VecSlot {
     cx<double>* V;              // GMRES basis of this rhs: V_i at V + i N
     const double* scale;        // v_i = scale[i] V_i
     const cx<double>* coef;     // combine: t = sum_i coef[i] V_i
-    const cx<double>* hin;      // update passes: h_i at hin[i]
-    int j;                      // newest basis index
+    const cx<double>* hin;      // update pass: h_i at hin[i]
+    int j;                      // newest basis index (unless jp is set)
     int block0;                 // first workgroup of this slot in the launch
+    const int* jp;              // device newest basis index, overrides j when set
+    const int* gate;            // slot skipped when *gate == 0
 };
 
 struct VecSlots {
     int n;
     int nblocks;                // total workgroups of the launch
-    VecSlot s[MAX_SLOTS];
+    const VecSlot* s;           // device table of n slots, increasing block0
 };
 
 // Vector kernels: partial sums at part[(slot * pstride + i) * bstride + b],
@@ -174,7 +191,7 @@ struct ReduceArgs {
     cx<double>* out;
     double* rout;
     int nvals, pstride, bstride, ostride;
-    int cnt[MAX_SLOTS];
+    const int* cnt;             // device, one count per slot
 };
 
 // A slot of the pointwise passes of the GMRES(3) smoother.
@@ -186,12 +203,14 @@ struct SmSlot {
     double fscale;
     int block0;                 // first workgroup of this slot in the launch
     int pad_;
+    const double* fsp;          // device scale of f, overrides fscale when set
+    const int* gate;
 };
 
 struct SmSlots {
     int n;
     int nblocks;
-    SmSlot s[MAX_SLOTS];
+    const SmSlot* s;            // device table of n slots, increasing block0
 };
 
 // Pointwise smoother passes; Gram partials at part[(slot * pstride + v) *
@@ -204,13 +223,74 @@ struct SmArgs {
     int bstride;
 };
 
-// Gram reduction and coefficient solve: per slot, sum cnt[slot] partials in
-// a fixed order and write c1, c2, c3, (G00, 0) to coef[slot][0..3].
+// Gram reduction and coefficient solve: per slot, sum cnt partials in a
+// fixed order and write c1, c2, c3, (G00, 0) to coef[0..3].
+struct CoefSlot {
+    cx<double>* coef;
+    int cnt;
+    int pad_;
+    const int* gate;
+};
 struct SmCoefArgs {
     const cx<double>* part;
     int pstride, bstride;
-    int cnt[MAX_SLOTS];
-    cx<double>* coef[MAX_SLOTS];
+    const CoefSlot* s;          // device table, one per slot of the Gram launch
+};
+
+// ---------------------------------------------------------------------------
+// Krylov control on the device.  Per item (one right-hand side of one
+// problem): flags read back by the host once per restart cycle, and the
+// small dense state of restarted (F)GMRES: Hessenberg columns, Givens
+// rotations, the rotated right-hand side g and the Gram matrix of the
+// stored basis (used by the one-reduction second Gram-Schmidt pass).
+// ---------------------------------------------------------------------------
+struct GmFlags {
+    int live;      // 1: runs the next Arnoldi step / standalone cycle
+    int fin;       // 1: the restart cycle ends (solution update, new residual)
+    int zero;      // 1: zero right-hand side, solution 0
+    int state;     // 0 running, 1 converged, 2 maxit, 3 diverged
+    int its;       // outer steps (GMRES) or cycles (standalone) taken
+    int hlen;      // history entries written
+    int j;         // newest basis index (GMRES) / cycle counter (standalone)
+    int kk;        // index of the last basis vector combined at a restart
+};
+
+struct GmState {
+    cx<double> H[MAX_RESTART][MAX_RESTART + 1];     // H[col][row], rotated
+    cx<double> G[MAX_RESTART + 1][MAX_RESTART + 1]; // G[k][i] = <v_i, v_k>, i <= k
+    cx<double> h[MAX_RESTART + 1];                  // column of the step in progress
+    cx<double> g[MAX_RESTART + 1];
+    cx<double> sn[MAX_RESTART];
+    double cs[MAX_RESTART];
+    double nf;                                      // ||f||
+};
+
+// Solve parameters, device resident (uploaded once per solve).
+struct GmParams {
+    double rtol;
+    double* hist;      // [item][hstride] relative residual histories
+    int hstride;       // maxit + 1
+    int maxit;
+    int m;             // restart length
+    int flexible;
+};
+
+struct GmItem {
+    GmState* st;
+    GmFlags* fl;
+    double* scale;         // v_i = scale[i] V_i
+    cx<double>* coef;      // combination coefficients of a finished restart cycle
+    int cnt;               // partials of this item in the producing launch
+    int slot;              // slot of this item in the producing launch
+};
+
+struct GmArgs {
+    const GmItem* it;      // device table, one per workgroup
+    const GmParams* prm;
+    const cx<double>* part;
+    const double* rpart;
+    int pstride, bstride;
+    int j;                 // Arnoldi step of k_gm_h / k_gm_col
 };
 
 // ---------------------------------------------------------------------------
@@ -237,8 +317,11 @@ int mv_blocks(int dim, const int n[3], int per);
 hipError_t launch_residual(int dim, const VecArgs& a, hipStream_t s);
 hipError_t launch_norm(const VecArgs& a, hipStream_t s);
 hipError_t launch_matvec_dot(int dim, int jmax, const VecArgs& a, hipStream_t s);
-hipError_t launch_update_dot(int jmax, const VecArgs& a, hipStream_t s);
-hipError_t launch_update_norm(int jmax, const VecArgs& a, hipStream_t s);
+// V_{j+1} = w - sum_i hin_i v_i with partials <v_i, V_{j+1}> (i <= j) and
+// ||V_{j+1}||^2 (value j + 1)
+hipError_t launch_update_gram(int jmax, const VecArgs& a, hipStream_t s);
+// y = 0 for every slot that is not gated off
+hipError_t launch_vzero(const VecArgs& a, hipStream_t s);
 hipError_t launch_combine(int jmax, bool accumulate, const VecArgs& a, hipStream_t s);
 hipError_t launch_reduce(const ReduceArgs& a, int nslots, bool real, hipStream_t s);
 
@@ -262,6 +345,21 @@ hipError_t launch_sm2_apply_restrict(bool f32, bool level0, bool nonzero, int sh
 hipError_t launch_sm2_apply_out(bool f32, bool level0, bool accumulate, int shape, const CycleArgs& a, hipStream_t s);
 
 hipError_t launch_tail(int dim, bool f32, const TailArgs& a, hipStream_t s);
+
+// Krylov control kernels (mg_krylov.hip), one workgroup per item of a.it:
+//   gm_init     ||f|| from the norm partials; zero right-hand sides finish
+//               at once; histories set to -1
+//   gm_restart  (gated by fin) ||f - A x|| from the residual partials, stop
+//               tests, start of a restart cycle
+//   gm_h        (gated by live) h = (2 I - G) h1 from the matvec-dot partials
+//   gm_col      (gated by live) new basis norm and Gram column, Hessenberg
+//               column, Givens rotation, estimate, stop tests, and on a
+//               finished restart cycle the coefficients y = R^{-1} g
+//   sa_init     standalone: ||f||, zero right-hand sides, histories
+//   sa_step     standalone (gated by live): ratio of the incoming iterate
+//               from the norm partials, stop tests
+hipError_t launch_gm(int which, int nitems, const GmArgs& a, hipStream_t s);
+enum { GM_INIT = 0, GM_RESTART = 1, GM_H = 2, GM_COL = 3, SA_INIT = 4, SA_STEP = 5 };
 
 hipError_t launch_inject_k2(int dim, const double* fine, const int nf[3], double* coarse, const int nc[3],
                             hipStream_t s);

@@ -1,7 +1,9 @@
 // Host runtime of the level-dependent multigrid: hierarchy set-up, tile-shape
-// autotuning, the V-cycle driver (coarse part captured as a HIP graph), the
-// standalone and GMRES solvers over "items" (one right-hand side of one
-// problem), batches of problems, the adjoint, and the C ABI of include/mg.h.
+// and sweep-schedule autotuning, recorded operations (fixed launch sequences
+// with device-resident slot tables, replayed as HIP graphs), the standalone
+// and (F)GMRES solvers over "items" (one right-hand side of one problem) with
+// their control on the device, batches of problems, the adjoint, and the C
+// ABI of include/mg.h.
 //
 // Paper: Cools, Reps, Vanroose, "A new level-dependent coarse grid correction
 // scheme for indefinite Helmholtz problems" (NLAA 2013).
@@ -14,6 +16,7 @@
 #include <cstdint>
 #include <cstdio>
 #include <cstring>
+#include <functional>
 #include <map>
 #include <new>
 #include <vector>
@@ -32,13 +35,9 @@ using mg::VecSlot;
 
 namespace {
 
-constexpr int MAX_RESTART = 32;
-constexpr int HSTRIDE = MAX_RESTART + 1;     // per-slot stride of one set of dot results
-constexpr int TOT = 2 * HSTRIDE;             // per-slot totals: H1 | H2
-constexpr double DIVERGE = 1e8;
+using mg::HSTRIDE;
+using mg::MAX_RESTART;
 constexpr long long AUTOTUNE_MIN_POINTS = 4096;
-constexpr int VEC_PER_DOT = 64;    // points per thread, Arnoldi dot passes
-constexpr int VEC_PER_NORM = 16;   // points per thread, Arnoldi norm pass
 
 #define CK(expr)                                        \
     do {                                                \
@@ -139,22 +138,59 @@ struct Prof {
     size_t used = 0;
 };
 
-// Reduction work space and pinned mirrors.
+// Reduction work space and the device state of the Krylov control, for the
+// items (right-hand sides) of one context or one batch.
 struct Work {
-    cx<double>* part = nullptr;   // [(slot * HSTRIDE + i) * bstride + b]
+    cx<double>* part = nullptr;   // [(slot * HSTRIDE + v) * bstride + b]
     double* rpart = nullptr;      // [slot * bstride + b]
     int bstride = 0;
-    cx<double>* tot = nullptr;    // [slot * TOT + v]
-    double* rtot = nullptr;       // [slot]
-    cx<double>* tot_h = nullptr;  // pinned [item * TOT + v]
-    double* rtot_h = nullptr;     // pinned [item]
     int items = 0;
+    double* rtot = nullptr;       // [slot]: generic reductions
+    double* rtot_h = nullptr;     // pinned mirror
+    mg::GmState* gst = nullptr;   // [item]
+    mg::GmFlags* gfl = nullptr;   // [item]
+    mg::GmFlags* gfl_h = nullptr; // pinned mirror
+    mg::GmParams* prm = nullptr;  // device
+    mg::GmParams* prm_h = nullptr;// pinned
+    double* hist = nullptr;       // [item][hstride]
+    size_t hcap = 0;              // doubles
 };
 
-// Captured coarse parts of the V-cycle, keyed by direction and item list.
-struct GraphCache {
-    std::map<std::vector<uintptr_t>, hipGraphExec_t> execs;
-    hipStream_t capture = nullptr;    // private stream used only for capture
+// ---------------------------------------------------------------------------
+// Recorded operations.  An operation is a fixed sequence of kernel launches
+// whose slot tables are staged on the host while it is recorded and then
+// live in one device buffer; it runs either launch by launch or, captured
+// once, as a HIP graph.  Everything that changes from run to run (which
+// right-hand sides still iterate, step coefficients, scales) is read by the
+// kernels from device memory, so a recording stays valid.
+// ---------------------------------------------------------------------------
+constexpr int TAG_ALWAYS = -1;    // step runs for every item of the operation
+constexpr int TAG_FIN = -2;       // step of the end of a restart cycle
+
+struct ItemBytes {
+    int k;             // item
+    double base;       // algorithmic bytes of the launch for this item
+    double per;        // plus this many per Arnoldi step of the restart cycle
+};
+
+struct Step {
+    std::function<hipError_t(hipStream_t, const char*)> fn;
+    int cls;                      // profiling class
+    int tag;                      // TAG_ALWAYS, TAG_FIN or the step / cycle index
+    std::vector<ItemBytes> ib;
+};
+
+struct Op {
+    std::vector<char> tab;        // staged device tables
+    char* dtab = nullptr;
+    std::vector<Step> steps;
+    hipGraphExec_t exec = nullptr;
+    bool uploaded = false;
+};
+
+struct OpCache {
+    std::map<std::vector<uintptr_t>, Op*> ops;
+    hipStream_t capture = nullptr;   // private stream used only for capture
 };
 
 }  // namespace
@@ -189,19 +225,20 @@ struct mg_ctx {
     int lt = 1;                       // first level of the coarse tail (levels lt..L-1 in one launch)
     mg::SmoothBufs* sb_d = nullptr;   // [rhs * L + l]
     cx<double>* gcoef = nullptr;      // [(rhs * L + l) * 8]
-    double* scale_d = nullptr;     // [rhs * HSTRIDE + i]
-    double* scale_h = nullptr;     // pinned
-    cx<double>* coef_d = nullptr;  // [rhs * HSTRIDE + i]
-    cx<double>* coef_h = nullptr;  // pinned
+    double* scale_d = nullptr;        // [rhs * HSTRIDE + i]
+    cx<double>* coef_d = nullptr;     // [rhs * HSTRIDE + i]
+    int vper = 64;                    // points per thread of the Arnoldi passes (sweep schedule)
+    bool vtuned = false;
+    unsigned gen = 0;                 // bumped when buffers baked into recordings move
     Work work;
     Prof prof;
-    GraphCache graphs;
+    OpCache cache;
 };
 
 struct mg_batch {
     std::vector<mg_ctx*> ctxs;
     Work work;
-    GraphCache graphs;
+    OpCache cache;
 };
 
 namespace {
@@ -243,45 +280,79 @@ void hfree(P*& p) {
 mg_status work_alloc(Work& w, int items, int bstride) {
     w.items = items;
     w.bstride = bstride;
-    CKS(dalloc(&w.part, (size_t)mg::MAX_SLOTS * HSTRIDE * bstride * sizeof(cx<double>)));
-    CKS(dalloc(&w.rpart, (size_t)mg::MAX_SLOTS * bstride * sizeof(double)));
-    CKS(dalloc(&w.tot, (size_t)mg::MAX_SLOTS * TOT * sizeof(cx<double>)));
-    CKS(dalloc(&w.rtot, (size_t)mg::MAX_SLOTS * sizeof(double)));
-    CKS(halloc(&w.tot_h, (size_t)std::max(items, mg::MAX_SLOTS) * TOT * sizeof(cx<double>)));
-    CKS(halloc(&w.rtot_h, (size_t)std::max(items, mg::MAX_SLOTS) * sizeof(double)));
+    CKS(dalloc(&w.part, (size_t)items * HSTRIDE * bstride * sizeof(cx<double>)));
+    CKS(dalloc(&w.rpart, (size_t)items * bstride * sizeof(double)));
+    CKS(dalloc(&w.rtot, (size_t)items * sizeof(double)));
+    CKS(halloc(&w.rtot_h, (size_t)items * sizeof(double)));
+    CKS(dalloc(&w.gst, (size_t)items * sizeof(mg::GmState)));
+    CKS(dalloc(&w.gfl, (size_t)items * sizeof(mg::GmFlags)));
+    CKS(halloc(&w.gfl_h, (size_t)items * sizeof(mg::GmFlags)));
+    CKS(dalloc(&w.prm, sizeof(mg::GmParams)));
+    CKS(halloc(&w.prm_h, sizeof(mg::GmParams)));
     return MG_OK;
 }
 
 void work_free(Work& w) {
     dfree(w.part);
     dfree(w.rpart);
-    dfree(w.tot);
     dfree(w.rtot);
-    hfree(w.tot_h);
     hfree(w.rtot_h);
+    dfree(w.gst);
+    dfree(w.gfl);
+    hfree(w.gfl_h);
+    dfree(w.prm);
+    hfree(w.prm_h);
+    dfree(w.hist);
+    w.hcap = 0;
 }
 
-void graphs_free(GraphCache& g) {
-    for (auto& kv : g.execs) (void)hipGraphExecDestroy(kv.second);
-    g.execs.clear();
-    if (g.capture) (void)hipStreamDestroy(g.capture);
-    g.capture = nullptr;
+// History rows of every item (the stream must be idle).
+mg_status ensure_hist(Work& w, size_t doubles) {
+    if (w.hcap >= doubles) return MG_OK;
+    dfree(w.hist);
+    w.hcap = 0;
+    CKS(dalloc(&w.hist, doubles * sizeof(double)));
+    w.hcap = doubles;
+    return MG_OK;
 }
 
-// One solve invocation: where launches go and what they record.
-struct Run {
+void op_free(Op* op) {
+    if (!op) return;
+    if (op->exec) (void)hipGraphExecDestroy(op->exec);
+    dfree(op->dtab);
+    delete op;
+}
+
+void cache_clear(OpCache& c) {
+    for (auto& kv : c.ops) op_free(kv.second);
+    c.ops.clear();
+}
+
+void cache_free(OpCache& c) {
+    cache_clear(c);
+    if (c.capture) (void)hipStreamDestroy(c.capture);
+    c.capture = nullptr;
+}
+
+template <typename T>
+size_t put(Op& op, const std::vector<T>& v) {
+    const size_t off = (op.tab.size() + 255) & ~(size_t)255;
+    op.tab.resize(off + std::max<size_t>(1, v.size()) * sizeof(T));
+    if (!v.empty()) std::memcpy(op.tab.data() + off, v.data(), v.size() * sizeof(T));
+    return off;
+}
+
+// Where and how operations run.
+struct Exec {
     hipStream_t s;
     Prof* prof;
-    Work* w;
-    GraphCache* gc;
-    int dim;
-    bool mixed;
+    OpCache* cache;
+    bool graphs;
 };
 
-// bytes: algorithmic (compulsory) traffic of the launch
-int prof_begin(Run& R, int cls, double bytes = 0.0) {
-    if (!R.prof || !R.prof->on) return -1;
-    Prof& P = *R.prof;
+int prof_begin(Exec& E, int cls, double bytes) {
+    if (!E.prof || !E.prof->on) return -1;
+    Prof& P = *E.prof;
     while (P.pool.size() < 2 * (P.used + 1)) {
         hipEvent_t e;
         if (hipEventCreate(&e) != hipSuccess) return -1;
@@ -294,11 +365,113 @@ int prof_begin(Run& R, int cls, double bytes = 0.0) {
     }
     P.cls[idx] = cls;
     P.bytes[idx] = bytes;
-    (void)hipEventRecord(P.pool[2 * idx], R.s);
+    (void)hipEventRecord(P.pool[2 * idx], E.s);
     return idx;
 }
-void prof_end(Run& R, int idx) {
-    if (idx >= 0) (void)hipEventRecord(R.prof->pool[2 * idx + 1], R.s);
+void prof_end(Exec& E, int idx) {
+    if (idx >= 0) (void)hipEventRecord(E.prof->pool[2 * idx + 1], E.s);
+}
+
+double step_bytes(const Step& st, const std::vector<int>* live) {
+    double b = 0.0;
+    for (const ItemBytes& x : st.ib) {
+        const int n = live ? (*live)[x.k] : 0;
+        if (live) {
+            if (st.tag >= 0 && n <= st.tag) continue;
+            if (st.tag == TAG_FIN && n <= 0) continue;
+        }
+        b += x.base + x.per * n;
+    }
+    return b;
+}
+
+// Run op on E.s.  Profiling runs it launch by launch between HIP events;
+// the index of its first record is returned in *first (bytes are fixed up
+// by prof_fix once the caller knows which items iterated).
+mg_status op_run(Exec& E, Op& op, int* first = nullptr) {
+    if (first) *first = -1;
+    if (op.steps.empty()) return MG_OK;
+    if (!op.uploaded) {
+        if (!op.tab.empty()) {
+            CKS(dalloc(&op.dtab, op.tab.size()));
+            CK(hipMemcpy(op.dtab, op.tab.data(), op.tab.size(), hipMemcpyHostToDevice));
+        }
+        op.uploaded = true;
+    }
+    if (E.prof && E.prof->on) {
+        for (size_t i = 0; i < op.steps.size(); ++i) {
+            const Step& st = op.steps[i];
+            const int pi = prof_begin(E, st.cls, step_bytes(st, nullptr));
+            if (first && i == 0) *first = pi;
+            CK(st.fn(E.s, op.dtab));
+            prof_end(E, pi);
+        }
+        return MG_OK;
+    }
+    if (!E.graphs || !E.cache) {
+        for (const Step& st : op.steps) CK(st.fn(E.s, op.dtab));
+        return MG_OK;
+    }
+    if (!op.exec) {
+        if (!E.cache->capture) CK(hipStreamCreateWithFlags(&E.cache->capture, hipStreamNonBlocking));
+        hipStream_t cs = E.cache->capture;
+        CK(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+        hipError_t err = hipSuccess;
+        for (const Step& st : op.steps) {
+            err = st.fn(cs, op.dtab);
+            if (err != hipSuccess) break;
+        }
+        hipGraph_t g = nullptr;
+        const hipError_t e2 = hipStreamEndCapture(cs, &g);
+        if (err != hipSuccess || e2 != hipSuccess) {
+            if (g) (void)hipGraphDestroy(g);
+            return MG_E_DEVICE;
+        }
+        const hipError_t ei = hipGraphInstantiate(&op.exec, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        CK(ei);
+    }
+    CK(hipGraphLaunch(op.exec, E.s));
+    return MG_OK;
+}
+
+// Algorithmic bytes of a profiled run once the per-item counts of Arnoldi
+// steps (or cycles) are known.
+void prof_fix(Exec& E, const Op& op, int first, const std::vector<int>& live) {
+    if (first < 0 || !E.prof) return;
+    for (size_t i = 0; i < op.steps.size(); ++i) E.prof->bytes[first + i] = step_bytes(op.steps[i], &live);
+}
+
+template <typename F>
+mg_status cached(OpCache& cache, const std::vector<uintptr_t>& key, Op** out, F record) {
+    auto f = cache.ops.find(key);
+    if (f != cache.ops.end()) {
+        *out = f->second;
+        return MG_OK;
+    }
+    Op* op = new (std::nothrow) Op();
+    if (!op) return MG_E_NOMEM;
+    const mg_status st = record(*op);
+    if (st != MG_OK) {
+        op_free(op);
+        return st;
+    }
+    cache.ops.emplace(key, op);
+    *out = op;
+    return MG_OK;
+}
+
+// Recording context.
+struct Rec {
+    Op* op;
+    Work* w;
+    int dim;
+    bool mixed;
+    int tag;
+};
+
+void add(Rec& R, int cls, std::vector<ItemBytes> ib, std::function<hipError_t(hipStream_t, const char*)> fn) {
+    R.op->steps.push_back(Step{std::move(fn), cls, R.tag, std::move(ib)});
 }
 
 // One right-hand side of one problem.
@@ -307,10 +480,24 @@ struct Item {
     int rhs;
 };
 
+// Gates: which device flag of an item lets a slot run.
+enum Gate { G_NONE = 0, G_LIVE = 1, G_FIN = 2, G_ZERO = 3 };
+
+const int* gate_of(const Rec& R, int gk, int k) {
+    mg::GmFlags* f = R.w->gfl + k;
+    switch (gk) {
+        case G_LIVE: return &f->live;
+        case G_FIN: return &f->fin;
+        case G_ZERO: return &f->zero;
+        default: return nullptr;
+    }
+}
+
 // Level-0 inputs and outputs of one item's cycle.
 struct L0 {
     const void* f;            // right-hand side (complex double)
     double fs;                // scale applied to f
+    const double* fsp;        // device scale of f (overrides fs) or null
     const cx<double>* u;      // incoming iterate or null (zero guess)
     cx<double>* out;          // result (written, or accumulated)
 };
@@ -322,23 +509,16 @@ size_t elem(const mg_ctx* c) { return c->mixed ? sizeof(cx<float>) : sizeof(cx<d
 void* lvec(const mg_ctx* c, void* base, int l, int rhs) {
     return (char*)base + (size_t)rhs * c->lv[l].N * elem(c);
 }
-
-// Launch groups of at most MAX_SLOTS items each.
-template <typename F>
-mg_status for_groups(const std::vector<int>& idx, F fn) {
-    for (size_t g = 0; g < idx.size(); g += mg::MAX_SLOTS) {
-        const size_t n = std::min<size_t>(mg::MAX_SLOTS, idx.size() - g);
-        std::vector<int> sub(idx.begin() + g, idx.begin() + g + n);
-        CKS(fn(sub, (int)g));
-    }
-    return MG_OK;
+const mg::SmoothBufs* sbuf(const mg_ctx* c, int l, int rhs) { return c->sb_d + (size_t)rhs * c->L + l; }
+cx<double>* gcoef_of(const mg_ctx* c, int l, int rhs, int phase) {
+    return c->gcoef + ((size_t)rhs * c->L + l) * 8 + 4 * phase;
 }
 
 // Shape of a launch at depth d: the one tuned for the largest level in it.
-int launch_shape(const std::vector<Item>& it, const std::vector<int>& sub, int d) {
+int launch_shape(const std::vector<Item>& it, const std::vector<int>& who, int d) {
     long long best = -1;
     int shape = 0;
-    for (int k : sub) {
+    for (int k : who) {
         const Level& V = it[k].c->lv[d];
         if (V.N > best) {
             best = V.N;
@@ -348,301 +528,480 @@ int launch_shape(const std::vector<Item>& it, const std::vector<int>& sub, int d
     return shape;
 }
 
+std::vector<int> above_tail(const std::vector<Item>& it, int d) {
+    std::vector<int> who;
+    for (int k = 0; k < (int)it.size(); ++k)
+        if (d < it[k].c->lt) who.push_back(k);
+    return who;
+}
+
 // ---------------------------------------------------------------------------
 // V-cycle pieces (Sec. 3.1)
 // ---------------------------------------------------------------------------
 
-// K_A at depth d for the items that have a coarser level below d.  With norm
-// (level 0 with incoming iterates) ||f - A u||^2 of item k lands in
-// w->rtot_h[k] once the stream gets there.
-mg_status launch_ka(Run& R, int dir, const std::vector<Item>& it, const std::vector<L0>* l0, int d,
-                    bool norm) {
-    std::vector<int> who;
-    for (int k = 0; k < (int)it.size(); ++k)
-        if (d < it[k].c->lt) who.push_back(k);
+// K_A (omega-Jacobi) at depth d for the items that have a coarser level
+// below d.  With norm (level 0 with incoming iterates) the partials of
+// ||f - A u||^2 of item k land in rpart[k * bstride + tile], (*cnt)[k] tiles.
+mg_status rec_ka(Rec& R, int dir, const std::vector<Item>& it, int gk, const std::vector<L0>* l0, int d,
+                 bool norm, std::vector<int>* cnt) {
+    const std::vector<int> who = above_tail(it, d);
+    if (who.empty()) return MG_OK;
     const bool zero = !(d == 0 && l0 && (*l0)[0].u);
-    return for_groups(who, [&](const std::vector<int>& sub, int gbase) -> mg_status {
-        const int shape = launch_shape(it, sub, d);
-        CycleArgs a{};
-        a.st.n = (int)sub.size();
-        int tiles = 0;
-        double by = 0.0;
-        const double ct = R.mixed ? 8.0 : 16.0, sk = R.mixed ? 4.0 : 8.0;
-        for (int q = 0; q < a.st.n; ++q) {
-            const Item& I = it[sub[q]];
-            mg_ctx* c = I.c;
-            CycleSlot& s = a.st.s[q];
-            s.lv = view_ptr(c, dir, d);
-            if (d == 0) {
-                const L0& z = (*l0)[sub[q]];
-                s.f = z.f;
-                s.fscale = z.fs;
-                s.u = z.u;
-                s.u1 = z.u ? (void*)(c->U1 + (size_t)I.rhs * c->lv[0].N) : nullptr;
-            } else {
-                s.f = lvec(c, c->lv[d].F, d, I.rhs);
-                s.fscale = 1.0;
-            }
-            s.c = lvec(c, c->lv[d + 1].F, d + 1, I.rhs);
-            s.tile0 = tiles;
-            int nt[3];
-            mg::tile_counts(R.dim, shape, c->lv[d].n, nt);
-            tiles += nt[0] * nt[1] * nt[2];
-            by += c->lv[d].N * ((d == 0 ? 16.0 : ct) + sk) + c->lv[d + 1].N * ct;
-            if (!zero) by += c->lv[0].N * 2.0 * ct;
+    norm = norm && !zero;
+    if (norm && who.size() != it.size()) return MG_E_STATE;
+    const int shape = launch_shape(it, who, d);
+    const double ct = R.mixed ? 8.0 : 16.0, sk = R.mixed ? 4.0 : 8.0;
+    std::vector<mg::CycleSlot> sl(who.size());
+    std::vector<ItemBytes> ib;
+    if (cnt) cnt->assign(it.size(), 0);
+    int tiles = 0;
+    for (size_t q = 0; q < who.size(); ++q) {
+        const int k = who[q];
+        const Item& I = it[k];
+        mg_ctx* c = I.c;
+        mg::CycleSlot& s = sl[q];
+        s = mg::CycleSlot{};
+        s.lv = view_ptr(c, dir, d);
+        if (d == 0) {
+            const L0& z = (*l0)[k];
+            s.f = z.f;
+            s.fscale = z.fs;
+            s.fsp = z.fsp;
+            s.u = z.u;
+            s.u1 = z.u ? (void*)(c->U1 + (size_t)I.rhs * c->lv[0].N) : nullptr;
+        } else {
+            s.f = lvec(c, c->lv[d].F, d, I.rhs);
+            s.fscale = 1.0;
         }
-        a.st.ntiles = tiles;
-        a.norm_part = (norm && !zero) ? R.w->rpart : nullptr;
-        a.pstride = R.w->bstride;
-        const int pi = prof_begin(R, d == 0 ? MG_K_SMOOTH_RESTRICT_FINE : MG_K_COARSE_LEVELS, by);
-        CK(mg::launch_smooth_restrict(R.dim, R.mixed, d == 0, zero, shape, a, R.s));
-        prof_end(R, pi);
-        if (a.norm_part) {
-            ReduceArgs ra{};
-            ra.rpart = R.w->rpart;
-            ra.rout = R.w->rtot;
-            ra.bstride = R.w->bstride;
-            for (int q = 0; q < a.st.n; ++q) {
-                const int next = q + 1 < a.st.n ? a.st.s[q + 1].tile0 : tiles;
-                ra.cnt[q] = next - a.st.s[q].tile0;
-            }
-            const int pr = prof_begin(R, MG_K_REDUCE);
-            CK(mg::launch_reduce(ra, a.st.n, true, R.s));
-            prof_end(R, pr);
-            CK(hipMemcpyAsync(R.w->rtot_h + gbase, R.w->rtot, a.st.n * sizeof(double), hipMemcpyDeviceToHost,
-                              R.s));
-        }
-        return MG_OK;
+        s.c = lvec(c, c->lv[d + 1].F, d + 1, I.rhs);
+        s.gate = gate_of(R, gk, k);
+        s.tile0 = tiles;
+        int nt[3];
+        mg::tile_counts(R.dim, shape, c->lv[d].n, nt);
+        const int n = nt[0] * nt[1] * nt[2];
+        if (norm && n > R.w->bstride) return MG_E_STATE;
+        if (cnt) (*cnt)[k] = n;
+        tiles += n;
+        double by = c->lv[d].N * ((d == 0 ? 16.0 : ct) + sk) + c->lv[d + 1].N * ct;
+        if (!zero) by += c->lv[0].N * 2.0 * ct;
+        ib.push_back({k, by, 0.0});
+    }
+    mg::CycleArgs a{};
+    a.st.n = (int)sl.size();
+    a.st.ntiles = tiles;
+    a.norm_part = norm ? R.w->rpart : nullptr;
+    a.pstride = R.w->bstride;
+    const size_t off = put(*R.op, sl);
+    const int dim = R.dim;
+    const bool mixed = R.mixed;
+    add(R, d == 0 ? MG_K_SMOOTH_RESTRICT_FINE : MG_K_COARSE_LEVELS, ib, [=](hipStream_t s, const char* base) {
+        mg::CycleArgs b = a;
+        b.st.s = (const mg::CycleSlot*)(base + off);
+        return mg::launch_smooth_restrict(dim, mixed, d == 0, zero, shape, b, s);
     });
+    return MG_OK;
 }
 
-const mg::SmoothBufs* sbuf(const mg_ctx* c, int l, int rhs);
+// K_B (omega-Jacobi) at depth d.
+mg_status rec_kb(Rec& R, int dir, const std::vector<Item>& it, int gk, const std::vector<L0>* l0, int d, bool acc) {
+    const std::vector<int> who = above_tail(it, d);
+    if (who.empty()) return MG_OK;
+    const bool zero = !(d == 0 && l0 && (*l0)[0].u);
+    const int shape = launch_shape(it, who, d);
+    const double ct = R.mixed ? 8.0 : 16.0, sk = R.mixed ? 4.0 : 8.0;
+    std::vector<mg::CycleSlot> sl(who.size());
+    std::vector<ItemBytes> ib;
+    int tiles = 0;
+    for (size_t q = 0; q < who.size(); ++q) {
+        const int k = who[q];
+        const Item& I = it[k];
+        mg_ctx* c = I.c;
+        mg::CycleSlot& s = sl[q];
+        s = mg::CycleSlot{};
+        s.lv = view_ptr(c, dir, d);
+        if (d == 0) {
+            const L0& z = (*l0)[k];
+            s.f = z.f;
+            s.fscale = z.fs;
+            s.fsp = z.fsp;
+            s.u1 = z.u ? (void*)(c->U1 + (size_t)I.rhs * c->lv[0].N) : nullptr;
+            s.out = z.out;
+        } else {
+            s.f = lvec(c, c->lv[d].F, d, I.rhs);
+            s.fscale = 1.0;
+            s.out = lvec(c, c->lv[d].E, d, I.rhs);
+        }
+        s.c = lvec(c, c->lv[d + 1].E, d + 1, I.rhs);
+        s.gate = gate_of(R, gk, k);
+        s.tile0 = tiles;
+        int nt[3];
+        mg::tile_counts(R.dim, shape, c->lv[d].n, nt);
+        tiles += nt[0] * nt[1] * nt[2];
+        const double cf = d == 0 ? 16.0 : ct;
+        double by = c->lv[d].N * (cf + sk + cf) + c->lv[d + 1].N * ct;
+        if (!zero) by += c->lv[0].N * ct;
+        if (d == 0 && acc) by += c->lv[0].N * 16.0;
+        ib.push_back({k, by, 0.0});
+    }
+    mg::CycleArgs a{};
+    a.st.n = (int)sl.size();
+    a.st.ntiles = tiles;
+    const size_t off = put(*R.op, sl);
+    const int dim = R.dim;
+    const bool mixed = R.mixed;
+    const bool ac = d == 0 && acc;
+    add(R, d == 0 ? MG_K_PROLONG_SMOOTH_FINE : MG_K_COARSE_LEVELS, ib, [=](hipStream_t s, const char* base) {
+        mg::CycleArgs b = a;
+        b.st.s = (const mg::CycleSlot*)(base + off);
+        return mg::launch_prolong_smooth(dim, mixed, d == 0, zero, ac, shape, b, s);
+    });
+    return MG_OK;
+}
 
 // The coarse tail of every item (levels lt..L-1 and the coarsest solve),
 // one workgroup per item: its correction lands in E_lt.
-mg_status launch_tail_items(Run& R, int dir, const std::vector<Item>& it) {
-    std::vector<int> all(it.size());
-    for (size_t k = 0; k < it.size(); ++k) all[k] = (int)k;
-    return for_groups(all, [&](const std::vector<int>& sub, int) -> mg_status {
-        mg::TailArgs a{};
-        a.n = (int)sub.size();
-        a.gmres = it[sub[0]].c->gsmooth ? 1 : 0;
-        a.brk = R.mixed ? 1e-5 : 1e-13;
+mg_status rec_tail(Rec& R, int dir, const std::vector<Item>& it, int gk) {
+    std::vector<mg::TailSlot> sl(it.size());
+    std::vector<ItemBytes> ib;
+    for (size_t k = 0; k < it.size(); ++k) {
+        const Item& I = it[k];
+        mg_ctx* c = I.c;
+        mg::TailSlot& s = sl[k];
+        s = mg::TailSlot{};
+        s.lv = view_ptr(c, dir, c->lt);
+        s.sb = sbuf(c, c->lt, I.rhs);
+        s.nlev = c->L - c->lt;
+        s.gate = gate_of(R, gk, (int)k);
         double by = 0.0;
-        for (int q = 0; q < a.n; ++q) {
-            const Item& I = it[sub[q]];
-            mg_ctx* c = I.c;
-            mg::TailSlot& s = a.s[q];
-            s.lv = view_ptr(c, dir, c->lt);
-            s.sb = sbuf(c, c->lt, I.rhs);
-            s.nlev = c->L - c->lt;
-            for (int l = c->lt; l < c->L; ++l) by += 2.0 * c->lv[l].N * (R.mixed ? 8.0 : 16.0);
-        }
-        const int pi = prof_begin(R, MG_K_COARSEST_SOLVE, by);
-        CK(mg::launch_tail(R.dim, R.mixed, a, R.s));
-        prof_end(R, pi);
-        return MG_OK;
+        for (int l = c->lt; l < c->L; ++l) by += 2.0 * c->lv[l].N * (R.mixed ? 8.0 : 16.0);
+        ib.push_back({(int)k, by, 0.0});
+    }
+    mg::TailArgs a{};
+    a.n = (int)sl.size();
+    a.gmres = it[0].c->gsmooth ? 1 : 0;
+    a.brk = R.mixed ? 1e-5 : 1e-13;
+    const size_t off = put(*R.op, sl);
+    const int dim = R.dim;
+    const bool mixed = R.mixed;
+    add(R, MG_K_COARSEST_SOLVE, ib, [=](hipStream_t s, const char* base) {
+        mg::TailArgs b = a;
+        b.s = (const mg::TailSlot*)(base + off);
+        return mg::launch_tail(dim, mixed, b, s);
     });
+    return MG_OK;
 }
 
-// K_B at depth d for the items that have a coarser level below d.
-mg_status launch_kb(Run& R, int dir, const std::vector<Item>& it, const std::vector<L0>* l0, int d, bool acc) {
-    std::vector<int> who;
-    for (int k = 0; k < (int)it.size(); ++k)
-        if (d < it[k].c->lt) who.push_back(k);
-    const bool zero = !(d == 0 && l0 && (*l0)[0].u);
-    return for_groups(who, [&](const std::vector<int>& sub, int) -> mg_status {
-        const int shape = launch_shape(it, sub, d);
-        CycleArgs a{};
-        a.st.n = (int)sub.size();
-        int tiles = 0;
-        double by = 0.0;
-        const double ct = R.mixed ? 8.0 : 16.0, sk = R.mixed ? 4.0 : 8.0;
-        for (int q = 0; q < a.st.n; ++q) {
-            const Item& I = it[sub[q]];
-            mg_ctx* c = I.c;
-            CycleSlot& s = a.st.s[q];
-            s.lv = view_ptr(c, dir, d);
-            if (d == 0) {
-                const L0& z = (*l0)[sub[q]];
-                s.f = z.f;
-                s.fscale = z.fs;
-                s.u1 = z.u ? (void*)(c->U1 + (size_t)I.rhs * c->lv[0].N) : nullptr;
-                s.out = z.out;
-            } else {
-                s.f = lvec(c, c->lv[d].F, d, I.rhs);
-                s.fscale = 1.0;
-                s.out = lvec(c, c->lv[d].E, d, I.rhs);
-            }
-            s.c = lvec(c, c->lv[d + 1].E, d + 1, I.rhs);
-            s.tile0 = tiles;
-            int nt[3];
-            mg::tile_counts(R.dim, shape, c->lv[d].n, nt);
-            tiles += nt[0] * nt[1] * nt[2];
-            const double cf = d == 0 ? 16.0 : ct;
-            by += c->lv[d].N * (cf + sk + cf) + c->lv[d + 1].N * ct;
-            if (!zero) by += c->lv[0].N * ct;
-            if (d == 0 && acc) by += c->lv[0].N * 16.0;
-        }
-        a.st.ntiles = tiles;
-        const int pi = prof_begin(R, d == 0 ? MG_K_PROLONG_SMOOTH_FINE : MG_K_COARSE_LEVELS, by);
-        CK(mg::launch_prolong_smooth(R.dim, R.mixed, d == 0, zero, d == 0 && acc, shape, a, R.s));
-        prof_end(R, pi);
-        return MG_OK;
+// ---------------------------------------------------------------------------
+// Vector passes on level 0 (residual, norm, Arnoldi passes, combination)
+// ---------------------------------------------------------------------------
+enum Blk { B_VEC = 0, B_DOT = 1, B_MV = 2 };
+
+int blocks_of(const mg_ctx* c, int bk) {
+    if (bk == B_DOT) return mg::vec_blocks(c->lv[0].N, c->vper);
+    if (bk == B_MV) return mg::mv_blocks(c->dim, c->lv[0].n, c->vper);
+    return mg::vec_blocks(c->lv[0].N);
+}
+
+// One vector launch over every item: fill(k, slot, bytes) completes the
+// slots; (*cnt)[k] = workgroups of item k (= its partials).
+template <typename F, typename L>
+mg_status rec_vec(Rec& R, int dir, const std::vector<Item>& it, int gk, int bk, int cls, std::vector<int>* cnt,
+                  F fill, L launch) {
+    std::vector<mg::VecSlot> sl(it.size());
+    std::vector<ItemBytes> ib;
+    if (cnt) cnt->assign(it.size(), 0);
+    int blocks = 0;
+    for (size_t k = 0; k < it.size(); ++k) {
+        const Item& I = it[k];
+        mg::VecSlot& s = sl[k];
+        s = mg::VecSlot{};
+        s.lv = I.c->outer_d[dir];
+        s.block0 = blocks;
+        s.gate = gate_of(R, gk, (int)k);
+        const int nb = blocks_of(I.c, bk);
+        if (nb > R.w->bstride) return MG_E_STATE;
+        if (cnt) (*cnt)[k] = nb;
+        blocks += nb;
+        ItemBytes b{(int)k, 0.0, 0.0};
+        fill((int)k, s, b);
+        ib.push_back(b);
+    }
+    mg::VecArgs a{};
+    a.st.n = (int)sl.size();
+    a.st.nblocks = blocks;
+    a.part = R.w->part;
+    a.rpart = R.w->rpart;
+    a.pstride = HSTRIDE;
+    a.bstride = R.w->bstride;
+    const size_t off = put(*R.op, sl);
+    add(R, cls, ib, [=](hipStream_t s, const char* base) {
+        mg::VecArgs b = a;
+        b.st.s = (const mg::VecSlot*)(base + off);
+        return launch(b, s);
     });
+    return MG_OK;
+}
+
+// y_k = f_k - A x_k (f_k null: A x_k) on level 0, with ||y_k||^2 partials.
+mg_status rec_residual(Rec& R, int dir, const std::vector<Item>& it, int gk, const std::vector<const cx<double>*>& x,
+                       const std::vector<const cx<double>*>& f, const std::vector<cx<double>*>& y, bool norm,
+                       std::vector<int>* cnt) {
+    const int dim = R.dim;
+    return rec_vec(
+        R, dir, it, gk, B_VEC, MG_K_RESIDUAL, cnt,
+        [&](int k, mg::VecSlot& s, ItemBytes& b) {
+            s.x = x[k];
+            s.f = f[k];
+            s.y = y[k];
+            b.base = it[k].c->lv[0].N * (40.0 + (f[k] ? 16.0 : 0.0));
+        },
+        [=](mg::VecArgs b, hipStream_t s) {
+            if (!norm) b.rpart = nullptr;
+            return mg::launch_residual(dim, b, s);
+        });
+}
+
+mg_status rec_norm(Rec& R, const std::vector<Item>& it, int gk, const std::vector<const cx<double>*>& x,
+                   std::vector<int>* cnt) {
+    return rec_vec(
+        R, 0, it, gk, B_VEC, MG_K_OTHER, cnt,
+        [&](int k, mg::VecSlot& s, ItemBytes& b) {
+            s.x = x[k];
+            b.base = it[k].c->lv[0].N * 16.0;
+        },
+        [](const mg::VecArgs& b, hipStream_t s) { return mg::launch_norm(b, s); });
+}
+
+mg_status rec_vzero(Rec& R, const std::vector<Item>& it, int gk, const std::vector<cx<double>*>& y) {
+    return rec_vec(
+        R, 0, it, gk, B_VEC, MG_K_OTHER, nullptr,
+        [&](int k, mg::VecSlot& s, ItemBytes& b) {
+            s.y = y[k];
+            b.base = it[k].c->lv[0].N * 16.0;
+        },
+        [](const mg::VecArgs& b, hipStream_t s) { return mg::launch_vzero(b, s); });
+}
+
+// Fixed-order sum of the real partials of each item into w->rtot[k].
+mg_status rec_reduce_real(Rec& R, const std::vector<int>& cnt) {
+    const size_t off = put(*R.op, cnt);
+    mg::ReduceArgs a{};
+    a.rpart = R.w->rpart;
+    a.rout = R.w->rtot;
+    a.bstride = R.w->bstride;
+    const int n = (int)cnt.size();
+    add(R, MG_K_REDUCE, {}, [=](hipStream_t s, const char* base) {
+        mg::ReduceArgs b = a;
+        b.cnt = (const int*)(base + off);
+        return mg::launch_reduce(b, n, true, s);
+    });
+    return MG_OK;
+}
+
+// Krylov control kernels, one workgroup per item; cnt: partials per item of
+// the producing launch (slot k = item k).
+mg_status rec_gm(Rec& R, int which, const std::vector<Item>& it, const std::vector<int>* cnt, int j) {
+    std::vector<mg::GmItem> t(it.size());
+    for (size_t k = 0; k < it.size(); ++k) {
+        const Item& I = it[k];
+        mg::GmItem& g = t[k];
+        g.st = R.w->gst + k;
+        g.fl = R.w->gfl + k;
+        g.scale = I.c->scale_d + (size_t)I.rhs * HSTRIDE;
+        g.coef = I.c->coef_d + (size_t)I.rhs * HSTRIDE;
+        g.cnt = cnt ? (*cnt)[k] : 0;
+        g.slot = (int)k;
+    }
+    mg::GmArgs a{};
+    a.prm = R.w->prm;
+    a.part = R.w->part;
+    a.rpart = R.w->rpart;
+    a.pstride = HSTRIDE;
+    a.bstride = R.w->bstride;
+    a.j = j;
+    const size_t off = put(*R.op, t);
+    const int n = (int)t.size();
+    add(R, MG_K_REDUCE, {}, [=](hipStream_t s, const char* base) {
+        mg::GmArgs b = a;
+        b.it = (const mg::GmItem*)(base + off);
+        return mg::launch_gm(which, n, b, s);
+    });
+    return MG_OK;
 }
 
 // ---------------------------------------------------------------------------
 // GMRES(3) smoothing (Sec. 3.2.2): pre-smoothing at depth d ends in the
 // restriction of its residual, post-smoothing starts from u1 + P e.
 // ---------------------------------------------------------------------------
-mg_status build_vec(Run& R, int dir, const std::vector<Item>& it, const std::vector<int>& sub, VecArgs& a,
-                    int* cnt);
-mg_status reduce_real(Run& R, int n, const int* cnt);
 
-const mg::SmoothBufs* sbuf(const mg_ctx* c, int l, int rhs) { return c->sb_d + (size_t)rhs * c->L + l; }
-cx<double>* gcoef_of(const mg_ctx* c, int l, int rhs, int phase) {
-    return c->gcoef + ((size_t)rhs * c->L + l) * 8 + 4 * phase;
+// Coefficient solve of each slot of a Gram launch (partials per slot: cnt).
+void rec_coef(Rec& R, int d, int phase, const std::vector<Item>& it, const std::vector<int>& who,
+              const std::vector<int>& cnt, int gk) {
+    std::vector<mg::CoefSlot> cs(who.size());
+    for (size_t q = 0; q < who.size(); ++q) {
+        const Item& I = it[who[q]];
+        cs[q].coef = gcoef_of(I.c, d, I.rhs, phase);
+        cs[q].cnt = cnt[q];
+        cs[q].gate = gate_of(R, gk, who[q]);
+    }
+    mg::SmCoefArgs a{};
+    a.part = R.w->part;
+    a.pstride = HSTRIDE;
+    a.bstride = R.w->bstride;
+    const size_t off = put(*R.op, cs);
+    const bool mixed = R.mixed;
+    const int n = (int)cs.size();
+    add(R, d == 0 ? MG_K_REDUCE : MG_K_COARSE_LEVELS, {}, [=](hipStream_t s, const char* base) {
+        mg::SmCoefArgs b = a;
+        b.s = (const mg::CoefSlot*)(base + off);
+        return mg::launch_sm_coef(mixed, b, n, s);
+    });
 }
 
-// Powers, Gram partials and coefficients of one smoothing step for the slots
-// of sa (q0 given by slot.f or the q0 buffer).
-mg_status smooth_coef(Run& R, int d, int phase, const std::vector<Item>& it, const std::vector<int>& sub,
-                      mg::SmArgs& sa, bool q0f) {
-    const bool fine = d == 0;
-    const double ct = R.mixed ? 8.0 : 16.0, sk = R.mixed ? 4.0 : 8.0;
-    double n = 0.0;
-    for (int k : sub) n += (double)it[k].c->lv[d].N;
-    const double q0b = (fine && q0f) ? 16.0 : ct;
-    for (int stage = 1; stage <= 2; ++stage) {
-        const double by = n * ((stage == 1 ? q0b : ct) + sk + ct);
-        const int pi = prof_begin(R, fine ? MG_K_SMOOTH_POWER_FINE : MG_K_COARSE_LEVELS, by);
-        CK(mg::launch_sm_power(R.dim, R.mixed, fine, stage, sa, R.s));
-        prof_end(R, pi);
-    }
-    const int gcls = phase ? MG_K_SMOOTH_GRAM_POST_FINE : MG_K_SMOOTH_GRAM_FINE;
-    int pi = prof_begin(R, fine ? gcls : MG_K_COARSE_LEVELS, n * (q0b + 2.0 * ct + sk));
-    CK(mg::launch_sm_gram(R.dim, R.mixed, fine, sa, R.s));
-    prof_end(R, pi);
-    mg::SmCoefArgs ca{};
-    ca.part = R.w->part;
-    ca.pstride = HSTRIDE;
-    ca.bstride = R.w->bstride;
-    for (int q = 0; q < sa.st.n; ++q) {
-        const Item& I = it[sub[q]];
-        ca.cnt[q] = mg::vec_blocks(I.c->lv[d].N);
-        ca.coef[q] = gcoef_of(I.c, d, I.rhs, phase);
-    }
-    pi = prof_begin(R, fine ? MG_K_REDUCE : MG_K_COARSE_LEVELS);
-    CK(mg::launch_sm_coef(R.mixed, ca, sa.st.n, R.s));
-    prof_end(R, pi);
-    return MG_OK;
-}
-
-mg_status build_sm(Run& R, int dir, int d, const std::vector<Item>& it, const std::vector<int>& sub,
-                   mg::SmArgs& sa) {
-    sa.st.n = (int)sub.size();
-    int blocks = 0;
-    for (int q = 0; q < sa.st.n; ++q) {
-        const Item& I = it[sub[q]];
-        mg::SmSlot& s = sa.st.s[q];
+// Slot table of the pointwise 3D smoother passes; (*cnt)[q] partials.
+mg_status sm_slots(Rec& R, int dir, int d, const std::vector<Item>& it, const std::vector<int>& who, int gk,
+                   std::vector<mg::SmSlot>& sl, std::vector<int>& cnt, int& blocks) {
+    sl.assign(who.size(), mg::SmSlot{});
+    cnt.assign(who.size(), 0);
+    blocks = 0;
+    for (size_t q = 0; q < who.size(); ++q) {
+        const Item& I = it[who[q]];
+        mg::SmSlot& s = sl[q];
         s.lv = view_ptr(I.c, dir, d);
         s.sb = sbuf(I.c, d, I.rhs);
+        s.gate = gate_of(R, gk, who[q]);
         s.block0 = blocks;
         const int nb = mg::vec_blocks(I.c->lv[d].N);
         if (nb > R.w->bstride) return MG_E_STATE;
+        cnt[q] = nb;
         blocks += nb;
     }
-    sa.st.nblocks = blocks;
-    sa.part = R.w->part;
-    sa.pstride = HSTRIDE;
-    sa.bstride = R.w->bstride;
     return MG_OK;
 }
 
-// 2D: the fused tile passes of mg_smooth2d.hip.  Slots carry f (q0 source;
-// null: the q0 buffer), u (incoming iterate, NZ), c (coarse rhs out for the
-// pre-smoothing step, coarse correction in for the post-smoothing step), out.
-mg_status coef_from_tiles(Run& R, int d, int phase, const std::vector<Item>& it, const std::vector<int>& sub,
-                          const CycleArgs& a) {
-    mg::SmCoefArgs ca{};
-    ca.part = R.w->part;
-    ca.pstride = HSTRIDE;
-    ca.bstride = R.w->bstride;
-    for (int q = 0; q < a.st.n; ++q) {
-        const Item& I = it[sub[q]];
-        const int next = q + 1 < a.st.n ? a.st.s[q + 1].tile0 : a.st.ntiles;
-        ca.cnt[q] = next - a.st.s[q].tile0;
-        ca.coef[q] = gcoef_of(I.c, d, I.rhs, phase);
-    }
-    const int pi = prof_begin(R, d == 0 ? MG_K_REDUCE : MG_K_COARSE_LEVELS);
-    CK(mg::launch_sm_coef(R.mixed, ca, a.st.n, R.s));
-    prof_end(R, pi);
-    return MG_OK;
-}
-
-mg_status pre_fused_2d(Run& R, int dir, const std::vector<Item>& it, const std::vector<L0>* l0, int d, bool nz,
-                       const std::vector<int>& sub) {
-    const int shape = launch_shape(it, sub, d);
+// 3D: powers, Gram partials and coefficients of one smoothing step (q0
+// given by the slots' f or the q0 buffer).
+mg_status rec_smooth_coef(Rec& R, int d, int phase, const std::vector<Item>& it, const std::vector<int>& who,
+                          const std::vector<mg::SmSlot>& sl, const std::vector<int>& cnt, int blocks, bool q0f,
+                          int gk) {
+    const bool fine = d == 0;
     const double ct = R.mixed ? 8.0 : 16.0, sk = R.mixed ? 4.0 : 8.0;
-    CycleArgs a{};
-    a.st.n = (int)sub.size();
+    const double q0b = (fine && q0f) ? 16.0 : ct;
+    std::vector<ItemBytes> ib1, ib2, ibg;
+    for (int k : who) {
+        const double n = (double)it[k].c->lv[d].N;
+        ib1.push_back({k, n * (q0b + sk + ct), 0.0});
+        ib2.push_back({k, n * (ct + sk + ct), 0.0});
+        ibg.push_back({k, n * (q0b + 2.0 * ct + sk), 0.0});
+    }
+    mg::SmArgs a{};
+    a.st.n = (int)sl.size();
+    a.st.nblocks = blocks;
+    a.part = R.w->part;
+    a.pstride = HSTRIDE;
+    a.bstride = R.w->bstride;
+    const size_t off = put(*R.op, sl);
+    const int dim = R.dim;
+    const bool mixed = R.mixed;
+    for (int stage = 1; stage <= 2; ++stage)
+        add(R, fine ? MG_K_SMOOTH_POWER_FINE : MG_K_COARSE_LEVELS, stage == 1 ? ib1 : ib2,
+            [=](hipStream_t s, const char* base) {
+                mg::SmArgs b = a;
+                b.st.s = (const mg::SmSlot*)(base + off);
+                return mg::launch_sm_power(dim, mixed, fine, stage, b, s);
+            });
+    add(R, fine ? (phase ? MG_K_SMOOTH_GRAM_POST_FINE : MG_K_SMOOTH_GRAM_FINE) : MG_K_COARSE_LEVELS, ibg,
+        [=](hipStream_t s, const char* base) {
+            mg::SmArgs b = a;
+            b.st.s = (const mg::SmSlot*)(base + off);
+            return mg::launch_sm_gram(dim, mixed, fine, b, s);
+        });
+    rec_coef(R, d, phase, it, who, cnt, gk);
+    return MG_OK;
+}
+
+// 2D fused passes (mg_march2d.hip): Gram pass, coefficient solve, apply pass.
+mg_status rec_pre_2d(Rec& R, int dir, const std::vector<Item>& it, int gk, const std::vector<L0>* l0, int d,
+                     bool nz, const std::vector<int>& who) {
+    const int shape = launch_shape(it, who, d);
+    const double ct = R.mixed ? 8.0 : 16.0, sk = R.mixed ? 4.0 : 8.0;
+    std::vector<mg::CycleSlot> sl(who.size());
+    std::vector<int> cnt(who.size());
+    std::vector<ItemBytes> ibg, iba;
     int tiles = 0;
-    double bg = 0.0, ba = 0.0;
-    for (int q = 0; q < a.st.n; ++q) {
-        const Item& I = it[sub[q]];
+    for (size_t q = 0; q < who.size(); ++q) {
+        const int k = who[q];
+        const Item& I = it[k];
         mg_ctx* c = I.c;
-        CycleSlot& s = a.st.s[q];
+        mg::CycleSlot& s = sl[q];
+        s = mg::CycleSlot{};
         s.lv = view_ptr(c, dir, d);
         if (nz) {
             s.f = nullptr;
             s.fscale = 1.0;
-            s.u = (*l0)[sub[q]].u;
+            s.u = (*l0)[k].u;
         } else if (d == 0) {
-            s.f = (*l0)[sub[q]].f;
-            s.fscale = (*l0)[sub[q]].fs;
+            s.f = (*l0)[k].f;
+            s.fscale = (*l0)[k].fs;
+            s.fsp = (*l0)[k].fsp;
         } else {
             s.f = lvec(c, c->lv[d].F, d, I.rhs);
             s.fscale = 1.0;
         }
         s.c = lvec(c, c->lv[d + 1].F, d + 1, I.rhs);
         s.sb = sbuf(c, d, I.rhs);
+        s.gate = gate_of(R, gk, k);
         s.tile0 = tiles;
         int nt[3];
         mg::march_counts(shape, c->lv[d].n, nt);
-        tiles += nt[0] * nt[1];
+        cnt[q] = nt[0] * nt[1];
+        if (cnt[q] > R.w->bstride) return MG_E_STATE;
+        tiles += cnt[q];
         const double q0b = (d == 0 && !nz) ? 16.0 : ct;
-        bg += c->lv[d].N * (q0b + sk);
-        ba += c->lv[d].N * (q0b + sk + ct + (nz ? 16.0 : 0.0)) + c->lv[d + 1].N * ct;
+        ibg.push_back({k, c->lv[d].N * (q0b + sk), 0.0});
+        iba.push_back({k, c->lv[d].N * (q0b + sk + ct + (nz ? 16.0 : 0.0)) + c->lv[d + 1].N * ct, 0.0});
     }
+    mg::CycleArgs a{};
+    a.st.n = (int)sl.size();
     a.st.ntiles = tiles;
-    int pi = prof_begin(R, d == 0 ? MG_K_SMOOTH_GRAM_FINE : MG_K_COARSE_LEVELS, bg);
-    CK(mg::launch_sm2_gram(R.mixed, d == 0, false, shape, a, R.w->part, HSTRIDE, R.w->bstride, R.s));
-    prof_end(R, pi);
-    CKS(coef_from_tiles(R, d, 0, it, sub, a));
-    pi = prof_begin(R, d == 0 ? MG_K_SMOOTH_RESTRICT_FINE : MG_K_COARSE_LEVELS, ba);
-    CK(mg::launch_sm2_apply_restrict(R.mixed, d == 0, nz, shape, a, R.s));
-    prof_end(R, pi);
+    const size_t off = put(*R.op, sl);
+    const bool mixed = R.mixed;
+    cx<double>* part = R.w->part;
+    const int bstride = R.w->bstride;
+    add(R, d == 0 ? MG_K_SMOOTH_GRAM_FINE : MG_K_COARSE_LEVELS, ibg, [=](hipStream_t s, const char* base) {
+        mg::CycleArgs b = a;
+        b.st.s = (const mg::CycleSlot*)(base + off);
+        return mg::launch_sm2_gram(mixed, d == 0, false, shape, b, part, HSTRIDE, bstride, s);
+    });
+    rec_coef(R, d, 0, it, who, cnt, gk);
+    add(R, d == 0 ? MG_K_SMOOTH_RESTRICT_FINE : MG_K_COARSE_LEVELS, iba, [=](hipStream_t s, const char* base) {
+        mg::CycleArgs b = a;
+        b.st.s = (const mg::CycleSlot*)(base + off);
+        return mg::launch_sm2_apply_restrict(mixed, d == 0, nz, shape, b, s);
+    });
     return MG_OK;
 }
 
-mg_status post_fused_2d(Run& R, int dir, const std::vector<Item>& it, const std::vector<L0>* l0, int d, bool acc,
-                        const std::vector<int>& sub) {
-    const int shape = launch_shape(it, sub, d);
+mg_status rec_post_2d(Rec& R, int dir, const std::vector<Item>& it, int gk, const std::vector<L0>* l0, int d,
+                      bool acc, const std::vector<int>& who) {
+    const int shape = launch_shape(it, who, d);
     const double ct = R.mixed ? 8.0 : 16.0, sk = R.mixed ? 4.0 : 8.0;
-    CycleArgs a{};
-    a.st.n = (int)sub.size();
+    std::vector<mg::CycleSlot> sl(who.size());
+    std::vector<int> cnt(who.size());
+    std::vector<ItemBytes> ibg, iba;
     int tiles = 0;
-    double bg = 0.0, ba = 0.0;
-    for (int q = 0; q < a.st.n; ++q) {
-        const Item& I = it[sub[q]];
+    for (size_t q = 0; q < who.size(); ++q) {
+        const int k = who[q];
+        const Item& I = it[k];
         mg_ctx* c = I.c;
-        CycleSlot& s = a.st.s[q];
+        mg::CycleSlot& s = sl[q];
+        s = mg::CycleSlot{};
         s.lv = view_ptr(c, dir, d);
         if (d == 0) {
-            s.f = (*l0)[sub[q]].f;
-            s.fscale = (*l0)[sub[q]].fs;
-            s.out = (*l0)[sub[q]].out;
+            s.f = (*l0)[k].f;
+            s.fscale = (*l0)[k].fs;
+            s.fsp = (*l0)[k].fsp;
+            s.out = (*l0)[k].out;
         } else {
             s.f = lvec(c, c->lv[d].F, d, I.rhs);
             s.fscale = 1.0;
@@ -650,469 +1009,221 @@ mg_status post_fused_2d(Run& R, int dir, const std::vector<Item>& it, const std:
         }
         s.c = lvec(c, c->lv[d + 1].E, d + 1, I.rhs);
         s.sb = sbuf(c, d, I.rhs);
+        s.gate = gate_of(R, gk, k);
         s.tile0 = tiles;
         int nt[3];
         mg::march_counts(shape, c->lv[d].n, nt);
-        tiles += nt[0] * nt[1];
+        cnt[q] = nt[0] * nt[1];
+        if (cnt[q] > R.w->bstride) return MG_E_STATE;
+        tiles += cnt[q];
         const double fb = d == 0 ? 16.0 : ct;
-        bg += c->lv[d].N * (ct + fb + sk) + c->lv[d + 1].N * ct;
-        ba += c->lv[d].N * (ct + fb + sk + fb + (d == 0 && acc ? 16.0 : 0.0)) + c->lv[d + 1].N * ct;
+        ibg.push_back({k, c->lv[d].N * (ct + fb + sk) + c->lv[d + 1].N * ct, 0.0});
+        iba.push_back({k, c->lv[d].N * (ct + fb + sk + fb + (d == 0 && acc ? 16.0 : 0.0)) + c->lv[d + 1].N * ct, 0.0});
     }
+    mg::CycleArgs a{};
+    a.st.n = (int)sl.size();
     a.st.ntiles = tiles;
-    int pi = prof_begin(R, d == 0 ? MG_K_SMOOTH_GRAM_POST_FINE : MG_K_COARSE_LEVELS, bg);
-    CK(mg::launch_sm2_gram(R.mixed, d == 0, true, shape, a, R.w->part, HSTRIDE, R.w->bstride, R.s));
-    prof_end(R, pi);
-    CKS(coef_from_tiles(R, d, 1, it, sub, a));
-    pi = prof_begin(R, d == 0 ? MG_K_PROLONG_SMOOTH_FINE : MG_K_COARSE_LEVELS, ba);
-    CK(mg::launch_sm2_apply_out(R.mixed, d == 0, d == 0 && acc, shape, a, R.s));
-    prof_end(R, pi);
+    const size_t off = put(*R.op, sl);
+    const bool mixed = R.mixed;
+    cx<double>* part = R.w->part;
+    const int bstride = R.w->bstride;
+    const bool ac = d == 0 && acc;
+    add(R, d == 0 ? MG_K_SMOOTH_GRAM_POST_FINE : MG_K_COARSE_LEVELS, ibg, [=](hipStream_t s, const char* base) {
+        mg::CycleArgs b = a;
+        b.st.s = (const mg::CycleSlot*)(base + off);
+        return mg::launch_sm2_gram(mixed, d == 0, true, shape, b, part, HSTRIDE, bstride, s);
+    });
+    rec_coef(R, d, 1, it, who, cnt, gk);
+    add(R, d == 0 ? MG_K_PROLONG_SMOOTH_FINE : MG_K_COARSE_LEVELS, iba, [=](hipStream_t s, const char* base) {
+        mg::CycleArgs b = a;
+        b.st.s = (const mg::CycleSlot*)(base + off);
+        return mg::launch_sm2_apply_out(mixed, d == 0, ac, shape, b, s);
+    });
     return MG_OK;
 }
 
 // Pre-smoothing at depth d and restriction of its residual to depth d + 1.
 // Level 0 with incoming iterates (FP64 only): q0 = f - A u by the FP64
-// residual kernel, whose ||q0||^2 of item k lands in w->rtot_h[k] when norm.
-mg_status launch_pre_g(Run& R, int dir, const std::vector<Item>& it, const std::vector<L0>* l0, int d, bool norm) {
-    std::vector<int> who;
-    for (int k = 0; k < (int)it.size(); ++k)
-        if (d < it[k].c->lt) who.push_back(k);
+// residual kernel, whose ||q0||^2 partials of item k land in rpart (cnt).
+mg_status rec_pre_g(Rec& R, int dir, const std::vector<Item>& it, int gk, const std::vector<L0>* l0, int d,
+                    bool norm, std::vector<int>* cnt) {
+    const std::vector<int> who = above_tail(it, d);
+    if (who.empty()) return MG_OK;
     const bool nz = d == 0 && l0 && (*l0)[0].u;
     if (nz && R.mixed) return MG_E_STATE;
-    return for_groups(who, [&](const std::vector<int>& sub, int gbase) -> mg_status {
+    if (nz) {
+        if (who.size() != it.size()) return MG_E_STATE;
+        std::vector<const cx<double>*> xs(it.size()), fs(it.size());
+        std::vector<cx<double>*> ys(it.size());
+        for (size_t k = 0; k < it.size(); ++k) {
+            const L0& z = (*l0)[k];
+            if (z.fs != 1.0 || z.fsp) return MG_E_STATE;
+            xs[k] = z.u;
+            fs[k] = (const cx<double>*)z.f;
+            ys[k] = (cx<double>*)lvec(it[k].c, it[k].c->lv[0].Q[0], 0, it[k].rhs);
+        }
+        CKS(rec_residual(R, dir, it, gk, xs, fs, ys, norm, cnt));
+    }
+    if (R.dim == 2) return rec_pre_2d(R, dir, it, gk, l0, d, nz, who);
+    std::vector<mg::SmSlot> ss;
+    std::vector<int> scnt;
+    int blocks = 0;
+    CKS(sm_slots(R, dir, d, it, who, gk, ss, scnt, blocks));
+    for (size_t q = 0; q < who.size(); ++q) {
+        const int k = who[q];
+        const Item& I = it[k];
+        mg::SmSlot& s = ss[q];
         if (nz) {
-            VecArgs a{};
-            int cnt[mg::MAX_SLOTS];
-            CKS(build_vec(R, dir, it, sub, a, cnt));
-            double by = 0.0;
-            for (int q = 0; q < a.st.n; ++q) {
-                const Item& I = it[sub[q]];
-                const L0& z = (*l0)[sub[q]];
-                if (z.fs != 1.0) return MG_E_STATE;
-                a.st.s[q].x = z.u;
-                a.st.s[q].f = (const cx<double>*)z.f;
-                a.st.s[q].y = (cx<double>*)lvec(I.c, I.c->lv[0].Q[0], 0, I.rhs);
-                by += I.c->lv[0].N * 56.0;
-            }
-            if (!norm) a.rpart = nullptr;
-            const int pi = prof_begin(R, MG_K_RESIDUAL, by);
-            CK(mg::launch_residual(R.dim, a, R.s));
-            prof_end(R, pi);
-            if (norm) {
-                CKS(reduce_real(R, a.st.n, cnt));
-                CK(hipMemcpyAsync(R.w->rtot_h + gbase, R.w->rtot, a.st.n * sizeof(double), hipMemcpyDeviceToHost,
-                                  R.s));
-            }
+            s.f = nullptr;
+            s.fscale = 1.0;
+        } else if (d == 0) {
+            s.f = (*l0)[k].f;
+            s.fscale = (*l0)[k].fs;
+            s.fsp = (*l0)[k].fsp;
+        } else {
+            s.f = lvec(I.c, I.c->lv[d].F, d, I.rhs);
+            s.fscale = 1.0;
         }
-        if (R.dim == 2) return pre_fused_2d(R, dir, it, l0, d, nz, sub);
-        mg::SmArgs sa{};
-        CKS(build_sm(R, dir, d, it, sub, sa));
-        for (int q = 0; q < sa.st.n; ++q) {
-            const Item& I = it[sub[q]];
-            mg::SmSlot& s = sa.st.s[q];
-            if (nz) {
-                s.f = nullptr;
-                s.fscale = 1.0;
-            } else if (d == 0) {
-                s.f = (*l0)[sub[q]].f;
-                s.fscale = (*l0)[sub[q]].fs;
-            } else {
-                s.f = lvec(I.c, I.c->lv[d].F, d, I.rhs);
-                s.fscale = 1.0;
-            }
-        }
-        CKS(smooth_coef(R, d, 0, it, sub, sa, !nz));
-        const int shape = launch_shape(it, sub, d);
-        CycleArgs a{};
-        a.st.n = sa.st.n;
-        int tiles = 0;
-        double by = 0.0;
-        const double ct = R.mixed ? 8.0 : 16.0, sk = R.mixed ? 4.0 : 8.0;
-        for (int q = 0; q < a.st.n; ++q) {
-            const Item& I = it[sub[q]];
-            mg_ctx* c = I.c;
-            CycleSlot& s = a.st.s[q];
-            s.lv = sa.st.s[q].lv;
-            s.f = sa.st.s[q].f;
-            s.fscale = sa.st.s[q].fscale;
-            s.u = nz ? (const void*)(*l0)[sub[q]].u : nullptr;
-            s.c = lvec(c, c->lv[d + 1].F, d + 1, I.rhs);
-            s.sb = sbuf(c, d, I.rhs);
-            s.tile0 = tiles;
-            int nt[3];
-            mg::tile_counts(R.dim, shape, c->lv[d].n, nt);
-            tiles += nt[0] * nt[1] * nt[2];
-            const double q0b = (d == 0 && !nz) ? 16.0 : ct;
-            by += c->lv[d].N * (q0b + 3.0 * ct + sk + (nz ? 16.0 : 0.0)) + c->lv[d + 1].N * ct;
-        }
-        a.st.ntiles = tiles;
-        const int pi = prof_begin(R, d == 0 ? MG_K_SMOOTH_RESTRICT_FINE : MG_K_COARSE_LEVELS, by);
-        CK(mg::launch_sm_apply_restrict(R.dim, R.mixed, d == 0, nz, shape, a, R.s));
-        prof_end(R, pi);
-        return MG_OK;
+    }
+    CKS(rec_smooth_coef(R, d, 0, it, who, ss, scnt, blocks, !nz, gk));
+    const int shape = launch_shape(it, who, d);
+    const double ct = R.mixed ? 8.0 : 16.0, sk = R.mixed ? 4.0 : 8.0;
+    std::vector<mg::CycleSlot> sl(who.size());
+    std::vector<ItemBytes> ib;
+    int tiles = 0;
+    for (size_t q = 0; q < who.size(); ++q) {
+        const int k = who[q];
+        const Item& I = it[k];
+        mg_ctx* c = I.c;
+        mg::CycleSlot& s = sl[q];
+        s = mg::CycleSlot{};
+        s.lv = ss[q].lv;
+        s.f = ss[q].f;
+        s.fscale = ss[q].fscale;
+        s.fsp = ss[q].fsp;
+        s.u = nz ? (const void*)(*l0)[k].u : nullptr;
+        s.c = lvec(c, c->lv[d + 1].F, d + 1, I.rhs);
+        s.sb = sbuf(c, d, I.rhs);
+        s.gate = ss[q].gate;
+        s.tile0 = tiles;
+        int nt[3];
+        mg::tile_counts(R.dim, shape, c->lv[d].n, nt);
+        tiles += nt[0] * nt[1] * nt[2];
+        const double q0b = (d == 0 && !nz) ? 16.0 : ct;
+        ib.push_back({k, c->lv[d].N * (q0b + 3.0 * ct + sk + (nz ? 16.0 : 0.0)) + c->lv[d + 1].N * ct, 0.0});
+    }
+    mg::CycleArgs a{};
+    a.st.n = (int)sl.size();
+    a.st.ntiles = tiles;
+    const size_t off = put(*R.op, sl);
+    const int dim = R.dim;
+    const bool mixed = R.mixed;
+    add(R, d == 0 ? MG_K_SMOOTH_RESTRICT_FINE : MG_K_COARSE_LEVELS, ib, [=](hipStream_t s, const char* base) {
+        mg::CycleArgs b = a;
+        b.st.s = (const mg::CycleSlot*)(base + off);
+        return mg::launch_sm_apply_restrict(dim, mixed, d == 0, nz, shape, b, s);
     });
+    return MG_OK;
 }
 
 // Coarse-grid correction and post-smoothing at depth d.
-mg_status launch_post_g(Run& R, int dir, const std::vector<Item>& it, const std::vector<L0>* l0, int d, bool acc) {
-    std::vector<int> who;
-    for (int k = 0; k < (int)it.size(); ++k)
-        if (d < it[k].c->lt) who.push_back(k);
-    return for_groups(who, [&](const std::vector<int>& sub, int) -> mg_status {
-        if (R.dim == 2) return post_fused_2d(R, dir, it, l0, d, acc, sub);
-        const int shape = launch_shape(it, sub, d);
-        const double ct = R.mixed ? 8.0 : 16.0, sk = R.mixed ? 4.0 : 8.0;
-        CycleArgs a{};
-        a.st.n = (int)sub.size();
-        int tiles = 0;
-        double by = 0.0;
-        for (int q = 0; q < a.st.n; ++q) {
-            const Item& I = it[sub[q]];
-            mg_ctx* c = I.c;
-            CycleSlot& s = a.st.s[q];
-            s.lv = view_ptr(c, dir, d);
-            if (d == 0) {
-                s.f = (*l0)[sub[q]].f;
-                s.fscale = (*l0)[sub[q]].fs;
-            } else {
-                s.f = lvec(c, c->lv[d].F, d, I.rhs);
-                s.fscale = 1.0;
-            }
-            s.c = lvec(c, c->lv[d + 1].E, d + 1, I.rhs);
-            s.sb = sbuf(c, d, I.rhs);
-            s.tile0 = tiles;
-            int nt[3];
-            mg::tile_counts(R.dim, shape, c->lv[d].n, nt);
-            tiles += nt[0] * nt[1] * nt[2];
-            by += c->lv[d].N * (ct + (d == 0 ? 16.0 : ct) + sk + 2.0 * ct) + c->lv[d + 1].N * ct;
+mg_status rec_post_g(Rec& R, int dir, const std::vector<Item>& it, int gk, const std::vector<L0>* l0, int d,
+                     bool acc) {
+    const std::vector<int> who = above_tail(it, d);
+    if (who.empty()) return MG_OK;
+    if (R.dim == 2) return rec_post_2d(R, dir, it, gk, l0, d, acc, who);
+    const int shape = launch_shape(it, who, d);
+    const double ct = R.mixed ? 8.0 : 16.0, sk = R.mixed ? 4.0 : 8.0;
+    std::vector<mg::CycleSlot> sl(who.size());
+    std::vector<ItemBytes> ib;
+    int tiles = 0;
+    for (size_t q = 0; q < who.size(); ++q) {
+        const int k = who[q];
+        const Item& I = it[k];
+        mg_ctx* c = I.c;
+        mg::CycleSlot& s = sl[q];
+        s = mg::CycleSlot{};
+        s.lv = view_ptr(c, dir, d);
+        if (d == 0) {
+            s.f = (*l0)[k].f;
+            s.fscale = (*l0)[k].fs;
+            s.fsp = (*l0)[k].fsp;
+        } else {
+            s.f = lvec(c, c->lv[d].F, d, I.rhs);
+            s.fscale = 1.0;
         }
-        a.st.ntiles = tiles;
-        int pi = prof_begin(R, d == 0 ? MG_K_PROLONG_SMOOTH_FINE : MG_K_COARSE_LEVELS, by);
-        CK(mg::launch_sm_prolong_resid(R.dim, R.mixed, d == 0, shape, a, R.s));
-        prof_end(R, pi);
-        mg::SmArgs sa{};
-        CKS(build_sm(R, dir, d, it, sub, sa));
-        CKS(smooth_coef(R, d, 1, it, sub, sa, false));
-        by = 0.0;
-        for (int q = 0; q < sa.st.n; ++q) {
-            const Item& I = it[sub[q]];
-            mg_ctx* c = I.c;
-            sa.st.s[q].out = d == 0 ? (void*)(*l0)[sub[q]].out : lvec(c, c->lv[d].E, d, I.rhs);
-            by += c->lv[d].N * (4.0 * ct + (d == 0 ? 16.0 : ct) + (d == 0 && acc ? 16.0 : 0.0));
-        }
-        pi = prof_begin(R, d == 0 ? MG_K_PROLONG_SMOOTH_FINE : MG_K_COARSE_LEVELS, by);
-        CK(mg::launch_sm_apply_out(R.mixed, d == 0, d == 0 && acc, sa, R.s));
-        prof_end(R, pi);
-        return MG_OK;
+        s.c = lvec(c, c->lv[d + 1].E, d + 1, I.rhs);
+        s.sb = sbuf(c, d, I.rhs);
+        s.gate = gate_of(R, gk, k);
+        s.tile0 = tiles;
+        int nt[3];
+        mg::tile_counts(R.dim, shape, c->lv[d].n, nt);
+        tiles += nt[0] * nt[1] * nt[2];
+        ib.push_back({k, c->lv[d].N * (ct + (d == 0 ? 16.0 : ct) + sk + 2.0 * ct) + c->lv[d + 1].N * ct, 0.0});
+    }
+    mg::CycleArgs a{};
+    a.st.n = (int)sl.size();
+    a.st.ntiles = tiles;
+    const size_t off = put(*R.op, sl);
+    const int dim = R.dim;
+    const bool mixed = R.mixed;
+    add(R, d == 0 ? MG_K_PROLONG_SMOOTH_FINE : MG_K_COARSE_LEVELS, ib, [=](hipStream_t s, const char* base) {
+        mg::CycleArgs b = a;
+        b.st.s = (const mg::CycleSlot*)(base + off);
+        return mg::launch_sm_prolong_resid(dim, mixed, d == 0, shape, b, s);
     });
+    std::vector<mg::SmSlot> ss;
+    std::vector<int> scnt;
+    int blocks = 0;
+    CKS(sm_slots(R, dir, d, it, who, gk, ss, scnt, blocks));
+    CKS(rec_smooth_coef(R, d, 1, it, who, ss, scnt, blocks, false, gk));
+    std::vector<ItemBytes> ibo;
+    for (size_t q = 0; q < who.size(); ++q) {
+        const int k = who[q];
+        const Item& I = it[k];
+        mg_ctx* c = I.c;
+        ss[q].out = d == 0 ? (void*)(*l0)[k].out : lvec(c, c->lv[d].E, d, I.rhs);
+        ibo.push_back({k, c->lv[d].N * (4.0 * ct + (d == 0 ? 16.0 : ct) + (d == 0 && acc ? 16.0 : 0.0)), 0.0});
+    }
+    mg::SmArgs sa{};
+    sa.st.n = (int)ss.size();
+    sa.st.nblocks = blocks;
+    const size_t off2 = put(*R.op, ss);
+    const bool ac = d == 0 && acc;
+    add(R, d == 0 ? MG_K_PROLONG_SMOOTH_FINE : MG_K_COARSE_LEVELS, ibo, [=](hipStream_t s, const char* base) {
+        mg::SmArgs b = sa;
+        b.st.s = (const mg::SmSlot*)(base + off2);
+        return mg::launch_sm_apply_out(mixed, d == 0, ac, b, s);
+    });
+    return MG_OK;
 }
 
 // The descending / ascending halves of one level's cycle work.
-mg_status cycle_down(Run& R, int dir, const std::vector<Item>& it, const std::vector<L0>* l0, int d, bool norm) {
-    return it[0].c->gsmooth ? launch_pre_g(R, dir, it, l0, d, norm) : launch_ka(R, dir, it, l0, d, norm);
+mg_status rec_down(Rec& R, int dir, const std::vector<Item>& it, int gk, const std::vector<L0>* l0, int d, bool norm,
+                   std::vector<int>* cnt) {
+    return it[0].c->gsmooth ? rec_pre_g(R, dir, it, gk, l0, d, norm, cnt) : rec_ka(R, dir, it, gk, l0, d, norm, cnt);
 }
-mg_status cycle_up(Run& R, int dir, const std::vector<Item>& it, const std::vector<L0>* l0, int d, bool acc) {
-    return it[0].c->gsmooth ? launch_post_g(R, dir, it, l0, d, acc) : launch_kb(R, dir, it, l0, d, acc);
+mg_status rec_up(Rec& R, int dir, const std::vector<Item>& it, int gk, const std::vector<L0>* l0, int d, bool acc) {
+    return it[0].c->gsmooth ? rec_post_g(R, dir, it, gk, l0, d, acc) : rec_kb(R, dir, it, gk, l0, d, acc);
 }
 
-// Levels >= 1 and the coarsest solve of one cycle: captured once per
-// (direction, item list) as a HIP graph and replayed; every pointer in it is
-// fixed per item (F_l and E_l by rhs).
-mg_status coarse_part(Run& R, int dir, const std::vector<Item>& it) {
+// One V(1,1) cycle for the items, gated by gk.  With norms (and incoming
+// iterates) the ||f - A u||^2 partials of item k land in rpart, (*cnt)[k].
+mg_status rec_cycle(Rec& R, int dir, const std::vector<Item>& it, int gk, const std::vector<L0>& l0, bool acc,
+                    bool norms, std::vector<int>* cnt) {
+    if (R.mixed && l0[0].u) return MG_E_STATE;
     int maxT = 0;
     for (const Item& I : it) maxT = std::max(maxT, I.c->lt);
-    auto record = [&](Run& Q) -> mg_status {
-        for (int d = 1; d < maxT; ++d) CKS(cycle_down(Q, dir, it, nullptr, d, false));
-        CKS(launch_tail_items(Q, dir, it));
-        for (int d = maxT - 1; d >= 1; --d) CKS(cycle_up(Q, dir, it, nullptr, d, false));
-        return MG_OK;
-    };
-    if (!R.gc) return record(R);
-    std::vector<uintptr_t> key;
-    key.push_back((uintptr_t)dir);
-    for (const Item& I : it) {
-        key.push_back((uintptr_t)I.c);
-        key.push_back((uintptr_t)I.rhs);
-    }
-    auto f = R.gc->execs.find(key);
-    if (f == R.gc->execs.end()) {
-        if (!R.gc->capture) CK(hipStreamCreateWithFlags(&R.gc->capture, hipStreamNonBlocking));
-        Run Q = R;
-        Q.s = R.gc->capture;
-        Q.prof = nullptr;
-        CK(hipStreamBeginCapture(Q.s, hipStreamCaptureModeThreadLocal));
-        const mg_status st = record(Q);
-        hipGraph_t g = nullptr;
-        const hipError_t e = hipStreamEndCapture(Q.s, &g);
-        if (st != MG_OK) {
-            if (g) (void)hipGraphDestroy(g);
-            return st;
-        }
-        CK(e);
-        hipGraphExec_t ex = nullptr;
-        const hipError_t ei = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
-        (void)hipGraphDestroy(g);
-        CK(ei);
-        f = R.gc->execs.emplace(key, ex).first;
-    }
-    double by = 0.0;   // algorithmic bytes of every level >= 1 kernel
-    if (R.prof && R.prof->on) {
-        const double ct = R.mixed ? 8.0 : 16.0, sk = R.mixed ? 4.0 : 8.0;
-        for (const Item& I : it)
-            for (int l = 1; l < I.c->lt; ++l) {
-                if (I.c->gsmooth && I.c->dim == 2)   // fused Gram and apply passes of both steps
-                    by += I.c->lv[l].N * (8 * ct + 4 * sk) + 3 * I.c->lv[l + 1].N * ct;
-                else if (I.c->gsmooth)   // powers, Gram, apply passes of both smoothing steps
-                    by += I.c->lv[l].N * (27 * ct + 8 * sk) + 2 * I.c->lv[l + 1].N * ct;
-                else
-                    by += I.c->lv[l].N * (ct + sk) + I.c->lv[l + 1].N * ct +
-                          I.c->lv[l].N * (3 * ct + sk) + I.c->lv[l + 1].N * ct;
-            }
-    }
-    const int pi = prof_begin(R, MG_K_COARSE_LEVELS, by);
-    CK(hipGraphLaunch(f->second, R.s));
-    prof_end(R, pi);
+    CKS(rec_down(R, dir, it, gk, &l0, 0, norms, cnt));
+    for (int d = 1; d < maxT; ++d) CKS(rec_down(R, dir, it, gk, nullptr, d, false, nullptr));
+    CKS(rec_tail(R, dir, it, gk));
+    for (int d = maxT - 1; d >= 1; --d) CKS(rec_up(R, dir, it, gk, nullptr, d, false));
+    CKS(rec_up(R, dir, it, gk, &l0, 0, acc));
     return MG_OK;
 }
-
-// One V(1,1) cycle for the items.  With norms (and incoming iterates),
-// ||f - A u||^2 of item k lands in w->rtot_h[k] once the stream gets there.
-mg_status vcycle(Run& R, int dir, const std::vector<Item>& it, const std::vector<L0>& l0, bool acc,
-                 bool norms) {
-    if (R.mixed && l0[0].u) return MG_E_STATE;
-    CKS(cycle_down(R, dir, it, &l0, 0, norms));
-    CKS(coarse_part(R, dir, it));
-    CKS(cycle_up(R, dir, it, &l0, 0, acc));
-    return MG_OK;
-}
-
 // ---------------------------------------------------------------------------
-// Vector kernels over items
+// Arnoldi passes (Sec. 4.1: one cycle per outer step)
 // ---------------------------------------------------------------------------
-mg_status build_vec(Run& R, int dir, const std::vector<Item>& it, const std::vector<int>& sub,
-                    VecArgs& a, int* cnt) {
-    a.st.n = (int)sub.size();
-    int blocks = 0;
-    for (int q = 0; q < a.st.n; ++q) {
-        const Item& I = it[sub[q]];
-        VecSlot& s = a.st.s[q];
-        s.lv = I.c->outer_d[dir];
-        s.block0 = blocks;
-        const int nb = mg::vec_blocks(I.c->lv[0].N);
-        if (nb > R.w->bstride) return MG_E_STATE;
-        cnt[q] = nb;
-        blocks += nb;
-    }
-    a.st.nblocks = blocks;
-    a.part = R.w->part;
-    a.rpart = R.w->rpart;
-    a.pstride = HSTRIDE;
-    a.bstride = R.w->bstride;
-    return MG_OK;
-}
-
-mg_status reduce_real(Run& R, int n, const int* cnt) {
-    ReduceArgs ra{};
-    ra.rpart = R.w->rpart;
-    ra.rout = R.w->rtot;
-    ra.bstride = R.w->bstride;
-    for (int q = 0; q < n; ++q) ra.cnt[q] = cnt[q];
-    const int pi = prof_begin(R, MG_K_REDUCE);
-    CK(mg::launch_reduce(ra, n, true, R.s));
-    prof_end(R, pi);
-    return MG_OK;
-}
-
-mg_status reduce_complex(Run& R, int n, const int* cnt, int nvals, int toff) {
-    ReduceArgs ra{};
-    ra.part = R.w->part;
-    ra.out = R.w->tot + toff;
-    ra.nvals = nvals;
-    ra.pstride = HSTRIDE;
-    ra.bstride = R.w->bstride;
-    ra.ostride = TOT;
-    for (int q = 0; q < n; ++q) ra.cnt[q] = cnt[q];
-    const int pi = prof_begin(R, MG_K_REDUCE);
-    CK(mg::launch_reduce(ra, n, false, R.s));
-    prof_end(R, pi);
-    return MG_OK;
-}
-
-// ||x_k||^2 of every item (x[k] a full-length level-0 vector), synchronising.
-mg_status norms(Run& R, const std::vector<Item>& it, const std::vector<const cx<double>*>& x,
-                std::vector<double>& out) {
-    std::vector<int> all(it.size());
-    for (size_t k = 0; k < it.size(); ++k) all[k] = (int)k;
-    CKS(for_groups(all, [&](const std::vector<int>& sub, int gbase) -> mg_status {
-        VecArgs a{};
-        int cnt[mg::MAX_SLOTS];
-        CKS(build_vec(R, 0, it, sub, a, cnt));
-        for (int q = 0; q < a.st.n; ++q) a.st.s[q].x = x[sub[q]];
-        CK(mg::launch_norm(a, R.s));
-        CKS(reduce_real(R, a.st.n, cnt));
-        CK(hipMemcpyAsync(R.w->rtot_h + gbase, R.w->rtot, a.st.n * sizeof(double), hipMemcpyDeviceToHost, R.s));
-        return MG_OK;
-    }));
-    CK(hipStreamSynchronize(R.s));
-    out.resize(it.size());
-    for (size_t k = 0; k < it.size(); ++k) out[k] = R.w->rtot_h[k];
-    return MG_OK;
-}
-
-// y_k = f_k - A x_k (f_k null: y_k = A x_k) on level 0 for the items in
-// `who`; with nrm, ||y_k||^2 into (*nrm)[k] (synchronising).
-mg_status residual(Run& R, int dir, const std::vector<Item>& it, const std::vector<int>& who,
-                   const std::vector<const cx<double>*>& x, const std::vector<const cx<double>*>& f,
-                   const std::vector<cx<double>*>& y, std::vector<double>* nrm) {
-    CKS(for_groups(who, [&](const std::vector<int>& sub, int gbase) -> mg_status {
-        VecArgs a{};
-        int cnt[mg::MAX_SLOTS];
-        CKS(build_vec(R, dir, it, sub, a, cnt));
-        double by = 0.0;
-        for (int q = 0; q < a.st.n; ++q) {
-            a.st.s[q].x = x[sub[q]];
-            a.st.s[q].f = f[sub[q]];
-            a.st.s[q].y = y[sub[q]];
-            by += it[sub[q]].c->lv[0].N * (40.0 + (f[sub[q]] ? 16.0 : 0.0));
-        }
-        if (!nrm) a.rpart = nullptr;
-        const int pi = prof_begin(R, MG_K_RESIDUAL, by);
-        CK(mg::launch_residual(R.dim, a, R.s));
-        prof_end(R, pi);
-        if (nrm) {
-            CKS(reduce_real(R, a.st.n, cnt));
-            CK(hipMemcpyAsync(R.w->rtot_h + gbase, R.w->rtot, a.st.n * sizeof(double), hipMemcpyDeviceToHost,
-                              R.s));
-        }
-        return MG_OK;
-    }));
-    if (nrm) {
-        CK(hipStreamSynchronize(R.s));
-        nrm->assign(it.size(), 0.0);
-        for (size_t g = 0; g < who.size(); ++g) (*nrm)[who[g]] = R.w->rtot_h[g];
-    }
-    return MG_OK;
-}
-
-mg_status ensure_basis(mg_ctx* c, int restart, bool flexible) {
-    if (!c->V || c->vstride < restart + 1) {
-        dfree(c->V);
-        c->vstride = 0;
-        const size_t bytes = (size_t)c->nrhs * (restart + 1) * c->lv[0].N * sizeof(cx<double>);
-        CKS(dalloc(&c->V, bytes));
-        c->vstride = restart + 1;
-    }
-    if (flexible && (!c->Zb || c->zstride < restart)) {
-        dfree(c->Zb);
-        c->zstride = 0;
-        const size_t bytes = (size_t)c->nrhs * restart * c->lv[0].N * sizeof(cx<double>);
-        CKS(dalloc(&c->Zb, bytes));
-        c->zstride = restart;
-    }
-    return MG_OK;
-}
-
-// ---------------------------------------------------------------------------
-// Standalone iteration (Sec. 4.1, LVL-MG): repeated cycles; the residual of
-// the incoming iterate is formed inside the first fused kernel of each cycle
-// (FP64) or by the FP64 residual of the refinement step (mixed).
-// ---------------------------------------------------------------------------
-mg_status solve_standalone(Run& R, int dir, const std::vector<Item>& it, const std::vector<cx<double>*>& U,
-                           const std::vector<const cx<double>*>& F, double rtol, int maxit, int* iters,
-                           double* hist) {
-    const int n = (int)it.size();
-    std::vector<double> nf;
-    CKS(norms(R, it, F, nf));
-    std::vector<int> state(n, 0);   // 0 running, 1 converged, 2 maxit, 3 diverged
-    std::vector<int> its(n, 0);
-    std::vector<int> active;
-    for (int k = 0; k < n; ++k) {
-        if (nf[k] == 0.0) {   // f = 0: the solution is 0
-            CK(mg::launch_fill_zero(U[k], it[k].c->lv[0].N * sizeof(cx<double>), R.s));
-            state[k] = 1;
-            if (hist) hist[(size_t)k * (maxit + 1)] = 0.0;
-        } else {
-            active.push_back(k);
-        }
-    }
-    for (int cyc = 0; cyc < maxit && !active.empty(); ++cyc) {
-        std::vector<Item> sub;
-        std::vector<L0> l0;
-        for (int k : active) {
-            sub.push_back(it[k]);
-            mg_ctx* c = it[k].c;
-            if (!R.mixed && !c->shifted0)
-                l0.push_back(L0{F[k], 1.0, U[k], U[k]});
-            else
-                l0.push_back(L0{c->W + (size_t)it[k].rhs * c->lv[0].N, 1.0, nullptr, U[k]});
-        }
-        std::vector<double> rho(sub.size(), 0.0);
-        if (!R.mixed && !it[0].c->shifted0) {
-            CKS(vcycle(R, dir, sub, l0, false, true));
-            CK(hipStreamSynchronize(R.s));
-            for (size_t q = 0; q < sub.size(); ++q) rho[q] = R.w->rtot_h[q];
-        } else {
-            // iterative refinement form: r = f - A u (FP64), u += M r
-            std::vector<int> who(sub.size());
-            std::vector<const cx<double>*> xs, fs;
-            std::vector<cx<double>*> ys;
-            for (size_t q = 0; q < sub.size(); ++q) {
-                who[q] = (int)q;
-                xs.push_back(U[active[q]]);
-                fs.push_back(F[active[q]]);
-                ys.push_back((cx<double>*)l0[q].f);
-            }
-            std::vector<double> nr;
-            CKS(residual(R, dir, sub, who, xs, fs, ys, &nr));
-            rho = nr;
-            CKS(vcycle(R, dir, sub, l0, true, false));
-        }
-        std::vector<int> next;
-        for (size_t q = 0; q < sub.size(); ++q) {
-            const int k = active[q];
-            const double ratio = std::sqrt(rho[q]) / std::sqrt(nf[k]);
-            if (hist) hist[(size_t)k * (maxit + 1) + cyc] = ratio;
-            its[k] = cyc;
-            if (ratio <= rtol) {
-                state[k] = 1;
-            } else if (!std::isfinite(ratio) || ratio > DIVERGE) {
-                state[k] = 3;
-            } else {
-                its[k] = cyc + 1;
-                next.push_back(k);
-            }
-        }
-        active.swap(next);
-    }
-    CK(hipStreamSynchronize(R.s));
-    mg_status ret = MG_OK;
-    for (int k = 0; k < n; ++k) {
-        if (state[k] == 0) state[k] = 2;
-        if (iters) iters[k] = its[k];
-        if (state[k] == 3) ret = MG_E_DIVERGED;
-        else if (state[k] == 2 && ret == MG_OK) ret = MG_NOT_CONVERGED;
-    }
-    return ret;
-}
-
-// ---------------------------------------------------------------------------
-// Restarted right-preconditioned GMRES(m) (Sec. 4.1: one V(1,1) cycle from a
-// zero guess per outer step).  Arnoldi by classical Gram-Schmidt with one
-// re-orthogonalisation pass; Hessenberg least squares by complex Givens
-// rotations on the host; x += M (V y) at the end of each restart cycle (the
-// cycle is a fixed linear map).  Flexible GMRES (Sec. 3.2.2, for the
-// nonlinear GMRES(3)-smoothed cycle) keeps z_j = M v_j and adds Z y.
-// ---------------------------------------------------------------------------
-struct GmresState {
-    int j = 0;                  // basis vectors V_0..V_j exist
-    int its = 0;
-    int state = 0;              // 0 arnoldi, 1 converged, 2 maxit, 3 diverged
-    double nf = 0.0;
-    std::vector<cd> H;          // (m+1) x m, column-major
-    std::vector<double> cs;
-    std::vector<cd> sn;
-    std::vector<cd> g;
-};
-
 cx<double>* basis(const Item& I, int i) {
     mg_ctx* c = I.c;
     return c->V + ((size_t)I.rhs * c->vstride + i) * c->lv[0].N;
@@ -1121,290 +1232,336 @@ cx<double>* zbasis(const Item& I, int i) {
     mg_ctx* c = I.c;
     return c->Zb + ((size_t)I.rhs * c->zstride + i) * c->lv[0].N;
 }
+cx<double>* wvec(const Item& I) { return I.c->W + (size_t)I.rhs * I.c->lv[0].N; }
+cx<double>* zvec(const Item& I) { return I.c->Z + (size_t)I.rhs * I.c->lv[0].N; }
+double* scale_of(const Item& I) { return I.c->scale_d + (size_t)I.rhs * HSTRIDE; }
 
-mg_status solve_gmres(Run& R, int dir, const std::vector<Item>& it, const std::vector<cx<double>*>& X,
-                      const std::vector<const cx<double>*>& F, double rtol, int maxit, int m, bool flexible,
-                      int* iters, double* hist) {
-    const int n = (int)it.size();
-    for (const Item& I : it) CKS(ensure_basis(I.c, m, flexible));
-    std::vector<GmresState> gs(n);
-    for (int k = 0; k < n; ++k) {
-        gs[k].H.assign((size_t)(m + 1) * m, 0.0);
-        gs[k].cs.assign(m, 0.0);
-        gs[k].sn.assign(m, 0.0);
-        gs[k].g.assign(m + 1, 0.0);
+// Pass 1 of step j: w = A z, partials of h1 = V^H w.
+mg_status rec_matvec_dot(Rec& R, int dir, const std::vector<Item>& it, int gk, bool flexible, int j,
+                         std::vector<int>* cnt) {
+    const int dim = R.dim;
+    return rec_vec(
+        R, dir, it, gk, B_MV, MG_K_MATVEC_DOT, cnt,
+        [&](int k, mg::VecSlot& s, ItemBytes& b) {
+            const Item& I = it[k];
+            s.x = flexible ? zbasis(I, j) : zvec(I);
+            s.y = wvec(I);
+            s.V = basis(I, 0);
+            s.scale = scale_of(I);
+            s.j = j;
+            const double N = (double)I.c->lv[0].N;
+            b.base = N * (16.0 * (j + 1) + 16.0 + 8.0 + 16.0);
+        },
+        [=](const mg::VecArgs& b, hipStream_t s) { return mg::launch_matvec_dot(dim, j + 1, b, s); });
+}
+
+// Pass 2 of step j: V_{j+1} = w - V h, partials of V^H V_{j+1}, ||V_{j+1}||^2.
+mg_status rec_update_gram(Rec& R, int dir, const std::vector<Item>& it, int gk, int j, std::vector<int>* cnt) {
+    return rec_vec(
+        R, dir, it, gk, B_DOT, MG_K_UPDATE_DOT, cnt,
+        [&](int k, mg::VecSlot& s, ItemBytes& b) {
+            const Item& I = it[k];
+            s.y = wvec(I);
+            s.V = basis(I, 0);
+            s.scale = scale_of(I);
+            s.hin = R.w->gst[k].h;
+            s.j = j;
+            const double N = (double)I.c->lv[0].N;
+            b.base = N * (16.0 * (j + 1) + 16.0 + 16.0);
+        },
+        [=](const mg::VecArgs& b, hipStream_t s) { return mg::launch_update_gram(j + 1, b, s); });
+}
+
+// End of a restart cycle: t = sum_i coef_i V_i into W (flexible: x +=
+// sum_i coef_i Z_i), over the basis vectors the cycle built.
+mg_status rec_combine(Rec& R, const std::vector<Item>& it, int gk, const std::vector<cx<double>*>& X, bool flexible,
+                      int m) {
+    return rec_vec(
+        R, 0, it, gk, B_VEC, MG_K_COMBINE, nullptr,
+        [&](int k, mg::VecSlot& s, ItemBytes& b) {
+            const Item& I = it[k];
+            s.V = flexible ? zbasis(I, 0) : basis(I, 0);
+            s.coef = I.c->coef_d + (size_t)I.rhs * HSTRIDE;
+            s.y = flexible ? X[k] : wvec(I);
+            s.jp = &R.w->gfl[k].kk;
+            const double N = (double)I.c->lv[0].N;
+            b.base = N * (16.0 + (flexible ? 16.0 : 0.0));
+            b.per = N * 16.0;
+        },
+        [=](const mg::VecArgs& b, hipStream_t s) { return mg::launch_combine(m, flexible, b, s); });
+}
+
+// ---------------------------------------------------------------------------
+// Solver operations.  GMRES: an initial operation (||f||, zero right-hand
+// sides, first residual) and one restart cycle (m steps for every item,
+// items that stop early gated off, then the solution update and the new
+// residual).  Standalone: an initial operation and a chunk of cycles with
+// the stop test after each.
+// ---------------------------------------------------------------------------
+mg_status rec_gmres_init(Rec& R, int dir, const std::vector<Item>& it, const std::vector<cx<double>*>& X,
+                         const std::vector<const cx<double>*>& F) {
+    R.tag = TAG_ALWAYS;
+    std::vector<int> c1, c2;
+    CKS(rec_norm(R, it, G_NONE, F, &c1));
+    CKS(rec_gm(R, mg::GM_INIT, it, &c1, 0));
+    CKS(rec_vzero(R, it, G_ZERO, X));
+    std::vector<const cx<double>*> xs(X.begin(), X.end());
+    std::vector<cx<double>*> v0(it.size());
+    for (size_t k = 0; k < it.size(); ++k) v0[k] = basis(it[k], 0);
+    CKS(rec_residual(R, dir, it, G_FIN, xs, F, v0, true, &c2));
+    CKS(rec_gm(R, mg::GM_RESTART, it, &c2, 0));
+    return MG_OK;
+}
+
+mg_status rec_gmres_cycle(Rec& R, int dir, const std::vector<Item>& it, const std::vector<cx<double>*>& X,
+                          const std::vector<const cx<double>*>& F, int m, bool flexible) {
+    const size_t n = it.size();
+    for (int j = 0; j < m; ++j) {
+        R.tag = j;
+        std::vector<L0> l0(n);
+        for (size_t k = 0; k < n; ++k)
+            l0[k] = L0{basis(it[k], j), 1.0, scale_of(it[k]) + j, nullptr, flexible ? zbasis(it[k], j) : zvec(it[k])};
+        CKS(rec_cycle(R, dir, it, G_LIVE, l0, false, false, nullptr));
+        std::vector<int> c1, c2;
+        CKS(rec_matvec_dot(R, dir, it, G_LIVE, flexible, j, &c1));
+        CKS(rec_gm(R, mg::GM_H, it, &c1, j));
+        CKS(rec_update_gram(R, dir, it, G_LIVE, j, &c2));
+        CKS(rec_gm(R, mg::GM_COL, it, &c2, j));
     }
-    std::vector<double> nf;
-    CKS(norms(R, it, F, nf));
-    std::vector<int> hist_len(n, 0);
-    auto push_hist = [&](int k, double v) {
-        if (hist && hist_len[k] <= maxit) hist[(size_t)k * (maxit + 1) + hist_len[k]] = v;
-        hist_len[k]++;
-    };
-    auto scale_h = [&](int k, int i) -> double& { return it[k].c->scale_h[(size_t)it[k].rhs * HSTRIDE + i]; };
+    R.tag = TAG_FIN;
+    CKS(rec_combine(R, it, G_FIN, X, flexible, m));
+    if (!flexible) {
+        std::vector<L0> l0(n);
+        for (size_t k = 0; k < n; ++k) l0[k] = L0{wvec(it[k]), 1.0, nullptr, nullptr, X[k]};
+        CKS(rec_cycle(R, dir, it, G_FIN, l0, true, false, nullptr));
+    }
+    std::vector<const cx<double>*> xs(X.begin(), X.end());
+    std::vector<cx<double>*> v0(n);
+    for (size_t k = 0; k < n; ++k) v0[k] = basis(it[k], 0);
+    std::vector<int> c3;
+    CKS(rec_residual(R, dir, it, G_FIN, xs, F, v0, true, &c3));
+    CKS(rec_gm(R, mg::GM_RESTART, it, &c3, 0));
+    return MG_OK;
+}
 
-    // (Re)start: r = f - A x into V_0, beta = ||r||; decide per item.
-    auto restart = [&](const std::vector<int>& who) -> mg_status {
-        std::vector<const cx<double>*> xs(n), fs(n);
-        std::vector<cx<double>*> ys(n);
-        for (int k : who) {
-            xs[k] = X[k];
-            fs[k] = F[k];
-            ys[k] = basis(it[k], 0);
-        }
-        std::vector<double> beta2;
-        CKS(residual(R, dir, it, who, xs, fs, ys, &beta2));
-        for (int k : who) {
-            GmresState& G = gs[k];
-            const double beta = std::sqrt(beta2[k]);
-            const double ratio = beta / G.nf;
-            if (hist_len[k] == 0) push_hist(k, ratio);
-            if (ratio <= rtol) {
-                G.state = 1;
-            } else if (!std::isfinite(ratio)) {
-                G.state = 3;
-            } else if (G.its >= maxit) {
-                G.state = 2;
-            } else {
-                G.j = 0;
-                std::fill(G.g.begin(), G.g.end(), cd(0.0));
-                G.g[0] = beta;
-                scale_h(k, 0) = 1.0 / beta;
-            }
-        }
-        return MG_OK;
-    };
+mg_status rec_sa_init(Rec& R, const std::vector<Item>& it, const std::vector<cx<double>*>& U,
+                      const std::vector<const cx<double>*>& F) {
+    R.tag = TAG_ALWAYS;
+    std::vector<int> c1;
+    CKS(rec_norm(R, it, G_NONE, F, &c1));
+    CKS(rec_gm(R, mg::SA_INIT, it, &c1, 0));
+    CKS(rec_vzero(R, it, G_ZERO, U));
+    return MG_OK;
+}
 
-    std::vector<int> who;
-    for (int k = 0; k < n; ++k) {
-        gs[k].nf = std::sqrt(nf[k]);
-        if (nf[k] == 0.0) {
-            CK(mg::launch_fill_zero(X[k], it[k].c->lv[0].N * sizeof(cx<double>), R.s));
-            gs[k].state = 1;
-            push_hist(k, 0.0);
+// Standalone (Sec. 4.1, LVL-MG): the residual of the incoming iterate is
+// formed inside the first fused kernel of each cycle (FP64), or by the FP64
+// residual of the refinement step u <- u + M (f - A u) (mixed precision,
+// fixed-shift cycle); the stop test follows the cycle.
+mg_status rec_sa_chunk(Rec& R, int dir, const std::vector<Item>& it, const std::vector<cx<double>*>& U,
+                       const std::vector<const cx<double>*>& F, int K) {
+    const size_t n = it.size();
+    const bool direct = !R.mixed && !it[0].c->shifted0;
+    for (int q = 0; q < K; ++q) {
+        R.tag = q;
+        std::vector<int> cnt;
+        std::vector<L0> l0(n);
+        if (direct) {
+            for (size_t k = 0; k < n; ++k) l0[k] = L0{F[k], 1.0, nullptr, U[k], U[k]};
+            CKS(rec_cycle(R, dir, it, G_LIVE, l0, false, true, &cnt));
         } else {
-            who.push_back(k);
+            std::vector<const cx<double>*> xs(U.begin(), U.end());
+            std::vector<cx<double>*> ws(n);
+            for (size_t k = 0; k < n; ++k) ws[k] = wvec(it[k]);
+            CKS(rec_residual(R, dir, it, G_LIVE, xs, F, ws, true, &cnt));
+            for (size_t k = 0; k < n; ++k) l0[k] = L0{ws[k], 1.0, nullptr, nullptr, U[k]};
+            CKS(rec_cycle(R, dir, it, G_LIVE, l0, true, false, nullptr));
+        }
+        CKS(rec_gm(R, mg::SA_STEP, it, &cnt, 0));
+    }
+    return MG_OK;
+}
+
+mg_status ensure_basis(mg_ctx* c, int restart, bool flexible) {
+    if (!c->V || c->vstride < restart + 1) {
+        CK(hipStreamSynchronize(c->stream));
+        dfree(c->V);
+        c->vstride = 0;
+        const size_t bytes = (size_t)c->nrhs * (restart + 1) * c->lv[0].N * sizeof(cx<double>);
+        CKS(dalloc(&c->V, bytes));
+        c->vstride = restart + 1;
+        c->gen++;
+        cache_clear(c->cache);
+    }
+    if (flexible && (!c->Zb || c->zstride < restart)) {
+        CK(hipStreamSynchronize(c->stream));
+        dfree(c->Zb);
+        c->zstride = 0;
+        const size_t bytes = (size_t)c->nrhs * restart * c->lv[0].N * sizeof(cx<double>);
+        CKS(dalloc(&c->Zb, bytes));
+        c->zstride = restart;
+        c->gen++;
+        cache_clear(c->cache);
+    }
+    return MG_OK;
+}
+
+// Sweep schedule of the Arnoldi passes: points per thread (so workgroups
+// per right-hand side), picked by timing both passes at a mid-restart step
+// on the context's own basis.  The choice depends on the context only, so a
+// batch reduces in the same order as a single solve.
+mg_status tune_arnoldi(mg_ctx* c, int m) {
+    if (c->vtuned) return MG_OK;
+    c->vtuned = true;
+    const int j = std::min(8, m - 1);
+    static const int cand[3] = {64, 32, 16};
+    std::vector<Item> it;
+    for (int r = 0; r < c->nrhs; ++r) it.push_back(Item{c, r});
+    hipEvent_t e0, e1;
+    CK(hipEventCreate(&e0));
+    CK(hipEventCreate(&e1));
+    Exec E{c->stream, nullptr, nullptr, false};
+    float best = 1e30f;
+    int pick = c->vper;
+    mg_status st = MG_OK;
+    for (int per : cand) {
+        c->vper = per;
+        Op op;
+        Rec R{&op, &c->work, c->dim, c->mixed, TAG_ALWAYS};
+        st = rec_matvec_dot(R, 0, it, G_NONE, c->Zb != nullptr && c->zstride > j, j, nullptr);
+        if (st == MG_OK) st = rec_update_gram(R, 0, it, G_NONE, j, nullptr);
+        if (st != MG_OK) {   // the work space does not hold this split
+            st = MG_OK;
+            dfree(op.dtab);
+            continue;
+        }
+        float tot = 0.0f;
+        for (int rep = 0; rep < 4 && st == MG_OK; ++rep) {
+            if (hipEventRecord(e0, c->stream) != hipSuccess) st = MG_E_DEVICE;
+            if (st == MG_OK) st = op_run(E, op);
+            if (st == MG_OK && hipEventRecord(e1, c->stream) != hipSuccess) st = MG_E_DEVICE;
+            if (st == MG_OK && hipEventSynchronize(e1) != hipSuccess) st = MG_E_DEVICE;
+            float ms = 0.0f;
+            if (st == MG_OK && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) st = MG_E_DEVICE;
+            if (rep > 0) tot += ms;
+        }
+        dfree(op.dtab);
+        if (st != MG_OK) break;
+        if (tot < 0.97f * best) {
+            best = tot;
+            pick = per;
         }
     }
-    CKS(restart(who));
+    c->vper = pick;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return st;
+}
 
-    std::vector<mg_ctx*> ctxs;
-    for (const Item& I : it)
-        if (std::find(ctxs.begin(), ctxs.end(), I.c) == ctxs.end()) ctxs.push_back(I.c);
+std::vector<uintptr_t> item_key(int kind, int dir, const std::vector<Item>& it, const std::vector<cx<double>*>& U,
+                                const std::vector<const cx<double>*>& F) {
+    std::vector<uintptr_t> key{(uintptr_t)kind, (uintptr_t)dir};
+    for (size_t k = 0; k < it.size(); ++k) {
+        key.push_back((uintptr_t)it[k].c);
+        key.push_back((uintptr_t)it[k].rhs);
+        key.push_back((uintptr_t)it[k].c->gen);
+        key.push_back((uintptr_t)it[k].c->vper);
+        key.push_back((uintptr_t)U[k]);
+        key.push_back((uintptr_t)F[k]);
+    }
+    return key;
+}
 
-    for (;;) {
-        std::vector<int> act;
-        int jmax = 0;
-        for (int k = 0; k < n; ++k)
-            if (gs[k].state == 0) {
-                act.push_back(k);
-                jmax = std::max(jmax, gs[k].j + 1);
-            }
-        if (act.empty()) break;
-        // scales of every basis to the device
-        for (mg_ctx* c : ctxs)
-            CK(hipMemcpyAsync(c->scale_d, c->scale_h, (size_t)c->nrhs * HSTRIDE * sizeof(double),
-                              hipMemcpyHostToDevice, R.s));
-        // z = M v_j for every active item
-        std::vector<Item> sub;
-        std::vector<L0> l0;
-        for (int k : act) {
-            sub.push_back(it[k]);
-            mg_ctx* c = it[k].c;
-            l0.push_back(L0{basis(it[k], gs[k].j), scale_h(k, gs[k].j), nullptr,
-                            flexible ? zbasis(it[k], gs[k].j) : c->Z + (size_t)it[k].rhs * c->lv[0].N});
+enum OpKind { K_GM_INIT = 1, K_GM_CYCLE = 2, K_SA_INIT = 3, K_SA_CHUNK = 4, K_CYCLE = 5, K_APPLY = 6 };
+constexpr int SA_CHUNK = 8;   // standalone cycles per operation
+
+mg_status read_flags(Exec& E, Work& w, int n) {
+    CK(hipMemcpyAsync(w.gfl_h, w.gfl, (size_t)n * sizeof(mg::GmFlags), hipMemcpyDeviceToHost, E.s));
+    CK(hipStreamSynchronize(E.s));
+    return MG_OK;
+}
+
+// Solve for the items: device-driven (F)GMRES(m) or standalone cycles.
+mg_status solve_items(Exec& E, Work& w, int dir, const std::vector<Item>& it, const std::vector<cx<double>*>& U,
+                      const std::vector<const cx<double>*>& F, int mode, double rtol, int maxit, int restart,
+                      int* iters, double* hist) {
+    if (maxit < 0 || !(rtol >= 0.0)) return MG_E_INVAL;
+    const int n = (int)it.size();
+    if (n > w.items) return MG_E_STATE;
+    const bool gm = mode == MG_MODE_GMRES || mode == MG_MODE_FGMRES;
+    if (!gm && mode != MG_MODE_STANDALONE) return MG_E_INVAL;
+    if (gm && (restart < 1 || restart > MAX_RESTART)) return MG_E_INVAL;
+    const bool flexible = gm && (mode == MG_MODE_FGMRES || it[0].c->gsmooth);
+    const int dim = it[0].c->dim;
+    const bool mixed = it[0].c->mixed;
+    CK(hipStreamSynchronize(E.s));
+    if (gm)
+        for (const Item& I : it) {
+            CKS(ensure_basis(I.c, restart, flexible));
+            CKS(tune_arnoldi(I.c, restart));
         }
-        CKS(vcycle(R, dir, sub, l0, false, false));
-        std::vector<int> local(act.size());
-        for (size_t q = 0; q < act.size(); ++q) local[q] = (int)q;
-        CKS(for_groups(local, [&](const std::vector<int>& g, int gbase) -> mg_status {
-            VecArgs a{};
-            int cnt[mg::MAX_SLOTS];
-            CKS(build_vec(R, dir, sub, g, a, cnt));
-            double nvsum = 0.0, vb = 0.0;
-            for (int q = 0; q < a.st.n; ++q) {
-                const int k = act[g[q]];
-                mg_ctx* c = it[k].c;
-                VecSlot& s = a.st.s[q];
-                s.x = flexible ? zbasis(it[k], gs[k].j) : c->Z + (size_t)it[k].rhs * c->lv[0].N;
-                s.y = c->W + (size_t)it[k].rhs * c->lv[0].N;
-                s.V = basis(it[k], 0);
-                s.scale = c->scale_d + (size_t)it[k].rhs * HSTRIDE;
-                s.j = gs[k].j;
-                s.hin = R.w->tot + (size_t)q * TOT;
-                nvsum += 16.0 * c->lv[0].N * (gs[k].j + 1);
-                vb += 16.0 * c->lv[0].N;
-            }
-            // Workgroups per pass: the two dot passes hold 2 (j+1) complex
-            // values per thread and run at 1-2 waves per SIMD, so a round or
-            // two of 64-point-per-thread workgroups fills the chip for the
-            // 8-rhs batch; the lighter norm pass wants more, smaller ones.
-            // The split depends on N only, so a batched solve reduces in the
-            // same order as a single one.
-            auto split = [&](int per, bool mv) -> mg_status {
-                int blocks = 0;
-                for (int q = 0; q < a.st.n; ++q) {
-                    const Level& l0 = it[act[g[q]]].c->lv[0];
-                    cnt[q] = mv ? mg::mv_blocks(R.dim, l0.n, per) : mg::vec_blocks(l0.N, per);
-                    if (cnt[q] > R.w->bstride) return MG_E_STATE;
-                    a.st.s[q].block0 = blocks;
-                    blocks += cnt[q];
-                }
-                a.st.nblocks = blocks;
-                return MG_OK;
-            };
-            // pass 1: w = A z, h1 = V^H w; reads z, k^2, V_0..V_j, writes w
-            CKS(split(VEC_PER_DOT, true));
-            int pi = prof_begin(R, MG_K_MATVEC_DOT, nvsum + 2.0 * vb + 0.5 * vb);
-            CK(mg::launch_matvec_dot(R.dim, jmax, a, R.s));
-            prof_end(R, pi);
-            CKS(reduce_complex(R, a.st.n, cnt, jmax, 0));
-            // pass 2: w -= V h1, h2 = V^H w
-            CKS(split(VEC_PER_DOT, false));
-            pi = prof_begin(R, MG_K_UPDATE_DOT, nvsum + 2.0 * vb);
-            CK(mg::launch_update_dot(jmax, a, R.s));
-            prof_end(R, pi);
-            CKS(reduce_complex(R, a.st.n, cnt, jmax, HSTRIDE));
-            // pass 3: V_{j+1} = w - V h2, ||V_{j+1}||^2
-            CKS(split(VEC_PER_NORM, false));
-            for (int q = 0; q < a.st.n; ++q) a.st.s[q].hin = R.w->tot + (size_t)q * TOT + HSTRIDE;
-            pi = prof_begin(R, MG_K_UPDATE_NORM, nvsum + 2.0 * vb);
-            CK(mg::launch_update_norm(jmax, a, R.s));
-            prof_end(R, pi);
-            CKS(reduce_real(R, a.st.n, cnt));
-            CK(hipMemcpyAsync(R.w->tot_h + (size_t)gbase * TOT, R.w->tot, (size_t)a.st.n * TOT * sizeof(cx<double>),
-                              hipMemcpyDeviceToHost, R.s));
-            CK(hipMemcpyAsync(R.w->rtot_h + gbase, R.w->rtot, a.st.n * sizeof(double), hipMemcpyDeviceToHost,
-                              R.s));
-            return MG_OK;
-        }));
-        CK(hipStreamSynchronize(R.s));
+    const size_t hstride = (size_t)maxit + 1;
+    CKS(ensure_hist(w, (size_t)n * hstride));
+    *w.prm_h = mg::GmParams{rtol, w.hist, (int)hstride, maxit, gm ? restart : 0, flexible ? 1 : 0};
+    CK(hipMemcpyAsync(w.prm, w.prm_h, sizeof(mg::GmParams), hipMemcpyHostToDevice, E.s));
 
-        std::vector<int> fin;
-        for (size_t q = 0; q < act.size(); ++q) {
-            const int k = act[q];
-            GmresState& G = gs[k];
-            const cx<double>* T = R.w->tot_h + q * TOT;
-            const int j = G.j;
-            cd* col = &G.H[(size_t)j * (m + 1)];
-            for (int i = 0; i <= j; ++i) col[i] = cd(T[i].r, T[i].i) + cd(T[HSTRIDE + i].r, T[HSTRIDE + i].i);
-            const double hn = std::sqrt(std::max(0.0, R.w->rtot_h[q]));
-            col[j + 1] = hn;
-            for (int i = 0; i < j; ++i) {
-                const cd a = col[i], b = col[i + 1];
-                col[i] = G.cs[i] * a + G.sn[i] * b;
-                col[i + 1] = -std::conj(G.sn[i]) * a + G.cs[i] * b;
-            }
-            // rotation j zeroing col[j+1] below col[j]
-            const cd a = col[j], b = col[j + 1];
-            double cj;
-            cd sj;
-            if (b == 0.0) {
-                cj = 1.0;
-                sj = 0.0;
-            } else if (a == 0.0) {
-                cj = 0.0;
-                sj = std::conj(b) / std::abs(b);
-            } else {
-                const double t = std::hypot(std::abs(a), std::abs(b));
-                cj = std::abs(a) / t;
-                sj = (a / std::abs(a)) * std::conj(b) / t;
-            }
-            G.cs[j] = cj;
-            G.sn[j] = sj;
-            col[j] = cj * a + sj * b;
-            col[j + 1] = 0.0;
-            G.g[j + 1] = -std::conj(sj) * G.g[j];
-            G.g[j] = cj * G.g[j];
-            G.its++;
-            const double est = std::abs(G.g[j + 1]) / G.nf;
-            push_hist(k, est);
-            if (!std::isfinite(est)) {
-                G.state = 3;
-                continue;
-            }
-            if (hn != 0.0) scale_h(k, j + 1) = 1.0 / hn;
-            if (est <= rtol || G.its >= maxit || j + 1 == m || hn == 0.0)
-                fin.push_back(k);
-            else
-                G.j = j + 1;
+    Op *init = nullptr, *body = nullptr;
+    std::vector<uintptr_t> k0 = item_key(gm ? K_GM_INIT : K_SA_INIT, dir, it, U, F);
+    std::vector<uintptr_t> k1 = item_key(gm ? K_GM_CYCLE : K_SA_CHUNK, dir, it, U, F);
+    if (gm) {
+        k1.push_back((uintptr_t)restart);
+        k1.push_back((uintptr_t)flexible);
+    }
+    CKS(cached(*E.cache, k0, &init, [&](Op& op) {
+        Rec R{&op, &w, dim, mixed, TAG_ALWAYS};
+        return gm ? rec_gmres_init(R, dir, it, U, F) : rec_sa_init(R, it, U, F);
+    }));
+    CKS(cached(*E.cache, k1, &body, [&](Op& op) {
+        Rec R{&op, &w, dim, mixed, TAG_ALWAYS};
+        return gm ? rec_gmres_cycle(R, dir, it, U, F, restart, flexible) : rec_sa_chunk(R, dir, it, U, F, SA_CHUNK);
+    }));
+    int first = -1;
+    CKS(op_run(E, *init, &first));
+    std::vector<int> before(n, 0), live(n, 0), sbefore(n, 0);
+    if (first >= 0) prof_fix(E, *init, first, std::vector<int>(n, 0));
+    // every run of the body advances each running item by at least one step
+    const long long guard = (long long)maxit + 2;
+    for (long long run = 0;; ++run) {
+        CKS(read_flags(E, w, n));
+        bool any = false;
+        for (int k = 0; k < n; ++k) {
+            const mg::GmFlags& f = w.gfl_h[k];
+            before[k] = f.its;
+            sbefore[k] = f.state;
+            any = any || (gm ? f.state == 0 : f.live != 0);
         }
-        if (!fin.empty()) {
-            // y = R^{-1} g, x += M (V y) (flexible: x += Z y)
-            int jm = 0;
-            std::vector<Item> fs;
-            std::vector<L0> fl0;
-            for (int k : fin) {
-                GmresState& G = gs[k];
-                const int kk = G.j + 1;
-                std::vector<cd> y(kk);
-                for (int i = kk - 1; i >= 0; --i) {
-                    cd s = G.g[i];
-                    for (int l = i + 1; l < kk; ++l) s -= G.H[(size_t)l * (m + 1) + i] * y[l];
-                    y[i] = s / G.H[(size_t)i * (m + 1) + i];
-                }
-                mg_ctx* c = it[k].c;
-                for (int i = 0; i < kk; ++i)
-                    c->coef_h[(size_t)it[k].rhs * HSTRIDE + i] = tocx(flexible ? y[i] : y[i] * scale_h(k, i));
-                jm = std::max(jm, kk);
-                fs.push_back(it[k]);
-                fl0.push_back(L0{c->W + (size_t)it[k].rhs * c->lv[0].N, 1.0, nullptr, X[k]});
+        if (!any) break;
+        if (run >= guard) return MG_E_STATE;
+        CKS(op_run(E, *body, &first));
+        if (first >= 0) {
+            CKS(read_flags(E, w, n));
+            for (int k = 0; k < n; ++k) {
+                const mg::GmFlags& f = w.gfl_h[k];
+                live[k] = f.its - before[k];
+                if (!gm && sbefore[k] == 0 && (f.state == 1 || f.state == 3)) live[k]++;
             }
-            for (mg_ctx* c : ctxs)
-                CK(hipMemcpyAsync(c->coef_d, c->coef_h, (size_t)c->nrhs * HSTRIDE * sizeof(cx<double>),
-                                  hipMemcpyHostToDevice, R.s));
-            std::vector<int> local2(fin.size());
-            for (size_t q = 0; q < fin.size(); ++q) local2[q] = (int)q;
-            CKS(for_groups(local2, [&](const std::vector<int>& g, int) -> mg_status {
-                VecArgs a{};
-                int cnt[mg::MAX_SLOTS];
-                CKS(build_vec(R, dir, fs, g, a, cnt));
-                double by = 0.0;
-                for (int q = 0; q < a.st.n; ++q) {
-                    const int k = fin[g[q]];
-                    mg_ctx* c = it[k].c;
-                    VecSlot& s = a.st.s[q];
-                    s.V = flexible ? zbasis(it[k], 0) : basis(it[k], 0);
-                    s.coef = c->coef_d + (size_t)it[k].rhs * HSTRIDE;
-                    s.y = flexible ? X[k] : c->W + (size_t)it[k].rhs * c->lv[0].N;
-                    s.j = gs[k].j;
-                    by += 16.0 * c->lv[0].N * (gs[k].j + 2 + (flexible ? 1 : 0));
-                }
-                const int pi = prof_begin(R, MG_K_COMBINE, by);
-                CK(mg::launch_combine(jm, flexible, a, R.s));
-                prof_end(R, pi);
-                return MG_OK;
-            }));
-            if (!flexible) CKS(vcycle(R, dir, fs, fl0, true, false));
-            CKS(restart(fin));
+            prof_fix(E, *body, first, live);
         }
     }
-    CK(hipStreamSynchronize(R.s));
+    if (hist) CK(hipMemcpyAsync(hist, w.hist, (size_t)n * hstride * sizeof(double), hipMemcpyDeviceToHost, E.s));
+    CK(hipStreamSynchronize(E.s));
     mg_status ret = MG_OK;
     for (int k = 0; k < n; ++k) {
-        if (iters) iters[k] = gs[k].its;
-        if (gs[k].state == 3) ret = MG_E_DIVERGED;
-        else if (gs[k].state == 2 && ret == MG_OK) ret = MG_NOT_CONVERGED;
+        const mg::GmFlags& f = w.gfl_h[k];
+        if (iters) iters[k] = f.its;
+        const int state = (!gm && f.state == 0) ? 2 : f.state;
+        if (state == 3) ret = MG_E_DIVERGED;
+        else if (state == 2 && ret == MG_OK) ret = MG_NOT_CONVERGED;
     }
     return ret;
 }
 
-mg_status solve_items(Run& R, int dir, const std::vector<Item>& it, const std::vector<cx<double>*>& U,
-                      const std::vector<const cx<double>*>& F, int mode, double rtol, int maxit, int restart,
-                      int* iters, double* hist) {
-    if (maxit < 0 || !(rtol >= 0.0)) return MG_E_INVAL;
-    if (hist)
-        for (size_t i = 0; i < it.size() * (size_t)(maxit + 1); ++i) hist[i] = -1.0;
-    if (mode == MG_MODE_STANDALONE) return solve_standalone(R, dir, it, U, F, rtol, maxit, iters, hist);
-    if (mode == MG_MODE_GMRES || mode == MG_MODE_FGMRES) {
-        if (restart < 1 || restart > MAX_RESTART) return MG_E_INVAL;
-        const bool flexible = mode == MG_MODE_FGMRES || it[0].c->gsmooth;
-        return solve_gmres(R, dir, it, U, F, rtol, maxit, restart, flexible, iters, hist);
-    }
-    return MG_E_INVAL;
-}
-
-Run ctx_run(mg_ctx* c) { return Run{c->stream, &c->prof, &c->work, &c->graphs, c->dim, c->mixed}; }
+Exec ctx_exec(mg_ctx* c) { return Exec{c->stream, &c->prof, &c->cache, true}; }
 
 mg_status ctx_solve(mg_ctx* c, int dir, double* u, const double* f, int mode, double rtol, int maxit,
                     int restart, int* iters, double* hist) {
@@ -1418,16 +1575,15 @@ mg_status ctx_solve(mg_ctx* c, int dir, double* u, const double* f, int mode, do
         U.push_back((cx<double>*)u + (size_t)r * N);
         F.push_back((const cx<double>*)f + (size_t)r * N);
     }
-    Run R = ctx_run(c);
-    return solve_items(R, dir, it, U, F, mode, rtol, maxit, restart, iters, hist);
+    Exec E = ctx_exec(c);
+    return solve_items(E, c->work, dir, it, U, F, mode, rtol, maxit, restart, iters, hist);
 }
-
 // ---------------------------------------------------------------------------
 // Set-up
 // ---------------------------------------------------------------------------
 void release(mg_ctx* c) {
     if (!c) return;
-    graphs_free(c->graphs);
+    cache_free(c->cache);
     for (Level& L : c->lv) {
         for (int d = 0; d < 2; ++d) {
             dfree(L.coef_d[d]);
@@ -1457,12 +1613,11 @@ void release(mg_ctx* c) {
     dfree(c->V);
     dfree(c->scale_d);
     dfree(c->coef_d);
-    hfree(c->scale_h);
-    hfree(c->coef_h);
     work_free(c->work);
     for (hipEvent_t e : c->prof.pool) (void)hipEventDestroy(e);
     c->prof.pool.clear();
 }
+
 
 // Device descriptors of every level, both directions and precisions.
 mg_status upload_views(mg_ctx* c) {
@@ -1523,17 +1678,19 @@ mg_status upload_views(mg_ctx* c) {
     return MG_OK;
 }
 
+
 // Pick the tile shape of every large enough level by timing the two fused
-// kernels (zero-guess variants, all right-hand sides) for every shape.
+// passes of the level (zero-guess variants, all right-hand sides) for every
+// shape, launched one by one.
 mg_status autotune(mg_ctx* c) {
-    std::vector<Item> it;
-    std::vector<L0> l0;
     const long long N0 = c->lv[0].N;
     if (N0 < AUTOTUNE_MIN_POINTS) return MG_OK;
+    std::vector<Item> it;
+    std::vector<L0> l0;
     CK(mg::launch_fill_zero(c->Z, (long long)c->nrhs * N0 * sizeof(cx<double>), c->stream));
     for (int r = 0; r < c->nrhs; ++r) {
         it.push_back(Item{c, r});
-        l0.push_back(L0{c->Z + (size_t)r * N0, 1.0, nullptr, c->W + (size_t)r * N0});
+        l0.push_back(L0{c->Z + (size_t)r * N0, 1.0, nullptr, nullptr, c->W + (size_t)r * N0});
     }
     for (int l = 1; l < c->L; ++l) {
         CK(mg::launch_fill_zero(c->lv[l].F, (long long)c->nrhs * c->lv[l].N * elem(c), c->stream));
@@ -1542,9 +1699,7 @@ mg_status autotune(mg_ctx* c) {
     hipEvent_t e0, e1;
     CK(hipEventCreate(&e0));
     CK(hipEventCreate(&e1));
-    Run R = ctx_run(c);
-    R.prof = nullptr;
-    R.gc = nullptr;
+    Exec E{c->stream, nullptr, nullptr, false};
     mg_status st = MG_OK;
     for (int l = 0; l < c->lt && st == MG_OK; ++l) {
         if (c->lv[l].N < AUTOTUNE_MIN_POINTS) break;
@@ -1552,17 +1707,21 @@ mg_status autotune(mg_ctx* c) {
         int best_shape = 0;
         for (int shape = 0; shape < mg::NUM_TILE_SHAPES && st == MG_OK; ++shape) {
             c->lv[l].shape = shape;
+            Op op;
+            Rec R{&op, &c->work, c->dim, c->mixed, TAG_ALWAYS};
+            st = rec_down(R, 0, it, G_NONE, &l0, l, false, nullptr);
+            if (st == MG_OK) st = rec_up(R, 0, it, G_NONE, &l0, l, false);
             float tot = 0.0f;
             for (int rep = 0; rep < 4 && st == MG_OK; ++rep) {
                 if (hipEventRecord(e0, c->stream) != hipSuccess) st = MG_E_DEVICE;
-                if (st == MG_OK) st = cycle_down(R, 0, it, &l0, l, false);
-                if (st == MG_OK) st = cycle_up(R, 0, it, &l0, l, false);
+                if (st == MG_OK) st = op_run(E, op);
                 if (st == MG_OK && hipEventRecord(e1, c->stream) != hipSuccess) st = MG_E_DEVICE;
                 if (st == MG_OK && hipEventSynchronize(e1) != hipSuccess) st = MG_E_DEVICE;
                 float ms = 0.0f;
                 if (st == MG_OK && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) st = MG_E_DEVICE;
                 if (rep > 0) tot += ms;
             }
+            dfree(op.dtab);
             if (tot < best) {
                 best = tot;
                 best_shape = shape;
@@ -1573,6 +1732,26 @@ mg_status autotune(mg_ctx* c) {
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     return st;
+}
+
+// Workgroups per right-hand side that any launch of this context may use
+// (so the partial sums it writes fit the work space).
+int max_blocks(const mg_ctx* c) {
+    int m = mg::vec_blocks(c->lv[0].N);
+    for (int shape = 0; shape < mg::NUM_TILE_SHAPES; ++shape) {
+        int nt[3];
+        mg::tile_counts(c->dim, shape, c->lv[0].n, nt);
+        m = std::max(m, nt[0] * nt[1] * nt[2]);
+        if (c->dim == 2) {
+            mg::march_counts(shape, c->lv[0].n, nt);
+            m = std::max(m, nt[0] * nt[1]);
+        }
+    }
+    for (int per : {16, 32, 64}) {
+        m = std::max(m, mg::mv_blocks(c->dim, c->lv[0].n, per));
+        m = std::max(m, mg::vec_blocks(c->lv[0].N, per));
+    }
+    return m;
 }
 
 mg_status setup(const mg_params* p, const double* k2_dev, void* stream, mg_ctx* c) {
@@ -1766,22 +1945,9 @@ mg_status setup(const mg_params* p, const double* k2_dev, void* stream, mg_ctx* 
     if (!c->mixed) CKS(dalloc(&c->U1, vbytes));
     CKS(dalloc(&c->Z, vbytes));
     CKS(dalloc(&c->W, vbytes));
-    int maxt = 0;
-    for (int shape = 0; shape < mg::NUM_TILE_SHAPES; ++shape) {
-        int nt[3];
-        mg::tile_counts(d, shape, c->lv[0].n, nt);
-        maxt = std::max(maxt, nt[0] * nt[1] * nt[2]);
-        if (d == 2) {
-            mg::march_counts(shape, c->lv[0].n, nt);
-            maxt = std::max(maxt, nt[0] * nt[1]);
-        }
-    }
-    maxt = std::max(maxt, mg::mv_blocks(c->dim, c->lv[0].n, VEC_PER_DOT));
-    CKS(work_alloc(c->work, c->nrhs, std::max(maxt, mg::vec_blocks(c->lv[0].N))));
+    CKS(work_alloc(c->work, c->nrhs, max_blocks(c)));
     CKS(dalloc(&c->scale_d, (size_t)c->nrhs * HSTRIDE * sizeof(double)));
     CKS(dalloc(&c->coef_d, (size_t)c->nrhs * HSTRIDE * sizeof(cx<double>)));
-    CKS(halloc(&c->scale_h, (size_t)c->nrhs * HSTRIDE * sizeof(double)));
-    CKS(halloc(&c->coef_h, (size_t)c->nrhs * HSTRIDE * sizeof(cx<double>)));
     CK(hipStreamSynchronize(c->stream));
     CKS(autotune(c));
     CK(hipStreamSynchronize(c->stream));
@@ -1840,39 +2006,45 @@ mg_status mg_setup(const mg_params* p, const double* k2_dev, void* stream, mg_ct
 mg_status mg_cycle(mg_ctx* c, double* u, const double* f, double* res_before) {
     if (!c || !u || !f) return MG_E_INVAL;
     const long long N = c->lv[0].N;
+    const int n = c->nrhs;
     std::vector<Item> it;
-    std::vector<L0> l0;
-    Run R = ctx_run(c);
-    for (int r = 0; r < c->nrhs; ++r) {
+    std::vector<cx<double>*> U;
+    std::vector<const cx<double>*> F;
+    for (int r = 0; r < n; ++r) {
         it.push_back(Item{c, r});
-        cx<double>* ur = (cx<double>*)u + (size_t)r * N;
-        const cx<double>* fr = (const cx<double>*)f + (size_t)r * N;
-        if (!c->mixed && !c->shifted0)
-            l0.push_back(L0{fr, 1.0, ur, ur});
-        else
-            l0.push_back(L0{c->W + (size_t)r * N, 1.0, nullptr, ur});
+        U.push_back((cx<double>*)u + (size_t)r * N);
+        F.push_back((const cx<double>*)f + (size_t)r * N);
     }
-    if (!c->mixed && !c->shifted0) {
-        CKS(vcycle(R, 0, it, l0, false, res_before != nullptr));
-        if (res_before) {
-            CK(hipStreamSynchronize(c->stream));
-            for (int r = 0; r < c->nrhs; ++r) res_before[r] = std::sqrt(c->work.rtot_h[r]);
+    const bool want = res_before != nullptr;
+    const bool direct = !c->mixed && !c->shifted0;
+    std::vector<uintptr_t> key = item_key(K_CYCLE, 0, it, U, F);
+    key.push_back(want ? 1 : 0);
+    Op* op = nullptr;
+    CKS(cached(c->cache, key, &op, [&](Op& o) -> mg_status {
+        Rec R{&o, &c->work, c->dim, c->mixed, TAG_ALWAYS};
+        std::vector<int> cnt;
+        std::vector<L0> l0(n);
+        if (direct) {
+            for (int r = 0; r < n; ++r) l0[r] = L0{F[r], 1.0, nullptr, U[r], U[r]};
+            CKS(rec_cycle(R, 0, it, G_NONE, l0, false, want, &cnt));
+            if (want) CKS(rec_reduce_real(R, cnt));
+        } else {
+            std::vector<const cx<double>*> xs(U.begin(), U.end());
+            std::vector<cx<double>*> ws(n);
+            for (int r = 0; r < n; ++r) ws[r] = wvec(it[r]);
+            CKS(rec_residual(R, 0, it, G_NONE, xs, F, ws, want, &cnt));
+            if (want) CKS(rec_reduce_real(R, cnt));
+            for (int r = 0; r < n; ++r) l0[r] = L0{ws[r], 1.0, nullptr, nullptr, U[r]};
+            CKS(rec_cycle(R, 0, it, G_NONE, l0, true, false, nullptr));
         }
-    } else {
-        std::vector<int> who(c->nrhs);
-        std::vector<const cx<double>*> xs, fs;
-        std::vector<cx<double>*> ys;
-        for (int r = 0; r < c->nrhs; ++r) {
-            who[r] = r;
-            xs.push_back((const cx<double>*)u + (size_t)r * N);
-            fs.push_back((const cx<double>*)f + (size_t)r * N);
-            ys.push_back(c->W + (size_t)r * N);
-        }
-        std::vector<double> nr;
-        CKS(residual(R, 0, it, who, xs, fs, ys, res_before ? &nr : nullptr));
-        if (res_before)
-            for (int r = 0; r < c->nrhs; ++r) res_before[r] = std::sqrt(nr[r]);
-        CKS(vcycle(R, 0, it, l0, true, false));
+        return MG_OK;
+    }));
+    Exec E = ctx_exec(c);
+    CKS(op_run(E, *op));
+    if (want) {
+        CK(hipMemcpyAsync(c->work.rtot_h, c->work.rtot, n * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        CK(hipStreamSynchronize(c->stream));
+        for (int r = 0; r < n; ++r) res_before[r] = std::sqrt(c->work.rtot_h[r]);
     }
     return MG_OK;
 }
@@ -1889,10 +2061,10 @@ mg_status mg_solve_adjoint(mg_ctx* c, double* lam, const double* g, int mode, do
 
 mg_status mg_grad_k2(mg_ctx* c, const double* u, const double* lam, double* grad) {
     if (!c || !u || !lam || !grad) return MG_E_INVAL;
-    Run R = ctx_run(c);
-    const int pi = prof_begin(R, MG_K_OTHER, (double)c->lv[0].N * (32.0 * c->nrhs + 16.0));
+    Exec E = ctx_exec(c);
+    const int pi = prof_begin(E, MG_K_OTHER, (double)c->lv[0].N * (32.0 * c->nrhs + 16.0));
     CK(mg::launch_grad_k2((const cx<double>*)u, (const cx<double>*)lam, c->nrhs, c->lv[0].N, grad, c->stream));
-    prof_end(R, pi);
+    prof_end(E, pi);
     return MG_OK;
 }
 
@@ -1900,23 +2072,35 @@ mg_status mg_apply(mg_ctx* c, int level, int adjoint, const double* x, double* y
     if (!c || !x || !y || level < 0 || level >= c->L) return MG_E_INVAL;
     const long long N = c->lv[level].N;
     const int dir = adjoint ? 1 : 0;
-    for (int r0 = 0; r0 < c->nrhs; r0 += mg::MAX_SLOTS) {
-        VecArgs a{};
-        a.st.n = std::min(mg::MAX_SLOTS, c->nrhs - r0);
+    std::vector<uintptr_t> key{(uintptr_t)K_APPLY, (uintptr_t)level, (uintptr_t)dir, (uintptr_t)x, (uintptr_t)y};
+    Op* op = nullptr;
+    CKS(cached(c->cache, key, &op, [&](Op& o) -> mg_status {
+        std::vector<VecSlot> sl(c->nrhs);
         int blocks = 0;
-        for (int q = 0; q < a.st.n; ++q) {
-            VecSlot& s = a.st.s[q];
+        for (int r = 0; r < c->nrhs; ++r) {
+            VecSlot& s = sl[r];
+            s = VecSlot{};
             s.lv = c->views_d[dir] + level;
-            s.x = (const cx<double>*)x + (size_t)(r0 + q) * N;
-            s.y = (cx<double>*)y + (size_t)(r0 + q) * N;
+            s.x = (const cx<double>*)x + (size_t)r * N;
+            s.y = (cx<double>*)y + (size_t)r * N;
             s.block0 = blocks;
             blocks += mg::vec_blocks(N);
         }
+        VecArgs a{};
+        a.st.n = c->nrhs;
         a.st.nblocks = blocks;
-        a.bstride = c->work.bstride;
-        CK(mg::launch_residual(c->dim, a, c->stream));
-    }
-    return MG_OK;
+        const size_t off = put(o, sl);
+        const int dim = c->dim;
+        o.steps.push_back(Step{[=](hipStream_t s, const char* base) {
+                                   VecArgs b = a;
+                                   b.st.s = (const VecSlot*)(base + off);
+                                   return mg::launch_residual(dim, b, s);
+                               },
+                               MG_K_OTHER, TAG_ALWAYS, {}});
+        return MG_OK;
+    }));
+    Exec E = ctx_exec(c);
+    return op_run(E, *op);
 }
 
 int mg_tile_shape(mg_ctx* c, int level, int shape) {
@@ -1925,7 +2109,7 @@ int mg_tile_shape(mg_ctx* c, int level, int shape) {
     if (shape >= 0) {
         if (hipStreamSynchronize(c->stream) != hipSuccess) return MG_E_DEVICE;
         c->lv[level].shape = shape;
-        graphs_free(c->graphs);   // captured coarse parts hold the old shapes
+        cache_clear(c->cache);   // recorded operations hold the old shapes
     }
     return c->lv[level].shape;
 }
@@ -1975,14 +2159,14 @@ mg_status mg_batch_solve(mg_batch* b, double* const* u, const double* const* f, 
         }
     }
     mg_ctx* c0 = b->ctxs[0];
-    Run R{c0->stream, &c0->prof, &b->work, &b->graphs, c0->dim, c0->mixed};
-    return solve_items(R, 0, it, U, F, mode, rtol, maxit, restart, iters, hist);
+    Exec E{c0->stream, &c0->prof, &b->cache, true};
+    return solve_items(E, b->work, 0, it, U, F, mode, rtol, maxit, restart, iters, hist);
 }
 
 void mg_batch_destroy(mg_batch* b) {
     if (!b) return;
     if (!b->ctxs.empty()) (void)hipStreamSynchronize(b->ctxs[0]->stream);
-    graphs_free(b->graphs);
+    cache_free(b->cache);
     work_free(b->work);
     delete b;
 }

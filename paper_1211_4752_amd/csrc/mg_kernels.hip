@@ -10,10 +10,12 @@
 //   k_prolong_smooth   (bi/tri)linear interpolation of the coarse correction,
 //                      v <- v + e (Sec. 3.1), and omega-Jacobi
 //                      post-smoothing, fused through LDS tiles.
-//   k_matvec_dot / k_update_dot / k_update_norm
+//   k_matvec_dot / k_update_gram
 //                      the GMRES Arnoldi step (Sec. 4.1: one cycle per outer
-//                      step) as three passes of classical Gram-Schmidt with
-//                      re-orthogonalisation, each fused with its dot products.
+//                      step) as two passes: w = A z fused with h1 = V^H w,
+//                      then v = w - V h fused with V^H v and ||v||^2, where h
+//                      is h1 plus the second Gram-Schmidt projection formed
+//                      from the Gram matrix of the stored basis.
 // Reductions are two-stage and deterministic: per-workgroup partials in a
 // fixed tree, then a fixed-order sum per value.
 //
@@ -52,6 +54,7 @@ __global__ void __launch_bounds__(NT) k_smooth_restrict(const CycleArgs a) {
     const int pid = xcd_remap(blockIdx.x, gridDim.x);
     const int slot = find_slot(a.st.s, a.st.n, pid);
     const CycleSlot& sl = a.st.s[slot];
+    if (gated_off(sl.gate)) return;
     const int tile = pid - sl.tile0;
     const LevelView<T>* Lp = static_cast<const LevelView<T>*>(sl.lv);
     const LevelView<T> L = *Lp;
@@ -63,7 +66,7 @@ __global__ void __launch_bounds__(NT) k_smooth_restrict(const CycleArgs a) {
     const int tz = rest / nty;
     const int x0 = tx * TX, y0 = ty * TY, z0 = tz * TZE;
     const cx<TF>* f = static_cast<const cx<TF>*>(sl.f);
-    const T fs = (T)sl.fscale;
+    const T fs = (T)fscale_of(sl);
     cx<T>* u1p = static_cast<cx<T>*>(sl.u1);
 
     if constexpr (!ZERO) {
@@ -195,6 +198,7 @@ __global__ void __launch_bounds__(NT) k_prolong_smooth(const CycleArgs a) {
     const int pid = xcd_remap(blockIdx.x, gridDim.x);
     const int slot = find_slot(a.st.s, a.st.n, pid);
     const CycleSlot& sl = a.st.s[slot];
+    if (gated_off(sl.gate)) return;
     const int tile = pid - sl.tile0;
     const LevelView<T>* Lp = static_cast<const LevelView<T>*>(sl.lv);
     const LevelView<T> L = *Lp;
@@ -207,7 +211,7 @@ __global__ void __launch_bounds__(NT) k_prolong_smooth(const CycleArgs a) {
     const int tz = rest / nty;
     const int x0 = tx * TX, y0 = ty * TY, z0 = tz * TZE;
     const cx<TF>* f = static_cast<const cx<TF>*>(sl.f);
-    const T fs = (T)sl.fscale;
+    const T fs = (T)fscale_of(sl);
     const cx<T>* ec = static_cast<const cx<T>*>(sl.c);
     const cx<T>* u1in = static_cast<const cx<T>*>(sl.u1);
     const int cxs = x0 / 2 - 1, cys = y0 / 2 - 1, czs = (D == 3) ? z0 / 2 - 1 : 0;
@@ -321,6 +325,7 @@ __global__ void __launch_bounds__(NT) k_residual(const VecArgs a) {
     __shared__ double sred[NT / 64];
     VecPos q = vec_pos(a.st);
     const VecSlot& sl = a.st.s[q.slot];
+    if (gated_off(sl.gate)) return;
     const LevelView<double> L = *static_cast<const LevelView<double>*>(sl.lv);
     chunk_range(L.N, q.nb, q.b, q.lo, q.hi);
     double nrm = 0.0;
@@ -346,6 +351,7 @@ __global__ void __launch_bounds__(NT) k_norm(const VecArgs a) {
     __shared__ double sred[NT / 64];
     VecPos q = vec_pos(a.st);
     const VecSlot& sl = a.st.s[q.slot];
+    if (gated_off(sl.gate)) return;
     const long long N = static_cast<const LevelView<double>*>(sl.lv)->N;
     chunk_range(N, q.nb, q.b, q.lo, q.hi);
     double nrm = 0.0;
@@ -387,6 +393,7 @@ __global__ void __launch_bounds__(NT) k_matvec_dot(const VecArgs a) {
     __shared__ cx<double> sm[(NT / 64) * MAXJ];
     VecPos q = vec_pos(a.st);
     const VecSlot& sl = a.st.s[q.slot];
+    if (gated_off(sl.gate)) return;
     const LevelView<double> L = *static_cast<const LevelView<double>*>(sl.lv);
     const long long N = L.N;
     const int nv = sl.j + 1;
@@ -466,68 +473,61 @@ __global__ void __launch_bounds__(NT) k_matvec_dot(const VecArgs a) {
     block_sum_vec<MAXJ>(acc, nv, sm, a.part + (long long)q.slot * a.pstride * a.bstride, a.bstride, q.b);
 }
 
-// w -= sum_i h_i v_i, then h2_i = <v_i, w>.
+// Second pass of the Arnoldi step (classical Gram-Schmidt applied twice
+// with one reduction per pass): V_{j+1} = w - sum_i h_i v_i, where h already
+// contains the second projection (formed on the device from the Gram
+// matrix of the stored basis), fused with the partials of <v_i, V_{j+1}>
+// (i <= j; the next column of that Gram matrix) and of ||V_{j+1}||^2 (value
+// j + 1).  The coefficients scale_i h_i are staged in LDS.
 template <int MAXJ>
-__global__ void __launch_bounds__(NT) k_update_dot(const VecArgs a) {
-    __shared__ cx<double> sm[(NT / 64) * MAXJ];
+__global__ void __launch_bounds__(NT) k_update_gram(const VecArgs a) {
+    __shared__ cx<double> sm[(NT / 64) * (MAXJ + 1)];
+    __shared__ cx<double> sc[MAXJ];
     VecPos q = vec_pos(a.st);
     const VecSlot& sl = a.st.s[q.slot];
+    if (gated_off(sl.gate)) return;
     const long long N = static_cast<const LevelView<double>*>(sl.lv)->N;
     const int nv = sl.j + 1;
-    cx<double>* w = sl.y;
+    const cx<double>* w = sl.y;
     const cx<double>* V = sl.V;
-    cx<double> coef[MAXJ];
-#pragma unroll
-    for (int i = 0; i < MAXJ; ++i) coef[i] = (i < nv) ? sl.scale[i] * sl.hin[i] : mk(0.0, 0.0);
+    if ((int)threadIdx.x < MAXJ) sc[threadIdx.x] = ((int)threadIdx.x < nv) ? sl.scale[threadIdx.x] * sl.hin[threadIdx.x]
+                                                                          : mk(0.0, 0.0);
+    __syncthreads();
     chunk_range(N, q.nb, q.b, q.lo, q.hi);
-    cx<double> acc[MAXJ];
+    cx<double>* vout = sl.V + (long long)nv * N;
+    cx<double> acc[MAXJ + 1];
 #pragma unroll
-    for (int i = 0; i < MAXJ; ++i) acc[i] = mk(0.0, 0.0);
+    for (int i = 0; i <= MAXJ; ++i) acc[i] = mk(0.0, 0.0);
     for (int p = q.lo + (int)threadIdx.x; p < q.hi; p += NT) {
         cx<double> vv[MAXJ];
 #pragma unroll
         for (int i = 0; i < MAXJ; ++i) vv[i] = (i < nv) ? V[(long long)i * N + p] : mk(0.0, 0.0);
         cx<double> wv = w[p];
 #pragma unroll
-        for (int i = 0; i < MAXJ; ++i) wv = wv - coef[i] * vv[i];
-        w[p] = wv;
+        for (int i = 0; i < MAXJ; ++i) wv = wv - sc[i] * vv[i];
+        vout[p] = wv;
 #pragma unroll
         for (int i = 0; i < MAXJ; ++i) acc[i] = acc[i] + cmulc(vv[i], wv);
+        acc[MAXJ].r += abs2(wv);
     }
 #pragma unroll
     for (int i = 0; i < MAXJ; ++i)
         if (i < nv) acc[i] = sl.scale[i] * acc[i];
-    block_sum_vec<MAXJ>(acc, nv, sm, a.part + (long long)q.slot * a.pstride * a.bstride, a.bstride, q.b);
+    // value nv carries the norm
+    cx<double> out[MAXJ + 1];
+#pragma unroll
+    for (int i = 0; i <= MAXJ; ++i) out[i] = (i < nv) ? acc[i] : (i == nv ? acc[MAXJ] : mk(0.0, 0.0));
+    block_sum_vec<MAXJ + 1>(out, nv + 1, sm, a.part + (long long)q.slot * a.pstride * a.bstride, a.bstride, q.b);
 }
 
-// V_{j+1} = w - sum_i h_i v_i, ||V_{j+1}||^2 partials.
-template <int MAXJ>
-__global__ void __launch_bounds__(NT) k_update_norm(const VecArgs a) {
-    __shared__ double sred[NT / 64];
+// y = 0 (gated).
+__global__ void __launch_bounds__(NT) k_vzero(const VecArgs a) {
     VecPos q = vec_pos(a.st);
     const VecSlot& sl = a.st.s[q.slot];
+    if (gated_off(sl.gate)) return;
     const long long N = static_cast<const LevelView<double>*>(sl.lv)->N;
-    const int nv = sl.j + 1;
-    const cx<double>* w = sl.y;
-    cx<double>* V = sl.V;
-    cx<double> coef[MAXJ];
-#pragma unroll
-    for (int i = 0; i < MAXJ; ++i) coef[i] = (i < nv) ? sl.scale[i] * sl.hin[i] : mk(0.0, 0.0);
     chunk_range(N, q.nb, q.b, q.lo, q.hi);
-    cx<double>* vout = V + (long long)nv * N;
-    double nrm = 0.0;
-    for (int p = q.lo + (int)threadIdx.x; p < q.hi; p += NT) {
-        cx<double> vv[MAXJ];
-#pragma unroll
-        for (int i = 0; i < MAXJ; ++i) vv[i] = (i < nv) ? V[(long long)i * N + p] : mk(0.0, 0.0);
-        cx<double> wv = w[p];
-#pragma unroll
-        for (int i = 0; i < MAXJ; ++i) wv = wv - coef[i] * vv[i];
-        vout[p] = wv;
-        nrm += abs2(wv);
-    }
-    const double s = block_sum(nrm, sred);
-    if (threadIdx.x == 0) a.rpart[(long long)q.slot * a.bstride + q.b] = s;
+    for (int p = q.lo + (int)threadIdx.x; p < q.hi; p += NT) sl.y[p] = mk(0.0, 0.0);
 }
 
 // t = sum_i coef_i V_i (ACC: t += ...).
@@ -535,8 +535,9 @@ template <int MAXJ, bool ACC>
 __global__ void __launch_bounds__(NT) k_combine(const VecArgs a) {
     VecPos q = vec_pos(a.st);
     const VecSlot& sl = a.st.s[q.slot];
+    if (gated_off(sl.gate)) return;
     const long long N = static_cast<const LevelView<double>*>(sl.lv)->N;
-    const int nv = sl.j + 1;
+    const int nv = (sl.jp ? *sl.jp : sl.j) + 1;
     const cx<double>* V = sl.V;
     cx<double> coef[MAXJ];
 #pragma unroll
@@ -731,7 +732,7 @@ hipError_t launch_norm(const VecArgs& a, hipStream_t s) {
 }
 
 static int jbucket(int jmax) {
-    return jmax <= 4 ? 4 : jmax <= 8 ? 8 : jmax <= 16 ? 16 : jmax <= 24 ? 24 : 33;
+    return jmax <= 4 ? 4 : jmax <= 8 ? 8 : jmax <= 16 ? 16 : jmax <= 24 ? 24 : 32;
 }
 
 // MAXJ buckets of the GMRES pass kernels (registers scale with MAXJ)
@@ -741,7 +742,7 @@ static int jbucket(int jmax) {
         case 8: CASE(8) break;   \
         case 16: CASE(16) break; \
         case 24: CASE(24) break; \
-        default: CASE(33) break; \
+        default: CASE(32) break; \
     }
 
 hipError_t launch_matvec_dot(int dim, int jmax, const VecArgs& a, hipStream_t s) {
@@ -757,21 +758,18 @@ hipError_t launch_matvec_dot(int dim, int jmax, const VecArgs& a, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_update_dot(int jmax, const VecArgs& a, hipStream_t s) {
+hipError_t launch_update_gram(int jmax, const VecArgs& a, hipStream_t s) {
     if (a.st.n <= 0) return hipSuccess;
     dim3 grid(a.st.nblocks);
-#define UD(J) hipLaunchKernelGGL((k_update_dot<J>), grid, dim3(NT), 0, s, a);
-    MG_JSWITCH(UD)
-#undef UD
+#define UG(J) hipLaunchKernelGGL((k_update_gram<J>), grid, dim3(NT), 0, s, a);
+    MG_JSWITCH(UG)
+#undef UG
     return hipGetLastError();
 }
 
-hipError_t launch_update_norm(int jmax, const VecArgs& a, hipStream_t s) {
+hipError_t launch_vzero(const VecArgs& a, hipStream_t s) {
     if (a.st.n <= 0) return hipSuccess;
-    dim3 grid(a.st.nblocks);
-#define UN(J) hipLaunchKernelGGL((k_update_norm<J>), grid, dim3(NT), 0, s, a);
-    MG_JSWITCH(UN)
-#undef UN
+    hipLaunchKernelGGL(k_vzero, dim3(a.st.nblocks), dim3(NT), 0, s, a);
     return hipGetLastError();
 }
 

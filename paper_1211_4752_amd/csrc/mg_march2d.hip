@@ -224,6 +224,7 @@ __global__ void __launch_bounds__(MW) k_mg_gram(const CycleArgs a, cx<double>* p
     const int pid = xcd_remap(blockIdx.x, gridDim.x);
     const int slot = find_slot(a.st.s, a.st.n, pid);
     const CycleSlot& sl = a.st.s[slot];
+    if (gated_off(sl.gate)) return;
     const int tile = pid - sl.tile0;
     const LevelView<T>* Lp = static_cast<const LevelView<T>*>(sl.lv);
     const LevelView<T> L = *Lp;
@@ -235,7 +236,7 @@ __global__ void __launch_bounds__(MW) k_mg_gram(const CycleArgs a, cx<double>* p
     const Lane<T> c = lane_of(L, x0);
     InterpX<T> ix;
     interp_axis<T>(c.colv ? c.gx : 0, Lc.n[0], ix.i0, ix.i1, ix.w0, ix.w1);
-    const T fs = (T)sl.fscale;
+    const T fs = (T)fscale_of(sl);
     const cx<T> Z = mk<T>(0, 0);
     cx<double> g[NUM_GRAM];
 #pragma unroll
@@ -348,6 +349,7 @@ __global__ void __launch_bounds__(MW) k_mg_apply_restrict(const CycleArgs a) {
     const int pid = xcd_remap(blockIdx.x, gridDim.x);
     const int slot = find_slot(a.st.s, a.st.n, pid);
     const CycleSlot& sl = a.st.s[slot];
+    if (gated_off(sl.gate)) return;
     const LevelView<T>* Lp = static_cast<const LevelView<T>*>(sl.lv);
     const LevelView<T> L = *Lp;
     const LevelView<T> Lc = Lp[1];
@@ -360,7 +362,7 @@ __global__ void __launch_bounds__(MW) k_mg_apply_restrict(const CycleArgs a) {
     InterpX<T> ix;
     ix.i0 = ix.i1 = 0;
     ix.w0 = ix.w1 = T(0);
-    const T fs = (T)sl.fscale;
+    const T fs = (T)fscale_of(sl);
     const bool q0buf = sl.f == nullptr;
     const void* src = q0buf ? B.q[0] : sl.f;
     const T qs = q0buf ? T(1) : fs;
@@ -445,6 +447,7 @@ __global__ void __launch_bounds__(MW) k_mg_apply_out(const CycleArgs a) {
     const int pid = xcd_remap(blockIdx.x, gridDim.x);
     const int slot = find_slot(a.st.s, a.st.n, pid);
     const CycleSlot& sl = a.st.s[slot];
+    if (gated_off(sl.gate)) return;
     const LevelView<T>* Lp = static_cast<const LevelView<T>*>(sl.lv);
     const LevelView<T> L = *Lp;
     const LevelView<T> Lc = Lp[1];
@@ -456,7 +459,7 @@ __global__ void __launch_bounds__(MW) k_mg_apply_out(const CycleArgs a) {
     const Lane<T> c = lane_of(L, x0);
     InterpX<T> ix;
     interp_axis<T>(c.colv ? c.gx : 0, Lc.n[0], ix.i0, ix.i1, ix.w0, ix.w1);
-    const T fs = (T)sl.fscale;
+    const T fs = (T)fscale_of(sl);
     const cx<T>* u1 = static_cast<const cx<T>*>(B.u1);
     const cx<T>* e = static_cast<const cx<T>*>(sl.c);
     cx<TO>* out = static_cast<cx<TO>*>(sl.out);

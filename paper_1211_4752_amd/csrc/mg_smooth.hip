@@ -62,7 +62,7 @@ __device__ __forceinline__ void grid_pos(int p, int nx, int ny, int& gx, int& gy
 // q0 at p: fscale f (f typed TQ) or the q0 buffer.
 template <typename T, typename TQ>
 __device__ __forceinline__ cx<T> load_q0(const SmSlot& sl, const SmoothBufs& B, long long p) {
-    if (sl.f) return (T)sl.fscale * cvt<T>(static_cast<const cx<TQ>*>(sl.f)[p]);
+    if (sl.f) return (T)fscale_of(sl) * cvt<T>(static_cast<const cx<TQ>*>(sl.f)[p]);
     return static_cast<const cx<T>*>(B.q[0])[p];
 }
 
@@ -71,6 +71,7 @@ template <int D, typename T, typename TQ>
 __global__ void __launch_bounds__(NT) k_sm_power(const SmArgs a, int stage) {
     const SmPos q = sm_pos(a.st);
     const SmSlot& sl = a.st.s[q.slot];
+    if (gated_off(sl.gate)) return;
     const LevelView<T> L = *static_cast<const LevelView<T>*>(sl.lv);
     const SmoothBufs B = *sl.sb;
     int lo, hi;
@@ -83,7 +84,7 @@ __global__ void __launch_bounds__(NT) k_sm_power(const SmArgs a, int stage) {
         grid_pos(p, nx, ny, gx, gy, gz);
         cx<T> ax;
         if (from_f)
-            ax = stencil_at<D, T, TQ>(L, static_cast<const cx<TQ>*>(sl.f), (T)sl.fscale, p, gx, gy, gz);
+            ax = stencil_at<D, T, TQ>(L, static_cast<const cx<TQ>*>(sl.f), (T)fscale_of(sl), p, gx, gy, gz);
         else
             ax = stencil_at<D, T, T>(L, static_cast<const cx<T>*>(B.q[stage - 1]), T(1), p, gx, gy, gz);
         y[p] = L.sinv * ax;
@@ -96,6 +97,7 @@ __global__ void __launch_bounds__(NT) k_sm_gram(const SmArgs a) {
     __shared__ cx<double> sm[(NT / 64) * NUM_GRAM];
     const SmPos q = sm_pos(a.st);
     const SmSlot& sl = a.st.s[q.slot];
+    if (gated_off(sl.gate)) return;
     const LevelView<T> L = *static_cast<const LevelView<T>*>(sl.lv);
     const SmoothBufs B = *sl.sb;
     int lo, hi;
@@ -146,7 +148,9 @@ __global__ void __launch_bounds__(NT) k_sm_coef(const SmCoefArgs a, double brk) 
     __shared__ cx<double> sm[(NT / 64) * NUM_GRAM];
     __shared__ cx<double> G[NUM_GRAM];
     const int slot = blockIdx.x;
-    const int cnt = a.cnt[slot];
+    const CoefSlot& cs = a.s[slot];
+    if (gated_off(cs.gate)) return;
+    const int cnt = cs.cnt;
     cx<double> g[NUM_GRAM];
 #pragma unroll
     for (int v = 0; v < NUM_GRAM; ++v) g[v] = mk(0.0, 0.0);
@@ -171,7 +175,7 @@ __global__ void __launch_bounds__(NT) k_sm_coef(const SmCoefArgs a, double brk) 
         G[threadIdx.x] = s;
     }
     __syncthreads();
-    if (threadIdx.x == 0) solve_coef(G, brk, a.coef[slot]);
+    if (threadIdx.x == 0) solve_coef(G, brk, cs.coef);
 }
 
 template <typename T>
@@ -214,6 +218,7 @@ __global__ void __launch_bounds__(NT) k_sm_apply_restrict(const CycleArgs a) {
     const int pid = xcd_remap(blockIdx.x, gridDim.x);
     const int slot = find_slot(a.st.s, a.st.n, pid);
     const CycleSlot& sl = a.st.s[slot];
+    if (gated_off(sl.gate)) return;
     const LevelView<T>* Lp = static_cast<const LevelView<T>*>(sl.lv);
     const LevelView<T> L = *Lp;
     const SmoothBufs B = *sl.sb;
@@ -224,7 +229,7 @@ __global__ void __launch_bounds__(NT) k_sm_apply_restrict(const CycleArgs a) {
     const cx<T>* q2p = static_cast<const cx<T>*>(B.q[2]);
     const cx<T>* q0p = static_cast<const cx<T>*>(B.q[0]);
     const cx<TQ>* f = static_cast<const cx<TQ>*>(sl.f);
-    const T fs = (T)sl.fscale;
+    const T fs = (T)fscale_of(sl);
     cx<T> c1, c2, c3;
     load_coef<T>(B.coef, c1, c2, c3);
 
@@ -324,6 +329,7 @@ __global__ void __launch_bounds__(NT) k_sm_prolong_resid(const CycleArgs a) {
     const int pid = xcd_remap(blockIdx.x, gridDim.x);
     const int slot = find_slot(a.st.s, a.st.n, pid);
     const CycleSlot& sl = a.st.s[slot];
+    if (gated_off(sl.gate)) return;
     const LevelView<T>* Lp = static_cast<const LevelView<T>*>(sl.lv);
     const LevelView<T> L = *Lp;
     const SmoothBufs B = *sl.sb;
@@ -332,7 +338,7 @@ __global__ void __launch_bounds__(NT) k_sm_prolong_resid(const CycleArgs a) {
     int x0, y0, z0;
     tile_origin<D, TX, TY, TZE>(pid - sl.tile0, nx, ny, x0, y0, z0);
     const cx<TF>* f = static_cast<const cx<TF>*>(sl.f);
-    const T fs = (T)sl.fscale;
+    const T fs = (T)fscale_of(sl);
     const cx<T>* ec = static_cast<const cx<T>*>(sl.c);
     const cx<T>* u1p = static_cast<const cx<T>*>(B.u1);
     const int cxs = x0 / 2 - 1, cys = y0 / 2 - 1, czs = (D == 3) ? z0 / 2 - 1 : 0;
@@ -412,6 +418,7 @@ template <typename T, typename TO, bool ACC>
 __global__ void __launch_bounds__(NT) k_sm_apply_out(const SmArgs a) {
     const SmPos q = sm_pos(a.st);
     const SmSlot& sl = a.st.s[q.slot];
+    if (gated_off(sl.gate)) return;
     const LevelView<T> L = *static_cast<const LevelView<T>*>(sl.lv);
     const SmoothBufs B = *sl.sb;
     int lo, hi;

@@ -162,6 +162,7 @@ __global__ void __launch_bounds__(NTT) k_tail(const TailArgs a) {
     __shared__ cx<double> sc[4];
     __shared__ cx<double> b[MAX_COARSE];
     const TailSlot& ts = a.s[blockIdx.x];
+    if (gated_off(ts.gate)) return;
     const LevelView<T>* Lv = static_cast<const LevelView<T>*>(ts.lv);
     const SmoothBufs* SB = ts.sb;
     const int last = ts.nlev - 1;
