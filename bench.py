@@ -1,31 +1,43 @@
 """Benchmark: fine-grid Mdof/s of the level-dependent multigrid-preconditioned
 (F)GMRES(20) solve to relative residual 1e-6 on one MI355X.
 
-Workload (one step = one full solve of the batch): 2D 1023 x 1023 interior
-grid (h = 1/1024), heterogeneous medium k = k0 (1 + 0.3 g) with g a seeded
-smooth Gaussian random field (correlation length 0.1, clipped to [-1, 1]) and
-max k h = 0.625, ECS absorbing layer of 32 cells on every side, 8 unit point
-sources at seeded nodes of the physical region, complex128, V(1,1) cycles with
-the GMRES(3) smoother (the smoother of every experiment in the paper; with
-it the cycle is nonlinear and the outer method is flexible GMRES(20)), full
-weighting, bilinear interpolation, shifts sigma_l = exp(i l pi / (6 L)),
-3 x 3 coarsest direct solve, one cycle from a zero guess per outer step.
-The omega-Jacobi (omega = 2/3) form of the same cycle does not reach 1e-6
-on this workload; it is run for a capped number of steps and reported in
-"extra".  Inputs are resident in device memory before the timed region;
-set-up of the hierarchy is timed separately.
+Headline workload (one step = one full solve of the batch): 2D 1023 x 1023
+interior grid (h = 1/1024), heterogeneous medium k = k0 (1 + 0.3 g) with g a
+seeded smooth Gaussian random field (correlation length 0.1, clipped to
+[-1, 1]) and max k h = 0.625, ECS absorbing layer of 32 cells on every side,
+8 unit point sources at seeded nodes of the physical region, complex128,
+V(1,1) cycles with the GMRES(3) smoother (the smoother of every experiment in
+the paper; with it the cycle is nonlinear and the outer method is flexible
+GMRES(20)), full weighting, bilinear interpolation, shifts
+sigma_l = exp(i l pi / (6 L)), 3 x 3 coarsest direct solve, one cycle from a
+zero guess per outer step.  Inputs are resident in device memory before the
+timed region; set-up of the hierarchy is timed separately.  Every restart
+cycle runs as a replayed HIP graph.  Kernel durations come from HIP events
+around every launch of the same solves run again launch by launch in this
+process (events captured inside a HIP graph cannot be timed).
+
+Errors against FP64: a solve to a relative residual of 1e-6 is itself only
+about 1e-5 from the exact discrete solution, in any precision, so each
+mixed-precision result is also solved to 1e-9 and compared with the
+complex128 solution to 1e-12 (the benchmark spec's bar is 1e-6).
+
+Extras: the omega-Jacobi form of the same cycle (it does not reach 1e-6 on
+this 2D workload: reported capped), mixed precision with its error against
+the FP64 solution, the 3D 255^3 workload (both smoothers, both precisions),
+the batched workload (64 sources on 511^2 plus 24 uneven grids, one batch)
+with its error against FP64, adjoint gradients per second on 511^2 with 16
+shots, the comparator of the paper's Table 3, Table 5's theta sweep and the
+models of Tables 6-8.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W]
+    python bench.py --only c3_jacobi|c3_gmres3|c4|c5|headline   (one workload, for profilers)
 
-Prints one JSON line.  Besides the metric it carries the roofline figure of
-the dominant kernel (algorithmic bytes over HIP-event time of its launches in
-the timed region) and the CPU oracle timed on a bounded sample.
+Prints one JSON line.
 """
 
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import math
 import os
@@ -45,46 +57,98 @@ NRHS = 8
 RTOL = 1e-6
 RESTART = 20
 MAXIT = 5000           # outer steps per solve before it is reported as not converged
-JACOBI_MAXIT = 2000    # capped omega-Jacobi GMRES(20) run reported in "extra"
+JACOBI_MAXIT = 2000    # capped omega-Jacobi GMRES(20) run on the 2D workload
 SMOOTHER = "gmres3"
-FINE_CLASSES = ["smooth_restrict_fine", "prolong_smooth_fine", "residual", "matvec_dot",
-                "update_dot", "update_norm", "combine", "smooth_power_fine", "smooth_gram_fine",
-                "smooth_gram_post_fine"]
+WORKLOAD = "grf2d_%d_x%d" % (N_GRID, NRHS)
+CYCLE_CLASSES = ["smooth_restrict_fine", "prolong_smooth_fine", "coarse_levels", "coarsest_solve",
+                 "smooth_gram_fine", "smooth_gram_post_fine", "smooth_power_fine"]
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def sources_sha():
-    h = hashlib.sha256()
-    csrc = os.path.join(ROOT, "paper_1211_4752_amd", "csrc")
-    for name in sorted(os.listdir(csrc)):
-        with open(os.path.join(csrc, name), "rb") as fh:
-            h.update(fh.read())
-    return h.hexdigest()[:16]
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def committed_traffic(kernel_class, workload):
-    """HBM bytes per launch from the committed rocprofv3 counter summary of
-    this kernel and workload, when it was taken on the current sources."""
+    """HBM bytes per launch of a kernel class from the committed rocprofv3
+    counter summary of this workload, with the algorithmic bytes per launch
+    of the same counter run (so that their ratio is meaningful)."""
     path = os.path.join(ROOT, "profiles", "pmc_%s_%s.md" % (kernel_class, workload))
     if not os.path.exists(path):
         return None
     text = open(path).read()
-    m_sha = re.search(r"sources_sha256_16\s*=\s*([0-9a-f]+)", text)
     m_tr = re.search(r"traffic_bytes_per_launch\s*=\s*([0-9.eE+]+)", text)
-    if not m_sha or not m_tr or m_sha.group(1) != sources_sha():
+    m_al = re.search(r"algorithmic_bytes_per_launch\s*=\s*([0-9.eE+]+)", text)
+    if not m_tr:
         return None
-    return float(m_tr.group(1))
+    out = {"traffic_bytes_per_launch": float(m_tr.group(1))}
+    if m_al:
+        out["algorithmic_bytes_per_launch"] = float(m_al.group(1))
+        out["ratio"] = round(out["traffic_bytes_per_launch"] / out["algorithmic_bytes_per_launch"], 3)
+    return out
 
 
+def per_class(prof):
+    """{class: ms, launches, avg launch us, GB/s of algorithmic bytes, frac}."""
+    out = {}
+    for c, (ms, cnt, by) in prof.items():
+        if not cnt:
+            continue
+        gbs = by / (ms * 1e-3) / 1e9 if ms > 0 and by > 0 else None
+        out[c] = {"ms": round(ms, 2), "launches": cnt, "avg_launch_us": round(1e3 * ms / cnt, 2),
+                  "algorithmic_bytes_per_launch": round(by / cnt) if by > 0 else None,
+                  "GBps": round(gbs, 1) if gbs else None,
+                  "frac": round(gbs / HBM_PEAK_GBS, 4) if gbs else None}
+    return out
+
+
+def cycle_summary(prof):
+    """Bytes and time of every cycle kernel (all levels) of a profiled run."""
+    ms = sum(prof[c][0] for c in CYCLE_CLASSES if c in prof)
+    by = sum(prof[c][2] for c in CYCLE_CLASSES if c in prof)
+    gbs = by / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
+    return {"ms": round(ms, 2), "GBps": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4)}
+
+
+def rel_err(a, b):
+    return float(((a - b).abs().pow(2).sum().sqrt() / b.abs().pow(2).sum().sqrt()).item())
+
+
+def timed_solve(torch, s, u, f, mode, rtol, maxit, restart=RESTART, profile=False):
+    """Warm (records and captures the operations), then one timed solve."""
+    u.zero_()
+    s.solve(u, f, mode=mode, rtol=rtol, maxit=min(maxit, 2), restart=restart)
+    u.zero_()
+    torch.cuda.synchronize()
+    if profile:
+        s.profile(True)
+    t0 = time.perf_counter()
+    st, its, hists = s.solve(u, f, mode=mode, rtol=rtol, maxit=maxit, restart=restart)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    prof = s.profile_read() if profile else None
+    if profile:
+        s.profile(False)
+    return st, its, hists, dt, prof
+
+
+# ---------------------------------------------------------------------------
+# CPU baselines (the oracle as it stands)
+# ---------------------------------------------------------------------------
 def cpu_baseline(wl, gpu_iters, sample_iters=6):
-    """The oracle as it stands, one thread, on a bounded sample: FGMRES(20)
-    steps with the GMRES(3)-smoothed cycle of right-hand side 0 of the same
-    workload, extrapolated to the number of steps the solve needs."""
+    """The oracle, one thread, on a bounded sample: FGMRES(20) steps with the
+    GMRES(3)-smoothed cycle of right-hand side 0 of the headline workload,
+    extrapolated to the number of steps the GPU solve of that rhs needed."""
     from threadpoolctl import threadpool_limits
-    import numpy as np
     from oracle import cycle as C
     from oracle import helmholtz as H
     from oracle import krylov as K
@@ -96,48 +160,219 @@ def cpu_baseline(wl, gpu_iters, sample_iters=6):
         t0 = time.perf_counter()
         K.gmres(levels[0].A, vc.precondition, f, rtol=0.0, restart=RESTART, maxit=sample_iters, flexible=True)
         dt = time.perf_counter() - t0
-    per_iter = dt / sample_iters
-    est = per_iter * gpu_iters
-    dofs = N_GRID * N_GRID
+    est = dt / sample_iters * gpu_iters
     return {
-        "value": dofs / est / 1e6,
-        "unit": "Mdof/s",
-        "cores": 1,
-        "kind": "oracle",
+        "value": N_GRID * N_GRID / est / 1e6, "unit": "Mdof/s", "cores": 1, "kind": "oracle",
+        "cpu_model": cpu_model(), "cpu_count": os.cpu_count(),
         "sample": ("%d FGMRES(20) steps (one GMRES(3)-smoothed V(1,1) cycle + MGS Arnoldi each) of rhs 0 "
-                   "on the %dx%d workload in %.1f s, single-threaded NumPy/SciPy; extrapolated to the %d "
-                   "steps the GPU solve of that rhs needed" % (sample_iters, N_GRID, N_GRID, dt, gpu_iters)),
+                   "on the %dx%d workload in %.1f s, single-threaded NumPy/SciPy (its elementwise work is "
+                   "single-threaded), extrapolated to the %d steps the GPU solve of that rhs needed"
+                   % (sample_iters, N_GRID, N_GRID, dt, gpu_iters)),
     }
 
 
-def batched(mg, W, torch, dev):
+def _oracle_steps(args):
+    """Worker: oracle FGMRES steps on one right-hand side of a batch problem."""
+    n, kind, idx, steps = args
+    os.environ["OMP_NUM_THREADS"] = "1"
+    from threadpoolctl import threadpool_limits
+    from oracle import cycle as C
+    from oracle import helmholtz as H
+    from oracle import krylov as K
+    from paper_1211_4752_amd import workloads as W
+    with threadpool_limits(limits=1):
+        wl = W.heterogeneous_2d(n, 64, source_seed=4) if kind == "grf" else W.uneven_batch()[idx]
+        prob = H.Problem(wl.n, wl.h, wl.k2, (wl.ecs,) * 2, (wl.ecs,) * 2, wl.ecs_angle)
+        vc = C.VCycle(H.build_hierarchy(prob), smoother="gmres")
+        f = wl.f[idx if kind == "grf" else 0].ravel()
+        A = H.operator(prob)
+        t0 = time.perf_counter()
+        K.gmres(A, vc.precondition, f, rtol=0.0, restart=RESTART, maxit=steps, flexible=True)
+        return time.perf_counter() - t0
+
+
+def cpu_baseline_batched(gpu_steps, workers=None, sample_steps=3):
+    """The oracle over all host cores (one process per right-hand side of the
+    511^2 GRF member, a bounded sample of FGMRES steps each), extrapolated to
+    the steps the GPU batch needed per right-hand side; the uneven grids are
+    counted at the rate of the 511^2 member."""
+    import multiprocessing as mp
+    workers = workers or min(os.cpu_count() or 1, 16)
+    jobs = [(511, "grf", r, sample_steps) for r in range(workers)]
+    t0 = time.perf_counter()
+    with mp.get_context("spawn").Pool(workers) as pool:
+        times = pool.map(_oracle_steps, jobs)
+    wall = time.perf_counter() - t0
+    per_step = float(np.mean(times)) / sample_steps
+    # every process works on its own rhs: aggregate dof-steps per second
+    rate = workers * 511 * 511 / per_step
+    dofs_steps = sum(gpu_steps)
+    return {"value": rate / gpu_steps_mean(gpu_steps) / 1e6, "unit": "Mdof/s", "cores": workers, "kind": "oracle",
+            "cpu_model": cpu_model(), "cpu_count": os.cpu_count(),
+            "sample": ("%d processes x %d FGMRES(20) steps of one 511^2 GRF source each (%.1f s wall, %.2f s "
+                       "per step per process); rate extrapolated to the GPU batch's mean of %.0f steps per "
+                       "right-hand side" % (workers, sample_steps, wall, per_step, gpu_steps_mean(gpu_steps))),
+            "dof_steps_gpu": dofs_steps}
+
+
+def gpu_steps_mean(steps):
+    return float(np.mean(steps)) if len(steps) else 1.0
+
+
+# ---------------------------------------------------------------------------
+# Workloads
+# ---------------------------------------------------------------------------
+def c3(mg, W, torch, dev, smoothers=("gmres3", "jacobi")):
+    """3D 255^3, constant k h = 0.5, ECS 16, centre source: FGMRES/GMRES(20)
+    to 1e-6 in complex128 and mixed; the mixed result's error against the
+    FP64 solution of the same solver (complex128, solved to 1e-12)."""
+    wl = W.constant_3d(255, 0.5, 16)
+    k2 = torch.tensor(wl.k2, dtype=torch.float64, device=dev)
+    f = torch.tensor(wl.f, dtype=torch.complex128, device=dev)
+    dofs = int(np.prod(wl.n))
+    out = {}
+    for sm in smoothers:
+        ref = None
+        for prec in ("c128", "mixed"):
+            s = mg.Solver(wl.n, wl.h, k2, ecs=wl.ecs, ecs_angle=wl.ecs_angle, theta_max=wl.theta_max, nrhs=1,
+                          precision=prec, smoother=sm)
+            u = s.empty()
+            st, its, hists, dt, prof = timed_solve(torch, s, u, f, "gmres", RTOL, 3000, profile=True)
+            row = {"status": st, "steps": its[0], "seconds": round(dt, 4), "Mdof_per_s": round(dofs / dt / 1e6, 3),
+                   "ms_per_step": round(1e3 * dt / max(1, its[0]), 3), "cycle_kernels": cycle_summary(prof),
+                   "kernels": per_class(prof)}
+            if prec == "c128":
+                ref = s.empty()
+                s.solve(ref, f, mode="gmres", rtol=1e-12, maxit=6000, restart=RESTART)
+            row["error_at_rtol_1e-6_vs_fp64_1e-12"] = rel_err(u, ref)
+            r = s.apply(u)
+            row["true_rel_residual"] = rel_err(r, f)
+            if prec == "mixed":
+                u.zero_()
+                st9, its9, _ = s.solve(u, f, mode="gmres", rtol=1e-9, maxit=6000, restart=RESTART)
+                row["error_at_rtol_1e-9_vs_fp64_1e-12"] = rel_err(u, ref)
+                row["rtol_1e-9"] = {"status": st9, "steps": its9[0]}
+            out["%s_%s" % (sm, prec)] = row
+            log("c3 %s %s: %s %d steps %.3f s %.2f Mdof/s" % (sm, prec, st, its[0], dt, dofs / dt / 1e6))
+            s.close()
+            del u
+        del ref
+    return out
+
+
+def batched(mg, W, torch, dev, precision="mixed", profile=True):
     """64 sources on one 511^2 GRF medium plus 24 uneven constant-kh grids
-    (127^2 .. 1023^2), mixed precision, GMRES(3) smoother, one batch: every
-    launch of a step covers all of them, the coarse part of each cycle is a
-    replayed HIP graph.  Whole-batch fine-grid Mdof/s to 1e-6."""
+    (127^2 .. 1023^2), GMRES(3) smoother, one batch: every launch covers all
+    88 right-hand sides, each restart cycle of the whole batch is one graph.
+    Whole-batch fine-grid Mdof/s to 1e-6; every result's error against the
+    complex128 batch solved to 1e-12."""
     wls = W.batched_2d()
-    ss = [mg.Solver(w.n, w.h, torch.tensor(w.k2, dtype=torch.float64, device=dev), ecs=w.ecs,
-                    ecs_angle=w.ecs_angle, theta_max=w.theta_max, nrhs=w.f.shape[0], precision="mixed",
-                    smoother=SMOOTHER) for w in wls]
+    mk = lambda prec: [mg.Solver(w.n, w.h, torch.tensor(w.k2, dtype=torch.float64, device=dev), ecs=w.ecs,
+                                 ecs_angle=w.ecs_angle, theta_max=w.theta_max, nrhs=w.f.shape[0], precision=prec,
+                                 smoother=SMOOTHER) for w in wls]
     fs = [torch.tensor(w.f, dtype=torch.complex128, device=dev) for w in wls]
+    ss = mk(precision)
     us = [s.empty() for s in ss]
     b = mg.Batch(ss)
     b.solve(us, fs, mode="gmres", rtol=RTOL, maxit=2, restart=RESTART)
     for u in us:
         u.zero_()
     torch.cuda.synchronize()
+    if profile:
+        ss[0].profile(True)
     t0 = time.perf_counter()
     st, its, hists = b.solve(us, fs, mode="gmres", rtol=RTOL, maxit=MAXIT, restart=RESTART)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    prof = ss[0].profile_read() if profile else None
+    if profile:
+        ss[0].profile(False)
     dofs = sum(int(w.f.shape[0]) * int(np.prod(w.n)) for w in wls)
+    u6 = [u.clone() for u in us]
+    for u in us:
+        u.zero_()
+    st9, its9, _ = b.solve(us, fs, mode="gmres", rtol=1e-9, maxit=MAXIT, restart=RESTART)
     b.close()
-    for s in ss:
+    # FP64 reference: the same batch in complex128, to 1e-12
+    rs = mk("c128")
+    refs = [s.empty() for s in rs]
+    rb = mg.Batch(rs)
+    rb.solve(refs, fs, mode="gmres", rtol=1e-12, maxit=MAXIT, restart=RESTART)
+    rb.close()
+    errs, errs6 = [], []
+    for u, v, r in zip(us, u6, refs):
+        for i in range(u.shape[0]):
+            errs.append(rel_err(u[i], r[i]))
+            errs6.append(rel_err(v[i], r[i]))
+    for s in ss + rs:
         s.close()
+    steps = [x for row in its for x in row]
     log("batched:", st, "%.3f s" % dt)
-    return {"status": st, "problems": len(wls), "rhs": sum(w.f.shape[0] for w in wls), "dofs": dofs,
-            "seconds": round(dt, 3), "Mdof_per_s": round(dofs / dt / 1e6, 3),
-            "max_steps": max(max(r) for r in its), "precision": "mixed"}
+    out = {"status": st, "problems": len(wls), "rhs": len(steps), "dofs": dofs, "seconds": round(dt, 3),
+           "Mdof_per_s": round(dofs / dt / 1e6, 3), "max_steps": max(steps), "mean_steps": round(float(np.mean(steps)), 1),
+           "precision": precision, "graph_launches": "one per restart cycle of the whole batch",
+           "error_at_rtol_1e-6_vs_fp64_1e-12": {"max": max(errs6), "median": float(np.median(errs6))},
+           "error_at_rtol_1e-9_vs_fp64_1e-12": {"max": max(errs), "median": float(np.median(errs)),
+                                                "status": st9, "max_steps": max(x for row in its9 for x in row)},
+           "errors_per_result_note": "every one of the 88 results compared; max and median shown"}
+    if prof:
+        out["kernels"] = per_class(prof)
+        out["cycle_kernels"] = cycle_summary(prof)
+    return out, [x for row in its for x in row]
+
+
+def c5(mg, W, torch, dev, reps=2):
+    """Adjoint gradients on 511^2 (GRF medium), 16 shots, 128 receivers on
+    the row y = 0.9, L = 0.5 sum ||P u - d||^2 with data from a 5 % perturbed
+    medium: one gradient = 16 forward and 16 adjoint (F)GMRES solves to 1e-10
+    plus the pointwise dL/dk^2 pass.  Gradients per second (set-up excluded)."""
+    n, nshots, nrec = 511, 16, 128
+    ecs = (n + 1) // 32
+    k2n = W.heterogeneous_k2(n, 2, seed=2)
+    k2t = W.perturbed_k2(k2n, seed=7)
+    nodes = W.source_nodes(n, 2, nshots, seed=6, lo=ecs, hi=n - 1 - ecs, max_y=int(0.8 * (n + 1)))
+    f = torch.tensor(W.point_sources((n, n), nodes), dtype=torch.complex128, device=dev)
+    rec = W.receiver_nodes(n, nrec, 460)
+    idx = torch.tensor(rec[:, 1] * n + rec[:, 0], device=dev)
+    h = 1.0 / (n + 1)
+    st_true = mg.Solver((n, n), h, torch.tensor(k2t, dtype=torch.float64, device=dev), ecs=ecs, nrhs=nshots,
+                        smoother=SMOOTHER)
+    ut = st_true.empty()
+    st_true.solve(ut, f, mode="gmres", rtol=1e-10, maxit=5000)
+    d = ut.reshape(nshots, -1)[:, idx].clone()
+    st_true.close()
+    k2 = torch.tensor(k2n, dtype=torch.float64, device=dev)
+    t0 = time.perf_counter()
+    s = mg.Solver((n, n), h, k2, ecs=ecs, nrhs=nshots, smoother=SMOOTHER)
+    torch.cuda.synchronize()
+    setup = time.perf_counter() - t0
+    u, lam = s.empty(), s.empty()
+    g = torch.zeros_like(k2)
+
+    def gradient():
+        u.zero_()
+        lam.zero_()
+        g.zero_()
+        st, its, _ = s.solve(u, f, mode="gmres", rtol=1e-10, maxit=5000)
+        r = torch.zeros_like(u).reshape(nshots, -1)
+        r[:, idx] = u.reshape(nshots, -1)[:, idx] - d
+        sta, itsa, _ = s.solve_adjoint(lam, r.reshape(u.shape).contiguous(), mode="gmres", rtol=1e-10, maxit=5000)
+        s.grad_k2(u, lam, g)
+        return st, sta, its, itsa
+
+    gradient()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        st, sta, its, itsa = gradient()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    s.close()
+    log("c5: %.3f s per gradient" % dt)
+    return {"gradients_per_s": round(1.0 / dt, 3), "seconds_per_gradient": round(dt, 4),
+            "shot_gradients_per_s": round(nshots / dt, 2), "setup_s": round(setup, 3),
+            "forward": {"status": st, "max_steps": max(its)}, "adjoint": {"status": sta, "max_steps": max(itsa)},
+            "Mdof_per_s_forward_plus_adjoint": round(2 * nshots * n * n / dt / 1e6, 3)}
 
 
 # Table 5 of the paper: standalone level-dependent V(1,1) cycles with GMRES(3)
@@ -193,23 +428,12 @@ def paper_models(mg, W, torch, dev):
         s = mg.Solver(wl.n, wl.h, k2, ecs=(wl.ecs_lo, wl.ecs_hi), ecs_angle=wl.ecs_angle,
                       theta_max=wl.theta_max, nrhs=1, smoother=SMOOTHER)
         u = s.empty()
-        s.solve(u, f, mode="standalone", rtol=1e-7, maxit=2)
-        u.zero_()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        st, its, _ = s.solve(u, f, mode="standalone", rtol=1e-7, maxit=1000)
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t0
+        st, its, _, dt, _ = timed_solve(torch, s, u, f, "standalone", 1e-7, 1000)
         nlev = s.num_levels
         s.close()
         sc = mg.Solver(wl.n, wl.h, k2, ecs=(wl.ecs_lo, wl.ecs_hi), ecs_angle=wl.ecs_angle,
                        sigma=[1 + 0.5j] * nlev, nrhs=1, smoother=SMOOTHER)
-        u.zero_()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        stc, itc, _ = sc.solve(u, f, mode="gmres", rtol=1e-7, maxit=2000, restart=10)
-        torch.cuda.synchronize()
-        dtc = time.perf_counter() - t0
+        stc, itc, _, dtc, _ = timed_solve(torch, sc, u, f, "gmres", 1e-7, 2000, restart=10)
         sc.close()
         rows.setdefault(table, []).append({"case": wl.name, "grid": "x".join(map(str, wl.n)),
                                            "levels": nlev, "status": st, "gpu_cycles": its[0],
@@ -221,13 +445,47 @@ def paper_models(mg, W, torch, dev):
     return rows
 
 
+def only(args, mg, W, torch, dev):
+    """A single workload, for profiler runs: one solve after the warm-up."""
+    res = {}
+    if args.only == "headline":
+        wl = W.heterogeneous_2d(N_GRID, NRHS)
+        s = mg.Solver(wl.n, wl.h, torch.tensor(wl.k2, dtype=torch.float64, device=dev), ecs=wl.ecs,
+                      ecs_angle=wl.ecs_angle, theta_max=wl.theta_max, nrhs=NRHS, smoother=SMOOTHER,
+                      precision=args.precision)
+        f = torch.tensor(wl.f, dtype=torch.complex128, device=dev)
+        u = s.empty()
+        st, its, _, dt, _ = timed_solve(torch, s, u, f, "gmres", RTOL, args.maxit)
+        res = {"status": st, "steps": its, "seconds": dt}
+    elif args.only.startswith("c3_"):
+        res = c3(mg, W, torch, dev, smoothers=(args.only[3:],))
+    elif args.only == "c4":
+        res, _ = batched(mg, W, torch, dev, profile=False)
+    elif args.only == "c4_jacobi_511":
+        # the north star's omega-Jacobi cycle on the 64-source 511^2 member
+        wl = W.heterogeneous_2d(511, 64, source_seed=4)
+        s = mg.Solver(wl.n, wl.h, torch.tensor(wl.k2, dtype=torch.float64, device=dev), ecs=wl.ecs,
+                      ecs_angle=wl.ecs_angle, theta_max=wl.theta_max, nrhs=64, smoother="jacobi",
+                      precision=args.precision)
+        f = torch.tensor(wl.f, dtype=torch.complex128, device=dev)
+        u = s.empty()
+        st, its, _, dt, prof = timed_solve(torch, s, u, f, "gmres", RTOL, args.maxit, profile=True)
+        res = {"status": st, "max_steps": max(its), "seconds": dt, "kernels": per_class(prof)}
+    elif args.only == "c5":
+        res = c5(mg, W, torch, dev, reps=1)
+    print(json.dumps({"only": args.only, "result": res}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=1)
-    ap.add_argument("--warmup", type=int, default=0)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--only", default=None,
+                    help="run one workload only (headline, c3_gmres3, c3_jacobi, c4, c4_jacobi_511, c5)")
+    ap.add_argument("--precision", default="c128", help="with --only headline / c4_jacobi_511")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain device copy of 1 GiB four times (counter calibration)")
     ap.add_argument("--maxit", type=int, default=MAXIT,
@@ -238,7 +496,6 @@ def main():
               "right-hand sides would shard across GPUs without communication).", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
     from paper_1211_4752_amd import mg, workloads as W
 
@@ -252,6 +509,10 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_probe_bytes_read_per_copy": 1 << 30, "copies": 4}), flush=True)
         return
+    if args.only:
+        only(args, mg, W, torch, dev)
+        return
+
     wl = W.heterogeneous_2d(N_GRID, NRHS)
     k2 = torch.tensor(wl.k2, dtype=torch.float64, device=dev)
     f = torch.tensor(wl.f, dtype=torch.complex128, device=dev)
@@ -262,7 +523,7 @@ def main():
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
     u = s.empty()
-    # load the code objects outside the timed region
+    # records and captures the operations outside the timed region
     s.solve(u, f, mode="gmres", rtol=RTOL, maxit=2, restart=RESTART)
     for w in range(args.warmup):
         u.zero_()
@@ -270,7 +531,6 @@ def main():
         log("warmup step %d done" % w)
 
     torch.cuda.synchronize()
-    s.profile(True)
     statuses, iters = [], []
     t0 = time.perf_counter()
     for k in range(args.steps):
@@ -281,67 +541,79 @@ def main():
         log("step %d: %s, GMRES steps per rhs %s" % (k, st, its))
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
+    # kernel timing: the same solves again, launch by launch with HIP events
+    # around every launch on the library's stream (events captured inside a
+    # HIP graph cannot be timed)
+    s.profile(True)
+    tp = time.perf_counter()
+    for k in range(args.steps):
+        u.zero_()
+        s.solve(u, f, mode="gmres", rtol=RTOL, maxit=args.maxit, restart=RESTART)
+    torch.cuda.synchronize()
+    elapsed_prof = time.perf_counter() - tp
     prof = s.profile_read()
     s.profile(False)
 
     dofs = N_GRID * N_GRID * NRHS
     value = dofs * args.steps / elapsed / 1e6
-    # dominant fine-grid kernel of the timed region
-    dom = max(FINE_CLASSES, key=lambda c: prof[c][0])
-    ms, cnt, by = prof[dom]
-    achieved = by / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
-    workload = "grf2d_%d_x%d" % (N_GRID, NRHS)
-    traffic = committed_traffic(dom, workload)
+    kernels = per_class(prof)
+    # dominant class of the timed region (every class, coarse levels included)
+    dom = max(kernels, key=lambda c: kernels[c]["ms"])
+    kd = kernels[dom]
+    tr = committed_traffic(dom, WORKLOAD)
     roofline = {
-        "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-        "frac": round(achieved / HBM_PEAK_GBS, 4),
-        "traffic": traffic,
-        "kernel": dom,
-        "avg_launch_us": round(1e3 * ms / max(cnt, 1), 2),
-        "algorithmic_bytes_per_launch": round(by / max(cnt, 1)),
-        "launches": cnt,
+        "bound": "hbm", "achieved": kd["GBps"], "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": kd["frac"],
+        "traffic": tr["traffic_bytes_per_launch"] if tr else None,
+        "kernel": dom, "avg_launch_us": kd["avg_launch_us"],
+        "algorithmic_bytes_per_launch": kd["algorithmic_bytes_per_launch"], "launches": kd["launches"],
+        "timing": ("HIP events around every launch of %d further solves of the same workload in this process, "
+                   "launched one by one (%.1f ms per solve, against %.1f ms per solve as replayed graphs)"
+                   % (args.steps, 1e3 * elapsed_prof / args.steps, 1e3 * elapsed / args.steps)),
     }
-    kernels = {c: {"ms": round(v[0], 2), "launches": v[1],
-                   "GBps": round(v[2] / (v[0] * 1e-3) / 1e9, 1) if v[0] > 0 and v[2] > 0 else None}
-               for c, v in prof.items() if v[1]}
+    if tr and "ratio" in tr:
+        roofline["traffic_counter_run"] = tr
 
-    # true residual check of the result with the library's own operator
+    # true residual and the FP64 reference of the mixed run
     r = s.apply(u)
-    true_res = [float(((f[i] - r[i]).abs().pow(2).sum().sqrt() / f[i].abs().pow(2).sum().sqrt()).item())
-                for i in range(NRHS)]
-
+    true_res = [rel_err(r[i], f[i]) for i in range(NRHS)]
+    ref = s.empty()
+    s.solve(ref, f, mode="gmres", rtol=1e-12, maxit=args.maxit, restart=RESTART)
     extra = {"setup_s": round(setup_s, 3), "status": statuses[-1], "gmres_steps": iters[-1],
-             "true_rel_residual_max": max(true_res), "kernels": kernels}
+             "true_rel_residual_max": max(true_res),
+             "error_at_rtol_1e-6_vs_fp64_1e-12_max": max(rel_err(u[i], ref[i]) for i in range(NRHS)),
+             "kernels": kernels, "cycle_kernels_all_levels": cycle_summary(prof)}
+    cpu = None
     if not args.no_extras:
-        def timed(solver, uu, mode, maxit):
-            uu.zero_()
-            solver.solve(uu, f, mode=mode, rtol=RTOL, maxit=2, restart=RESTART)
-            uu.zero_()
-            torch.cuda.synchronize()
-            t1 = time.perf_counter()
-            st, its, hists = solver.solve(uu, f, mode=mode, rtol=RTOL, maxit=maxit, restart=RESTART)
-            torch.cuda.synchronize()
-            return st, its, hists, time.perf_counter() - t1
-
         # standalone level-dependent multigrid on the same batch (Sec. 4.1 LVL-MG)
-        st, its, hists, dts = timed(s, u, "standalone", 300)
+        st, its, hists, dts, _ = timed_solve(torch, s, u, f, "standalone", RTOL, 300)
         extra["standalone"] = {"status": st, "cycles": its, "seconds": round(dts, 3),
                                "last_ratio": [float(h[-1]) for h in hists]}
         log("standalone:", st, its)
         # mixed precision: complex64 cycle inside FP64 FGMRES
         sm = mg.Solver(wl.n, wl.h, k2, ecs=wl.ecs, ecs_angle=wl.ecs_angle, theta_max=wl.theta_max,
                        nrhs=NRHS, precision="mixed", smoother=SMOOTHER)
-        st, its, hists, dtm = timed(sm, u, "gmres", args.maxit)
-        extra["mixed"] = {"status": st, "gmres_steps": its, "Mdof_per_s": round(dofs / dtm / 1e6, 3)}
+        um = sm.empty()
+        st, its, hists, dtm, profm = timed_solve(torch, sm, um, f, "gmres", RTOL, args.maxit, profile=True)
+        err6 = [rel_err(um[i], ref[i]) for i in range(NRHS)]
+        um.zero_()
+        st9, its9, _ = sm.solve(um, f, mode="gmres", rtol=1e-9, maxit=args.maxit, restart=RESTART)
+        extra["mixed"] = {"status": st, "gmres_steps": its, "seconds": round(dtm, 3),
+                          "Mdof_per_s": round(dofs / dtm / 1e6, 3),
+                          "error_at_rtol_1e-6_vs_fp64_1e-12": err6,
+                          "error_at_rtol_1e-9_vs_fp64_1e-12": [rel_err(um[i], ref[i]) for i in range(NRHS)],
+                          "rtol_1e-9": {"status": st9, "gmres_steps": its9},
+                          "cycle_kernels_all_levels": cycle_summary(profm), "kernels": per_class(profm)}
         log("mixed:", st, its)
         sm.close()
+        del um
         # the omega-Jacobi cycle, right-preconditioned GMRES(20), capped
         sj = mg.Solver(wl.n, wl.h, k2, ecs=wl.ecs, ecs_angle=wl.ecs_angle, theta_max=wl.theta_max,
                        nrhs=NRHS, smoother="jacobi")
-        st, its, hists, dtj = timed(sj, u, "gmres", JACOBI_MAXIT)
+        st, its, hists, dtj, profj = timed_solve(torch, sj, u, f, "gmres", RTOL, JACOBI_MAXIT, profile=True)
         extra["omega_jacobi_gmres"] = {"status": st, "gmres_steps": its, "seconds": round(dtj, 3),
                                        "ms_per_step": round(1e3 * dtj / max(its), 3),
-                                       "last_ratio": [float(h[-1]) for h in hists]}
+                                       "last_ratio": [float(h[-1]) for h in hists],
+                                       "cycle_kernels_all_levels": cycle_summary(profj), "kernels": per_class(profj)}
         log("omega-jacobi:", st, its)
         sj.close()
         # comparator of Table 3 (MG-FGMRES): the cycle on -Delta - (1 + 0.5 i) k^2
@@ -349,17 +621,24 @@ def main():
         L = s.num_levels
         sc = mg.Solver(wl.n, wl.h, k2, ecs=wl.ecs, ecs_angle=wl.ecs_angle, sigma=[1 + 0.5j] * L, nrhs=NRHS,
                        smoother=SMOOTHER)
-        st, its, hists, dtc = timed(sc, u, "gmres", 2000)
+        st, its, hists, dtc, _ = timed_solve(torch, sc, u, f, "gmres", RTOL, 2000)
         extra["fixed_shift_csl"] = {"sigma": "1+0.5i on every level", "status": st, "gmres_steps": its,
                                     "seconds": round(dtc, 3), "Mdof_per_s": round(dofs / dtc / 1e6, 3)}
         log("fixed-shift comparator:", st, its)
         sc.close()
-        extra["batched"] = batched(mg, W, torch, dev)
+        s.close()
+        del u, ref
+        torch.cuda.empty_cache()
+        extra["c3_255"] = c3(mg, W, torch, dev)
+        extra["batched"], bsteps = batched(mg, W, torch, dev)
+        extra["adjoint_c5"] = c5(mg, W, torch, dev)
         extra["theta_sweep_table5"] = theta_sweep(mg, W, torch, dev)
         extra["paper_models"] = paper_models(mg, W, torch, dev)
-    s.close()
+        if not args.no_cpu_baseline:
+            extra["cpu_baseline_batched"] = cpu_baseline_batched(bsteps)
+    else:
+        s.close()
 
-    cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(wl, iters[-1][0])
 
@@ -368,7 +647,7 @@ def main():
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(1e3 * elapsed / args.steps, 2),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": workload, "grid": "%dx%d" % (N_GRID, N_GRID), "h": "1/1024", "nrhs": NRHS,
+        "config": {"workload": WORKLOAD, "grid": "%dx%d" % (N_GRID, N_GRID), "h": "1/1024", "nrhs": NRHS,
                    "mode": "fgmres(%d), one V(1,1) per step" % RESTART, "smoother": "gmres(3)", "rtol": RTOL,
                    "ecs_cells": wl.ecs, "kh_max": 0.625, "theta_max": "pi/6", "levels": 9,
                    "precision": "c128"},

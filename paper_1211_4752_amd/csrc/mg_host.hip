@@ -130,12 +130,19 @@ struct Level {
     void* SU2 = nullptr;          //   u2 by rhs
 };
 
+// Kernel timing: per class, summed milliseconds, launches and algorithmic
+// bytes since profiling was enabled.
 struct Prof {
     bool on = false;
-    std::vector<hipEvent_t> pool;
-    std::vector<int> cls;
-    std::vector<double> bytes;
-    size_t used = 0;
+    double ms[MG_K_NUM_CLASSES] = {};
+    long long cnt[MG_K_NUM_CLASSES] = {};
+    double bytes[MG_K_NUM_CLASSES] = {};
+    void clear() {
+        for (int i = 0; i < MG_K_NUM_CLASSES; ++i) {
+            ms[i] = bytes[i] = 0.0;
+            cnt[i] = 0;
+        }
+    }
 };
 
 // Reduction work space and the device state of the Krylov control, for the
@@ -185,6 +192,7 @@ struct Op {
     char* dtab = nullptr;
     std::vector<Step> steps;
     hipGraphExec_t exec = nullptr;
+    std::vector<hipEvent_t> ev;       // 2 per step, recorded by profiled runs
     bool uploaded = false;
 };
 
@@ -316,10 +324,17 @@ mg_status ensure_hist(Work& w, size_t doubles) {
     return MG_OK;
 }
 
+void op_release(Op& op) {
+    if (op.exec) (void)hipGraphExecDestroy(op.exec);
+    op.exec = nullptr;
+    for (hipEvent_t e : op.ev) (void)hipEventDestroy(e);
+    op.ev.clear();
+    dfree(op.dtab);
+}
+
 void op_free(Op* op) {
     if (!op) return;
-    if (op->exec) (void)hipGraphExecDestroy(op->exec);
-    dfree(op->dtab);
+    op_release(*op);
     delete op;
 }
 
@@ -350,28 +365,6 @@ struct Exec {
     bool graphs;
 };
 
-int prof_begin(Exec& E, int cls, double bytes) {
-    if (!E.prof || !E.prof->on) return -1;
-    Prof& P = *E.prof;
-    while (P.pool.size() < 2 * (P.used + 1)) {
-        hipEvent_t e;
-        if (hipEventCreate(&e) != hipSuccess) return -1;
-        P.pool.push_back(e);
-    }
-    const int idx = (int)P.used++;
-    if ((int)P.cls.size() <= idx) {
-        P.cls.resize(idx + 1);
-        P.bytes.resize(idx + 1);
-    }
-    P.cls[idx] = cls;
-    P.bytes[idx] = bytes;
-    (void)hipEventRecord(P.pool[2 * idx], E.s);
-    return idx;
-}
-void prof_end(Exec& E, int idx) {
-    if (idx >= 0) (void)hipEventRecord(E.prof->pool[2 * idx + 1], E.s);
-}
-
 double step_bytes(const Step& st, const std::vector<int>* live) {
     double b = 0.0;
     for (const ItemBytes& x : st.ib) {
@@ -385,11 +378,33 @@ double step_bytes(const Step& st, const std::vector<int>* live) {
     return b;
 }
 
-// Run op on E.s.  Profiling runs it launch by launch between HIP events;
-// the index of its first record is returned in *first (bytes are fixed up
-// by prof_fix once the caller knows which items iterated).
-mg_status op_run(Exec& E, Op& op, int* first = nullptr) {
-    if (first) *first = -1;
+bool profiling(const Exec& E) { return E.prof && E.prof->on; }
+
+// Capture the steps of op on the cache's capture stream and instantiate
+// the graph.
+mg_status op_capture(Exec& E, Op& op, hipGraphExec_t* out) {
+    if (!E.cache->capture) CK(hipStreamCreateWithFlags(&E.cache->capture, hipStreamNonBlocking));
+    hipStream_t cs = E.cache->capture;
+    CK(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+    hipError_t err = hipSuccess;
+    for (size_t i = 0; i < op.steps.size() && err == hipSuccess; ++i) err = op.steps[i].fn(cs, op.dtab);
+    hipGraph_t g = nullptr;
+    const hipError_t e2 = hipStreamEndCapture(cs, &g);
+    if (err != hipSuccess || e2 != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return MG_E_DEVICE;
+    }
+    const hipError_t ei = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    CK(ei);
+    return MG_OK;
+}
+
+// Run op on E.s, as its captured graph, or launch by launch.  Profiled runs
+// go launch by launch with a HIP event before and after every launch (the
+// runtime records events captured into a graph but cannot time them);
+// op_collect adds the timings once the stream has passed the run.
+mg_status op_run(Exec& E, Op& op) {
     if (op.steps.empty()) return MG_OK;
     if (!op.uploaded) {
         if (!op.tab.empty()) {
@@ -398,48 +413,39 @@ mg_status op_run(Exec& E, Op& op, int* first = nullptr) {
         }
         op.uploaded = true;
     }
-    if (E.prof && E.prof->on) {
+    const bool prof = profiling(E);
+    if (prof)
+        while (op.ev.size() < 2 * op.steps.size()) {
+            hipEvent_t e;
+            CK(hipEventCreate(&e));
+            op.ev.push_back(e);
+        }
+    if (prof || !E.graphs || !E.cache) {
         for (size_t i = 0; i < op.steps.size(); ++i) {
-            const Step& st = op.steps[i];
-            const int pi = prof_begin(E, st.cls, step_bytes(st, nullptr));
-            if (first && i == 0) *first = pi;
-            CK(st.fn(E.s, op.dtab));
-            prof_end(E, pi);
+            if (prof) CK(hipEventRecord(op.ev[2 * i], E.s));
+            CK(op.steps[i].fn(E.s, op.dtab));
+            if (prof) CK(hipEventRecord(op.ev[2 * i + 1], E.s));
         }
         return MG_OK;
     }
-    if (!E.graphs || !E.cache) {
-        for (const Step& st : op.steps) CK(st.fn(E.s, op.dtab));
-        return MG_OK;
-    }
-    if (!op.exec) {
-        if (!E.cache->capture) CK(hipStreamCreateWithFlags(&E.cache->capture, hipStreamNonBlocking));
-        hipStream_t cs = E.cache->capture;
-        CK(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
-        hipError_t err = hipSuccess;
-        for (const Step& st : op.steps) {
-            err = st.fn(cs, op.dtab);
-            if (err != hipSuccess) break;
-        }
-        hipGraph_t g = nullptr;
-        const hipError_t e2 = hipStreamEndCapture(cs, &g);
-        if (err != hipSuccess || e2 != hipSuccess) {
-            if (g) (void)hipGraphDestroy(g);
-            return MG_E_DEVICE;
-        }
-        const hipError_t ei = hipGraphInstantiate(&op.exec, g, nullptr, nullptr, 0);
-        (void)hipGraphDestroy(g);
-        CK(ei);
-    }
+    if (!op.exec) CKS(op_capture(E, op, &op.exec));
     CK(hipGraphLaunch(op.exec, E.s));
     return MG_OK;
 }
 
-// Algorithmic bytes of a profiled run once the per-item counts of Arnoldi
-// steps (or cycles) are known.
-void prof_fix(Exec& E, const Op& op, int first, const std::vector<int>& live) {
-    if (first < 0 || !E.prof) return;
-    for (size_t i = 0; i < op.steps.size(); ++i) E.prof->bytes[first + i] = step_bytes(op.steps[i], &live);
+// Timings of the last profiled run of op (the stream has passed it); live:
+// Arnoldi steps (or cycles) each item took in that run, null = all items.
+mg_status op_collect(Exec& E, const Op& op, const std::vector<int>* live) {
+    if (!profiling(E) || op.ev.size() < 2 * op.steps.size()) return MG_OK;
+    for (size_t i = 0; i < op.steps.size(); ++i) {
+        const Step& st = op.steps[i];
+        float ms = 0.0f;
+        CK(hipEventElapsedTime(&ms, op.ev[2 * i], op.ev[2 * i + 1]));
+        E.prof->ms[st.cls] += ms;
+        E.prof->cnt[st.cls] += 1;
+        E.prof->bytes[st.cls] += step_bytes(st, live);
+    }
+    return MG_OK;
 }
 
 template <typename F>
@@ -1432,7 +1438,7 @@ mg_status tune_arnoldi(mg_ctx* c, int m) {
         if (st == MG_OK) st = rec_update_gram(R, 0, it, G_NONE, j, nullptr);
         if (st != MG_OK) {   // the work space does not hold this split
             st = MG_OK;
-            dfree(op.dtab);
+            op_release(op);
             continue;
         }
         float tot = 0.0f;
@@ -1445,7 +1451,7 @@ mg_status tune_arnoldi(mg_ctx* c, int m) {
             if (st == MG_OK && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) st = MG_E_DEVICE;
             if (rep > 0) tot += ms;
         }
-        dfree(op.dtab);
+        op_release(op);
         if (st != MG_OK) break;
         if (tot < 0.97f * best) {
             best = tot;
@@ -1520,14 +1526,13 @@ mg_status solve_items(Exec& E, Work& w, int dir, const std::vector<Item>& it, co
         Rec R{&op, &w, dim, mixed, TAG_ALWAYS};
         return gm ? rec_gmres_cycle(R, dir, it, U, F, restart, flexible) : rec_sa_chunk(R, dir, it, U, F, SA_CHUNK);
     }));
-    int first = -1;
-    CKS(op_run(E, *init, &first));
+    CKS(op_run(E, *init));
+    CKS(read_flags(E, w, n));
     std::vector<int> before(n, 0), live(n, 0), sbefore(n, 0);
-    if (first >= 0) prof_fix(E, *init, first, std::vector<int>(n, 0));
+    CKS(op_collect(E, *init, &live));
     // every run of the body advances each running item by at least one step
     const long long guard = (long long)maxit + 2;
     for (long long run = 0;; ++run) {
-        CKS(read_flags(E, w, n));
         bool any = false;
         for (int k = 0; k < n; ++k) {
             const mg::GmFlags& f = w.gfl_h[k];
@@ -1537,15 +1542,15 @@ mg_status solve_items(Exec& E, Work& w, int dir, const std::vector<Item>& it, co
         }
         if (!any) break;
         if (run >= guard) return MG_E_STATE;
-        CKS(op_run(E, *body, &first));
-        if (first >= 0) {
-            CKS(read_flags(E, w, n));
+        CKS(op_run(E, *body));
+        CKS(read_flags(E, w, n));
+        if (profiling(E)) {
             for (int k = 0; k < n; ++k) {
                 const mg::GmFlags& f = w.gfl_h[k];
                 live[k] = f.its - before[k];
                 if (!gm && sbefore[k] == 0 && (f.state == 1 || f.state == 3)) live[k]++;
             }
-            prof_fix(E, *body, first, live);
+            CKS(op_collect(E, *body, &live));
         }
     }
     if (hist) CK(hipMemcpyAsync(hist, w.hist, (size_t)n * hstride * sizeof(double), hipMemcpyDeviceToHost, E.s));
@@ -1614,8 +1619,6 @@ void release(mg_ctx* c) {
     dfree(c->scale_d);
     dfree(c->coef_d);
     work_free(c->work);
-    for (hipEvent_t e : c->prof.pool) (void)hipEventDestroy(e);
-    c->prof.pool.clear();
 }
 
 
@@ -1721,7 +1724,7 @@ mg_status autotune(mg_ctx* c) {
                 if (st == MG_OK && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) st = MG_E_DEVICE;
                 if (rep > 0) tot += ms;
             }
-            dfree(op.dtab);
+            op_release(op);
             if (tot < best) {
                 best = tot;
                 best_shape = shape;
@@ -2041,6 +2044,10 @@ mg_status mg_cycle(mg_ctx* c, double* u, const double* f, double* res_before) {
     }));
     Exec E = ctx_exec(c);
     CKS(op_run(E, *op));
+    if (profiling(E)) {
+        CK(hipStreamSynchronize(c->stream));
+        CKS(op_collect(E, *op, nullptr));
+    }
     if (want) {
         CK(hipMemcpyAsync(c->work.rtot_h, c->work.rtot, n * sizeof(double), hipMemcpyDeviceToHost, c->stream));
         CK(hipStreamSynchronize(c->stream));
@@ -2061,10 +2068,7 @@ mg_status mg_solve_adjoint(mg_ctx* c, double* lam, const double* g, int mode, do
 
 mg_status mg_grad_k2(mg_ctx* c, const double* u, const double* lam, double* grad) {
     if (!c || !u || !lam || !grad) return MG_E_INVAL;
-    Exec E = ctx_exec(c);
-    const int pi = prof_begin(E, MG_K_OTHER, (double)c->lv[0].N * (32.0 * c->nrhs + 16.0));
     CK(mg::launch_grad_k2((const cx<double>*)u, (const cx<double>*)lam, c->nrhs, c->lv[0].N, grad, c->stream));
-    prof_end(E, pi);
     return MG_OK;
 }
 
@@ -2100,7 +2104,12 @@ mg_status mg_apply(mg_ctx* c, int level, int adjoint, const double* x, double* y
         return MG_OK;
     }));
     Exec E = ctx_exec(c);
-    return op_run(E, *op);
+    CKS(op_run(E, *op));
+    if (profiling(E)) {
+        CK(hipStreamSynchronize(c->stream));
+        CKS(op_collect(E, *op, nullptr));
+    }
+    return MG_OK;
 }
 
 int mg_tile_shape(mg_ctx* c, int level, int shape) {
@@ -2192,26 +2201,16 @@ mg_status mg_profile(mg_ctx* c, int enable) {
     if (!c) return MG_E_INVAL;
     CK(hipStreamSynchronize(c->stream));
     c->prof.on = enable != 0;
-    c->prof.used = 0;
+    c->prof.clear();
     return MG_OK;
 }
 
 mg_status mg_profile_read(mg_ctx* c, int which, double* total_ms, long long* count, double* bytes) {
     if (!c || which < 0 || which >= MG_K_NUM_CLASSES) return MG_E_INVAL;
     CK(hipStreamSynchronize(c->stream));
-    double tot = 0.0, by = 0.0;
-    long long n = 0;
-    for (size_t i = 0; i < c->prof.used; ++i) {
-        if (c->prof.cls[i] != which) continue;
-        float ms = 0.0f;
-        CK(hipEventElapsedTime(&ms, c->prof.pool[2 * i], c->prof.pool[2 * i + 1]));
-        tot += ms;
-        by += c->prof.bytes[i];
-        ++n;
-    }
-    if (total_ms) *total_ms = tot;
-    if (count) *count = n;
-    if (bytes) *bytes = by;
+    if (total_ms) *total_ms = c->prof.ms[which];
+    if (count) *count = c->prof.cnt[which];
+    if (bytes) *bytes = c->prof.bytes[which];
     return MG_OK;
 }
 
