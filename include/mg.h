@@ -128,13 +128,34 @@ mg_status mg_setup(const mg_params *p, const double *k2_dev, void *stream,
                    mg_ctx **out);
 
 /* One V(nu1, nu2) cycle for all nrhs right-hand sides, in place on u_dev
- * (A~_0 u = f).  res_before: NULL or host array of nrhs doubles receiving
- * ||f - A u|| of the incoming u (unscaled 2-norm), computed inside the
- * cycle; when non-NULL the call synchronises. */
+ * (A~_0 u = f): the level-dependent cycle of Sec. 3.1 (eq. cslvariant, coarse
+ * right-hand side by eq. erreq1 with c = 1).  res_before: NULL or host array
+ * of nrhs doubles receiving ||f - A u|| of the incoming u (unscaled 2-norm),
+ * computed inside the cycle; when non-NULL the call synchronises.  With
+ * mixed precision or a fixed-shift cycle (sigma_0 != 1) the call performs
+ * u <- u + M (f - A u) with the residual in FP64. */
 mg_status mg_cycle(mg_ctx *c, double *u_dev, const double *f_dev,
                    double *res_before);
 
-/* Solve A u = f for all right-hand sides to ||f - A u|| / ||f|| <= rtol.
+/* mg_cycle for callers that cannot allocate memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the same
+ * kernels and results, with every work vector, reduction buffer and launch
+ * table in a fixed device array of the library (64 MiB per GPU, held until
+ * the process ends) instead of the context's own work space; the slot
+ * tables are staged through a pinned host buffer allocated by mg_setup.
+ * Calls no hipMalloc or hipFree.  Errors: MG_E_INVAL when the context needs
+ * more than 64 MiB of work space (roughly more than 2M complex128 fine
+ * points times right-hand sides), MG_E_STATE when the current device is not
+ * the context's.  Every call on a GPU shares that array: calls that overlap
+ * on one GPU (other streams, other host threads, other contexts) race; calls
+ * ordered on one stream do not.  res_before as in mg_cycle. */
+mg_status mg_cycle_noalloc(mg_ctx *c, double *u_dev, const double *f_dev,
+                           double *res_before);
+
+/* Solve A u = f for all right-hand sides to ||f - A u|| / ||f|| <= rtol, by
+ * repeated cycles (Sec. 4.1, LVL-MG) or restarted right-preconditioned
+ * (F)GMRES with one cycle per outer step (Sec. 4.1, Table 3; flexible as
+ * Sec. 3.2.2 requires for the GMRES(3) smoother).
  * u_dev holds the initial guess on entry (zeros for a cold start) and the
  * result on exit.  mode: enum mg_mode.  maxit counts V-cycles (standalone)
  * or outer GMRES steps; restart is the GMRES(m) restart length (1..32,
@@ -174,17 +195,24 @@ mg_status mg_apply(mg_ctx *c, int level, int adjoint, const double *x_dev,
  * omega-Jacobi kernels, and strips of 56 columns by 32, 16, 8 rows for the
  * 2D GMRES(3) kernels.  mg_setup picks one per level by timing every shape
  * on the level's own arrays (levels of at least 4096 points above the coarse
- * tail; other levels use shape 0).
+ * tail; other levels use shape 0).  The sweep schedule of the two Arnoldi
+ * passes (points per thread, so workgroups per right-hand side) is picked
+ * the same way at the context's first GMRES solve.
  * shape >= 0 sets it, shape < 0 only queries; returns the shape in force or
  * a negative mg_status. */
 int mg_tile_shape(mg_ctx *c, int level, int shape);
 
 /* Batched solves (extension): the right-hand sides of several contexts --
  * grids of different sizes, one stream, one dimension and precision -- are
- * iterated together: every kernel launch of a step covers all of them, and
- * the coarse part of each V-cycle (levels >= 1 and the coarsest solve) is
- * captured once as a HIP graph and replayed.  The batch borrows the
- * contexts; destroy it before them.  u_dev[i], f_dev[i] are context i's
+ * iterated together: every kernel launch covers all of them (any number of
+ * right-hand sides), and a whole restart cycle of the batch (m Arnoldi steps
+ * with their V-cycles, the solution update and the new residual; in
+ * standalone mode, 8 cycles) is one HIP graph captured at the first solve
+ * and replayed; right-hand sides that stop early are skipped by device
+ * flags, and the host reads those flags once per graph launch.  Every
+ * right-hand side follows its own context's iteration: results equal the
+ * single-context solves bit for bit when the tile shapes agree.  The batch
+ * borrows the contexts; destroy it before them.  u_dev[i], f_dev[i] are context i's
  * vectors; iters and hist are laid out context after context, rhs after rhs
  * (hist: maxit + 1 doubles per rhs).  Same semantics and statuses as
  * mg_solve; MG_E_INVAL if the contexts do not match. */

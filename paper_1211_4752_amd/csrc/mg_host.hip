@@ -238,6 +238,9 @@ struct mg_ctx {
     int vper = 64;                    // points per thread of the Arnoldi passes (sweep schedule)
     bool vtuned = false;
     unsigned gen = 0;                 // bumped when buffers baked into recordings move
+    int device = 0;                   // HIP device of the context
+    char* stage = nullptr;            // pinned staging of mg_cycle_noalloc's tables
+    hipEvent_t stage_ev = nullptr;    // marks the end of the last staging copy
     Work work;
     Prof prof;
     OpCache cache;
@@ -1583,6 +1586,48 @@ mg_status ctx_solve(mg_ctx* c, int dir, double* u, const double* f, int mode, do
     Exec E = ctx_exec(c);
     return solve_items(E, c->work, dir, it, U, F, mode, rtol, maxit, restart, iters, hist);
 }
+// The GMRES(3) smoother's buffer table of a context (pointers per rhs and
+// level).
+std::vector<mg::SmoothBufs> smooth_table(const mg_ctx* c) {
+    const int L = c->L;
+    std::vector<mg::SmoothBufs> sb((size_t)c->nrhs * L);
+    for (int l = 0; l < L; ++l) {
+        const Level& V = c->lv[l];
+        for (int r = 0; r < c->nrhs; ++r) {
+            mg::SmoothBufs& b = sb[(size_t)r * L + l];
+            for (int i = 0; i < 3; ++i) b.q[i] = V.Q[i] ? lvec(c, V.Q[i], l, r) : nullptr;
+            b.u1 = V.SU1 ? lvec(c, V.SU1, l, r) : nullptr;
+            b.u2 = V.SU2 ? lvec(c, V.SU2, l, r) : nullptr;
+            b.coef = c->gcoef + ((size_t)r * L + l) * 8;
+            b.f = l > 0 ? lvec(c, V.F, l, r) : nullptr;
+            b.e = l > 0 ? lvec(c, V.E, l, r) : nullptr;
+        }
+    }
+    return sb;
+}
+
+// ---------------------------------------------------------------------------
+// Scratch of the allocation-free cycle: one file-scope device array per GPU
+// (kept until the process ends).  Host code uses the address obtained from
+// hipGetSymbolAddress on that device, never the array's name.
+// ---------------------------------------------------------------------------
+constexpr size_t SCRATCH_BYTES = (size_t)64 << 20;
+constexpr size_t STAGE_BYTES = (size_t)1 << 20;
+constexpr int MAX_DEVICES = 64;
+static __device__ __align__(256) unsigned char scratch[SCRATCH_BYTES];
+void* scratch_ptr[MAX_DEVICES] = {};
+
+// Address of this device's scratch (the device is current).
+mg_status scratch_init(int dev) {
+    if (dev < 0 || dev >= MAX_DEVICES) return MG_E_DEVICE;
+    if (scratch_ptr[dev]) return MG_OK;
+    void* p = nullptr;
+    CK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return MG_E_DEVICE;
+    scratch_ptr[dev] = p;
+    return MG_OK;
+}
+
 // ---------------------------------------------------------------------------
 // Set-up
 // ---------------------------------------------------------------------------
@@ -1618,6 +1663,9 @@ void release(mg_ctx* c) {
     dfree(c->V);
     dfree(c->scale_d);
     dfree(c->coef_d);
+    hfree(c->stage);
+    if (c->stage_ev) (void)hipEventDestroy(c->stage_ev);
+    c->stage_ev = nullptr;
     work_free(c->work);
 }
 
@@ -1919,7 +1967,6 @@ mg_status setup(const mg_params* p, const double* k2_dev, void* stream, mg_ctx* 
             break;
         }
     {
-        std::vector<mg::SmoothBufs> sb((size_t)c->nrhs * L);
         CKS(dalloc(&c->gcoef, (size_t)c->nrhs * L * 8 * sizeof(cx<double>)));
         for (int l = 0; l < L; ++l) {
             Level& V = c->lv[l];
@@ -1931,16 +1978,8 @@ mg_status setup(const mg_params* p, const double* k2_dev, void* stream, mg_ctx* 
                 if (tail || (c->gsmooth && (d == 3 || (i == 0 && l == 0)))) CKS(dalloc(&V.Q[i], bytes));
             if (tail || c->gsmooth) CKS(dalloc(&V.SU1, bytes));
             if (c->gsmooth && d == 3 && !tail) CKS(dalloc(&V.SU2, bytes));
-            for (int r = 0; r < c->nrhs; ++r) {
-                mg::SmoothBufs& b = sb[(size_t)r * L + l];
-                for (int i = 0; i < 3; ++i) b.q[i] = V.Q[i] ? lvec(c, V.Q[i], l, r) : nullptr;
-                b.u1 = V.SU1 ? lvec(c, V.SU1, l, r) : nullptr;
-                b.u2 = V.SU2 ? lvec(c, V.SU2, l, r) : nullptr;
-                b.coef = c->gcoef + ((size_t)r * L + l) * 8;
-                b.f = l > 0 ? lvec(c, V.F, l, r) : nullptr;
-                b.e = l > 0 ? lvec(c, V.E, l, r) : nullptr;
-            }
         }
+        const std::vector<mg::SmoothBufs> sb = smooth_table(c);
         CKS(dalloc(&c->sb_d, sb.size() * sizeof(mg::SmoothBufs)));
         CK(hipMemcpy(c->sb_d, sb.data(), sb.size() * sizeof(mg::SmoothBufs), hipMemcpyHostToDevice));
     }
@@ -1951,6 +1990,12 @@ mg_status setup(const mg_params* p, const double* k2_dev, void* stream, mg_ctx* 
     CKS(work_alloc(c->work, c->nrhs, max_blocks(c)));
     CKS(dalloc(&c->scale_d, (size_t)c->nrhs * HSTRIDE * sizeof(double)));
     CKS(dalloc(&c->coef_d, (size_t)c->nrhs * HSTRIDE * sizeof(cx<double>)));
+    // the allocation-free cycle: this device's scratch, pinned table staging
+    CK(hipGetDevice(&c->device));
+    CKS(scratch_init(c->device));
+    CKS(halloc(&c->stage, STAGE_BYTES));
+    CK(hipEventCreate(&c->stage_ev));
+    CK(hipEventRecord(c->stage_ev, c->stream));
     CK(hipStreamSynchronize(c->stream));
     CKS(autotune(c));
     CK(hipStreamSynchronize(c->stream));
@@ -2050,6 +2095,117 @@ mg_status mg_cycle(mg_ctx* c, double* u, const double* f, double* res_before) {
     }
     if (want) {
         CK(hipMemcpyAsync(c->work.rtot_h, c->work.rtot, n * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        CK(hipStreamSynchronize(c->stream));
+        for (int r = 0; r < n; ++r) res_before[r] = std::sqrt(c->work.rtot_h[r]);
+    }
+    return MG_OK;
+}
+
+// Allocation-free form of mg_cycle: the same recorded launches, with every
+// work vector, reduction buffer and table in this device's scratch.
+mg_status mg_cycle_noalloc(mg_ctx* c, double* u, const double* f, double* res_before) {
+    if (!c || !u || !f) return MG_E_INVAL;
+    int dev = -1;
+    CK(hipGetDevice(&dev));
+    if (dev != c->device || dev < 0 || dev >= MAX_DEVICES || !scratch_ptr[dev]) return MG_E_STATE;
+    char* base = (char*)scratch_ptr[dev];
+    size_t used = 0;
+    auto take = [&](size_t bytes) -> char* {
+        used = (used + 255) & ~(size_t)255;
+        char* p = base + used;
+        used += bytes;
+        return p;
+    };
+    // a shadow of the context whose work space lies in the scratch
+    mg_ctx sh;
+    sh.p = c->p;
+    sh.dim = c->dim;
+    sh.L = c->L;
+    sh.mixed = c->mixed;
+    sh.nrhs = c->nrhs;
+    sh.stream = c->stream;
+    sh.lv = c->lv;
+    sh.ncoarse = c->ncoarse;
+    for (int d = 0; d < 2; ++d) {
+        sh.lu[d] = c->lu[d];
+        sh.piv[d] = c->piv[d];
+        sh.views_d[d] = c->views_d[d];
+        sh.outer_d[d] = c->outer_d[d];
+        sh.views_f[d] = c->views_f[d];
+    }
+    sh.shifted0 = c->shifted0;
+    sh.gsmooth = c->gsmooth;
+    sh.lt = c->lt;
+    const size_t esz = elem(c);
+    for (int l = 0; l < c->L; ++l) {
+        Level& V = sh.lv[l];
+        const size_t bytes = (size_t)c->nrhs * V.N * esz;
+        if (V.F) V.F = take(bytes);
+        if (V.E) V.E = take(bytes);
+        for (int i = 0; i < 3; ++i)
+            if (V.Q[i]) V.Q[i] = take(bytes);
+        if (V.SU1) V.SU1 = take(bytes);
+        if (V.SU2) V.SU2 = take(bytes);
+    }
+    const size_t vbytes = (size_t)c->nrhs * c->lv[0].N * sizeof(cx<double>);
+    if (c->U1) sh.U1 = (cx<double>*)take(vbytes);
+    sh.W = (cx<double>*)take(vbytes);
+    sh.gcoef = (cx<double>*)take((size_t)c->nrhs * c->L * 8 * sizeof(cx<double>));
+    sh.sb_d = (mg::SmoothBufs*)take((size_t)c->nrhs * c->L * sizeof(mg::SmoothBufs));
+    Work w;
+    w.items = c->nrhs;
+    w.bstride = c->work.bstride;
+    w.part = (cx<double>*)take((size_t)c->nrhs * HSTRIDE * w.bstride * sizeof(cx<double>));
+    w.rpart = (double*)take((size_t)c->nrhs * w.bstride * sizeof(double));
+    w.rtot = (double*)take((size_t)c->nrhs * sizeof(double));
+    if (used > SCRATCH_BYTES) return MG_E_INVAL;
+
+    const long long N = c->lv[0].N;
+    const int n = c->nrhs;
+    std::vector<Item> it;
+    std::vector<cx<double>*> U;
+    std::vector<const cx<double>*> F;
+    for (int r = 0; r < n; ++r) {
+        it.push_back(Item{&sh, r});
+        U.push_back((cx<double>*)u + (size_t)r * N);
+        F.push_back((const cx<double>*)f + (size_t)r * N);
+    }
+    const bool want = res_before != nullptr;
+    Op op;
+    {
+        Rec R{&op, &w, c->dim, c->mixed, TAG_ALWAYS};
+        std::vector<int> cnt;
+        std::vector<L0> l0(n);
+        if (!c->mixed && !c->shifted0) {
+            for (int r = 0; r < n; ++r) l0[r] = L0{F[r], 1.0, nullptr, U[r], U[r]};
+            CKS(rec_cycle(R, 0, it, G_NONE, l0, false, want, &cnt));
+            if (want) CKS(rec_reduce_real(R, cnt));
+        } else {
+            std::vector<const cx<double>*> xs(U.begin(), U.end());
+            std::vector<cx<double>*> ws(n);
+            for (int r = 0; r < n; ++r) ws[r] = wvec(it[r]);
+            CKS(rec_residual(R, 0, it, G_NONE, xs, F, ws, want, &cnt));
+            if (want) CKS(rec_reduce_real(R, cnt));
+            for (int r = 0; r < n; ++r) l0[r] = L0{ws[r], 1.0, nullptr, nullptr, U[r]};
+            CKS(rec_cycle(R, 0, it, G_NONE, l0, true, false, nullptr));
+        }
+    }
+    char* dtab = take(op.tab.size());
+    if (used > SCRATCH_BYTES) return MG_E_INVAL;
+    const std::vector<mg::SmoothBufs> sb = smooth_table(&sh);
+    const size_t sbb = sb.size() * sizeof(mg::SmoothBufs);
+    if (sbb + op.tab.size() > STAGE_BYTES) return MG_E_INVAL;
+    // the staging buffer is free once the previous call's copies are done
+    CK(hipEventSynchronize(c->stage_ev));
+    std::memcpy(c->stage, sb.data(), sbb);
+    if (!op.tab.empty()) std::memcpy(c->stage + sbb, op.tab.data(), op.tab.size());
+    CK(hipMemcpyAsync(sh.sb_d, c->stage, sbb, hipMemcpyHostToDevice, c->stream));
+    if (!op.tab.empty())
+        CK(hipMemcpyAsync(dtab, c->stage + sbb, op.tab.size(), hipMemcpyHostToDevice, c->stream));
+    CK(hipEventRecord(c->stage_ev, c->stream));
+    for (const Step& st : op.steps) CK(st.fn(c->stream, dtab));
+    if (want) {
+        CK(hipMemcpyAsync(c->work.rtot_h, w.rtot, n * sizeof(double), hipMemcpyDeviceToHost, c->stream));
         CK(hipStreamSynchronize(c->stream));
         for (int r = 0; r < n; ++r) res_before[r] = std::sqrt(c->work.rtot_h[r]);
     }

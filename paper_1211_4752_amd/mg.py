@@ -35,7 +35,7 @@ EXPORTS = [
     "mg_params_default", "mg_setup", "mg_cycle", "mg_solve", "mg_solve_adjoint",
     "mg_grad_k2", "mg_apply", "mg_num_levels", "mg_level_dims", "mg_get_sigma",
     "mg_profile", "mg_profile_read", "mg_destroy", "mg_status_str",
-    "mg_tile_shape", "mg_batch_create", "mg_batch_solve", "mg_batch_destroy",
+    "mg_tile_shape", "mg_batch_create", "mg_batch_solve", "mg_batch_destroy", "mg_cycle_noalloc",
 ]
 
 
@@ -80,6 +80,7 @@ def lib():
         L.mg_params_default.restype = None
         L.mg_setup.argtypes = [ctypes.POINTER(Params), vp, vp, ctypes.POINTER(vp)]
         L.mg_cycle.argtypes = [vp, vp, vp, dp]
+        L.mg_cycle_noalloc.argtypes = [vp, vp, vp, dp]
         L.mg_solve.argtypes = [vp, vp, vp, ctypes.c_int, ctypes.c_double, ctypes.c_int, ctypes.c_int, ip, dp]
         L.mg_solve_adjoint.argtypes = L.mg_solve.argtypes
         L.mg_grad_k2.argtypes = [vp, vp, vp, vp]
@@ -102,7 +103,7 @@ def lib():
         L.mg_batch_destroy.restype = None
         L.mg_status_str.argtypes = [ctypes.c_int]
         L.mg_status_str.restype = ctypes.c_char_p
-        for name in ("mg_setup", "mg_cycle", "mg_solve", "mg_solve_adjoint", "mg_grad_k2", "mg_apply",
+        for name in ("mg_setup", "mg_cycle", "mg_cycle_noalloc", "mg_solve", "mg_solve_adjoint", "mg_grad_k2", "mg_apply",
                      "mg_level_dims", "mg_get_sigma", "mg_profile", "mg_profile_read"):
             getattr(L, name).restype = ctypes.c_int
         L.mg_num_levels.restype = ctypes.c_int
@@ -235,6 +236,16 @@ class Solver:
         st = lib().mg_cycle(self.ctx, _ptr(u), _ptr(f), res)
         if st != MG_OK:
             raise MGError(st, "mg_cycle")
+        return np.array(res[:]) if residual else None
+
+    def cycle_noalloc(self, u, f, residual=False):
+        """mg_cycle_noalloc: the cycle with the library's fixed scratch."""
+        self._check_vec(u)
+        self._check_vec(f)
+        res = (ctypes.c_double * self.nrhs)() if residual else None
+        st = lib().mg_cycle_noalloc(self.ctx, _ptr(u), _ptr(f), res)
+        if st != MG_OK:
+            raise MGError(st, "mg_cycle_noalloc")
         return np.array(res[:]) if residual else None
 
     def _solve(self, fn, u, f, mode, rtol, maxit, restart):
