@@ -76,8 +76,7 @@ struct LevelView {
     const cx<T>* c0[3];
     const cx<T>* cp[3];
     const T* k2;               // k^2 sampled on this level
-    const cx<double>* lu;      // coarsest level only: LU factors (FP64), row-major
-    const int* piv;            //   and row interchanges
+    const cx<double>* cinv;    // coarsest level only: inverse of the level operator (FP64), row-major
     cx<T> sigma;               // shift multiplying k^2
     cx<T> omega;               // Jacobi weight
     T sinv;                    // 1 / s, s the scale of the smoother's power basis
@@ -98,8 +97,8 @@ struct SmoothBufs {
 
 // The coarse tail: one workgroup per slot runs the cycle from level lt
 // (rhs in sb[0].f, zero guess) down to the coarsest and back, leaving the
-// correction in sb[0].e.  lv and sb point at level lt; both tables are
-// contiguous by level.
+// correction in sb[0].e, with every vector of those levels in LDS.  lv and
+// sb point at level lt; both tables are contiguous by level.
 struct TailSlot {
     const void* lv;
     const SmoothBufs* sb;
@@ -115,6 +114,8 @@ struct TailArgs {
     const TailSlot* s;         // device table of n slots
 };
 constexpr int TAIL_POINTS = 4096;   // levels of at most this many points go to the tail
+constexpr int SMALL_POINTS = 1024;  // tail levels of at most this many points live in LDS
+constexpr int TAIL_LDS = 1408;      // points of all LDS tail levels together
 
 // A slot of the two fused cycle kernels and of the coarsest solve.
 struct CycleSlot {

@@ -111,6 +111,19 @@ bool lu_factor(std::vector<cd>& A, std::vector<int>& piv, int n) {
     return true;
 }
 
+// Solve (LU) x = b in place with the factors and interchanges of lu_factor.
+void lu_solve(const std::vector<cd>& A, const std::vector<int>& piv, int n, std::vector<cd>& b) {
+    for (int k = 0; k < n; ++k)
+        if (piv[k] != k) std::swap(b[k], b[piv[k]]);
+    for (int k = 0; k < n; ++k)
+        for (int i = k + 1; i < n; ++i) b[i] -= A[(size_t)i * n + k] * b[k];
+    for (int k = n - 1; k >= 0; --k) {
+        cd s = b[k];
+        for (int j = k + 1; j < n; ++j) s -= A[(size_t)k * n + j] * b[j];
+        b[k] = s / A[(size_t)k * n + k];
+    }
+}
+
 struct Level {
     int n[3] = {1, 1, 1};
     long long N = 0;
@@ -212,8 +225,7 @@ struct mg_ctx {
     hipStream_t stream = nullptr;
     std::vector<Level> lv;
     int ncoarse = 0;
-    cx<double>* lu[2] = {nullptr, nullptr};
-    int* piv[2] = {nullptr, nullptr};
+    cx<double>* cinv[2] = {nullptr, nullptr};   // inverse of the coarsest operator per direction
     LevelView<double>* views_d[2] = {nullptr, nullptr};   // device, one per level
     LevelView<double>* outer_d[2] = {nullptr, nullptr};   // the unshifted level-0 operator (sigma = 1)
     bool shifted0 = false;            // the cycle's level-0 shift differs from 1 (fixed-shift preconditioner)
@@ -1651,8 +1663,7 @@ void release(mg_ctx* c) {
     dfree(c->gcoef);
     dfree(c->Zb);
     for (int d = 0; d < 2; ++d) {
-        dfree(c->lu[d]);
-        dfree(c->piv[d]);
+        dfree(c->cinv[d]);
         dfree(c->views_d[d]);
         dfree(c->outer_d[d]);
         dfree(c->views_f[d]);
@@ -1709,16 +1720,14 @@ mg_status upload_views(mg_ctx* c) {
             a.sinv = 1.0 / sc;
             b.sinv = (float)(1.0 / sc);
             if (l == c->L - 1) {
-                a.lu = b.lu = c->lu[dir];
-                a.piv = b.piv = c->piv[dir];
+                a.cinv = b.cinv = c->cinv[dir];
             }
         }
         CKS(dalloc(&c->views_d[dir], vd.size() * sizeof(LevelView<double>)));
         CK(hipMemcpy(c->views_d[dir], vd.data(), vd.size() * sizeof(LevelView<double>), hipMemcpyHostToDevice));
         LevelView<double> outer = vd[0];   // residuals and Krylov steps: the problem's own operator
         outer.sigma = mg::mk(1.0, 0.0);
-        outer.lu = nullptr;
-        outer.piv = nullptr;
+        outer.cinv = nullptr;
         CKS(dalloc(&c->outer_d[dir], sizeof(LevelView<double>)));
         CK(hipMemcpy(c->outer_d[dir], &outer, sizeof(LevelView<double>), hipMemcpyHostToDevice));
         if (c->mixed) {
@@ -1942,12 +1951,18 @@ mg_status setup(const mg_params* p, const double* k2_dev, void* stream, mg_ctx* 
             std::vector<cd>& M = dir ? AH : A;
             std::vector<int> piv;
             if (!lu_factor(M, piv, nc)) return MG_E_INVAL;
-            std::vector<cx<double>> Mc(M.size());
-            for (size_t i = 0; i < M.size(); ++i) Mc[i] = tocx(M[i]);
-            CKS(dalloc(&c->lu[dir], Mc.size() * sizeof(cx<double>)));
-            CKS(dalloc(&c->piv[dir], nc * sizeof(int)));
-            CK(hipMemcpy(c->lu[dir], Mc.data(), Mc.size() * sizeof(cx<double>), hipMemcpyHostToDevice));
-            CK(hipMemcpy(c->piv[dir], piv.data(), nc * sizeof(int), hipMemcpyHostToDevice));
+            // the direct solve on the coarsest level applies the inverse,
+            // formed column by column from the LU factors in FP64
+            std::vector<cx<double>> inv((size_t)nc * nc);
+            std::vector<cd> col(nc);
+            for (int j = 0; j < nc; ++j) {
+                std::fill(col.begin(), col.end(), cd(0.0));
+                col[j] = 1.0;
+                lu_solve(M, piv, nc, col);
+                for (int i = 0; i < nc; ++i) inv[(size_t)i * nc + j] = tocx(col[i]);
+            }
+            CKS(dalloc(&c->cinv[dir], inv.size() * sizeof(cx<double>)));
+            CK(hipMemcpy(c->cinv[dir], inv.data(), inv.size() * sizeof(cx<double>), hipMemcpyHostToDevice));
         }
     }
     CKS(upload_views(c));
@@ -1966,6 +1981,13 @@ mg_status setup(const mg_params* p, const double* k2_dev, void* stream, mg_ctx* 
             c->lt = l;
             break;
         }
+    {   // the levels of the tail with at most SMALL_POINTS points share its LDS
+        long long small = 0;
+        for (int l = c->lt; l < L; ++l)
+            if (c->lv[l].N <= mg::SMALL_POINTS || l == L - 1) small += c->lv[l].N;
+        if (c->lv[c->lt].N > mg::TAIL_POINTS || small > mg::TAIL_LDS || c->lv[L - 1].N > mg::SMALL_POINTS)
+            return MG_E_INVAL;
+    }
     {
         CKS(dalloc(&c->gcoef, (size_t)c->nrhs * L * 8 * sizeof(cx<double>)));
         for (int l = 0; l < L; ++l) {
@@ -2127,8 +2149,7 @@ mg_status mg_cycle_noalloc(mg_ctx* c, double* u, const double* f, double* res_be
     sh.lv = c->lv;
     sh.ncoarse = c->ncoarse;
     for (int d = 0; d < 2; ++d) {
-        sh.lu[d] = c->lu[d];
-        sh.piv[d] = c->piv[d];
+        sh.cinv[d] = c->cinv[d];
         sh.views_d[d] = c->views_d[d];
         sh.outer_d[d] = c->outer_d[d];
         sh.views_f[d] = c->views_f[d];

@@ -1,11 +1,14 @@
 // The coarse tail of the V-cycle (Sec. 3.1) in one launch: every level of at
 // most TAIL_POINTS points, the coarsest direct solve and the way back up, one
 // 1024-thread workgroup per right-hand side, passes separated by workgroup
-// barriers.  On these levels a pass is a few points per thread, so the cost
-// of a cycle there is set by dependent steps, not bytes: one launch replaces
-// about six per level.  Smoothing is omega-Jacobi (Sec. 3.2.1) or one GMRES(3)
-// step (Sec. 3.2.2) with the minimiser from the Gram matrix of the scaled
-// power basis, reduced inside the workgroup.
+// barriers.  The vectors of levels of at most SMALL_POINTS points (right-hand
+// sides, iterates, corrections, the smoother's powers) live in LDS and each
+// thread holds its point's stencil coefficients in registers through a
+// level's passes; larger tail levels (up to 4 points per thread) use global
+// work vectors.  The coarsest solve multiplies by the inverse of the
+// coarsest operator, formed in FP64 at set-up.  Smoothing is omega-Jacobi
+// (Sec. 3.2.1) or one GMRES(3) step (Sec. 3.2.2) with the minimiser from the
+// Gram matrix of the scaled power basis, reduced inside the workgroup.
 
 #include "mg_kcommon.hpp"
 
@@ -16,24 +19,7 @@ using namespace kc;
 namespace {
 
 constexpr int NTT = 1024;
-constexpr int PPT = TAIL_POINTS / NTT;   // points per thread on a tail level
-
-// out[p] = fn(p) for the level's points: every value first, then every store,
-// so that the loads of all of a thread's points are in flight together.
-template <typename T, typename F>
-__device__ __forceinline__ void map_store(int N, cx<T>* out, F fn) {
-    cx<T> v[PPT];
-#pragma unroll
-    for (int i = 0; i < PPT; ++i) {
-        const int p = threadIdx.x + i * NTT;
-        v[i] = p < N ? fn(p) : mk<T>(0, 0);
-    }
-#pragma unroll
-    for (int i = 0; i < PPT; ++i) {
-        const int p = threadIdx.x + i * NTT;
-        if (p < N) out[p] = v[i];
-    }
-}
+constexpr int MAX_TAIL_LEVELS = 16;
 
 template <int D>
 __device__ __forceinline__ void pos3(int p, int nx, int ny, int& gx, int& gy, int& gz) {
@@ -73,7 +59,7 @@ __device__ __forceinline__ cx<T> prolong_at(const LevelView<T>& Lc, const cx<T>*
     axis_w<T>(gx, Lc.n[0], x0, x1, wx0, wx1);
     axis_w<T>(gy, Lc.n[1], y0, y1, wy0, wy1);
     if constexpr (D == 3) axis_w<T>(gz, Lc.n[2], z0, z1, wz0, wz1);
-    const long long sx = Lc.n[0], sxy = (long long)Lc.n[0] * Lc.n[1];
+    const int sx = Lc.n[0], sxy = Lc.n[0] * Lc.n[1];
     cx<T> v = mk<T>(0, 0);
 #pragma unroll
     for (int kz = 0; kz < (D == 3 ? 2 : 1); ++kz) {
@@ -98,11 +84,11 @@ __device__ __forceinline__ cx<T> restrict_at(const LevelView<T>& L, const cx<T>*
 #pragma unroll
     for (int oz = (D == 3 ? -1 : 0); oz <= (D == 3 ? 1 : 0); ++oz) {
         const T wz = (D == 3) ? (oz == 0 ? T(0.5) : T(0.25)) : T(1);
-        const long long zb = (D == 3) ? (long long)(2 * cz + 1 + oz) * nx * ny : 0;
+        const int zb = (D == 3) ? (2 * cz + 1 + oz) * nx * ny : 0;
 #pragma unroll
         for (int oy = -1; oy <= 1; ++oy) {
             const T wy = wz * (oy == 0 ? T(0.5) : T(0.25));
-            const cx<T>* row = r + zb + (long long)(2 * cy + 1 + oy) * nx + 2 * cx_ + 1;
+            const cx<T>* row = r + zb + (2 * cy + 1 + oy) * nx + 2 * cx_ + 1;
 #pragma unroll
             for (int ox = -1; ox <= 1; ++ox) acc = acc + (wy * (ox == 0 ? T(0.5) : T(0.25))) * row[ox];
         }
@@ -110,35 +96,61 @@ __device__ __forceinline__ cx<T> restrict_at(const LevelView<T>& L, const cx<T>*
     return acc;
 }
 
-// Workgroup Gram matrix of (q0, q1, q2, q3 = (A/s) q2) and the coefficient
-// solve; the coefficients land in sc[0..2] for every thread.
+// Stencil coefficients of one point, held in registers through a level's
+// passes (LDS levels: one point per thread).
+template <typename T>
+struct PtCoef {
+    cx<T> d;                       // sum of the c0 - sigma k^2
+    cx<T> m[3], pl[3];             // minus / plus neighbour per axis (0 at the boundary)
+    int gx, gy, gz;
+};
+
 template <int D, typename T>
-__device__ void tail_gram(const LevelView<T>& L, const cx<T>* q0, const cx<T>* q1, const cx<T>* q2, double brk,
-                          cx<double>* sred, cx<double>* sc) {
-    const int nx = L.n[0], ny = L.n[1];
-    const int N = (int)L.N;
-    cx<double> g[NUM_GRAM];
+__device__ __forceinline__ PtCoef<T> pt_coef(const LevelView<T>& L, int p) {
+    PtCoef<T> c;
+    pos3<D>(p, L.n[0], L.n[1], c.gx, c.gy, c.gz);
+    c.d = diag_at<D>(L, c.gx, c.gy, c.gz, L.k2[p]);
+    const int g[3] = {c.gx, c.gy, c.gz};
 #pragma unroll
-    for (int v = 0; v < NUM_GRAM; ++v) g[v] = mk(0.0, 0.0);
-#pragma unroll
-    for (int i = 0; i < PPT; ++i) {
-        const int p = threadIdx.x + i * NTT;
-        if (p >= N) continue;
-        int gx, gy, gz;
-        pos3<D>(p, nx, ny, gx, gy, gz);
-        const cx<double> v0 = cvt<double>(q0[p]), v1 = cvt<double>(q1[p]), v2 = cvt<double>(q2[p]);
-        const cx<double> v3 = cvt<double>(L.sinv * stencil_at<D, T, T>(L, q2, T(1), p, gx, gy, gz));
-        g[0].r += abs2(v0);
-        g[1].r += abs2(v1);
-        g[2].r += abs2(v2);
-        g[3].r += abs2(v3);
-        g[4] = g[4] + cmulc(v0, v1);
-        g[5] = g[5] + cmulc(v0, v2);
-        g[6] = g[6] + cmulc(v0, v3);
-        g[7] = g[7] + cmulc(v1, v2);
-        g[8] = g[8] + cmulc(v1, v3);
-        g[9] = g[9] + cmulc(v2, v3);
+    for (int a = 0; a < 3; ++a) {
+        c.m[a] = c.pl[a] = mk<T>(0, 0);
+        if (a < D) {
+            if (g[a] > 0) c.m[a] = L.cm[a][g[a]];
+            if (g[a] < L.n[a] - 1) c.pl[a] = L.cp[a][g[a]];
+        }
     }
+    return c;
+}
+
+// (A x)(p) * sc with the point's coefficients in registers.
+template <int D, typename T>
+__device__ __forceinline__ cx<T> apply_pt(const PtCoef<T>& c, const LevelView<T>& L, const cx<T>* x, int p, T sc) {
+    const int nx = L.n[0], nxy = L.n[0] * L.n[1];
+    cx<T> ax = c.d * x[p];
+    if (c.gx > 0) ax = ax + c.m[0] * x[p - 1];
+    if (c.gx < nx - 1) ax = ax + c.pl[0] * x[p + 1];
+    if (c.gy > 0) ax = ax + c.m[1] * x[p - nx];
+    if (c.gy < L.n[1] - 1) ax = ax + c.pl[1] * x[p + nx];
+    if constexpr (D == 3) {
+        if (c.gz > 0) ax = ax + c.m[2] * x[p - nxy];
+        if (c.gz < L.n[2] - 1) ax = ax + c.pl[2] * x[p + nxy];
+    }
+    return sc * ax;
+}
+
+// (A x)(p) * sc reading the coefficients from global memory.
+template <int D, typename T>
+__device__ __forceinline__ cx<T> apply_gl(const LevelView<T>& L, const cx<T>* x, int p, T sc) {
+    int gx, gy, gz;
+    pos3<D>(p, L.n[0], L.n[1], gx, gy, gz);
+    return stencil_at<D, T, T>(L, x, sc, p, gx, gy, gz);
+}
+
+constexpr int PPT = TAIL_POINTS / NTT;   // points per thread on a tail level in global memory
+
+// Gram partials of the thread's points and the workgroup coefficient solve
+// (coefficients land in sc[0..2]).
+__device__ void gram_finish(cx<double>* g, double brk, cx<double>* sred, cx<double>* sc) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
     for (int v = 0; v < NUM_GRAM; ++v) {
@@ -156,174 +168,265 @@ __device__ void tail_gram(const LevelView<T>& L, const cx<T>* q0, const cx<T>* q
     __syncthreads();
 }
 
+template <typename T>
+__device__ __forceinline__ void gram_add(cx<double>* g, cx<T> a0, cx<T> a1, cx<T> a2, cx<T> a3) {
+    const cx<double> v0 = cvt<double>(a0), v1 = cvt<double>(a1), v2 = cvt<double>(a2), v3 = cvt<double>(a3);
+    g[0].r += abs2(v0);
+    g[1].r += abs2(v1);
+    g[2].r += abs2(v2);
+    g[3].r += abs2(v3);
+    g[4] = g[4] + cmulc(v0, v1);
+    g[5] = g[5] + cmulc(v0, v2);
+    g[6] = g[6] + cmulc(v0, v3);
+    g[7] = g[7] + cmulc(v1, v2);
+    g[8] = g[8] + cmulc(v1, v3);
+    g[9] = g[9] + cmulc(v2, v3);
+}
+
+// Vectors of one level of the tail: in LDS (small levels) or global memory.
+template <typename T>
+struct LvVec {
+    cx<T>* f;
+    cx<T>* u;
+    cx<T>* q[3];
+};
+
+// Pre-smoothing of level k (zero initial guess) and the restriction of its
+// residual into fc.  SMALL: at most one point per thread, coefficients in
+// registers; otherwise up to PPT points per thread.
+template <int D, typename T, bool GM, bool SMALL>
+__device__ void level_down(const LevelView<T>& L, const LevelView<T>& Lc, const LvVec<T>& v, cx<T>* fc, double brk,
+                           cx<double>* sred, cx<double>* sc) {
+    const int N = (int)L.N;
+    constexpr int NP = SMALL ? 1 : PPT;
+    PtCoef<T> pc;
+    if constexpr (SMALL)
+        if ((int)threadIdx.x < N) pc = pt_coef<D, T>(L, threadIdx.x);
+    auto A = [&](const cx<T>* x, int p, T s) -> cx<T> {
+        if constexpr (SMALL) return apply_pt<D, T>(pc, L, x, p, s);
+        else return apply_gl<D, T>(L, x, p, s);
+    };
+    if constexpr (GM) {
+#pragma unroll
+        for (int i = 0; i < NP; ++i) {
+            const int p = threadIdx.x + i * NTT;
+            if (p < N) v.q[1][p] = A(v.f, p, L.sinv);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < NP; ++i) {
+            const int p = threadIdx.x + i * NTT;
+            if (p < N) v.q[2][p] = A(v.q[1], p, L.sinv);
+        }
+        __syncthreads();
+        cx<double> g[NUM_GRAM];
+#pragma unroll
+        for (int j = 0; j < NUM_GRAM; ++j) g[j] = mk(0.0, 0.0);
+        cx<T> q3[NP];
+#pragma unroll
+        for (int i = 0; i < NP; ++i) {
+            const int p = threadIdx.x + i * NTT;
+            q3[i] = mk<T>(0, 0);
+            if (p < N) {
+                q3[i] = A(v.q[2], p, L.sinv);
+                gram_add<T>(g, v.f[p], v.q[1][p], v.q[2][p], q3[i]);
+            }
+        }
+        gram_finish(g, brk, sred, sc);
+        const cx<T> c1 = cvt<T>(sc[0]), c2 = cvt<T>(sc[1]), c3 = cvt<T>(sc[2]);
+#pragma unroll
+        for (int i = 0; i < NP; ++i) {
+            const int p = threadIdx.x + i * NTT;
+            if (p < N) {
+                const cx<T> q0 = v.f[p], q1 = v.q[1][p], q2 = v.q[2][p];
+                v.u[p] = mk<T>(0, 0) - L.sinv * (c1 * q0 + c2 * q1 + c3 * q2);
+                v.q[1][p] = q0 + c1 * q1 + c2 * q2 + c3 * q3[i];   // the new residual
+            }
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < NP; ++i) {
+            const int p = threadIdx.x + i * NTT;
+            if (p < N) {
+                cx<T> d;
+                if constexpr (SMALL) d = pc.d;
+                else {
+                    int gx, gy, gz;
+                    pos3<D>(p, L.n[0], L.n[1], gx, gy, gz);
+                    d = diag_at<D>(L, gx, gy, gz, L.k2[p]);
+                }
+                v.u[p] = cdiv(L.omega * v.f[p], d);
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < NP; ++i) {
+            const int p = threadIdx.x + i * NTT;
+            if (p < N) v.q[1][p] = v.f[p] - A(v.u, p, T(1));
+        }
+    }
+    __syncthreads();
+    for (int p = threadIdx.x; p < (int)Lc.N; p += NTT) {
+        int cx_, cy, cz;
+        pos3<D>(p, Lc.n[0], Lc.n[1], cx_, cy, cz);
+        fc[p] = restrict_at<D, T>(L, v.q[1], cx_, cy, cz);
+    }
+    __syncthreads();
+}
+
+// Coarse-grid correction u2 = u1 + P ec and post-smoothing of level k; the
+// correction of the level lands in v.u.
+template <int D, typename T, bool GM, bool SMALL>
+__device__ void level_up(const LevelView<T>& L, const LevelView<T>& Lc, const LvVec<T>& v, const cx<T>* ec,
+                         double brk, cx<double>* sred, cx<double>* sc) {
+    const int N = (int)L.N;
+    constexpr int NP = SMALL ? 1 : PPT;
+    PtCoef<T> pc;
+    if constexpr (SMALL)
+        if ((int)threadIdx.x < N) pc = pt_coef<D, T>(L, threadIdx.x);
+    auto A = [&](const cx<T>* x, int p, T s) -> cx<T> {
+        if constexpr (SMALL) return apply_pt<D, T>(pc, L, x, p, s);
+        else return apply_gl<D, T>(L, x, p, s);
+    };
+#pragma unroll
+    for (int i = 0; i < NP; ++i) {
+        const int p = threadIdx.x + i * NTT;
+        if (p < N) {
+            int gx, gy, gz;
+            pos3<D>(p, L.n[0], L.n[1], gx, gy, gz);
+            v.u[p] = v.u[p] + prolong_at<D, T>(Lc, ec, gx, gy, gz);
+        }
+    }
+    __syncthreads();
+    if constexpr (GM) {
+#pragma unroll
+        for (int i = 0; i < NP; ++i) {
+            const int p = threadIdx.x + i * NTT;
+            if (p < N) v.q[0][p] = v.f[p] - A(v.u, p, T(1));
+        }
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < NP; ++i) {
+            const int p = threadIdx.x + i * NTT;
+            if (p < N) v.q[1][p] = A(v.q[0], p, L.sinv);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < NP; ++i) {
+            const int p = threadIdx.x + i * NTT;
+            if (p < N) v.q[2][p] = A(v.q[1], p, L.sinv);
+        }
+        __syncthreads();
+        cx<double> g[NUM_GRAM];
+#pragma unroll
+        for (int j = 0; j < NUM_GRAM; ++j) g[j] = mk(0.0, 0.0);
+#pragma unroll
+        for (int i = 0; i < NP; ++i) {
+            const int p = threadIdx.x + i * NTT;
+            if (p < N) gram_add<T>(g, v.q[0][p], v.q[1][p], v.q[2][p], A(v.q[2], p, L.sinv));
+        }
+        gram_finish(g, brk, sred, sc);
+        const cx<T> c1 = cvt<T>(sc[0]), c2 = cvt<T>(sc[1]), c3 = cvt<T>(sc[2]);
+#pragma unroll
+        for (int i = 0; i < NP; ++i) {
+            const int p = threadIdx.x + i * NTT;
+            if (p < N) v.u[p] = v.u[p] - L.sinv * (c1 * v.q[0][p] + c2 * v.q[1][p] + c3 * v.q[2][p]);
+        }
+        __syncthreads();
+    } else {
+#pragma unroll
+        for (int i = 0; i < NP; ++i) {
+            const int p = threadIdx.x + i * NTT;
+            if (p < N) {
+                cx<T> d;
+                if constexpr (SMALL) d = pc.d;
+                else {
+                    int gx, gy, gz;
+                    pos3<D>(p, L.n[0], L.n[1], gx, gy, gz);
+                    d = diag_at<D>(L, gx, gy, gz, L.k2[p]);
+                }
+                v.q[0][p] = v.u[p] + cdiv(L.omega * (v.f[p] - A(v.u, p, T(1))), d);
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < NP; ++i) {
+            const int p = threadIdx.x + i * NTT;
+            if (p < N) v.u[p] = v.q[0][p];
+        }
+        __syncthreads();
+    }
+}
+
 template <int D, typename T, bool GM>
 __global__ void __launch_bounds__(NTT) k_tail(const TailArgs a) {
+    __shared__ cx<T> sf[TAIL_LDS];            // right-hand side of every LDS level
+    __shared__ cx<T> su[TAIL_LDS];            // iterate, then correction, of every LDS level
+    __shared__ cx<T> sq[3][SMALL_POINTS];     // powers / residuals of the LDS level in progress
     __shared__ cx<double> sred[(NTT / 64 + 1) * NUM_GRAM];
     __shared__ cx<double> sc[4];
-    __shared__ cx<double> b[MAX_COARSE];
     const TailSlot& ts = a.s[blockIdx.x];
     if (gated_off(ts.gate)) return;
     const LevelView<T>* Lv = static_cast<const LevelView<T>*>(ts.lv);
     const SmoothBufs* SB = ts.sb;
     const int last = ts.nlev - 1;
-
-    for (int k = 0; k < last; ++k) {
-        const LevelView<T> L = Lv[k];
-        const SmoothBufs B = SB[k];
-        const int nx = L.n[0], ny = L.n[1], N = (int)L.N;
-        const cx<T>* f = static_cast<const cx<T>*>(B.f);
-        cx<T>* u1 = static_cast<cx<T>*>(B.u1);
-        cx<T>* q1 = static_cast<cx<T>*>(B.q[1]);
-        if constexpr (GM) {
-            cx<T>* q2 = static_cast<cx<T>*>(B.q[2]);
-            map_store<T>(N, q1, [&](int p) {
-                int gx, gy, gz;
-                pos3<D>(p, nx, ny, gx, gy, gz);
-                return L.sinv * stencil_at<D, T, T>(L, f, T(1), p, gx, gy, gz);
-            });
-            __syncthreads();
-            map_store<T>(N, q2, [&](int p) {
-                int gx, gy, gz;
-                pos3<D>(p, nx, ny, gx, gy, gz);
-                return L.sinv * stencil_at<D, T, T>(L, q1, T(1), p, gx, gy, gz);
-            });
-            __syncthreads();
-            tail_gram<D, T>(L, f, q1, q2, a.brk, sred, sc);
-            const cx<T> c1 = cvt<T>(sc[0]), c2 = cvt<T>(sc[1]), c3 = cvt<T>(sc[2]);
-            // u1 and the new residual (into q1, pointwise in place)
-            cx<T> ru[PPT], rr[PPT];
-#pragma unroll
-            for (int i = 0; i < PPT; ++i) {
-                const int p = threadIdx.x + i * NTT;
-                ru[i] = rr[i] = mk<T>(0, 0);
-                if (p < N) {
-                    int gx, gy, gz;
-                    pos3<D>(p, nx, ny, gx, gy, gz);
-                    const cx<T> q0 = f[p], v1 = q1[p], v2 = q2[p];
-                    const cx<T> v3 = L.sinv * stencil_at<D, T, T>(L, q2, T(1), p, gx, gy, gz);
-                    ru[i] = mk<T>(0, 0) - L.sinv * (c1 * q0 + c2 * v1 + c3 * v2);
-                    rr[i] = q0 + c1 * v1 + c2 * v2 + c3 * v3;
-                }
-            }
-#pragma unroll
-            for (int i = 0; i < PPT; ++i) {
-                const int p = threadIdx.x + i * NTT;
-                if (p < N) {
-                    u1[p] = ru[i];
-                    q1[p] = rr[i];
-                }
-            }
+    // levels 0 .. big-1 of the tail keep their vectors in global memory
+    int big = 0;
+    while (big < last && Lv[big].N > SMALL_POINTS) ++big;
+    __shared__ int off[MAX_TAIL_LEVELS + 1];   // LDS offsets of the small levels
+    if (threadIdx.x == 0) {
+        for (int k = 0; k <= big; ++k) off[k] = 0;
+        for (int k = big; k <= last && k < MAX_TAIL_LEVELS; ++k) off[k + 1] = off[k] + (int)Lv[k].N;
+    }
+    __syncthreads();
+    auto vecs = [&](int k) -> LvVec<T> {
+        LvVec<T> v;
+        if (k < big) {
+            const SmoothBufs& B = SB[k];
+            v.f = static_cast<cx<T>*>(B.f);
+            v.u = static_cast<cx<T>*>(B.u1);
+            for (int i = 0; i < 3; ++i) v.q[i] = static_cast<cx<T>*>(B.q[i]);
         } else {
-            map_store<T>(N, u1, [&](int p) {
-                int gx, gy, gz;
-                pos3<D>(p, nx, ny, gx, gy, gz);
-                return cdiv(L.omega * f[p], diag_at<D>(L, gx, gy, gz, L.k2[p]));
-            });
-            __syncthreads();
-            map_store<T>(N, q1, [&](int p) {
-                int gx, gy, gz;
-                pos3<D>(p, nx, ny, gx, gy, gz);
-                return f[p] - stencil_at<D, T, T>(L, u1, T(1), p, gx, gy, gz);
-            });
+            v.f = sf + off[k];
+            v.u = su + off[k];
+            for (int i = 0; i < 3; ++i) v.q[i] = sq[i];
         }
-        __syncthreads();
-        const LevelView<T> Lc = Lv[k + 1];
-        cx<T>* fc = static_cast<cx<T>*>(SB[k + 1].f);
-        const int Nc = (int)Lc.N;
-        map_store<T>(Nc, fc, [&](int p) {
-            int cx_, cy, cz;
-            pos3<D>(p, Lc.n[0], Lc.n[1], cx_, cy, cz);
-            return restrict_at<D, T>(L, q1, cx_, cy, cz);
-        });
+        return v;
+    };
+
+    if (big == 0) {   // right-hand side of the first tail level into LDS
+        const cx<T>* fg = static_cast<const cx<T>*>(SB[0].f);
+        for (int p = threadIdx.x; p < (int)Lv[0].N; p += NTT) sf[p] = fg[p];
         __syncthreads();
     }
-
-    // coarsest: LU forward/back substitution in FP64
-    {
+    for (int k = 0; k < last; ++k) {
+        const LvVec<T> v = vecs(k);
+        cx<T>* fc = vecs(k + 1).f;
+        if (k < big) level_down<D, T, GM, false>(Lv[k], Lv[k + 1], v, fc, a.brk, sred, sc);
+        else level_down<D, T, GM, true>(Lv[k], Lv[k + 1], v, fc, a.brk, sred, sc);
+    }
+    {   // coarsest: e = A^{-1} f with the FP64 inverse
         const LevelView<T> C = Lv[last];
         const int n = (int)C.N;
-        const cx<double>* lu = C.lu;
-        const int* piv = C.piv;
-        const cx<T>* f = static_cast<const cx<T>*>(SB[last].f);
-        cx<T>* e = static_cast<cx<T>*>(SB[last].e);
-        for (int i = threadIdx.x; i < n; i += NTT) b[i] = cvt<double>(f[i]);
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            for (int i = 0; i < n; ++i) {
-                const int p = piv[i];
-                if (p != i) {
-                    const cx<double> tmp = b[i];
-                    b[i] = b[p];
-                    b[p] = tmp;
-                }
-            }
+        const LvVec<T> v = vecs(last);
+        for (int p = threadIdx.x; p < n; p += NTT) {
+            const cx<double>* row = C.cinv + (long long)p * n;
+            cx<double> s = mk(0.0, 0.0);
+            for (int j = 0; j < n; ++j) s = s + row[j] * cvt<double>(v.f[j]);
+            v.u[p] = cvt<T>(s);
         }
-        __syncthreads();
-        for (int k = 0; k < n; ++k) {
-            const cx<double> bk = b[k];
-            for (int i = k + 1 + threadIdx.x; i < n; i += NTT) b[i] = b[i] - lu[(long long)i * n + k] * bk;
-            __syncthreads();
-        }
-        for (int k = n - 1; k >= 0; --k) {
-            if (threadIdx.x == 0) b[k] = cdiv(b[k], lu[(long long)k * n + k]);
-            __syncthreads();
-            const cx<double> bk = b[k];
-            for (int i = threadIdx.x; i < k; i += NTT) b[i] = b[i] - lu[(long long)i * n + k] * bk;
-            __syncthreads();
-        }
-        for (int i = threadIdx.x; i < n; i += NTT) e[i] = cvt<T>(b[i]);
         __syncthreads();
     }
-
     for (int k = last - 1; k >= 0; --k) {
-        const LevelView<T> L = Lv[k];
-        const LevelView<T> Lc = Lv[k + 1];
-        const SmoothBufs B = SB[k];
-        const int nx = L.n[0], ny = L.n[1], N = (int)L.N;
-        const cx<T>* f = static_cast<const cx<T>*>(B.f);
-        cx<T>* u = static_cast<cx<T>*>(B.u1);   // u2 = u1 + P e, in place
-        cx<T>* e = static_cast<cx<T>*>(B.e);
-        const cx<T>* ec = static_cast<const cx<T>*>(SB[k + 1].e);
-        map_store<T>(N, u, [&](int p) {
-            int gx, gy, gz;
-            pos3<D>(p, nx, ny, gx, gy, gz);
-            return u[p] + prolong_at<D, T>(Lc, ec, gx, gy, gz);
-        });
-        __syncthreads();
-        if constexpr (GM) {
-            cx<T>* q0 = static_cast<cx<T>*>(B.q[0]);
-            cx<T>* q1 = static_cast<cx<T>*>(B.q[1]);
-            cx<T>* q2 = static_cast<cx<T>*>(B.q[2]);
-            map_store<T>(N, q0, [&](int p) {
-                int gx, gy, gz;
-                pos3<D>(p, nx, ny, gx, gy, gz);
-                return f[p] - stencil_at<D, T, T>(L, u, T(1), p, gx, gy, gz);
-            });
-            __syncthreads();
-            map_store<T>(N, q1, [&](int p) {
-                int gx, gy, gz;
-                pos3<D>(p, nx, ny, gx, gy, gz);
-                return L.sinv * stencil_at<D, T, T>(L, q0, T(1), p, gx, gy, gz);
-            });
-            __syncthreads();
-            map_store<T>(N, q2, [&](int p) {
-                int gx, gy, gz;
-                pos3<D>(p, nx, ny, gx, gy, gz);
-                return L.sinv * stencil_at<D, T, T>(L, q1, T(1), p, gx, gy, gz);
-            });
-            __syncthreads();
-            tail_gram<D, T>(L, q0, q1, q2, a.brk, sred, sc);
-            const cx<T> c1 = cvt<T>(sc[0]), c2 = cvt<T>(sc[1]), c3 = cvt<T>(sc[2]);
-            map_store<T>(N, e, [&](int p) { return u[p] - L.sinv * (c1 * q0[p] + c2 * q1[p] + c3 * q2[p]); });
-        } else {
-            map_store<T>(N, e, [&](int p) {
-                int gx, gy, gz;
-                pos3<D>(p, nx, ny, gx, gy, gz);
-                const cx<T> r = f[p] - stencil_at<D, T, T>(L, u, T(1), p, gx, gy, gz);
-                return u[p] + cdiv(L.omega * r, diag_at<D>(L, gx, gy, gz, L.k2[p]));
-            });
-        }
-        __syncthreads();
+        const LvVec<T> v = vecs(k);
+        const cx<T>* ec = vecs(k + 1).u;
+        if (k < big) level_up<D, T, GM, false>(Lv[k], Lv[k + 1], v, ec, a.brk, sred, sc);
+        else level_up<D, T, GM, true>(Lv[k], Lv[k + 1], v, ec, a.brk, sred, sc);
+    }
+    {   // correction of the first tail level
+        cx<T>* eg = static_cast<cx<T>*>(SB[0].e);
+        const cx<T>* src = vecs(0).u;
+        for (int p = threadIdx.x; p < (int)Lv[0].N; p += NTT) eg[p] = src[p];
     }
 }
 
