@@ -455,8 +455,17 @@ def only(args, mg, W, torch, dev):
                       precision=args.precision)
         f = torch.tensor(wl.f, dtype=torch.complex128, device=dev)
         u = s.empty()
-        st, its, _, dt, _ = timed_solve(torch, s, u, f, "gmres", RTOL, args.maxit)
-        res = {"status": st, "steps": its, "seconds": dt}
+        st, its, _, dt, prof = timed_solve(torch, s, u, f, "gmres", RTOL, args.maxit, profile=True)
+        res = {"status": st, "steps": its, "seconds": dt, "kernels": per_class(prof)}
+    elif args.only.startswith("c3_") and args.light:
+        wl = W.constant_3d(255, 0.5, 16)
+        s = mg.Solver(wl.n, wl.h, torch.tensor(wl.k2, dtype=torch.float64, device=dev), ecs=wl.ecs,
+                      ecs_angle=wl.ecs_angle, theta_max=wl.theta_max, nrhs=1, smoother=args.only[3:],
+                      precision=args.precision)
+        f = torch.tensor(wl.f, dtype=torch.complex128, device=dev)
+        u = s.empty()
+        st, its, _, dt, prof = timed_solve(torch, s, u, f, "gmres", RTOL, args.maxit, profile=True)
+        res = {"status": st, "steps": its, "seconds": dt, "kernels": per_class(prof)}
     elif args.only.startswith("c3_"):
         res = c3(mg, W, torch, dev, smoothers=(args.only[3:],))
     elif args.only == "c4":
@@ -485,7 +494,8 @@ def main():
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--only", default=None,
                     help="run one workload only (headline, c3_gmres3, c3_jacobi, c4, c4_jacobi_511, c5)")
-    ap.add_argument("--precision", default="c128", help="with --only headline / c4_jacobi_511")
+    ap.add_argument("--precision", default="c128", help="with --only headline / c4_jacobi_511 / --light c3_*")
+    ap.add_argument("--light", action="store_true", help="with --only c3_*: one solve, no FP64 references")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain device copy of 1 GiB four times (counter calibration)")
     ap.add_argument("--maxit", type=int, default=MAXIT,
