@@ -97,6 +97,37 @@ def committed_traffic(kernel_class, workload):
     return out
 
 
+def hbm_probe(torch, dev):
+    """Bandwidth that plain torch kernels reach on this GPU (1 GiB float64
+    arrays, HIP events, best of 5): a copy (read + write), a sum (read) and a
+    fill (write).  Context for the roofline fractions, which use the
+    published 8 TB/s."""
+    a = torch.ones(1 << 27, dtype=torch.float64, device=dev)
+    b = torch.empty_like(a)
+    nbytes = float(1 << 30)
+    out = {}
+    for name, fn, moved in (("copy", lambda: b.copy_(a), 2 * nbytes), ("read", lambda: a.sum(), nbytes),
+                            ("write", lambda: b.fill_(2.0), nbytes)):
+        fn()
+        best = None
+        for _ in range(5):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            e1.synchronize()
+            ms = e0.elapsed_time(e1)
+            best = ms if best is None else min(best, ms)
+        out[name + "_GBps"] = round(moved / (best * 1e-3) / 1e9, 1)
+    del a, b
+    return out
+
+
+def shapes(s):
+    """Tile-shape id in force on each level (ids 3-5: plane sweeps)."""
+    return [s.tile_shape(l) for l in range(s.num_levels)]
+
+
 def per_class(prof):
     """{class: ms, launches, avg launch us, GB/s of algorithmic bytes, frac}."""
     out = {}
@@ -240,7 +271,7 @@ def c3(mg, W, torch, dev, smoothers=("gmres3", "jacobi")):
             st, its, hists, dt, prof = timed_solve(torch, s, u, f, "gmres", RTOL, 3000, profile=True)
             row = {"status": st, "steps": its[0], "seconds": round(dt, 4), "Mdof_per_s": round(dofs / dt / 1e6, 3),
                    "ms_per_step": round(1e3 * dt / max(1, its[0]), 3), "cycle_kernels": cycle_summary(prof),
-                   "kernels": per_class(prof)}
+                   "shapes": shapes(s), "kernels": per_class(prof)}
             if prec == "c128":
                 ref = s.empty()
                 s.solve(ref, f, mode="gmres", rtol=1e-12, maxit=6000, restart=RESTART)
@@ -456,7 +487,7 @@ def only(args, mg, W, torch, dev):
         f = torch.tensor(wl.f, dtype=torch.complex128, device=dev)
         u = s.empty()
         st, its, _, dt, prof = timed_solve(torch, s, u, f, "gmres", RTOL, args.maxit, profile=True)
-        res = {"status": st, "steps": its, "seconds": dt, "kernels": per_class(prof)}
+        res = {"status": st, "steps": its, "seconds": dt, "shapes": shapes(s), "kernels": per_class(prof)}
     elif args.only.startswith("c3_") and args.light:
         wl = W.constant_3d(255, 0.5, 16)
         s = mg.Solver(wl.n, wl.h, torch.tensor(wl.k2, dtype=torch.float64, device=dev), ecs=wl.ecs,
@@ -465,7 +496,7 @@ def only(args, mg, W, torch, dev):
         f = torch.tensor(wl.f, dtype=torch.complex128, device=dev)
         u = s.empty()
         st, its, _, dt, prof = timed_solve(torch, s, u, f, "gmres", RTOL, args.maxit, profile=True)
-        res = {"status": st, "steps": its, "seconds": dt, "kernels": per_class(prof)}
+        res = {"status": st, "steps": its, "seconds": dt, "shapes": shapes(s), "kernels": per_class(prof)}
     elif args.only.startswith("c3_"):
         res = c3(mg, W, torch, dev, smoothers=(args.only[3:],))
     elif args.only == "c4":
@@ -479,7 +510,7 @@ def only(args, mg, W, torch, dev):
         f = torch.tensor(wl.f, dtype=torch.complex128, device=dev)
         u = s.empty()
         st, its, _, dt, prof = timed_solve(torch, s, u, f, "gmres", RTOL, args.maxit, profile=True)
-        res = {"status": st, "max_steps": max(its), "seconds": dt, "kernels": per_class(prof)}
+        res = {"status": st, "max_steps": max(its), "seconds": dt, "shapes": shapes(s), "kernels": per_class(prof)}
     elif args.only == "c5":
         res = c5(mg, W, torch, dev, reps=1)
     print(json.dumps({"only": args.only, "result": res}), flush=True)
@@ -623,7 +654,8 @@ def main():
         extra["omega_jacobi_gmres"] = {"status": st, "gmres_steps": its, "seconds": round(dtj, 3),
                                        "ms_per_step": round(1e3 * dtj / max(its), 3),
                                        "last_ratio": [float(h[-1]) for h in hists],
-                                       "cycle_kernels_all_levels": cycle_summary(profj), "kernels": per_class(profj)}
+                                       "cycle_kernels_all_levels": cycle_summary(profj), "shapes": shapes(sj),
+                                       "kernels": per_class(profj)}
         log("omega-jacobi:", st, its)
         sj.close()
         # comparator of Table 3 (MG-FGMRES): the cycle on -Delta - (1 + 0.5 i) k^2
@@ -652,6 +684,10 @@ def main():
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(wl, iters[-1][0])
 
+    probe = hbm_probe(torch, dev)
+    roofline["hbm_probe"] = probe
+    if roofline["achieved"]:
+        roofline["frac_of_copy"] = round(roofline["achieved"] / probe["copy_GBps"], 4)
     line = {
         "metric": METRIC, "value": round(value, 4), "unit": "Mdof/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(1e3 * elapsed / args.steps, 2),

@@ -295,7 +295,7 @@ struct GmArgs {
 };
 
 // ---------------------------------------------------------------------------
-// Launchers (defined in mg_kernels.hip and mg_smooth.hip).  All return hipError_t of the launch.
+// Launchers (defined in mg_kernels.hip, mg_jacobi.hip and mg_smooth.hip).  All return hipError_t of the launch.
 // Tile shape of the fused kernels: a shape id (chosen per level by timing).
 // ---------------------------------------------------------------------------
 constexpr int NUM_TILE_SHAPES = 3;
@@ -306,6 +306,13 @@ hipError_t launch_smooth_restrict(int dim, bool f32, bool level0, bool zero, int
                                   hipStream_t s);
 hipError_t launch_prolong_smooth(int dim, bool f32, bool level0, bool zero, bool accumulate, int shape,
                                  const CycleArgs& a, hipStream_t s);
+// Plane-sweep variants of the two omega-Jacobi kernels for a zero incoming
+// iterate (mg_jacobi.hip): sweep configuration ids 0 .. NUM_SWEEP_SHAPES - 1.
+constexpr int NUM_SWEEP_SHAPES = 3;
+void sweep_counts(int dim, int sweep, const int n[3], int ntiles[3]);
+hipError_t launch_sweep_sr(int dim, bool f32, bool level0, int sweep, const CycleArgs& a, hipStream_t s);
+hipError_t launch_sweep_ps(int dim, bool f32, bool level0, bool accumulate, int sweep, const CycleArgs& a,
+                           hipStream_t s);
 
 // number of workgroups a vector kernel uses for N points
 // Workgroups per slot of a vector launch over N points: about per points

@@ -549,6 +549,25 @@ int launch_shape(const std::vector<Item>& it, const std::vector<int>& who, int d
     return shape;
 }
 
+// Shape ids of a context: the tile shapes, then (omega-Jacobi only) the
+// plane-sweep configurations of the zero-guess fused kernels.
+int num_shapes(const mg_ctx* c) { return mg::NUM_TILE_SHAPES + (c->gsmooth ? 0 : mg::NUM_SWEEP_SHAPES); }
+
+// Sweep configuration of an omega-Jacobi launch (-1: tiles) and its tile
+// shape; the sweeps serve the zero-guess kernels only.
+void split_shape(int shape, bool zero, int* sweep, int* tile) {
+    const bool sw = shape >= mg::NUM_TILE_SHAPES;
+    *sweep = sw && zero ? shape - mg::NUM_TILE_SHAPES : -1;
+    *tile = sw ? 0 : shape;
+}
+
+void fused_counts(int dim, int sweep, int tile, const int n[3], int nt[3]) {
+    if (sweep >= 0)
+        mg::sweep_counts(dim, sweep, n, nt);
+    else
+        mg::tile_counts(dim, tile, n, nt);
+}
+
 std::vector<int> above_tail(const std::vector<Item>& it, int d) {
     std::vector<int> who;
     for (int k = 0; k < (int)it.size(); ++k)
@@ -570,7 +589,8 @@ mg_status rec_ka(Rec& R, int dir, const std::vector<Item>& it, int gk, const std
     const bool zero = !(d == 0 && l0 && (*l0)[0].u);
     norm = norm && !zero;
     if (norm && who.size() != it.size()) return MG_E_STATE;
-    const int shape = launch_shape(it, who, d);
+    int sweep, shape;
+    split_shape(launch_shape(it, who, d), zero, &sweep, &shape);
     const double ct = R.mixed ? 8.0 : 16.0, sk = R.mixed ? 4.0 : 8.0;
     std::vector<mg::CycleSlot> sl(who.size());
     std::vector<ItemBytes> ib;
@@ -598,7 +618,7 @@ mg_status rec_ka(Rec& R, int dir, const std::vector<Item>& it, int gk, const std
         s.gate = gate_of(R, gk, k);
         s.tile0 = tiles;
         int nt[3];
-        mg::tile_counts(R.dim, shape, c->lv[d].n, nt);
+        fused_counts(R.dim, sweep, shape, c->lv[d].n, nt);
         const int n = nt[0] * nt[1] * nt[2];
         if (norm && n > R.w->bstride) return MG_E_STATE;
         if (cnt) (*cnt)[k] = n;
@@ -618,6 +638,7 @@ mg_status rec_ka(Rec& R, int dir, const std::vector<Item>& it, int gk, const std
     add(R, d == 0 ? MG_K_SMOOTH_RESTRICT_FINE : MG_K_COARSE_LEVELS, ib, [=](hipStream_t s, const char* base) {
         mg::CycleArgs b = a;
         b.st.s = (const mg::CycleSlot*)(base + off);
+        if (sweep >= 0) return mg::launch_sweep_sr(dim, mixed, d == 0, sweep, b, s);
         return mg::launch_smooth_restrict(dim, mixed, d == 0, zero, shape, b, s);
     });
     return MG_OK;
@@ -628,7 +649,8 @@ mg_status rec_kb(Rec& R, int dir, const std::vector<Item>& it, int gk, const std
     const std::vector<int> who = above_tail(it, d);
     if (who.empty()) return MG_OK;
     const bool zero = !(d == 0 && l0 && (*l0)[0].u);
-    const int shape = launch_shape(it, who, d);
+    int sweep, shape;
+    split_shape(launch_shape(it, who, d), zero, &sweep, &shape);
     const double ct = R.mixed ? 8.0 : 16.0, sk = R.mixed ? 4.0 : 8.0;
     std::vector<mg::CycleSlot> sl(who.size());
     std::vector<ItemBytes> ib;
@@ -656,7 +678,7 @@ mg_status rec_kb(Rec& R, int dir, const std::vector<Item>& it, int gk, const std
         s.gate = gate_of(R, gk, k);
         s.tile0 = tiles;
         int nt[3];
-        mg::tile_counts(R.dim, shape, c->lv[d].n, nt);
+        fused_counts(R.dim, sweep, shape, c->lv[d].n, nt);
         tiles += nt[0] * nt[1] * nt[2];
         const double cf = d == 0 ? 16.0 : ct;
         double by = c->lv[d].N * (cf + sk + cf) + c->lv[d + 1].N * ct;
@@ -674,6 +696,7 @@ mg_status rec_kb(Rec& R, int dir, const std::vector<Item>& it, int gk, const std
     add(R, d == 0 ? MG_K_PROLONG_SMOOTH_FINE : MG_K_COARSE_LEVELS, ib, [=](hipStream_t s, const char* base) {
         mg::CycleArgs b = a;
         b.st.s = (const mg::CycleSlot*)(base + off);
+        if (sweep >= 0) return mg::launch_sweep_ps(dim, mixed, d == 0, ac, sweep, b, s);
         return mg::launch_prolong_smooth(dim, mixed, d == 0, zero, ac, shape, b, s);
     });
     return MG_OK;
@@ -1765,7 +1788,7 @@ mg_status autotune(mg_ctx* c) {
         if (c->lv[l].N < AUTOTUNE_MIN_POINTS) break;
         float best = 1e30f;
         int best_shape = 0;
-        for (int shape = 0; shape < mg::NUM_TILE_SHAPES && st == MG_OK; ++shape) {
+        for (int shape = 0; shape < num_shapes(c) && st == MG_OK; ++shape) {
             c->lv[l].shape = shape;
             Op op;
             Rec R{&op, &c->work, c->dim, c->mixed, TAG_ALWAYS};
@@ -1806,6 +1829,11 @@ int max_blocks(const mg_ctx* c) {
             mg::march_counts(shape, c->lv[0].n, nt);
             m = std::max(m, nt[0] * nt[1]);
         }
+    }
+    for (int sweep = 0; sweep < mg::NUM_SWEEP_SHAPES; ++sweep) {
+        int nt[3];
+        mg::sweep_counts(c->dim, sweep, c->lv[0].n, nt);
+        m = std::max(m, nt[0] * nt[1] * nt[2]);
     }
     for (int per : {16, 32, 64}) {
         m = std::max(m, mg::mv_blocks(c->dim, c->lv[0].n, per));
@@ -2291,7 +2319,7 @@ mg_status mg_apply(mg_ctx* c, int level, int adjoint, const double* x, double* y
 
 int mg_tile_shape(mg_ctx* c, int level, int shape) {
     if (!c || level < 0 || level >= c->L) return MG_E_INVAL;
-    if (shape >= mg::NUM_TILE_SHAPES) return MG_E_INVAL;
+    if (shape >= num_shapes(c)) return MG_E_INVAL;
     if (shape >= 0) {
         if (hipStreamSynchronize(c->stream) != hipSuccess) return MG_E_DEVICE;
         c->lv[level].shape = shape;

@@ -23,6 +23,96 @@
 namespace mg {
 namespace kc {
 
+// Device memory seen as the global address space.  Pointers read out of the
+// slot tables and level descriptors are generic, and loads through generic
+// pointers are flat instructions, which also count against the LDS wait
+// counter: every LDS wait or barrier would then drain them.  Accesses
+// through these views are global instructions, so the loads of a pass stay
+// in flight across its LDS traffic.  Elements are read and written by value
+// (complex values member by member; the compiler merges the two halves).
+template <typename T>
+using gptr = __attribute__((address_space(1))) T*;
+
+template <typename T>
+struct GVal {
+    __device__ static __forceinline__ T get(gptr<const T> q) { return *q; }
+    __device__ static __forceinline__ void put(gptr<T> q, T v) { *q = v; }
+};
+template <typename U>
+struct GVal<cx<U>> {
+    __device__ static __forceinline__ cx<U> get(gptr<const cx<U>> q) { return mk<U>(q->r, q->i); }
+    __device__ static __forceinline__ void put(gptr<cx<U>> q, cx<U> v) {
+        q->r = v.r;
+        q->i = v.i;
+    }
+};
+
+// read-only view
+template <typename T>
+struct GIn {
+    gptr<const T> p;
+    __device__ __forceinline__ T operator[](long long i) const { return GVal<T>::get(p + i); }
+    __device__ __forceinline__ explicit operator bool() const { return p != nullptr; }
+};
+// element of a writable view
+template <typename T>
+struct GRef {
+    gptr<T> q;
+    __device__ __forceinline__ void operator=(T v) const { GVal<T>::put(q, v); }
+    __device__ __forceinline__ T get() const { return GVal<T>::get((gptr<const T>)q); }
+};
+// writable view
+template <typename T>
+struct GOut {
+    gptr<T> p;
+    __device__ __forceinline__ GRef<T> operator[](long long i) const { return GRef<T>{p + i}; }
+    __device__ __forceinline__ explicit operator bool() const { return p != nullptr; }
+};
+template <typename T>
+__device__ __forceinline__ GIn<T> gin(const T* p) {
+    return GIn<T>{(gptr<const T>)p};
+}
+template <typename T>
+__device__ __forceinline__ GOut<T> gout(T* p) {
+    return GOut<T>{(gptr<T>)p};
+}
+
+// A level descriptor with global views (same fields as LevelView).
+template <typename T>
+struct GLevel {
+    int n[3];
+    int ntiles[3];
+    long long N;
+    GIn<cx<T>> cm[3];
+    GIn<cx<T>> c0[3];
+    GIn<cx<T>> cp[3];
+    GIn<T> k2;
+    GIn<cx<double>> cinv;
+    cx<T> sigma;
+    cx<T> omega;
+    T sinv;
+};
+
+template <typename T>
+__device__ __forceinline__ GLevel<T> glevel(const LevelView<T>& v) {
+    GLevel<T> g;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        g.n[a] = v.n[a];
+        g.ntiles[a] = v.ntiles[a];
+        g.cm[a] = gin(v.cm[a]);
+        g.c0[a] = gin(v.c0[a]);
+        g.cp[a] = gin(v.cp[a]);
+    }
+    g.N = v.N;
+    g.k2 = gin(v.k2);
+    g.cinv = gin(v.cinv);
+    g.sigma = v.sigma;
+    g.omega = v.omega;
+    g.sinv = v.sinv;
+    return g;
+}
+
 constexpr int NT = 256;      // threads per workgroup (4 wave64)
 constexpr int NXCD = 8;      // MI355X: 8 XCDs, workgroups dealt round-robin
 
@@ -74,8 +164,8 @@ __device__ __forceinline__ int find_slot(const S* s, int n, int pid) {
     return lo;
 }
 
-template <int D, typename T>
-__device__ __forceinline__ cx<T> diag_at(const LevelView<T>& L, int gx, int gy, int gz, T k2) {
+template <int D, typename LV, typename T>
+__device__ __forceinline__ cx<T> diag_at(const LV& L, int gx, int gy, int gz, T k2) {
     cx<T> d = L.c0[0][gx] + L.c0[1][gy];
     if constexpr (D == 3) d = d + L.c0[2][gz];
     return d - k2 * L.sigma;
@@ -132,9 +222,8 @@ __device__ __forceinline__ void chunk_range(long long N, int nblocks, int b, int
 
 // 3-point-per-axis stencil of the level operator at point p of x, x scaled by
 // xs and converted to the compute precision T.
-template <int D, typename T, typename TX>
-__device__ __forceinline__ cx<T> stencil_at(const LevelView<T>& L, const cx<TX>* x, T xs, long long p, int gx,
-                                            int gy, int gz) {
+template <int D, typename T, typename TX, typename LV, typename PX>
+__device__ __forceinline__ cx<T> stencil_at(const LV& L, PX x, T xs, long long p, int gx, int gy, int gz) {
     const int nx = L.n[0], ny = L.n[1], nz = L.n[2];
     cx<T> ax = diag_at<D>(L, gx, gy, gz, L.k2[p]) * cvt<T>(x[p]);
     if (gx > 0) ax = ax + L.cm[0][gx] * cvt<T>(x[p - 1]);

@@ -1,15 +1,8 @@
-// gfx950 kernels of the level-dependent complex-shifted multigrid cycle.
+// gfx950 vector kernels of the level-dependent complex-shifted multigrid:
+// level-0 residual and norms, the GMRES Arnoldi passes and the set-up
+// helpers (the fused omega-Jacobi cycle kernels are in mg_jacobi.hip).
 //
 // Hot kernels (bandwidth-bound, no dense contraction anywhere, so no MFMA):
-//   k_smooth_restrict  omega-Jacobi pre-smoothing (Sec. 3.2.1, eq. wjacobi),
-//                      residual of the smoothed iterate and full-weighting
-//                      restriction to the next level (Sec. 2.1, Sec. 3.1,
-//                      eq. erreq1 with c = 1), fused through LDS tiles with
-//                      a two-point halo; optional ||f - A u||^2 partials of
-//                      the incoming iterate.
-//   k_prolong_smooth   (bi/tri)linear interpolation of the coarse correction,
-//                      v <- v + e (Sec. 3.1), and omega-Jacobi
-//                      post-smoothing, fused through LDS tiles.
 //   k_matvec_dot / k_update_gram
 //                      the GMRES Arnoldi step (Sec. 4.1: one cycle per outer
 //                      step) as two passes: w = A z fused with h1 = V^H w,
@@ -31,280 +24,12 @@ using namespace kc;
 namespace {
 
 // ---------------------------------------------------------------------------
-// Fused pre-smooth + residual + full weighting.
-// Tile: fine points [x0, x0+TX) x [y0, y0+TY) (x [z0, z0+TZ)); it owns the
-// coarse points whose centre 2C+1 lies in the tile.  LDS regions, relative to
-// the tile origin: u on [-2, T+2], u1 on [-1, T+1], r on [0, T].
-// ---------------------------------------------------------------------------
-template <int D, typename T, typename TF, bool ZERO, int TX, int TY, int TZ>
-__global__ void __launch_bounds__(NT) k_smooth_restrict(const CycleArgs a) {
-    constexpr int TZE = (D == 3) ? TZ : 1;
-    constexpr int UX = TX + 5, UY = TY + 5, UZ = (D == 3) ? TZ + 5 : 1;
-    constexpr int VX = TX + 3, VY = TY + 3, VZ = (D == 3) ? TZ + 3 : 1;
-    constexpr int RX = TX + 1, RY = TY + 1, RZ = (D == 3) ? TZ + 1 : 1;
-    constexpr int NU = UX * UY * UZ, NV = VX * VY * VZ, NR = RX * RY * RZ;
-    constexpr int NB0 = ZERO ? NR : (NU > NR ? NU : NR);
-    constexpr int CX = TX / 2, CY = TY / 2, CZ = (D == 3) ? TZ / 2 : 1;
-    static_assert(TX % 2 == 0 && TY % 2 == 0 && (D == 2 || TZ % 2 == 0), "even tiles");
-
-    __shared__ cx<T> s0[NB0];   // u, later r
-    __shared__ cx<T> s1[NV];    // u1
-    __shared__ double sred[NT / 64];
-
-    const int pid = xcd_remap(blockIdx.x, gridDim.x);
-    const int slot = find_slot(a.st.s, a.st.n, pid);
-    const CycleSlot& sl = a.st.s[slot];
-    if (gated_off(sl.gate)) return;
-    const int tile = pid - sl.tile0;
-    const LevelView<T>* Lp = static_cast<const LevelView<T>*>(sl.lv);
-    const LevelView<T> L = *Lp;
-    const int nx = L.n[0], ny = L.n[1], nz = L.n[2];
-    const int ntx = (nx + TX - 1) / TX, nty = (ny + TY - 1) / TY;
-    const int tx = tile % ntx;
-    const int rest = tile / ntx;
-    const int ty = rest % nty;
-    const int tz = rest / nty;
-    const int x0 = tx * TX, y0 = ty * TY, z0 = tz * TZE;
-    const cx<TF>* f = static_cast<const cx<TF>*>(sl.f);
-    const T fs = (T)fscale_of(sl);
-    cx<T>* u1p = static_cast<cx<T>*>(sl.u1);
-
-    if constexpr (!ZERO) {
-        const cx<T>* u = static_cast<const cx<T>*>(sl.u);
-        for (int idx = threadIdx.x; idx < NU; idx += NT) {
-            const int lx = idx % UX;
-            const int rr = idx / UX;
-            const int ly = rr % UY;
-            const int lz = rr / UY;
-            const int gx = x0 - 2 + lx, gy = y0 - 2 + ly;
-            const int gz = (D == 3) ? z0 - 2 + lz : 0;
-            cx<T> v = mk<T>(0, 0);
-            if (gx >= 0 && gx < nx && gy >= 0 && gy < ny && (D == 2 || (gz >= 0 && gz < nz)))
-                v = u[((long long)gz * ny + gy) * nx + gx];
-            s0[idx] = v;
-        }
-        __syncthreads();
-    }
-
-    double nrm = 0.0;
-    for (int idx = threadIdx.x; idx < NV; idx += NT) {
-        const int lx = idx % VX;
-        const int rr = idx / VX;
-        const int ly = rr % VY;
-        const int lz = rr / VY;
-        const int gx = x0 - 1 + lx, gy = y0 - 1 + ly;
-        const int gz = (D == 3) ? z0 - 1 + lz : 0;
-        cx<T> u1 = mk<T>(0, 0);
-        if (gx >= 0 && gx < nx && gy >= 0 && gy < ny && (D == 2 || (gz >= 0 && gz < nz))) {
-            const long long g = ((long long)gz * ny + gy) * nx + gx;
-            const cx<T> fv = fs * cvt<T>(f[g]);
-            const cx<T> d = diag_at<D>(L, gx, gy, gz, L.k2[g]);
-            if constexpr (ZERO) {
-                u1 = cdiv(L.omega * fv, d);
-            } else {
-                const int c = ((D == 3 ? lz + 1 : 0) * UY + (ly + 1)) * UX + (lx + 1);
-                const cx<T> uc = s0[c];
-                cx<T> au = d * uc + L.cm[0][gx] * s0[c - 1] + L.cp[0][gx] * s0[c + 1] +
-                           L.cm[1][gy] * s0[c - UX] + L.cp[1][gy] * s0[c + UX];
-                if constexpr (D == 3) au = au + L.cm[2][gz] * s0[c - UX * UY] + L.cp[2][gz] * s0[c + UX * UY];
-                const cx<T> res = fv - au;
-                u1 = uc + cdiv(L.omega * res, d);
-                const bool own = lx >= 1 && lx <= TX && ly >= 1 && ly <= TY && (D == 2 || (lz >= 1 && lz <= TZ));
-                if (own) {
-                    nrm += (double)abs2(res);
-                    if (u1p) u1p[g] = u1;
-                }
-            }
-        }
-        s1[idx] = u1;
-    }
-    __syncthreads();
-
-    for (int idx = threadIdx.x; idx < NR; idx += NT) {
-        const int lx = idx % RX;
-        const int rr = idx / RX;
-        const int ly = rr % RY;
-        const int lz = rr / RY;
-        const int gx = x0 + lx, gy = y0 + ly;
-        const int gz = (D == 3) ? z0 + lz : 0;
-        cx<T> r = mk<T>(0, 0);
-        if (gx < nx && gy < ny && (D == 2 || gz < nz)) {
-            const long long g = ((long long)gz * ny + gy) * nx + gx;
-            const cx<T> fv = fs * cvt<T>(f[g]);
-            const cx<T> d = diag_at<D>(L, gx, gy, gz, L.k2[g]);
-            const int c = ((D == 3 ? lz + 1 : 0) * VY + (ly + 1)) * VX + (lx + 1);
-            cx<T> au = d * s1[c] + L.cm[0][gx] * s1[c - 1] + L.cp[0][gx] * s1[c + 1] +
-                       L.cm[1][gy] * s1[c - VX] + L.cp[1][gy] * s1[c + VX];
-            if constexpr (D == 3) au = au + L.cm[2][gz] * s1[c - VX * VY] + L.cp[2][gz] * s1[c + VX * VY];
-            r = fv - au;
-        }
-        s0[idx] = r;
-    }
-    __syncthreads();
-
-    const int ncx = Lp[1].n[0], ncy = Lp[1].n[1], ncz = Lp[1].n[2];
-    cx<T>* fc = static_cast<cx<T>*>(sl.c);
-    for (int idx = threadIdx.x; idx < CX * CY * CZ; idx += NT) {
-        const int cxl = idx % CX;
-        const int rr = idx / CX;
-        const int cyl = rr % CY;
-        const int czl = rr / CY;
-        const int Cx = x0 / 2 + cxl, Cy = y0 / 2 + cyl;
-        const int Cz = (D == 3) ? z0 / 2 + czl : 0;
-        if (Cx < ncx && Cy < ncy && (D == 2 || Cz < ncz)) {
-            cx<T> acc = mk<T>(0, 0);
-#pragma unroll
-            for (int oz = (D == 3 ? -1 : 0); oz <= (D == 3 ? 1 : 0); ++oz) {
-                const int zz = (D == 3) ? 2 * czl + 1 + oz : 0;
-                const T wz = (D == 3) ? (oz == 0 ? T(0.5) : T(0.25)) : T(1);
-#pragma unroll
-                for (int oy = -1; oy <= 1; ++oy) {
-                    const T wy = wz * (oy == 0 ? T(0.5) : T(0.25));
-                    const int row = (zz * RY + 2 * cyl + 1 + oy) * RX + 2 * cxl + 1;
-#pragma unroll
-                    for (int ox = -1; ox <= 1; ++ox) {
-                        const T w = wy * (ox == 0 ? T(0.5) : T(0.25));
-                        acc = acc + w * s0[row + ox];
-                    }
-                }
-            }
-            fc[((long long)Cz * ncy + Cy) * ncx + Cx] = acc;
-        }
-    }
-
-    if constexpr (!ZERO) {
-        if (a.norm_part) {
-            const double s = block_sum(nrm, sred);
-            if (threadIdx.x == 0) a.norm_part[(long long)slot * a.pstride + tile] = s;
-        }
-    }
-}
-
-// ---------------------------------------------------------------------------
-// Fused prolongation + correction + post-smooth.
-// LDS: coarse correction on [x0/2 - 1, x0/2 + TX/2], corrected iterate u2 on
-// fine [-1, T] relative to the tile.
-// ---------------------------------------------------------------------------
-template <int D, typename T, typename TF, typename TO, bool ZERO, bool ACC, int TX, int TY, int TZ>
-__global__ void __launch_bounds__(NT) k_prolong_smooth(const CycleArgs a) {
-    constexpr int TZE = (D == 3) ? TZ : 1;
-    constexpr int EX = TX / 2 + 2, EY = TY / 2 + 2, EZ = (D == 3) ? TZ / 2 + 2 : 1;
-    constexpr int WX = TX + 2, WY = TY + 2, WZ = (D == 3) ? TZ + 2 : 1;
-    constexpr int NE = EX * EY * EZ, NW = WX * WY * WZ;
-
-    __shared__ cx<T> se[NE];
-    __shared__ cx<T> s2[NW];
-
-    const int pid = xcd_remap(blockIdx.x, gridDim.x);
-    const int slot = find_slot(a.st.s, a.st.n, pid);
-    const CycleSlot& sl = a.st.s[slot];
-    if (gated_off(sl.gate)) return;
-    const int tile = pid - sl.tile0;
-    const LevelView<T>* Lp = static_cast<const LevelView<T>*>(sl.lv);
-    const LevelView<T> L = *Lp;
-    const int nx = L.n[0], ny = L.n[1], nz = L.n[2];
-    const int ncx = Lp[1].n[0], ncy = Lp[1].n[1], ncz = Lp[1].n[2];
-    const int ntx = (nx + TX - 1) / TX, nty = (ny + TY - 1) / TY;
-    const int tx = tile % ntx;
-    const int rest = tile / ntx;
-    const int ty = rest % nty;
-    const int tz = rest / nty;
-    const int x0 = tx * TX, y0 = ty * TY, z0 = tz * TZE;
-    const cx<TF>* f = static_cast<const cx<TF>*>(sl.f);
-    const T fs = (T)fscale_of(sl);
-    const cx<T>* ec = static_cast<const cx<T>*>(sl.c);
-    const cx<T>* u1in = static_cast<const cx<T>*>(sl.u1);
-    const int cxs = x0 / 2 - 1, cys = y0 / 2 - 1, czs = (D == 3) ? z0 / 2 - 1 : 0;
-
-    for (int idx = threadIdx.x; idx < NE; idx += NT) {
-        const int lx = idx % EX;
-        const int rr = idx / EX;
-        const int ly = rr % EY;
-        const int lz = rr / EY;
-        const int Cx = cxs + lx, Cy = cys + ly, Cz = czs + lz;
-        cx<T> v = mk<T>(0, 0);
-        if (Cx >= 0 && Cx < ncx && Cy >= 0 && Cy < ncy && (D == 2 || (Cz >= 0 && Cz < ncz)))
-            v = ec[((long long)Cz * ncy + Cy) * ncx + Cx];
-        se[idx] = v;
-    }
-    __syncthreads();
-
-    for (int idx = threadIdx.x; idx < NW; idx += NT) {
-        const int lx = idx % WX;
-        const int rr = idx / WX;
-        const int ly = rr % WY;
-        const int lz = rr / WY;
-        const int gx = x0 - 1 + lx, gy = y0 - 1 + ly;
-        const int gz = (D == 3) ? z0 - 1 + lz : 0;
-        cx<T> u2 = mk<T>(0, 0);
-        if (gx >= 0 && gx < nx && gy >= 0 && gy < ny && (D == 2 || (gz >= 0 && gz < nz))) {
-            const long long g = ((long long)gz * ny + gy) * nx + gx;
-            cx<T> u1;
-            if constexpr (ZERO) {
-                const cx<T> fv = fs * cvt<T>(f[g]);
-                u1 = cdiv(L.omega * fv, diag_at<D>(L, gx, gy, gz, L.k2[g]));
-            } else {
-                u1 = u1in[g];
-            }
-            int ix0, ix1, iy0, iy1;
-            T wx0, wx1, wy0, wy1;
-            interp_1d<T>(gx, cxs, ix0, ix1, wx0, wx1);
-            interp_1d<T>(gy, cys, iy0, iy1, wy0, wy1);
-            cx<T> pe;
-            if constexpr (D == 2) {
-                pe = (wy0 * wx0) * se[iy0 * EX + ix0] + (wy0 * wx1) * se[iy0 * EX + ix1] +
-                     (wy1 * wx0) * se[iy1 * EX + ix0] + (wy1 * wx1) * se[iy1 * EX + ix1];
-            } else {
-                int iz0, iz1;
-                T wz0, wz1;
-                interp_1d<T>(gz, czs, iz0, iz1, wz0, wz1);
-                const int p00 = (iz0 * EY + iy0) * EX, p01 = (iz0 * EY + iy1) * EX;
-                const int p10 = (iz1 * EY + iy0) * EX, p11 = (iz1 * EY + iy1) * EX;
-                pe = (wz0 * wy0 * wx0) * se[p00 + ix0] + (wz0 * wy0 * wx1) * se[p00 + ix1] +
-                     (wz0 * wy1 * wx0) * se[p01 + ix0] + (wz0 * wy1 * wx1) * se[p01 + ix1] +
-                     (wz1 * wy0 * wx0) * se[p10 + ix0] + (wz1 * wy0 * wx1) * se[p10 + ix1] +
-                     (wz1 * wy1 * wx0) * se[p11 + ix0] + (wz1 * wy1 * wx1) * se[p11 + ix1];
-            }
-            u2 = u1 + pe;
-        }
-        s2[idx] = u2;
-    }
-    __syncthreads();
-
-    cx<TO>* out = static_cast<cx<TO>*>(sl.out);
-    for (int idx = threadIdx.x; idx < TX * TY * TZE; idx += NT) {
-        const int lx = idx % TX;
-        const int rr = idx / TX;
-        const int ly = rr % TY;
-        const int lz = rr / TY;
-        const int gx = x0 + lx, gy = y0 + ly;
-        const int gz = (D == 3) ? z0 + lz : 0;
-        if (gx < nx && gy < ny && (D == 2 || gz < nz)) {
-            const long long g = ((long long)gz * ny + gy) * nx + gx;
-            const cx<T> fv = fs * cvt<T>(f[g]);
-            const cx<T> d = diag_at<D>(L, gx, gy, gz, L.k2[g]);
-            const int c = ((D == 3 ? lz + 1 : 0) * WY + (ly + 1)) * WX + (lx + 1);
-            const cx<T> u2c = s2[c];
-            cx<T> au = d * u2c + L.cm[0][gx] * s2[c - 1] + L.cp[0][gx] * s2[c + 1] +
-                       L.cm[1][gy] * s2[c - WX] + L.cp[1][gy] * s2[c + WX];
-            if constexpr (D == 3) au = au + L.cm[2][gz] * s2[c - WX * WY] + L.cp[2][gz] * s2[c + WX * WY];
-            const cx<T> u3 = u2c + cdiv(L.omega * (fv - au), d);
-            if constexpr (ACC) {
-                out[g] = out[g] + cvt<TO>(u3);
-            } else {
-                out[g] = cvt<TO>(u3);
-            }
-        }
-    }
-}
-
-// ---------------------------------------------------------------------------
 // Vector kernels: one point per thread, a contiguous chunk of the slot's
 // vector per workgroup.
 // ---------------------------------------------------------------------------
-template <int D>
-__device__ __forceinline__ cx<double> apply_at(const LevelView<double>& L, const cx<double>* x, int p,
-                                               int gx, int gy, int gz) {
+template <int D, typename PX>
+__device__ __forceinline__ cx<double> apply_at(const GLevel<double>& L, const PX& x, int p, int gx, int gy,
+                                               int gz) {
     const int nx = L.n[0], ny = L.n[1], nz = L.n[2];
     cx<double> ax = diag_at<D>(L, gx, gy, gz, L.k2[p]) * x[p];
     if (gx > 0) ax = ax + L.cm[0][gx] * x[p - 1];
@@ -324,20 +49,23 @@ template <int D>
 __global__ void __launch_bounds__(NT) k_residual(const VecArgs a) {
     __shared__ double sred[NT / 64];
     VecPos q = vec_pos(a.st);
-    const VecSlot& sl = a.st.s[q.slot];
+    const VecSlot sl = a.st.s[q.slot];
     if (gated_off(sl.gate)) return;
-    const LevelView<double> L = *static_cast<const LevelView<double>*>(sl.lv);
+    const GLevel<double> L = glevel(*static_cast<const LevelView<double>*>(sl.lv));
     chunk_range(L.N, q.nb, q.b, q.lo, q.hi);
     double nrm = 0.0;
     const int nx = L.n[0], ny = L.n[1];
+    const auto x = gin(sl.x);
+    const auto fr = gin(sl.f);
+    const auto y = gout(sl.y);
     for (int p = q.lo + (int)threadIdx.x; p < q.hi; p += NT) {
         const int gx = p % nx;
         const int rr = p / nx;
         const int gy = rr % ny;
         const int gz = rr / ny;
-        cx<double> v = apply_at<D>(L, sl.x, p, gx, gy, gz);
-        if (sl.f) v = sl.f[p] - v;
-        sl.y[p] = v;
+        cx<double> v = apply_at<D>(L, x, p, gx, gy, gz);
+        if (sl.f) v = fr[p] - v;
+        y[p] = v;
         nrm += abs2(v);
     }
     if (a.rpart) {
@@ -350,12 +78,13 @@ __global__ void __launch_bounds__(NT) k_residual(const VecArgs a) {
 __global__ void __launch_bounds__(NT) k_norm(const VecArgs a) {
     __shared__ double sred[NT / 64];
     VecPos q = vec_pos(a.st);
-    const VecSlot& sl = a.st.s[q.slot];
+    const VecSlot sl = a.st.s[q.slot];
     if (gated_off(sl.gate)) return;
     const long long N = static_cast<const LevelView<double>*>(sl.lv)->N;
     chunk_range(N, q.nb, q.b, q.lo, q.hi);
     double nrm = 0.0;
-    for (int p = q.lo + (int)threadIdx.x; p < q.hi; p += NT) nrm += abs2(sl.x[p]);
+    const auto x = gin(sl.x);
+    for (int p = q.lo + (int)threadIdx.x; p < q.hi; p += NT) nrm += abs2(x[p]);
     const double s = block_sum(nrm, sred);
     if (threadIdx.x == 0) a.rpart[(long long)q.slot * a.bstride + q.b] = s;
 }
@@ -391,15 +120,18 @@ __device__ __forceinline__ void block_sum_vec(cx<double> (&acc)[MAXJ], int nv, c
 template <int D, int MAXJ>
 __global__ void __launch_bounds__(NT) k_matvec_dot(const VecArgs a) {
     __shared__ cx<double> sm[(NT / 64) * MAXJ];
+    __shared__ double ssc[MAXJ];   // scale_i, read at the end from LDS
     VecPos q = vec_pos(a.st);
-    const VecSlot& sl = a.st.s[q.slot];
+    const VecSlot sl = a.st.s[q.slot];
     if (gated_off(sl.gate)) return;
-    const LevelView<double> L = *static_cast<const LevelView<double>*>(sl.lv);
+    const GLevel<double> L = glevel(*static_cast<const LevelView<double>*>(sl.lv));
     const long long N = L.N;
     const int nv = sl.j + 1;
-    const cx<double>* z = sl.x;
-    cx<double>* w = sl.y;
-    const cx<double>* V = sl.V;
+    if ((int)threadIdx.x < MAXJ) ssc[threadIdx.x] = (int)threadIdx.x < nv ? sl.scale[threadIdx.x] : 0.0;
+    __syncthreads();
+    const auto z = gin(sl.x);
+    const auto w = gout(sl.y);
+    const auto V = gin(sl.V);
     chunk_range(N, q.nb, q.b, q.lo, q.hi);
     cx<double> acc[MAXJ];
 #pragma unroll
@@ -442,7 +174,7 @@ __global__ void __launch_bounds__(NT) k_matvec_dot(const VecArgs a) {
         }
 #pragma unroll
         for (int i = 0; i < MAXJ; ++i)
-            if (i < nv) acc[i] = sl.scale[i] * acc[i];
+            if (i < nv) acc[i] = ssc[i] * acc[i];
         block_sum_vec<MAXJ>(acc, nv, sm, a.part + (long long)q.slot * a.pstride * a.bstride, a.bstride, q.b);
         return;
     }
@@ -469,7 +201,7 @@ __global__ void __launch_bounds__(NT) k_matvec_dot(const VecArgs a) {
     }
 #pragma unroll
     for (int i = 0; i < MAXJ; ++i)
-        if (i < nv) acc[i] = sl.scale[i] * acc[i];
+        if (i < nv) acc[i] = ssc[i] * acc[i];
     block_sum_vec<MAXJ>(acc, nv, sm, a.part + (long long)q.slot * a.pstride * a.bstride, a.bstride, q.b);
 }
 
@@ -483,18 +215,22 @@ template <int MAXJ>
 __global__ void __launch_bounds__(NT) k_update_gram(const VecArgs a) {
     __shared__ cx<double> sm[(NT / 64) * (MAXJ + 1)];
     __shared__ cx<double> sc[MAXJ];
+    __shared__ double ssc[MAXJ];   // scale_i, read at the end from LDS
     VecPos q = vec_pos(a.st);
-    const VecSlot& sl = a.st.s[q.slot];
+    const VecSlot sl = a.st.s[q.slot];
     if (gated_off(sl.gate)) return;
     const long long N = static_cast<const LevelView<double>*>(sl.lv)->N;
     const int nv = sl.j + 1;
-    const cx<double>* w = sl.y;
-    const cx<double>* V = sl.V;
-    if ((int)threadIdx.x < MAXJ) sc[threadIdx.x] = ((int)threadIdx.x < nv) ? sl.scale[threadIdx.x] * sl.hin[threadIdx.x]
-                                                                          : mk(0.0, 0.0);
+    const auto w = gin(sl.y);
+    const auto V = gin(sl.V);
+    if ((int)threadIdx.x < MAXJ) {
+        const double sv = (int)threadIdx.x < nv ? sl.scale[threadIdx.x] : 0.0;
+        ssc[threadIdx.x] = sv;
+        sc[threadIdx.x] = (int)threadIdx.x < nv ? sv * sl.hin[threadIdx.x] : mk(0.0, 0.0);
+    }
     __syncthreads();
     chunk_range(N, q.nb, q.b, q.lo, q.hi);
-    cx<double>* vout = sl.V + (long long)nv * N;
+    const auto vout = gout(sl.V + (long long)nv * N);
     cx<double> acc[MAXJ + 1];
 #pragma unroll
     for (int i = 0; i <= MAXJ; ++i) acc[i] = mk(0.0, 0.0);
@@ -512,7 +248,7 @@ __global__ void __launch_bounds__(NT) k_update_gram(const VecArgs a) {
     }
 #pragma unroll
     for (int i = 0; i < MAXJ; ++i)
-        if (i < nv) acc[i] = sl.scale[i] * acc[i];
+        if (i < nv) acc[i] = ssc[i] * acc[i];
     // value nv carries the norm
     cx<double> out[MAXJ + 1];
 #pragma unroll
@@ -523,26 +259,27 @@ __global__ void __launch_bounds__(NT) k_update_gram(const VecArgs a) {
 // y = 0 (gated).
 __global__ void __launch_bounds__(NT) k_vzero(const VecArgs a) {
     VecPos q = vec_pos(a.st);
-    const VecSlot& sl = a.st.s[q.slot];
+    const VecSlot sl = a.st.s[q.slot];
     if (gated_off(sl.gate)) return;
     const long long N = static_cast<const LevelView<double>*>(sl.lv)->N;
     chunk_range(N, q.nb, q.b, q.lo, q.hi);
-    for (int p = q.lo + (int)threadIdx.x; p < q.hi; p += NT) sl.y[p] = mk(0.0, 0.0);
+    const auto y = gout(sl.y);
+    for (int p = q.lo + (int)threadIdx.x; p < q.hi; p += NT) y[p] = mk(0.0, 0.0);
 }
 
 // t = sum_i coef_i V_i (ACC: t += ...).
 template <int MAXJ, bool ACC>
 __global__ void __launch_bounds__(NT) k_combine(const VecArgs a) {
     VecPos q = vec_pos(a.st);
-    const VecSlot& sl = a.st.s[q.slot];
+    const VecSlot sl = a.st.s[q.slot];
     if (gated_off(sl.gate)) return;
     const long long N = static_cast<const LevelView<double>*>(sl.lv)->N;
     const int nv = (sl.jp ? *sl.jp : sl.j) + 1;
-    const cx<double>* V = sl.V;
+    const auto V = gin(sl.V);
     cx<double> coef[MAXJ];
 #pragma unroll
     for (int i = 0; i < MAXJ; ++i) coef[i] = (i < nv) ? sl.coef[i] : mk(0.0, 0.0);
-    cx<double>* t = sl.y;
+    const auto t = gout(sl.y);
     chunk_range(N, q.nb, q.b, q.lo, q.hi);
     for (int p = q.lo + (int)threadIdx.x; p < q.hi; p += NT) {
         cx<double> s = mk(0.0, 0.0);
@@ -550,7 +287,7 @@ __global__ void __launch_bounds__(NT) k_combine(const VecArgs a) {
         for (int i = 0; i < MAXJ; ++i)
             if (i < nv) s = s + coef[i] * V[(long long)i * N + p];
         if constexpr (ACC)
-            t[p] = t[p] + s;
+            t[p] = t[p].get() + s;
         else
             t[p] = s;
     }
@@ -655,52 +392,6 @@ void tile_counts(int dim, int shape, const int n[3], int ntiles[3]) {
     ntiles[0] = cdivi(n[0], t[0]);
     ntiles[1] = cdivi(n[1], t[1]);
     ntiles[2] = dim == 3 ? cdivi(n[2], t[2]) : 1;
-}
-
-template <typename T, typename TF, bool ZERO>
-static hipError_t sr_launch(int dim, int shape, const CycleArgs& a, hipStream_t s) {
-    dim3 grid(a.st.ntiles);
-#define SR(D, X, Y, Z) hipLaunchKernelGGL((k_smooth_restrict<D, T, TF, ZERO, X, Y, Z>), grid, dim3(NT), 0, s, a);
-    MG_SHAPE_SWITCH(SR)
-#undef SR
-    return hipGetLastError();
-}
-
-template <typename T, typename TF, typename TO, bool ZERO, bool ACC>
-static hipError_t ps_launch(int dim, int shape, const CycleArgs& a, hipStream_t s) {
-    dim3 grid(a.st.ntiles);
-#define PS(D, X, Y, Z) \
-    hipLaunchKernelGGL((k_prolong_smooth<D, T, TF, TO, ZERO, ACC, X, Y, Z>), grid, dim3(NT), 0, s, a);
-    MG_SHAPE_SWITCH(PS)
-#undef PS
-    return hipGetLastError();
-}
-
-hipError_t launch_smooth_restrict(int dim, bool f32, bool level0, bool zero, int shape, const CycleArgs& a,
-                                  hipStream_t s) {
-    if (a.st.n <= 0) return hipSuccess;
-    if (!f32) {
-        return zero ? sr_launch<double, double, true>(dim, shape, a, s)
-                    : sr_launch<double, double, false>(dim, shape, a, s);
-    }
-    if (!zero) return hipErrorInvalidValue;   // the complex64 cycle always starts from zero
-    return level0 ? sr_launch<float, double, true>(dim, shape, a, s) : sr_launch<float, float, true>(dim, shape, a, s);
-}
-
-hipError_t launch_prolong_smooth(int dim, bool f32, bool level0, bool zero, bool acc, int shape,
-                                 const CycleArgs& a, hipStream_t s) {
-    if (a.st.n <= 0) return hipSuccess;
-    if (!f32) {
-        if (zero)
-            return acc ? ps_launch<double, double, double, true, true>(dim, shape, a, s)
-                       : ps_launch<double, double, double, true, false>(dim, shape, a, s);
-        return acc ? ps_launch<double, double, double, false, true>(dim, shape, a, s)
-                   : ps_launch<double, double, double, false, false>(dim, shape, a, s);
-    }
-    if (!zero) return hipErrorInvalidValue;
-    if (!level0) return ps_launch<float, float, float, true, false>(dim, shape, a, s);
-    return acc ? ps_launch<float, double, double, true, true>(dim, shape, a, s)
-               : ps_launch<float, double, double, true, false>(dim, shape, a, s);
 }
 
 int mv_blocks(int dim, const int n[3], int per) {

@@ -72,7 +72,7 @@ struct Lane {
 };
 
 template <typename T>
-__device__ __forceinline__ Lane<T> lane_of(const LevelView<T>& L, int x0) {
+__device__ __forceinline__ Lane<T> lane_of(const GLevel<T>& L, int x0) {
     Lane<T> c;
     const int lane = threadIdx.x;
     c.gx = x0 - MH + lane;
@@ -88,7 +88,7 @@ __device__ __forceinline__ Lane<T> lane_of(const LevelView<T>& L, int x0) {
 // A at row y of the stage whose rows y-1, y, y+1 are am, a0, ap (this lane);
 // every lane must call it (shuffles).  Caller masks the result.
 template <typename T>
-__device__ __forceinline__ cx<T> row_apply(const LevelView<T>& L, const Lane<T>& c, cx<T> am, cx<T> a0, cx<T> ap, int y,
+__device__ __forceinline__ cx<T> row_apply(const GLevel<T>& L, const Lane<T>& c, cx<T> am, cx<T> a0, cx<T> ap, int y,
                                            T k2) {
     const cx<T> left = shfl_up1(a0);
     const cx<T> right = shfl_dn1(a0);
@@ -98,12 +98,12 @@ __device__ __forceinline__ cx<T> row_apply(const LevelView<T>& L, const Lane<T>&
 }
 
 template <typename T>
-__device__ __forceinline__ bool rowv(const LevelView<T>& L, int y) {
+__device__ __forceinline__ bool rowv(const GLevel<T>& L, int y) {
     return y >= 0 && y < L.n[1];
 }
 
 template <typename T>
-__device__ __forceinline__ T load_k2(const LevelView<T>& L, const Lane<T>& c, int y) {
+__device__ __forceinline__ T load_k2(const GLevel<T>& L, const Lane<T>& c, int y) {
     return (c.colv && rowv(L, y)) ? L.k2[(long long)y * L.n[0] + c.gx] : T(0);
 }
 
@@ -136,22 +136,6 @@ __device__ __forceinline__ void interp_axis(int g, int nc, int& i0, int& i1, T& 
     }
 }
 
-// u2 = u1 + P e at row y for this lane (zero outside the grid).
-template <typename T>
-__device__ __forceinline__ cx<T> u2_at(const LevelView<T>& L, const LevelView<T>& Lc, const Lane<T>& c,
-                                       const InterpX<T>& ix, const cx<T>* u1, const cx<T>* e, int y) {
-    if (!(c.colv && rowv(L, y))) return mk<T>(0, 0);
-    int j0, j1;
-    T v0, v1;
-    interp_axis<T>(y, Lc.n[1], j0, j1, v0, v1);
-    const int ncx = Lc.n[0];
-    const cx<T>* r0 = e + (long long)j0 * ncx;
-    const cx<T>* r1 = e + (long long)j1 * ncx;
-    const cx<T> pe = (v0 * ix.w0) * r0[ix.i0] + (v0 * ix.w1) * r0[ix.i1] + (v1 * ix.w0) * r1[ix.i0] +
-                     (v1 * ix.w1) * r1[ix.i1];
-    return u1[(long long)y * L.n[0] + c.gx] + pe;
-}
-
 template <typename T>
 __device__ __forceinline__ void gram_add(cx<double>* g, cx<T> a0, cx<T> a1, cx<T> a2, cx<T> a3) {
     const cx<double> v0 = cvt<double>(a0), v1 = cvt<double>(a1), v2 = cvt<double>(a2), v3 = cvt<double>(a3);
@@ -181,7 +165,7 @@ struct RowIn {
 };
 
 template <typename T, typename TQ, bool POST, bool Q0BUF>
-__device__ __forceinline__ void load_row(RowIn<T, TQ>& r, const LevelView<T>& L, const LevelView<T>& Lc,
+__device__ __forceinline__ void load_row(RowIn<T, TQ>& r, const GLevel<T>& L, const GLevel<T>& Lc,
                                          const Lane<T>& c, const InterpX<T>& ix, const cx<T>* u, const cx<T>* e,
                                          const void* f, int y) {
     const cx<T> Z = mk<T>(0, 0);
@@ -194,18 +178,18 @@ __device__ __forceinline__ void load_row(RowIn<T, TQ>& r, const LevelView<T>& L,
     if constexpr (POST) {
         int j0, j1;
         interp_axis<T>(y, Lc.n[1], j0, j1, r.v0, r.v1);
-        const cx<T>* r0 = e + (long long)j0 * Lc.n[0];
-        const cx<T>* r1 = e + (long long)j1 * Lc.n[0];
-        r.e00 = r0[ix.i0];
-        r.e01 = r0[ix.i1];
-        r.e10 = r1[ix.i0];
-        r.e11 = r1[ix.i1];
+        const auto ev = gin(e);
+        const long long r0 = (long long)j0 * Lc.n[0], r1 = (long long)j1 * Lc.n[0];
+        r.e00 = ev[r0 + ix.i0];
+        r.e01 = ev[r0 + ix.i1];
+        r.e10 = ev[r1 + ix.i0];
+        r.e11 = ev[r1 + ix.i1];
     }
-    if (u) r.u = u[gi];
+    if (u) r.u = gin(u)[gi];
     if constexpr (Q0BUF)
-        r.f = cvt<TQ>(static_cast<const cx<T>*>(f)[gi]);
+        r.f = cvt<TQ>(gin(static_cast<const cx<T>*>(f))[gi]);
     else
-        r.f = static_cast<const cx<TQ>*>(f)[gi];
+        r.f = gin(static_cast<const cx<TQ>*>(f))[gi];
     r.k2 = L.k2[gi];
 }
 
@@ -227,8 +211,8 @@ __global__ void __launch_bounds__(MW) k_mg_gram(const CycleArgs a, cx<double>* p
     if (gated_off(sl.gate)) return;
     const int tile = pid - sl.tile0;
     const LevelView<T>* Lp = static_cast<const LevelView<T>*>(sl.lv);
-    const LevelView<T> L = *Lp;
-    const LevelView<T> Lc = Lp[1];
+    const GLevel<T> L = glevel(*Lp);
+    const GLevel<T> Lc = glevel(Lp[1]);
     const SmoothBufs B = *sl.sb;
     const int nx = L.n[0];
     const int ntx = (nx + MTX - 1) / MTX;
@@ -351,8 +335,8 @@ __global__ void __launch_bounds__(MW) k_mg_apply_restrict(const CycleArgs a) {
     const CycleSlot& sl = a.st.s[slot];
     if (gated_off(sl.gate)) return;
     const LevelView<T>* Lp = static_cast<const LevelView<T>*>(sl.lv);
-    const LevelView<T> L = *Lp;
-    const LevelView<T> Lc = Lp[1];
+    const GLevel<T> L = glevel(*Lp);
+    const GLevel<T> Lc = glevel(Lp[1]);
     const SmoothBufs B = *sl.sb;
     const int nx = L.n[0], ny = L.n[1];
     const int ntx = (nx + MTX - 1) / MTX;
@@ -367,8 +351,8 @@ __global__ void __launch_bounds__(MW) k_mg_apply_restrict(const CycleArgs a) {
     const void* src = q0buf ? B.q[0] : sl.f;
     const T qs = q0buf ? T(1) : fs;
     const cx<T>* up = static_cast<const cx<T>*>(sl.u);
-    cx<T>* u1p = static_cast<cx<T>*>(B.u1);
-    cx<T>* fc = static_cast<cx<T>*>(sl.c);
+    const auto u1p = gout(static_cast<cx<T>*>(B.u1));
+    const auto fc = gout(static_cast<cx<T>*>(sl.c));
     const int ncx = Lc.n[0], ncy = Lc.n[1];
     const cx<T> c1 = cvt<T>(B.coef[0]), cc2 = cvt<T>(B.coef[1]), cc3 = cvt<T>(B.coef[2]);
     const cx<T> Z = mk<T>(0, 0);
@@ -449,8 +433,8 @@ __global__ void __launch_bounds__(MW) k_mg_apply_out(const CycleArgs a) {
     const CycleSlot& sl = a.st.s[slot];
     if (gated_off(sl.gate)) return;
     const LevelView<T>* Lp = static_cast<const LevelView<T>*>(sl.lv);
-    const LevelView<T> L = *Lp;
-    const LevelView<T> Lc = Lp[1];
+    const GLevel<T> L = glevel(*Lp);
+    const GLevel<T> Lc = glevel(Lp[1]);
     const SmoothBufs B = *sl.sb;
     const int nx = L.n[0], ny = L.n[1];
     const int ntx = (nx + MTX - 1) / MTX;
@@ -462,7 +446,7 @@ __global__ void __launch_bounds__(MW) k_mg_apply_out(const CycleArgs a) {
     const T fs = (T)fscale_of(sl);
     const cx<T>* u1 = static_cast<const cx<T>*>(B.u1);
     const cx<T>* e = static_cast<const cx<T>*>(sl.c);
-    cx<TO>* out = static_cast<cx<TO>*>(sl.out);
+    const auto out = gout(static_cast<cx<TO>*>(sl.out));
     const cx<T> c1 = cvt<T>(B.coef[4]), cc2 = cvt<T>(B.coef[5]), cc3 = cvt<T>(B.coef[6]);
     const cx<T> Z = mk<T>(0, 0);
     const int yend = imin(y0 + TY, ny);
@@ -501,7 +485,7 @@ __global__ void __launch_bounds__(MW) k_mg_apply_out(const CycleArgs a) {
             const cx<T> q2 = L.sinv * v;
             const cx<T> w = a3 - L.sinv * (c1 * b3 + cc2 * c3 + cc3 * q2);
             if constexpr (ACC)
-                out[gi] = out[gi] + cvt<TO>(w);
+                out[gi] = out[gi].get() + cvt<TO>(w);
             else
                 out[gi] = cvt<TO>(w);
         }

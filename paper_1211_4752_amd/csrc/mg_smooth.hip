@@ -62,31 +62,34 @@ __device__ __forceinline__ void grid_pos(int p, int nx, int ny, int& gx, int& gy
 // q0 at p: fscale f (f typed TQ) or the q0 buffer.
 template <typename T, typename TQ>
 __device__ __forceinline__ cx<T> load_q0(const SmSlot& sl, const SmoothBufs& B, long long p) {
-    if (sl.f) return (T)fscale_of(sl) * cvt<T>(static_cast<const cx<TQ>*>(sl.f)[p]);
-    return static_cast<const cx<T>*>(B.q[0])[p];
+    if (sl.f) return (T)fscale_of(sl) * cvt<T>(gin(static_cast<const cx<TQ>*>(sl.f))[p]);
+    return gin(static_cast<const cx<T>*>(B.q[0]))[p];
 }
 
 // q_stage = (A/s) q_{stage-1}.
 template <int D, typename T, typename TQ>
 __global__ void __launch_bounds__(NT) k_sm_power(const SmArgs a, int stage) {
     const SmPos q = sm_pos(a.st);
-    const SmSlot& sl = a.st.s[q.slot];
+    const SmSlot sl = a.st.s[q.slot];
     if (gated_off(sl.gate)) return;
-    const LevelView<T> L = *static_cast<const LevelView<T>*>(sl.lv);
+    const GLevel<T> L = glevel(*static_cast<const LevelView<T>*>(sl.lv));
     const SmoothBufs B = *sl.sb;
     int lo, hi;
     chunk_range(L.N, q.nb, q.b, lo, hi);
-    cx<T>* y = static_cast<cx<T>*>(B.q[stage]);
+    const auto y = gout(static_cast<cx<T>*>(sl.sb->q[stage]));
     const int nx = L.n[0], ny = L.n[1];
     const bool from_f = stage == 1 && sl.f;
+    const T fsc = (T)fscale_of(sl);
+    const auto fin = gin(static_cast<const cx<TQ>*>(sl.f));
+    const auto qin = gin(static_cast<const cx<T>*>(sl.sb->q[stage > 0 ? stage - 1 : 0]));
     for (int p = lo + (int)threadIdx.x; p < hi; p += NT) {
         int gx, gy, gz;
         grid_pos(p, nx, ny, gx, gy, gz);
         cx<T> ax;
         if (from_f)
-            ax = stencil_at<D, T, TQ>(L, static_cast<const cx<TQ>*>(sl.f), (T)fscale_of(sl), p, gx, gy, gz);
+            ax = stencil_at<D, T, TQ>(L, fin, fsc, p, gx, gy, gz);
         else
-            ax = stencil_at<D, T, T>(L, static_cast<const cx<T>*>(B.q[stage - 1]), T(1), p, gx, gy, gz);
+            ax = stencil_at<D, T, T>(L, qin, T(1), p, gx, gy, gz);
         y[p] = L.sinv * ax;
     }
 }
@@ -96,14 +99,14 @@ template <int D, typename T, typename TQ>
 __global__ void __launch_bounds__(NT) k_sm_gram(const SmArgs a) {
     __shared__ cx<double> sm[(NT / 64) * NUM_GRAM];
     const SmPos q = sm_pos(a.st);
-    const SmSlot& sl = a.st.s[q.slot];
+    const SmSlot sl = a.st.s[q.slot];
     if (gated_off(sl.gate)) return;
-    const LevelView<T> L = *static_cast<const LevelView<T>*>(sl.lv);
+    const GLevel<T> L = glevel(*static_cast<const LevelView<T>*>(sl.lv));
     const SmoothBufs B = *sl.sb;
     int lo, hi;
     chunk_range(L.N, q.nb, q.b, lo, hi);
-    const cx<T>* q1p = static_cast<const cx<T>*>(B.q[1]);
-    const cx<T>* q2p = static_cast<const cx<T>*>(B.q[2]);
+    const auto q1p = gin(static_cast<const cx<T>*>(B.q[1]));
+    const auto q2p = gin(static_cast<const cx<T>*>(B.q[2]));
     const int nx = L.n[0], ny = L.n[1];
     cx<double> g[NUM_GRAM];
 #pragma unroll
@@ -217,18 +220,18 @@ __global__ void __launch_bounds__(NT) k_sm_apply_restrict(const CycleArgs a) {
 
     const int pid = xcd_remap(blockIdx.x, gridDim.x);
     const int slot = find_slot(a.st.s, a.st.n, pid);
-    const CycleSlot& sl = a.st.s[slot];
+    const CycleSlot sl = a.st.s[slot];
     if (gated_off(sl.gate)) return;
     const LevelView<T>* Lp = static_cast<const LevelView<T>*>(sl.lv);
-    const LevelView<T> L = *Lp;
+    const GLevel<T> L = glevel(*Lp);
     const SmoothBufs B = *sl.sb;
     const int nx = L.n[0], ny = L.n[1], nz = L.n[2];
     int x0, y0, z0;
     tile_origin<D, TX, TY, TZE>(pid - sl.tile0, nx, ny, x0, y0, z0);
-    const cx<T>* q1p = static_cast<const cx<T>*>(B.q[1]);
-    const cx<T>* q2p = static_cast<const cx<T>*>(B.q[2]);
-    const cx<T>* q0p = static_cast<const cx<T>*>(B.q[0]);
-    const cx<TQ>* f = static_cast<const cx<TQ>*>(sl.f);
+    const auto q1p = gin(static_cast<const cx<T>*>(B.q[1]));
+    const auto q2p = gin(static_cast<const cx<T>*>(B.q[2]));
+    const auto q0p = gin(static_cast<const cx<T>*>(B.q[0]));
+    const auto f = gin(static_cast<const cx<TQ>*>(sl.f));
     const T fs = (T)fscale_of(sl);
     cx<T> c1, c2, c3;
     load_coef<T>(B.coef, c1, c2, c3);
@@ -247,8 +250,8 @@ __global__ void __launch_bounds__(NT) k_sm_apply_restrict(const CycleArgs a) {
     }
     __syncthreads();
 
-    cx<T>* u1p = static_cast<cx<T>*>(B.u1);
-    const cx<T>* up = static_cast<const cx<T>*>(sl.u);
+    const auto u1p = gout(static_cast<cx<T>*>(B.u1));
+    const auto up = gin(static_cast<const cx<T>*>(sl.u));
     for (int idx = threadIdx.x; idx < NR; idx += NT) {
         const int lx = idx % RX;
         const int rr = idx / RX;
@@ -281,7 +284,7 @@ __global__ void __launch_bounds__(NT) k_sm_apply_restrict(const CycleArgs a) {
     __syncthreads();
 
     const int ncx = Lp[1].n[0], ncy = Lp[1].n[1], ncz = Lp[1].n[2];
-    cx<T>* fc = static_cast<cx<T>*>(sl.c);
+    const auto fc = gout(static_cast<cx<T>*>(sl.c));
     for (int idx = threadIdx.x; idx < CX * CY * CZ; idx += NT) {
         const int cxl = idx % CX;
         const int rr = idx / CX;
@@ -328,19 +331,19 @@ __global__ void __launch_bounds__(NT) k_sm_prolong_resid(const CycleArgs a) {
 
     const int pid = xcd_remap(blockIdx.x, gridDim.x);
     const int slot = find_slot(a.st.s, a.st.n, pid);
-    const CycleSlot& sl = a.st.s[slot];
+    const CycleSlot sl = a.st.s[slot];
     if (gated_off(sl.gate)) return;
     const LevelView<T>* Lp = static_cast<const LevelView<T>*>(sl.lv);
-    const LevelView<T> L = *Lp;
+    const GLevel<T> L = glevel(*Lp);
     const SmoothBufs B = *sl.sb;
     const int nx = L.n[0], ny = L.n[1], nz = L.n[2];
     const int ncx = Lp[1].n[0], ncy = Lp[1].n[1], ncz = Lp[1].n[2];
     int x0, y0, z0;
     tile_origin<D, TX, TY, TZE>(pid - sl.tile0, nx, ny, x0, y0, z0);
-    const cx<TF>* f = static_cast<const cx<TF>*>(sl.f);
+    const auto f = gin(static_cast<const cx<TF>*>(sl.f));
     const T fs = (T)fscale_of(sl);
-    const cx<T>* ec = static_cast<const cx<T>*>(sl.c);
-    const cx<T>* u1p = static_cast<const cx<T>*>(B.u1);
+    const auto ec = gin(static_cast<const cx<T>*>(sl.c));
+    const auto u1p = gin(static_cast<const cx<T>*>(B.u1));
     const int cxs = x0 / 2 - 1, cys = y0 / 2 - 1, czs = (D == 3) ? z0 / 2 - 1 : 0;
 
     for (int idx = threadIdx.x; idx < NE; idx += NT) {
@@ -391,8 +394,8 @@ __global__ void __launch_bounds__(NT) k_sm_prolong_resid(const CycleArgs a) {
     }
     __syncthreads();
 
-    cx<T>* u2p = static_cast<cx<T>*>(B.u2);
-    cx<T>* q0p = static_cast<cx<T>*>(B.q[0]);
+    const auto u2p = gout(static_cast<cx<T>*>(B.u2));
+    const auto q0p = gout(static_cast<cx<T>*>(B.q[0]));
     for (int idx = threadIdx.x; idx < TX * TY * TZE; idx += NT) {
         const int lx = idx % TX;
         const int rr = idx / TX;
@@ -417,23 +420,23 @@ __global__ void __launch_bounds__(NT) k_sm_prolong_resid(const CycleArgs a) {
 template <typename T, typename TO, bool ACC>
 __global__ void __launch_bounds__(NT) k_sm_apply_out(const SmArgs a) {
     const SmPos q = sm_pos(a.st);
-    const SmSlot& sl = a.st.s[q.slot];
+    const SmSlot sl = a.st.s[q.slot];
     if (gated_off(sl.gate)) return;
-    const LevelView<T> L = *static_cast<const LevelView<T>*>(sl.lv);
+    const GLevel<T> L = glevel(*static_cast<const LevelView<T>*>(sl.lv));
     const SmoothBufs B = *sl.sb;
     int lo, hi;
     chunk_range(L.N, q.nb, q.b, lo, hi);
     cx<T> c1, c2, c3;
     load_coef<T>(B.coef + 4, c1, c2, c3);
-    const cx<T>* q0p = static_cast<const cx<T>*>(B.q[0]);
-    const cx<T>* q1p = static_cast<const cx<T>*>(B.q[1]);
-    const cx<T>* q2p = static_cast<const cx<T>*>(B.q[2]);
-    const cx<T>* u2p = static_cast<const cx<T>*>(B.u2);
-    cx<TO>* out = static_cast<cx<TO>*>(sl.out);
+    const auto q0p = gin(static_cast<const cx<T>*>(B.q[0]));
+    const auto q1p = gin(static_cast<const cx<T>*>(B.q[1]));
+    const auto q2p = gin(static_cast<const cx<T>*>(B.q[2]));
+    const auto u2p = gin(static_cast<const cx<T>*>(B.u2));
+    const auto out = gout(static_cast<cx<TO>*>(sl.out));
     for (int p = lo + (int)threadIdx.x; p < hi; p += NT) {
         const cx<T> v = u2p[p] - L.sinv * (c1 * q0p[p] + c2 * q1p[p] + c3 * q2p[p]);
         if constexpr (ACC)
-            out[p] = out[p] + cvt<TO>(v);
+            out[p] = out[p].get() + cvt<TO>(v);
         else
             out[p] = cvt<TO>(v);
     }
