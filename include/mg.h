@@ -195,9 +195,10 @@ mg_status mg_apply(mg_ctx *c, int level, int adjoint, const double *x_dev,
  * omega-Jacobi kernels, and strips of 56 columns by 32, 16, 8 rows for the
  * 2D GMRES(3) kernels.  omega-Jacobi contexts also take ids 3, 4, 5: plane
  * sweeps of the zero-guess kernels (2D: row segments of 256, 512, 256 points
- * sweeping chunks of 16, 16, 32 rows; 3D: 64x8 columns sweeping chunks of 16,
- * 32, 16 planes with 384, 384, 256 threads), with tile shape 0 for the kernels that start
- * from a given iterate.  mg_setup picks one per level by timing every shape
+ * sweeping chunks of 16, 16, 32 rows with 320, 576, 320 threads; 3D: columns
+ * of 64x8, 32x8, 64x4 points sweeping chunks of 16 planes with 768, 448, 384
+ * threads), with tile shape 0 for the kernels that start from a given
+ * iterate.  mg_setup picks one per level by timing every shape
  * on the level's own arrays (levels of at least 4096 points above the coarse
  * tail; other levels use shape 0).  The sweep schedule of the two Arnoldi
  * passes (points per thread, so workgroups per right-hand side) is picked

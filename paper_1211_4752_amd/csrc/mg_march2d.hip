@@ -4,11 +4,11 @@
 // The minimiser of || q0 + c1 q1 + c2 q2 + c3 q3 ||, q_i = (A/s)^i r, comes
 // from the Gram matrix of the q_i (mg_smooth.hip).  Here one wavefront owns
 // a strip of MTX = 56 columns (lanes 4..59; 4 halo lanes on each side) and
-// TY rows, and marches down the rows: every step loads one new row of the
+// TY rows, and marches down the rows: every step takes one new row of the
 // inputs and produces one new row of each power, each from the three most
 // recent rows of the previous one held in registers; x-neighbours come from
-// the adjacent lanes by shuffles.  Each input is read once per pass (plus the
-// few warm-up rows and halo lanes, L2 hits), nothing but the outputs is
+// the adjacent lanes by DPP shifts.  Each input is read once per pass (plus
+// the few warm-up rows and halo lanes, L2 hits), nothing but the outputs is
 // written, and no LDS is used.
 //   k_mg_gram<PRE>    pre-smoothing: q0 = fscale f (or the q0 buffer);
 //   k_mg_gram<POST>   post-smoothing: u2 = u1 + P e, q0 = fscale f - A u2;
@@ -19,6 +19,19 @@
 //   k_mg_apply_out    u2 and q0..q2 again, out = u2 - (c1 q0 + c2 q1 +
 //                     c3 q2)/s (post-smoothing).
 // Values outside the grid are zero (Dirichlet ghosts) at every stage.
+//
+// Memory-level parallelism: the inputs of a row are loaded MAHEAD steps
+// before the step that uses them, into a ring of register sets that the
+// unrolled march indexes statically; every load is issued unconditionally
+// (addresses clamped into the grid, values masked where they are used), so
+// that no branch sits between a load and its use and the wait before a step
+// covers only the loads of that step's row.  The coarse correction enters
+// one coarse row (interpolated in x) every second fine row.  The y-axis
+// coefficients of the strip's rows sit in a per-lane table (lane l: row
+// y0 - YB + l) and are read with readlane, so the march makes no scalar
+// loads.
+
+#include <type_traits>
 
 #include "mg_kcommon.hpp"
 
@@ -31,8 +44,11 @@ namespace {
 constexpr int MW = 64;              // lanes per wavefront = workgroup size
 constexpr int MH = 4;               // halo lanes on the left
 constexpr int MTX = MW - 2 * MH;    // owned columns per strip
+constexpr int MAHEAD = 4;           // rows loaded ahead (even)
+constexpr int YB = 8;               // first row of the y table: y0 - YB
 
 __device__ __forceinline__ int imin(int a, int b) { return a < b ? a : b; }
+__device__ __forceinline__ int iclamp(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
 
 // Neighbour exchange across the wavefront by DPP lane shifts (VALU, no LDS):
 // wave_shr:1 gives lane i the value of lane i - 1, wave_shl:1 that of lane
@@ -62,10 +78,26 @@ __device__ __forceinline__ cx<T> shfl_dn1(cx<T> v) {
     return mk<T>(lane_shift<false>(v.r), lane_shift<false>(v.i));
 }
 
+// Value of lane l (uniform l) to every lane.
+__device__ __forceinline__ double rdlane(double v, int l) {
+    const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+    const int lo = __builtin_amdgcn_readlane((int)(unsigned)(b & 0xffffffffull), l);
+    const int hi = __builtin_amdgcn_readlane((int)(unsigned)(b >> 32), l);
+    return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+}
+__device__ __forceinline__ float rdlane(float v, int l) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), l));
+}
+template <typename T>
+__device__ __forceinline__ cx<T> rdlane(cx<T> v, int l) {
+    return mk<T>(rdlane(v.r, l), rdlane(v.i, l));
+}
+
 // Per-lane column data of a strip.
 template <typename T>
 struct Lane {
-    int gx;
+    int gx;       // column of the lane
+    int gxc;      // the same, clamped into the grid (load addresses)
     bool colv;
     bool own;
     cx<T> cmx, c0x, cpx;
@@ -78,33 +110,68 @@ __device__ __forceinline__ Lane<T> lane_of(const GLevel<T>& L, int x0) {
     c.gx = x0 - MH + lane;
     c.colv = c.gx >= 0 && c.gx < L.n[0];
     c.own = c.colv && lane >= MH && lane < MH + MTX;
-    const int g = c.colv ? c.gx : 0;
-    c.cmx = c.colv ? L.cm[0][g] : mk<T>(0, 0);
-    c.c0x = c.colv ? L.c0[0][g] : mk<T>(0, 0);
-    c.cpx = c.colv ? L.cp[0][g] : mk<T>(0, 0);
+    c.gxc = iclamp(c.gx, 0, L.n[0] - 1);
+    const cx<T> cm = L.cm[0][c.gxc], c0 = L.c0[0][c.gxc], cp = L.cp[0][c.gxc];
+    const cx<T> Z = mk<T>(0, 0);
+    c.cmx = c.colv ? cm : Z;
+    c.c0x = c.colv ? c0 : Z;
+    c.cpx = c.colv ? cp : Z;
     return c;
 }
 
-// A at row y of the stage whose rows y-1, y, y+1 are am, a0, ap (this lane);
-// every lane must call it (shuffles).  Caller masks the result.
+// y-axis coefficients of one row.
 template <typename T>
-__device__ __forceinline__ cx<T> row_apply(const GLevel<T>& L, const Lane<T>& c, cx<T> am, cx<T> a0, cx<T> ap, int y,
-                                           T k2) {
+struct YC {
+    cx<T> c0, cm, cp;
+};
+
+// The table: lane l holds row y0 - YB + l (clamped into the grid).
+template <typename T>
+__device__ __forceinline__ YC<T> ytab_of(const GLevel<T>& L, int y0) {
+    const int y = iclamp(y0 - YB + (int)threadIdx.x, 0, L.n[1] - 1);
+    return YC<T>{L.c0[1][y], L.cm[1][y], L.cp[1][y]};
+}
+
+template <typename T>
+__device__ __forceinline__ YC<T> yrow(const YC<T>& tab, int y0, int y) {
+    const int l = y - (y0 - YB);
+    return YC<T>{rdlane(tab.c0, l), rdlane(tab.cm, l), rdlane(tab.cp, l)};
+}
+
+// A at the row whose rows y-1, y, y+1 of the stage are am, a0, ap (this
+// lane); every lane must call it (lane shifts).  Caller masks the result.
+// d: the diagonal of that row at this lane.
+template <typename T>
+__device__ __forceinline__ cx<T> row_apply(const Lane<T>& c, const YC<T>& y, cx<T> d, cx<T> am, cx<T> a0, cx<T> ap) {
     const cx<T> left = shfl_up1(a0);
     const cx<T> right = shfl_dn1(a0);
-    const int yy = (y >= 0 && y < L.n[1]) ? y : 0;
-    const cx<T> d = c.c0x + L.c0[1][yy] - k2 * L.sigma;
-    return d * a0 + c.cmx * left + c.cpx * right + L.cm[1][yy] * am + L.cp[1][yy] * ap;
+    return d * a0 + c.cmx * left + c.cpx * right + y.cm * am + y.cp * ap;
+}
+
+// A register copy made exactly here.  The ring slot a value was loaded into
+// dies at the copy, so the slot's next load can reuse its registers; left to
+// itself the compiler may move the consumer of the slot past that load and
+// then rotate the whole ring with copies that wait for every load.
+__device__ __forceinline__ double pin(double v) {
+    double r;
+    asm volatile("v_mov_b64 %0, %1" : "=v"(r) : "v"(v));
+    return r;
+}
+__device__ __forceinline__ float pin(float v) {
+    float r;
+    asm volatile("v_mov_b32 %0, %1" : "=v"(r) : "v"(v));
+    return r;
+}
+
+// Diagonal of row y at this lane (y-table entry yn of that row).
+template <typename T>
+__device__ __forceinline__ cx<T> row_diag(const GLevel<T>& L, const Lane<T>& c, const YC<T>& yn, T k2) {
+    return c.c0x + yn.c0 - k2 * L.sigma;
 }
 
 template <typename T>
 __device__ __forceinline__ bool rowv(const GLevel<T>& L, int y) {
     return y >= 0 && y < L.n[1];
-}
-
-template <typename T>
-__device__ __forceinline__ T load_k2(const GLevel<T>& L, const Lane<T>& c, int y) {
-    return (c.colv && rowv(L, y)) ? L.k2[(long long)y * L.n[0] + c.gx] : T(0);
 }
 
 // Bilinear interpolation of the coarse correction: per-lane x part.
@@ -151,51 +218,132 @@ __device__ __forceinline__ void gram_add(cx<double>* g, cx<T> a0, cx<T> a1, cx<T
     g[9] = g[9] + cmulc(v2, v3);
 }
 
-// One row of a pass's inputs at this lane, loaded ahead of its use (two rows
-// in the Gram passes, one in the apply passes, where the extra registers
-// would cost occupancy) so that the loads are in flight while row t is
-// computed.
+template <typename T>
+__device__ __forceinline__ long long row_index(const GLevel<T>& L, const Lane<T>& c, int y) {
+    return (long long)iclamp(y, 0, L.n[1] - 1) * L.n[0] + c.gxc;
+}
+
+// Inputs of one fine row at this lane, as loaded (masked where used).
+// Pre-smoothing passes: q0 source and k^2, plus the incoming iterate (NZ).
 template <typename T, typename TQ>
-struct RowIn {
-    cx<T> u;                 // u1 (post-smoothing) or the incoming iterate
-    cx<T> e00, e01, e10, e11;   // coarse correction around the point
-    T v0, v1;                // row weights of the interpolation
-    cx<TQ> f;                // right-hand side (or q0)
+struct RowF {
+    cx<TQ> f;
     T k2;
+    cx<T> w;
+};
+// Post-smoothing passes: u1, f, k^2, plus out of row y - 3 (accumulating
+// output pass; loaded after the step's store, so that the old value is dead
+// when the new one is requested).
+template <typename T, typename TF, typename TO>
+struct RowU {
+    cx<T> u;
+    cx<TF> f;
+    T k2;
+    cx<TO> o;
+};
+// One coarse row of the correction at the lane's two interpolation columns.
+template <typename T>
+struct RowC {
+    cx<T> e0, e1;
 };
 
-template <typename T, typename TQ, bool POST, bool Q0BUF>
-__device__ __forceinline__ void load_row(RowIn<T, TQ>& r, const GLevel<T>& L, const GLevel<T>& Lc,
-                                         const Lane<T>& c, const InterpX<T>& ix, const cx<T>* u, const cx<T>* e,
-                                         const void* f, int y) {
-    const cx<T> Z = mk<T>(0, 0);
-    r.u = r.e00 = r.e01 = r.e10 = r.e11 = Z;
-    r.v0 = r.v1 = T(0);
-    r.f = mk<TQ>(0, 0);
-    r.k2 = T(0);
-    if (!(c.colv && rowv(L, y))) return;
-    const long long gi = (long long)y * L.n[0] + c.gx;
-    if constexpr (POST) {
-        int j0, j1;
-        interp_axis<T>(y, Lc.n[1], j0, j1, r.v0, r.v1);
-        const auto ev = gin(e);
-        const long long r0 = (long long)j0 * Lc.n[0], r1 = (long long)j1 * Lc.n[0];
-        r.e00 = ev[r0 + ix.i0];
-        r.e01 = ev[r0 + ix.i1];
-        r.e10 = ev[r1 + ix.i0];
-        r.e11 = ev[r1 + ix.i1];
-    }
-    if (u) r.u = gin(u)[gi];
-    if constexpr (Q0BUF)
-        r.f = cvt<TQ>(gin(static_cast<const cx<T>*>(f))[gi]);
-    else
-        r.f = gin(static_cast<const cx<TQ>*>(f))[gi];
+template <typename T, typename TQ, bool NZ>
+__device__ __forceinline__ void load_f(RowF<T, TQ>& r, const GLevel<T>& L, const Lane<T>& c, GIn<cx<TQ>> f,
+                                       GIn<cx<T>> w, int y) {
+    const long long gi = row_index(L, c, y);
+    r.f = f[gi];
+    r.k2 = L.k2[gi];
+    if constexpr (NZ) r.w = w[gi];
+}
+
+template <typename T, typename TF, typename TO>
+__device__ __forceinline__ void load_u(RowU<T, TF, TO>& r, const GLevel<T>& L, const Lane<T>& c, GIn<cx<T>> u,
+                                       GIn<cx<TF>> f, int y) {
+    const long long gi = row_index(L, c, y);
+    r.u = u[gi];
+    r.f = f[gi];
     r.k2 = L.k2[gi];
 }
 
+template <typename T>
+__device__ __forceinline__ void load_c(RowC<T>& r, const GLevel<T>& Lc, const InterpX<T>& ix, GIn<cx<T>> e, int J) {
+    const long long b = (long long)iclamp(J, 0, Lc.n[1] - 1) * Lc.n[0];
+    r.e0 = e[b + ix.i0];
+    r.e1 = e[b + ix.i1];
+}
+
+// x-interpolated coarse row J (zero outside the coarse grid).
+template <typename T>
+__device__ __forceinline__ cx<T> ex_of(const RowC<T>& r, const GLevel<T>& Lc, const InterpX<T>& ix, int J) {
+    const cx<T> v = ix.w0 * r.e0 + ix.w1 * r.e1;
+    return (J >= 0 && J < Lc.n[1]) ? v : mk<T>(0, 0);
+}
+
+// The coarse correction interpolated to the fine rows of a march that
+// starts at row tb: coarse row J = t / 2 enters at every even fine row t,
+// MAHEAD / 2 coarse rows ahead.  PAR = tb & 1 (static: strips start at even
+// rows).  The even steps of an unrolled group of MAHEAD steps are i = 2k + PAR.
+template <typename T, int PAR>
+struct CoarseRing {
+    static constexpr int PC = MAHEAD / 2;
+    RowC<T> pc[PC];
+    cx<T> exA, exB;   // coarse rows floor(t/2) - 1 and floor(t/2)
+
+    // Set-up, in the order of the loads in the march: the coarse row before
+    // the first fine row (first), then per step of the first group the coarse
+    // row that the step would load (prime<I>), then finish.
+    __device__ __forceinline__ void first(RowC<T>& r0, const GLevel<T>& Lc, const InterpX<T>& ix, GIn<cx<T>> e,
+                                          int tb) {
+        load_c(r0, Lc, ix, e, (tb - 1) >> 1);
+    }
+    template <int I>
+    __device__ __forceinline__ void prime(const GLevel<T>& Lc, const InterpX<T>& ix, GIn<cx<T>> e, int tb) {
+        if constexpr (((I + PAR) & 1) == 0) load_c(pc[(I - PAR) / 2], Lc, ix, e, ((tb + PAR) >> 1) + (I - PAR) / 2);
+    }
+    __device__ __forceinline__ void finish(const RowC<T>& r0, const GLevel<T>& Lc, const InterpX<T>& ix, int tb) {
+        exB = ex_of(r0, Lc, ix, (tb - 1) >> 1);
+        exA = mk<T>(0, 0);
+    }
+    // correction at fine row t = t0 + i (i static)
+    template <int I>
+    __device__ __forceinline__ cx<T> step(const GLevel<T>& Lc, const InterpX<T>& ix, GIn<cx<T>> e, int t) {
+        if constexpr (((I + PAR) & 1) == 0) {
+            constexpr int k = (I - PAR) / 2;
+            const int J = t >> 1;
+            exA = exB;
+            exB = ex_of(pc[k], Lc, ix, J);
+            load_c(pc[k], Lc, ix, e, J + PC);
+            return T(0.5) * (exA + exB);
+        } else {
+            return exB;
+        }
+    }
+};
+
+template <int N>
+struct IntC {
+    static constexpr int v = N;
+};
+
+// Static unroll: f(IntC<0>), ..., f(IntC<N-1>).
+template <int I, int N, typename F>
+__device__ __forceinline__ void unroll(F&& f) {
+    if constexpr (I < N) {
+        f(IntC<I>{});
+        unroll<I + 1, N>(f);
+    }
+}
+
+__device__ __forceinline__ int round_up(int v, int m) { return (v + m - 1) / m * m; }
+
 template <typename T, typename TQ>
-__device__ __forceinline__ cx<T> u2_of(const RowIn<T, TQ>& r, const InterpX<T>& ix) {
-    return r.u + (r.v0 * ix.w0) * r.e00 + (r.v0 * ix.w1) * r.e01 + (r.v1 * ix.w0) * r.e10 + (r.v1 * ix.w1) * r.e11;
+__device__ __forceinline__ GIn<cx<TQ>> q0_source(const CycleSlot& sl, const SmoothBufs& B) {
+    // The q0 buffer (sl.f null: level 0 with an incoming iterate) is FP64,
+    // which only FP64 passes read.
+    if constexpr (std::is_same<T, TQ>::value)
+        return gin(static_cast<const cx<TQ>*>(sl.f ? sl.f : B.q[0]));
+    else
+        return gin(static_cast<const cx<TQ>*>(sl.f));
 }
 
 // ---------------------------------------------------------------------------
@@ -205,6 +353,7 @@ __device__ __forceinline__ cx<T> u2_of(const RowIn<T, TQ>& r, const InterpX<T>& 
 // ---------------------------------------------------------------------------
 template <typename T, typename TQ, bool POST, int TY>
 __global__ void __launch_bounds__(MW) k_mg_gram(const CycleArgs a, cx<double>* part, int pstride, int bstride) {
+    static_assert(TY % 2 == 0 && MAHEAD % 2 == 0 && TY + MAHEAD + 11 <= MW, "strip geometry");
     const int pid = xcd_remap(blockIdx.x, gridDim.x);
     const int slot = find_slot(a.st.s, a.st.n, pid);
     const CycleSlot& sl = a.st.s[slot];
@@ -218,101 +367,137 @@ __global__ void __launch_bounds__(MW) k_mg_gram(const CycleArgs a, cx<double>* p
     const int ntx = (nx + MTX - 1) / MTX;
     const int x0 = (tile % ntx) * MTX, y0 = (tile / ntx) * TY;
     const Lane<T> c = lane_of(L, x0);
-    InterpX<T> ix;
-    interp_axis<T>(c.colv ? c.gx : 0, Lc.n[0], ix.i0, ix.i1, ix.w0, ix.w1);
+    const YC<T> yt = ytab_of(L, y0);
     const T fs = (T)fscale_of(sl);
     const cx<T> Z = mk<T>(0, 0);
     cx<double> g[NUM_GRAM];
 #pragma unroll
     for (int v = 0; v < NUM_GRAM; ++v) g[v] = mk(0.0, 0.0);
     const int yend = imin(y0 + TY, L.n[1]);
+    auto ok = [&](int y) { return c.colv && rowv(L, y); };
 
     if constexpr (POST) {
-        const cx<T>* u1 = static_cast<const cx<T>*>(B.u1);
-        const cx<T>* e = static_cast<const cx<T>*>(sl.c);
+        InterpX<T> ix;
+        interp_axis<T>(c.gxc, Lc.n[0], ix.i0, ix.i1, ix.w0, ix.w1);
+        const auto u1 = gin(static_cast<const cx<T>*>(B.u1));
+        const auto ev = gin(static_cast<const cx<T>*>(sl.c));
+        const auto fv = gin(static_cast<const cx<TQ>*>(sl.f));
         // u2 rows t, t-1, t-2; q0 rows t-1..t-4; q1 rows t-2..t-4; q2 rows t-3..t-5
         cx<T> a0 = Z, a1 = Z, a2 = Z;
         cx<T> b1 = Z, b2 = Z, b3 = Z, b4 = Z;
         cx<T> c2 = Z, c3 = Z, c4 = Z;
         cx<T> d3 = Z, d4 = Z, d5 = Z;
         cx<T> fprev = Z;
-        T k0 = 0, k1 = 0, kk2 = 0, k3 = 0, k4 = 0;   // k^2 at rows t..t-4
-        RowIn<T, TQ> cur, n1, n2;
-        load_row<T, TQ, true, false>(cur, L, Lc, c, ix, u1, e, sl.f, y0 - 4);
-        load_row<T, TQ, true, false>(n1, L, Lc, c, ix, u1, e, sl.f, y0 - 3);
-        for (int t = y0 - 4; t < yend + 4; ++t) {
-            load_row<T, TQ, true, false>(n2, L, Lc, c, ix, u1, e, sl.f, t + 2);
-            a2 = a1;
-            a1 = a0;
-            a0 = u2_of(cur, ix);
-            k4 = k3;
-            k3 = kk2;
-            kk2 = k1;
-            k1 = k0;
-            k0 = cur.k2;
-            const bool m1 = c.colv && rowv(L, t - 1);
-            cx<T> v = row_apply<T>(L, c, a2, a1, a0, t - 1, k1);
-            b4 = b3;
-            b3 = b2;
-            b2 = b1;
-            b1 = m1 ? fprev - v : Z;
-            fprev = fs * cvt<T>(cur.f);
-            v = row_apply<T>(L, c, b3, b2, b1, t - 2, kk2);
-            c4 = c3;
-            c3 = c2;
-            c2 = (c.colv && rowv(L, t - 2)) ? L.sinv * v : Z;
-            v = row_apply<T>(L, c, c4, c3, c2, t - 3, k3);
-            d5 = d4;
-            d4 = d3;
-            d3 = (c.colv && rowv(L, t - 3)) ? L.sinv * v : Z;
-            v = row_apply<T>(L, c, d5, d4, d3, t - 4, k4);
-            const int yr = t - 4;
-            if (c.own && yr >= y0 && yr < yend) gram_add<T>(g, b4, c4, d4, L.sinv * v);
-            cur = n1;
-            n1 = n2;
-        }
+        cx<T> dd0 = Z, dd1 = Z, dd2 = Z, dd3 = Z, dd4 = Z;   // diagonals at rows t..t-4
+        const int tb = y0 - 4;
+        const int tn = tb + round_up(yend - y0 + 8, MAHEAD);
+        RowU<T, TQ, T> pf[MAHEAD];
+        CoarseRing<T, 0> cr;
+        RowC<T> r0;
+        cr.first(r0, Lc, ix, ev, tb);
+        unroll<0, MAHEAD>([&](auto I) {
+            constexpr int i = decltype(I)::v;
+            cr.template prime<i>(Lc, ix, ev, tb);
+            load_u<T, TQ, T>(pf[i], L, c, u1, fv, tb + i);
+            __builtin_amdgcn_sched_barrier(0);
+        });
+        cr.finish(r0, Lc, ix, tb);
+        YC<T> ycur = yrow(yt, y0, tb - 1), y1 = yrow(yt, y0, tb - 2), y2 = yrow(yt, y0, tb - 3), y3 = yrow(yt, y0, tb - 4), y4 = y3;
+        int t0 = tb;   // at least one group: the march has at least 6 steps
+        do {
+            unroll<0, MAHEAD>([&](auto I) {
+                constexpr int i = decltype(I)::v;
+                const int t = t0 + i;
+                const cx<T> ey = cr.template step<i>(Lc, ix, ev, t);
+                a2 = a1;
+                a1 = a0;
+                a0 = ok(t) ? pf[i].u + ey : Z;
+                dd4 = dd3;
+                dd3 = dd2;
+                dd2 = dd1;
+                dd1 = dd0;
+                const YC<T> yn = yrow(yt, y0, t);
+                dd0 = row_diag(L, c, yn, pin(pf[i].k2));
+                const cx<T> fnew = fs * cvt<T>(pf[i].f);
+                __builtin_amdgcn_sched_barrier(0);   // the ring slot is consumed before it is reloaded
+                load_u<T, TQ, T>(pf[i], L, c, u1, fv, t + MAHEAD);
+                y4 = y3;
+                y3 = y2;
+                y2 = y1;
+                y1 = ycur;
+                ycur = yn;
+                cx<T> v = row_apply<T>(c, y1, dd1, a2, a1, a0);
+                b4 = b3;
+                b3 = b2;
+                b2 = b1;
+                b1 = ok(t - 1) ? fprev - v : Z;
+                fprev = fnew;
+                v = row_apply<T>(c, y2, dd2, b3, b2, b1);
+                c4 = c3;
+                c3 = c2;
+                c2 = ok(t - 2) ? L.sinv * v : Z;
+                v = row_apply<T>(c, y3, dd3, c4, c3, c2);
+                d5 = d4;
+                d4 = d3;
+                d3 = ok(t - 3) ? L.sinv * v : Z;
+                v = row_apply<T>(c, y4, dd4, d5, d4, d3);
+                const int yr = t - 4;
+                if (c.own && yr >= y0 && yr < yend) gram_add<T>(g, b4, c4, d4, L.sinv * v);
+            });
+            t0 += MAHEAD;
+        } while (t0 < tn);
     } else {
         // q0 rows t..t-3; q1 rows t-1..t-3; q2 rows t-2..t-4
-        const bool q0buf = sl.f == nullptr;
-        const void* src = q0buf ? B.q[0] : sl.f;
-        const T qs = q0buf ? T(1) : fs;
+        const GIn<cx<TQ>> src = q0_source<T, TQ>(sl, B);
+        const T qs = sl.f ? fs : T(1);
+        const GIn<cx<T>> none{};
         cx<T> a0 = Z, a1 = Z, a2 = Z, a3 = Z;
         cx<T> b1 = Z, b2 = Z, b3 = Z;
         cx<T> c2 = Z, c3 = Z, c4 = Z;
-        T k0 = 0, k1 = 0, kk2 = 0, k3 = 0;
-        RowIn<T, TQ> cur, n1, n2;
-        auto ld = [&](RowIn<T, TQ>& r, int y) {
-            if (q0buf)
-                load_row<T, TQ, false, true>(r, L, Lc, c, ix, nullptr, nullptr, src, y);
-            else
-                load_row<T, TQ, false, false>(r, L, Lc, c, ix, nullptr, nullptr, src, y);
-        };
-        ld(cur, y0 - 3);
-        ld(n1, y0 - 2);
-        for (int t = y0 - 3; t < yend + 3; ++t) {
-            ld(n2, t + 2);
-            a3 = a2;
-            a2 = a1;
-            a1 = a0;
-            a0 = qs * cvt<T>(cur.f);
-            k3 = kk2;
-            kk2 = k1;
-            k1 = k0;
-            k0 = cur.k2;
-            cx<T> v = row_apply<T>(L, c, a2, a1, a0, t - 1, k1);
-            b3 = b2;
-            b2 = b1;
-            b1 = (c.colv && rowv(L, t - 1)) ? L.sinv * v : Z;
-            v = row_apply<T>(L, c, b3, b2, b1, t - 2, kk2);
-            c4 = c3;
-            c3 = c2;
-            c2 = (c.colv && rowv(L, t - 2)) ? L.sinv * v : Z;
-            v = row_apply<T>(L, c, c4, c3, c2, t - 3, k3);
-            const int yr = t - 3;
-            if (c.own && yr >= y0 && yr < yend) gram_add<T>(g, a3, b3, c3, L.sinv * v);
-            cur = n1;
-            n1 = n2;
+        cx<T> dd0 = Z, dd1 = Z, dd2 = Z, dd3 = Z;   // diagonals at rows t..t-3
+        const int tb = y0 - 3;
+        const int tn = tb + round_up(yend - y0 + 6, MAHEAD);
+        RowF<T, TQ> pf[MAHEAD];
+#pragma unroll
+        for (int i = 0; i < MAHEAD; ++i) {
+            load_f<T, TQ, false>(pf[i], L, c, src, none, tb + i);
+            __builtin_amdgcn_sched_barrier(0);
         }
+        YC<T> ycur = yrow(yt, y0, tb - 1), y1 = yrow(yt, y0, tb - 2), y2 = yrow(yt, y0, tb - 3), y3 = y2;
+        int t0 = tb;   // at least one group: the march has at least 6 steps
+        do {
+            unroll<0, MAHEAD>([&](auto I) {
+                constexpr int i = decltype(I)::v;
+                const int t = t0 + i;
+                a3 = a2;
+                a2 = a1;
+                a1 = a0;
+                a0 = ok(t) ? qs * cvt<T>(pf[i].f) : Z;
+                dd3 = dd2;
+                dd2 = dd1;
+                dd1 = dd0;
+                const YC<T> yn = yrow(yt, y0, t);
+                dd0 = row_diag(L, c, yn, pin(pf[i].k2));
+                __builtin_amdgcn_sched_barrier(0);   // the ring slot is consumed before it is reloaded
+                load_f<T, TQ, false>(pf[i], L, c, src, none, t + MAHEAD);
+                y3 = y2;
+                y2 = y1;
+                y1 = ycur;
+                ycur = yn;
+                cx<T> v = row_apply<T>(c, y1, dd1, a2, a1, a0);
+                b3 = b2;
+                b2 = b1;
+                b1 = ok(t - 1) ? L.sinv * v : Z;
+                v = row_apply<T>(c, y2, dd2, b3, b2, b1);
+                c4 = c3;
+                c3 = c2;
+                c2 = ok(t - 2) ? L.sinv * v : Z;
+                v = row_apply<T>(c, y3, dd3, c4, c3, c2);
+                const int yr = t - 3;
+                if (c.own && yr >= y0 && yr < yend) gram_add<T>(g, a3, b3, c3, L.sinv * v);
+            });
+            t0 += MAHEAD;
+        } while (t0 < tn);
     }
     cx<double>* P = part + (long long)slot * pstride * bstride;
 #pragma unroll
@@ -330,6 +515,7 @@ __global__ void __launch_bounds__(MW) k_mg_gram(const CycleArgs a, cx<double>* p
 // ---------------------------------------------------------------------------
 template <typename T, typename TQ, bool NZ, int TY>
 __global__ void __launch_bounds__(MW) k_mg_apply_restrict(const CycleArgs a) {
+    static_assert(TY % 2 == 0 && MAHEAD % 2 == 0 && TY + MAHEAD + 11 <= MW, "strip geometry");
     const int pid = xcd_remap(blockIdx.x, gridDim.x);
     const int slot = find_slot(a.st.s, a.st.n, pid);
     const CycleSlot& sl = a.st.s[slot];
@@ -343,14 +529,11 @@ __global__ void __launch_bounds__(MW) k_mg_apply_restrict(const CycleArgs a) {
     const int tile = pid - sl.tile0;
     const int x0 = (tile % ntx) * MTX, y0 = (tile / ntx) * TY;
     const Lane<T> c = lane_of(L, x0);
-    InterpX<T> ix;
-    ix.i0 = ix.i1 = 0;
-    ix.w0 = ix.w1 = T(0);
+    const YC<T> yt = ytab_of(L, y0);
     const T fs = (T)fscale_of(sl);
-    const bool q0buf = sl.f == nullptr;
-    const void* src = q0buf ? B.q[0] : sl.f;
-    const T qs = q0buf ? T(1) : fs;
-    const cx<T>* up = static_cast<const cx<T>*>(sl.u);
+    const GIn<cx<TQ>> src = q0_source<T, TQ>(sl, B);
+    const T qs = sl.f ? fs : T(1);
+    const auto up = gin(static_cast<const cx<T>*>(sl.u));
     const auto u1p = gout(static_cast<cx<T>*>(B.u1));
     const auto fc = gout(static_cast<cx<T>*>(sl.c));
     const int ncx = Lc.n[0], ncy = Lc.n[1];
@@ -359,67 +542,80 @@ __global__ void __launch_bounds__(MW) k_mg_apply_restrict(const CycleArgs a) {
     const int yend = imin(y0 + TY, ny);
     // restriction centres of this strip: odd gx among the owned lanes
     const bool ccol = c.own && (c.gx & 1) && (c.gx - 1) / 2 < ncx;
+    auto ok = [&](int y) { return c.colv && rowv(L, y); };
 
     cx<T> a0 = Z, a1 = Z, a2 = Z, a3 = Z;
     cx<T> b1 = Z, b2 = Z, b3 = Z;
     cx<T> c2 = Z, c3 = Z, c4 = Z;
-    cx<T> r3 = Z, r4 = Z, r5 = Z;   // r1 at rows t-3, t-4, t-5
+    cx<T> r3 = Z, r4 = Z, r5 = Z;           // r1 at rows t-3, t-4, t-5
     cx<T> w0 = Z, w1 = Z, w2 = Z, w3 = Z;   // incoming iterate at rows t..t-3 (NZ)
-    T k0 = 0, k1 = 0, kk2 = 0, k3 = 0;
-    RowIn<T, TQ> cur, n1;
-    auto ld = [&](RowIn<T, TQ>& r, int y) {
-        if (q0buf)
-            load_row<T, TQ, false, true>(r, L, Lc, c, ix, NZ ? up : nullptr, nullptr, src, y);
-        else
-            load_row<T, TQ, false, false>(r, L, Lc, c, ix, NZ ? up : nullptr, nullptr, src, y);
-    };
-    ld(cur, y0 - 3);
-    for (int t = y0 - 3; t <= yend + 3; ++t) {
-        ld(n1, t + 1);
-        a3 = a2;
-        a2 = a1;
-        a1 = a0;
-        a0 = qs * cvt<T>(cur.f);
-        if constexpr (NZ) {
-            w3 = w2;
-            w2 = w1;
-            w1 = w0;
-            w0 = cur.u;
-        }
-        k3 = kk2;
-        kk2 = k1;
-        k1 = k0;
-        k0 = cur.k2;
-        cx<T> v = row_apply<T>(L, c, a2, a1, a0, t - 1, k1);
-        b3 = b2;
-        b2 = b1;
-        b1 = (c.colv && rowv(L, t - 1)) ? L.sinv * v : Z;
-        v = row_apply<T>(L, c, b3, b2, b1, t - 2, kk2);
-        c4 = c3;
-        c3 = c2;
-        c2 = (c.colv && rowv(L, t - 2)) ? L.sinv * v : Z;
-        v = row_apply<T>(L, c, c4, c3, c2, t - 3, k3);
-        const int yr = t - 3;
-        const bool m3 = c.colv && rowv(L, yr);
-        const cx<T> q3 = m3 ? L.sinv * v : Z;
-        r5 = r4;
-        r4 = r3;
-        r3 = m3 ? a3 + c1 * b3 + cc2 * c3 + cc3 * q3 : Z;
-        if (c.own && yr >= y0 && yr < yend) {
-            cx<T> u = L.sinv * (c1 * a3 + cc2 * b3 + cc3 * c3);
-            if constexpr (NZ) u = w3 - u;
-            else u = Z - u;
-            u1p[(long long)yr * nx + c.gx] = u;
-        }
-        const int yc = yr - 1;
-        const cx<T> vv = T(0.25) * r5 + T(0.5) * r4 + T(0.25) * r3;
-        const cx<T> vl = shfl_up1(vv), vr = shfl_dn1(vv);
-        if ((yc & 1) && yc >= y0 && yc < yend && (yc - 1) / 2 < ncy && ccol) {
-            const int C = (yc - 1) / 2, Cx = (c.gx - 1) / 2;
-            fc[(long long)C * ncx + Cx] = T(0.25) * vl + T(0.5) * vv + T(0.25) * vr;
-        }
-        cur = n1;
+    cx<T> dd0 = Z, dd1 = Z, dd2 = Z, dd3 = Z;   // diagonals at rows t..t-3
+    const int tb = y0 - 3;
+    const int tn = tb + round_up(yend - y0 + 7, MAHEAD);
+    RowF<T, TQ> pf[MAHEAD];
+#pragma unroll
+    for (int i = 0; i < MAHEAD; ++i) {
+        load_f<T, TQ, NZ>(pf[i], L, c, src, up, tb + i);
+        __builtin_amdgcn_sched_barrier(0);
     }
+    YC<T> ycur = yrow(yt, y0, tb - 1), y1 = yrow(yt, y0, tb - 2), y2 = yrow(yt, y0, tb - 3), y3 = y2;
+    int t0 = tb;   // at least one group: the march has at least 6 steps
+    do {
+        unroll<0, MAHEAD>([&](auto I) {
+            constexpr int i = decltype(I)::v;
+            const int t = t0 + i;
+            a3 = a2;
+            a2 = a1;
+            a1 = a0;
+            a0 = ok(t) ? qs * cvt<T>(pf[i].f) : Z;
+            if constexpr (NZ) {
+                w3 = w2;
+                w2 = w1;
+                w1 = w0;
+                w0 = mk<T>(pin(pf[i].w.r), pin(pf[i].w.i));
+            }
+            dd3 = dd2;
+            dd2 = dd1;
+            dd1 = dd0;
+            const YC<T> yn = yrow(yt, y0, t);
+            dd0 = row_diag(L, c, yn, pin(pf[i].k2));
+            __builtin_amdgcn_sched_barrier(0);   // the ring slot is consumed before it is reloaded
+            load_f<T, TQ, NZ>(pf[i], L, c, src, up, t + MAHEAD);
+            y3 = y2;
+            y2 = y1;
+            y1 = ycur;
+            ycur = yn;
+            cx<T> v = row_apply<T>(c, y1, dd1, a2, a1, a0);
+            b3 = b2;
+            b2 = b1;
+            b1 = ok(t - 1) ? L.sinv * v : Z;
+            v = row_apply<T>(c, y2, dd2, b3, b2, b1);
+            c4 = c3;
+            c3 = c2;
+            c2 = ok(t - 2) ? L.sinv * v : Z;
+            v = row_apply<T>(c, y3, dd3, c4, c3, c2);
+            const int yr = t - 3;
+            const bool m3 = ok(yr);
+            const cx<T> q3 = m3 ? L.sinv * v : Z;
+            r5 = r4;
+            r4 = r3;
+            r3 = m3 ? a3 + c1 * b3 + cc2 * c3 + cc3 * q3 : Z;
+            if (c.own && yr >= y0 && yr < yend) {
+                cx<T> u = L.sinv * (c1 * a3 + cc2 * b3 + cc3 * c3);
+                if constexpr (NZ) u = w3 - u;
+                else u = Z - u;
+                u1p[(long long)yr * nx + c.gx] = u;
+            }
+            const int yc = yr - 1;
+            const cx<T> vv = T(0.25) * r5 + T(0.5) * r4 + T(0.25) * r3;
+            const cx<T> vl = shfl_up1(vv), vr = shfl_dn1(vv);
+            if ((yc & 1) && yc >= y0 && yc < yend && (yc - 1) / 2 < ncy && ccol) {
+                const int C = (yc - 1) / 2, Cx = (c.gx - 1) / 2;
+                fc[(long long)C * ncx + Cx] = T(0.25) * vl + T(0.5) * vv + T(0.25) * vr;
+            }
+        });
+        t0 += MAHEAD;
+    } while (t0 < tn);
 }
 
 // ---------------------------------------------------------------------------
@@ -428,6 +624,7 @@ __global__ void __launch_bounds__(MW) k_mg_apply_restrict(const CycleArgs a) {
 // ---------------------------------------------------------------------------
 template <typename T, typename TF, typename TO, bool ACC, int TY>
 __global__ void __launch_bounds__(MW) k_mg_apply_out(const CycleArgs a) {
+    static_assert(TY % 2 == 0 && MAHEAD % 2 == 0 && TY + MAHEAD + 11 <= MW, "strip geometry");
     const int pid = xcd_remap(blockIdx.x, gridDim.x);
     const int slot = find_slot(a.st.s, a.st.n, pid);
     const CycleSlot& sl = a.st.s[slot];
@@ -441,59 +638,91 @@ __global__ void __launch_bounds__(MW) k_mg_apply_out(const CycleArgs a) {
     const int tile = pid - sl.tile0;
     const int x0 = (tile % ntx) * MTX, y0 = (tile / ntx) * TY;
     const Lane<T> c = lane_of(L, x0);
+    const YC<T> yt = ytab_of(L, y0);
     InterpX<T> ix;
-    interp_axis<T>(c.colv ? c.gx : 0, Lc.n[0], ix.i0, ix.i1, ix.w0, ix.w1);
+    interp_axis<T>(c.gxc, Lc.n[0], ix.i0, ix.i1, ix.w0, ix.w1);
     const T fs = (T)fscale_of(sl);
-    const cx<T>* u1 = static_cast<const cx<T>*>(B.u1);
-    const cx<T>* e = static_cast<const cx<T>*>(sl.c);
+    const auto u1 = gin(static_cast<const cx<T>*>(B.u1));
+    const auto ev = gin(static_cast<const cx<T>*>(sl.c));
+    const auto fv = gin(static_cast<const cx<TF>*>(sl.f));
     const auto out = gout(static_cast<cx<TO>*>(sl.out));
+    const auto outr = gin(static_cast<const cx<TO>*>(sl.out));
     const cx<T> c1 = cvt<T>(B.coef[4]), cc2 = cvt<T>(B.coef[5]), cc3 = cvt<T>(B.coef[6]);
     const cx<T> Z = mk<T>(0, 0);
     const int yend = imin(y0 + TY, ny);
+    auto ok = [&](int y) { return c.colv && rowv(L, y); };
 
     cx<T> a0 = Z, a1 = Z, a2 = Z, a3 = Z;
     cx<T> b1 = Z, b2 = Z, b3 = Z;
     cx<T> c2 = Z, c3 = Z, c4 = Z;
     cx<T> fprev = Z;
-    T k0 = 0, k1 = 0, kk2 = 0, k3 = 0;
-    RowIn<T, TF> cur, n1;
-    load_row<T, TF, true, false>(cur, L, Lc, c, ix, u1, e, sl.f, y0 - 3);
-    for (int t = y0 - 3; t < yend + 3; ++t) {
-        load_row<T, TF, true, false>(n1, L, Lc, c, ix, u1, e, sl.f, t + 1);
-        a3 = a2;
-        a2 = a1;
-        a1 = a0;
-        a0 = u2_of(cur, ix);
-        k3 = kk2;
-        kk2 = k1;
-        k1 = k0;
-        k0 = cur.k2;
-        const bool m1 = c.colv && rowv(L, t - 1);
-        cx<T> v = row_apply<T>(L, c, a2, a1, a0, t - 1, k1);
-        b3 = b2;
-        b2 = b1;
-        b1 = m1 ? fprev - v : Z;
-        fprev = fs * cvt<T>(cur.f);
-        v = row_apply<T>(L, c, b3, b2, b1, t - 2, kk2);
-        c4 = c3;
-        c3 = c2;
-        c2 = (c.colv && rowv(L, t - 2)) ? L.sinv * v : Z;
-        v = row_apply<T>(L, c, c4, c3, c2, t - 3, k3);
-        const int yr = t - 3;
-        if (c.own && yr >= y0 && yr < yend) {
-            const long long gi = (long long)yr * nx + c.gx;
-            const cx<T> q2 = L.sinv * v;
-            const cx<T> w = a3 - L.sinv * (c1 * b3 + cc2 * c3 + cc3 * q2);
-            if constexpr (ACC)
-                out[gi] = out[gi].get() + cvt<TO>(w);
-            else
-                out[gi] = cvt<TO>(w);
-        }
-        cur = n1;
-    }
+    cx<T> dd0 = Z, dd1 = Z, dd2 = Z, dd3 = Z;   // diagonals at rows t..t-3
+    const int tb = y0 - 3;
+    const int tn = tb + round_up(yend - y0 + 6, MAHEAD);
+    RowU<T, TF, TO> pf[MAHEAD];
+    CoarseRing<T, 1> cr;
+    RowC<T> r0;
+    cr.first(r0, Lc, ix, ev, tb);
+    unroll<0, MAHEAD>([&](auto I) {
+        constexpr int i = decltype(I)::v;
+        cr.template prime<i>(Lc, ix, ev, tb);
+        load_u<T, TF, TO>(pf[i], L, c, u1, fv, tb + i);
+        if constexpr (ACC) pf[i].o = outr[row_index(L, c, tb + i - 3)];
+        __builtin_amdgcn_sched_barrier(0);
+    });
+    cr.finish(r0, Lc, ix, tb);
+    YC<T> ycur = yrow(yt, y0, tb - 1), y1 = yrow(yt, y0, tb - 2), y2 = yrow(yt, y0, tb - 3), y3 = y2;
+    int t0 = tb;   // at least one group: the march has at least 6 steps
+    do {
+        unroll<0, MAHEAD>([&](auto I) {
+            constexpr int i = decltype(I)::v;
+            const int t = t0 + i;
+            const cx<T> ey = cr.template step<i>(Lc, ix, ev, t);
+            a3 = a2;
+            a2 = a1;
+            a1 = a0;
+            a0 = ok(t) ? pf[i].u + ey : Z;
+            dd3 = dd2;
+            dd2 = dd1;
+            dd1 = dd0;
+            const YC<T> yn = yrow(yt, y0, t);
+            dd0 = row_diag(L, c, yn, pin(pf[i].k2));
+            const cx<T> fnew = fs * cvt<T>(pf[i].f);
+            __builtin_amdgcn_sched_barrier(0);   // the ring slot is consumed before it is reloaded
+            load_u<T, TF, TO>(pf[i], L, c, u1, fv, t + MAHEAD);
+            y3 = y2;
+            y2 = y1;
+            y1 = ycur;
+            ycur = yn;
+            cx<T> v = row_apply<T>(c, y1, dd1, a2, a1, a0);
+            b3 = b2;
+            b2 = b1;
+            b1 = ok(t - 1) ? fprev - v : Z;
+            fprev = fnew;
+            v = row_apply<T>(c, y2, dd2, b3, b2, b1);
+            c4 = c3;
+            c3 = c2;
+            c2 = ok(t - 2) ? L.sinv * v : Z;
+            v = row_apply<T>(c, y3, dd3, c4, c3, c2);
+            const int yr = t - 3;
+            if (c.own && yr >= y0 && yr < yend) {
+                const long long gi = (long long)yr * nx + c.gx;
+                const cx<T> q2 = L.sinv * v;
+                const cx<T> w = a3 - L.sinv * (c1 * b3 + cc2 * c3 + cc3 * q2);
+                if constexpr (ACC)
+                    out[gi] = pf[i].o + cvt<TO>(w);
+                else
+                    out[gi] = cvt<TO>(w);
+            }
+            __builtin_amdgcn_sched_barrier(0);   // the ring slot is consumed before it is reloaded
+            if constexpr (ACC) pf[i].o = outr[row_index(L, c, t + MAHEAD - 3)];
+        });
+        t0 += MAHEAD;
+    } while (t0 < tn);
 }
 
 }  // namespace
+
 
 // ---------------------------------------------------------------------------
 // Geometry and launchers
