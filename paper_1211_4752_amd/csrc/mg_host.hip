@@ -2015,6 +2015,9 @@ mg_status setup(const mg_params* p, const double* k2_dev, void* stream, mg_ctx* 
             if (c->lv[l].N <= mg::SMALL_POINTS || l == L - 1) small += c->lv[l].N;
         if (c->lv[c->lt].N > mg::TAIL_POINTS || small > mg::TAIL_LDS || c->lv[L - 1].N > mg::SMALL_POINTS)
             return MG_E_INVAL;
+        // only the first tail level may keep its vectors in global memory
+        for (int l = c->lt + 1; l < L; ++l)
+            if (c->lv[l].N > mg::SMALL_POINTS) return MG_E_INVAL;
     }
     {
         CKS(dalloc(&c->gcoef, (size_t)c->nrhs * L * 8 * sizeof(cx<double>)));

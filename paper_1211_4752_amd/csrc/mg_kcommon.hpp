@@ -126,10 +126,31 @@ __device__ __forceinline__ int xcd_remap(int pid, int num) {
     return xcd * per + (xcd < extra ? xcd : extra) + local;
 }
 
+// v of the lane that DPP control CTRL selects (rows outside ROWMASK get 0).
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ double dpp_f64(double v) {
+    const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b & 0xffffffffull), CTRL, ROWMASK, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), CTRL, ROWMASK, 0xF, false);
+    return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+}
+
+// Sum over the 64 lanes of a wavefront (every lane active), returned to
+// every lane, in a fixed order.  All on the VALU through DPP (no LDS
+// permutes, which the waves of a CU would share): quad swaps, half-row and
+// row mirrors give each 16-lane row its sum, the two row broadcasts carry
+// the row sums into lane 63, which is read back.
 __device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
+    v += dpp_f64<0xB1, 0xF>(v);    // quad_perm [1,0,3,2]
+    v += dpp_f64<0x4E, 0xF>(v);    // quad_perm [2,3,0,1]
+    v += dpp_f64<0x141, 0xF>(v);   // row_half_mirror
+    v += dpp_f64<0x140, 0xF>(v);   // row_mirror
+    v += dpp_f64<0x142, 0xA>(v);   // row_bcast:15 into rows 1, 3
+    v += dpp_f64<0x143, 0xC>(v);   // row_bcast:31 into rows 2, 3
+    const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+    const int lo = __builtin_amdgcn_readlane((int)(unsigned)(b & 0xffffffffull), 63);
+    const int hi = __builtin_amdgcn_readlane((int)(unsigned)(b >> 32), 63);
+    return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
 }
 
 // Deterministic workgroup sum; the result is valid in thread 0.  sm holds
