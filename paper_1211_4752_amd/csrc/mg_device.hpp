@@ -309,6 +309,9 @@ hipError_t launch_prolong_smooth(int dim, bool f32, bool level0, bool zero, bool
 // Plane-sweep variants of the two omega-Jacobi kernels for a zero incoming
 // iterate (mg_jacobi.hip): sweep configuration ids 0 .. NUM_SWEEP_SHAPES - 1.
 constexpr int NUM_SWEEP_SHAPES = 3;
+// Row-marching strips of the 2D GMRES(3) passes (mg_march2d.hip): shape ids
+// 0 .. NUM_MARCH_SHAPES - 1.
+constexpr int NUM_MARCH_SHAPES = 4;
 void sweep_counts(int dim, int sweep, const int n[3], int ntiles[3]);
 hipError_t launch_sweep_sr(int dim, bool f32, bool level0, int sweep, const CycleArgs& a, hipStream_t s);
 hipError_t launch_sweep_ps(int dim, bool f32, bool level0, bool accumulate, int sweep, const CycleArgs& a,

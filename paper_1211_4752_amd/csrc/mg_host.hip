@@ -549,9 +549,13 @@ int launch_shape(const std::vector<Item>& it, const std::vector<int>& who, int d
     return shape;
 }
 
-// Shape ids of a context: the tile shapes, then (omega-Jacobi only) the
-// plane-sweep configurations of the zero-guess fused kernels.
-int num_shapes(const mg_ctx* c) { return mg::NUM_TILE_SHAPES + (c->gsmooth ? 0 : mg::NUM_SWEEP_SHAPES); }
+// Shape ids of a context: omega-Jacobi: the tile shapes, then the
+// plane-sweep configurations of the zero-guess fused kernels; GMRES(3): the
+// row-marching strips (2D) or the tile shapes (3D).
+int num_shapes(const mg_ctx* c) {
+    if (c->gsmooth) return c->dim == 2 ? mg::NUM_MARCH_SHAPES : mg::NUM_TILE_SHAPES;
+    return mg::NUM_TILE_SHAPES + mg::NUM_SWEEP_SHAPES;
+}
 
 // Sweep configuration of an omega-Jacobi launch (-1: tiles) and its tile
 // shape; the sweeps serve the zero-guess kernels only.
@@ -1825,11 +1829,13 @@ int max_blocks(const mg_ctx* c) {
         int nt[3];
         mg::tile_counts(c->dim, shape, c->lv[0].n, nt);
         m = std::max(m, nt[0] * nt[1] * nt[2]);
-        if (c->dim == 2) {
+    }
+    if (c->dim == 2)
+        for (int shape = 0; shape < mg::NUM_MARCH_SHAPES; ++shape) {
+            int nt[3];
             mg::march_counts(shape, c->lv[0].n, nt);
             m = std::max(m, nt[0] * nt[1]);
         }
-    }
     for (int sweep = 0; sweep < mg::NUM_SWEEP_SHAPES; ++sweep) {
         int nt[3];
         mg::sweep_counts(c->dim, sweep, c->lv[0].n, nt);

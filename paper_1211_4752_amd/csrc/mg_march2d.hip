@@ -728,11 +728,11 @@ __global__ void __launch_bounds__(MW) k_mg_apply_out(const CycleArgs a) {
 // Geometry and launchers
 // ---------------------------------------------------------------------------
 namespace {
-constexpr int MARCH_TY[NUM_TILE_SHAPES] = {32, 16, 8};
+constexpr int MARCH_TY[NUM_MARCH_SHAPES] = {32, 16, 8, 4};
 }
 
 void march_counts(int shape, const int n[3], int nt[3]) {
-    if (shape < 0 || shape >= NUM_TILE_SHAPES) shape = 0;
+    if (shape < 0 || shape >= NUM_MARCH_SHAPES) shape = 0;
     nt[0] = (n[0] + MTX - 1) / MTX;
     nt[1] = (n[1] + MARCH_TY[shape] - 1) / MARCH_TY[shape];
     nt[2] = 1;
@@ -742,6 +742,7 @@ void march_counts(int shape, const int n[3], int nt[3]) {
     switch (shape) {                    \
         case 1: LAUNCH(16); break;      \
         case 2: LAUNCH(8); break;       \
+        case 3: LAUNCH(4); break;       \
         default: LAUNCH(32); break;     \
     }
 
