@@ -336,6 +336,13 @@ __device__ __forceinline__ void unroll(F&& f) {
 
 __device__ __forceinline__ int round_up(int v, int m) { return (v + m - 1) / m * m; }
 
+// Register rings of the march: a value produced at step t sits in slot
+// (t - tb) mod MAHEAD, so in a group of MAHEAD unrolled steps every slot
+// index is static and the rotating rows need no register moves.  RI<I, K>:
+// slot of the value produced K steps before step I of the group.
+template <int I, int K>
+constexpr int RI = ((I - K) % MAHEAD + MAHEAD) % MAHEAD;
+
 template <typename T, typename TQ>
 __device__ __forceinline__ GIn<cx<TQ>> q0_source(const CycleSlot& sl, const SmoothBufs& B) {
     // The q0 buffer (sl.f null: level 0 with an incoming iterate) is FP64,
@@ -382,13 +389,14 @@ __global__ void __launch_bounds__(MW) k_mg_gram(const CycleArgs a, cx<double>* p
         const auto u1 = gin(static_cast<const cx<T>*>(B.u1));
         const auto ev = gin(static_cast<const cx<T>*>(sl.c));
         const auto fv = gin(static_cast<const cx<TQ>*>(sl.f));
-        // u2 rows t, t-1, t-2; q0 rows t-1..t-4; q1 rows t-2..t-4; q2 rows t-3..t-5
-        cx<T> a0 = Z, a1 = Z, a2 = Z;
-        cx<T> b1 = Z, b2 = Z, b3 = Z, b4 = Z;
-        cx<T> c2 = Z, c3 = Z, c4 = Z;
-        cx<T> d3 = Z, d4 = Z, d5 = Z;
-        cx<T> fprev = Z;
-        cx<T> dd0 = Z, dd1 = Z, dd2 = Z, dd3 = Z, dd4 = Z;   // diagonals at rows t..t-4
+        // rings by producing step: u2 of row s (A), fscale f of row s (F), q0 of
+        // row s-1 (Bq), q1 of row s-2 (Cq), q2 of row s-3 (Dq), diagonal and
+        // y coefficients of row s (DD, Y); the diagonal and y coefficients of
+        // row t-4 are taken out of their slot before row t replaces them
+        cx<T> A[MAHEAD], F[MAHEAD], Bq[MAHEAD], Cq[MAHEAD], Dq[MAHEAD], DD[MAHEAD];
+        YC<T> Y[MAHEAD];
+#pragma unroll
+        for (int k = 0; k < MAHEAD; ++k) A[k] = F[k] = Bq[k] = Cq[k] = Dq[k] = DD[k] = Z;
         const int tb = y0 - 4;
         const int tn = tb + round_up(yend - y0 + 8, MAHEAD);
         RowU<T, TQ, T> pf[MAHEAD];
@@ -402,59 +410,44 @@ __global__ void __launch_bounds__(MW) k_mg_gram(const CycleArgs a, cx<double>* p
             __builtin_amdgcn_sched_barrier(0);
         });
         cr.finish(r0, Lc, ix, tb);
-        YC<T> ycur = yrow(yt, y0, tb - 1), y1 = yrow(yt, y0, tb - 2), y2 = yrow(yt, y0, tb - 3), y3 = yrow(yt, y0, tb - 4), y4 = y3;
+#pragma unroll
+        for (int k = 0; k < MAHEAD; ++k) Y[k] = yrow(yt, y0, tb - MAHEAD + k);
         int t0 = tb;   // at least one group: the march has at least 6 steps
         do {
             unroll<0, MAHEAD>([&](auto I) {
                 constexpr int i = decltype(I)::v;
                 const int t = t0 + i;
                 const cx<T> ey = cr.template step<i>(Lc, ix, ev, t);
-                a2 = a1;
-                a1 = a0;
-                a0 = ok(t) ? pf[i].u + ey : Z;
-                dd4 = dd3;
-                dd3 = dd2;
-                dd2 = dd1;
-                dd1 = dd0;
-                const YC<T> yn = yrow(yt, y0, t);
-                dd0 = row_diag(L, c, yn, pin(pf[i].k2));
-                const cx<T> fnew = fs * cvt<T>(pf[i].f);
+                A[RI<i, 0>] = ok(t) ? pf[i].u + ey : Z;
+                const cx<T> dd4 = DD[RI<i, 0>];
+                const YC<T> y4 = Y[RI<i, 0>];
+                Y[RI<i, 0>] = yrow(yt, y0, t);
+                DD[RI<i, 0>] = row_diag(L, c, Y[RI<i, 0>], pin(pf[i].k2));
+                F[RI<i, 0>] = fs * cvt<T>(pf[i].f);
                 __builtin_amdgcn_sched_barrier(0);   // the ring slot is consumed before it is reloaded
                 load_u<T, TQ, T>(pf[i], L, c, u1, fv, t + MAHEAD);
-                y4 = y3;
-                y3 = y2;
-                y2 = y1;
-                y1 = ycur;
-                ycur = yn;
-                cx<T> v = row_apply<T>(c, y1, dd1, a2, a1, a0);
-                b4 = b3;
-                b3 = b2;
-                b2 = b1;
-                b1 = ok(t - 1) ? fprev - v : Z;
-                fprev = fnew;
-                v = row_apply<T>(c, y2, dd2, b3, b2, b1);
-                c4 = c3;
-                c3 = c2;
-                c2 = ok(t - 2) ? L.sinv * v : Z;
-                v = row_apply<T>(c, y3, dd3, c4, c3, c2);
-                d5 = d4;
-                d4 = d3;
-                d3 = ok(t - 3) ? L.sinv * v : Z;
-                v = row_apply<T>(c, y4, dd4, d5, d4, d3);
+                cx<T> v = row_apply<T>(c, Y[RI<i, 1>], DD[RI<i, 1>], A[RI<i, 2>], A[RI<i, 1>], A[RI<i, 0>]);
+                Bq[RI<i, 0>] = ok(t - 1) ? F[RI<i, 1>] - v : Z;
+                v = row_apply<T>(c, Y[RI<i, 2>], DD[RI<i, 2>], Bq[RI<i, 2>], Bq[RI<i, 1>], Bq[RI<i, 0>]);
+                Cq[RI<i, 0>] = ok(t - 2) ? L.sinv * v : Z;
+                v = row_apply<T>(c, Y[RI<i, 3>], DD[RI<i, 3>], Cq[RI<i, 2>], Cq[RI<i, 1>], Cq[RI<i, 0>]);
+                Dq[RI<i, 0>] = ok(t - 3) ? L.sinv * v : Z;
+                v = row_apply<T>(c, y4, dd4, Dq[RI<i, 2>], Dq[RI<i, 1>], Dq[RI<i, 0>]);
                 const int yr = t - 4;
-                if (c.own && yr >= y0 && yr < yend) gram_add<T>(g, b4, c4, d4, L.sinv * v);
+                if (c.own && yr >= y0 && yr < yend) gram_add<T>(g, Bq[RI<i, 3>], Cq[RI<i, 2>], Dq[RI<i, 1>], L.sinv * v);
             });
             t0 += MAHEAD;
         } while (t0 < tn);
     } else {
-        // q0 rows t..t-3; q1 rows t-1..t-3; q2 rows t-2..t-4
+        // rings by producing step: q0 of row s (A), q1 of row s-1 (Bq), q2 of
+        // row s-2 (Cq), diagonal and y coefficients of row s (DD, Y)
         const GIn<cx<TQ>> src = q0_source<T, TQ>(sl, B);
         const T qs = sl.f ? fs : T(1);
         const GIn<cx<T>> none{};
-        cx<T> a0 = Z, a1 = Z, a2 = Z, a3 = Z;
-        cx<T> b1 = Z, b2 = Z, b3 = Z;
-        cx<T> c2 = Z, c3 = Z, c4 = Z;
-        cx<T> dd0 = Z, dd1 = Z, dd2 = Z, dd3 = Z;   // diagonals at rows t..t-3
+        cx<T> A[MAHEAD], Bq[MAHEAD], Cq[MAHEAD], DD[MAHEAD];
+        YC<T> Y[MAHEAD];
+#pragma unroll
+        for (int k = 0; k < MAHEAD; ++k) A[k] = Bq[k] = Cq[k] = DD[k] = Z;
         const int tb = y0 - 3;
         const int tn = tb + round_up(yend - y0 + 6, MAHEAD);
         RowF<T, TQ> pf[MAHEAD];
@@ -463,38 +456,26 @@ __global__ void __launch_bounds__(MW) k_mg_gram(const CycleArgs a, cx<double>* p
             load_f<T, TQ, false>(pf[i], L, c, src, none, tb + i);
             __builtin_amdgcn_sched_barrier(0);
         }
-        YC<T> ycur = yrow(yt, y0, tb - 1), y1 = yrow(yt, y0, tb - 2), y2 = yrow(yt, y0, tb - 3), y3 = y2;
+#pragma unroll
+        for (int k = 0; k < MAHEAD; ++k) Y[k] = yrow(yt, y0, tb - MAHEAD + k);
         int t0 = tb;   // at least one group: the march has at least 6 steps
         do {
             unroll<0, MAHEAD>([&](auto I) {
                 constexpr int i = decltype(I)::v;
                 const int t = t0 + i;
-                a3 = a2;
-                a2 = a1;
-                a1 = a0;
-                a0 = ok(t) ? qs * cvt<T>(pf[i].f) : Z;
-                dd3 = dd2;
-                dd2 = dd1;
-                dd1 = dd0;
-                const YC<T> yn = yrow(yt, y0, t);
-                dd0 = row_diag(L, c, yn, pin(pf[i].k2));
+                A[RI<i, 0>] = ok(t) ? qs * cvt<T>(pf[i].f) : Z;
+                Y[RI<i, 0>] = yrow(yt, y0, t);
+                DD[RI<i, 0>] = row_diag(L, c, Y[RI<i, 0>], pin(pf[i].k2));
                 __builtin_amdgcn_sched_barrier(0);   // the ring slot is consumed before it is reloaded
                 load_f<T, TQ, false>(pf[i], L, c, src, none, t + MAHEAD);
-                y3 = y2;
-                y2 = y1;
-                y1 = ycur;
-                ycur = yn;
-                cx<T> v = row_apply<T>(c, y1, dd1, a2, a1, a0);
-                b3 = b2;
-                b2 = b1;
-                b1 = ok(t - 1) ? L.sinv * v : Z;
-                v = row_apply<T>(c, y2, dd2, b3, b2, b1);
-                c4 = c3;
-                c3 = c2;
-                c2 = ok(t - 2) ? L.sinv * v : Z;
-                v = row_apply<T>(c, y3, dd3, c4, c3, c2);
+                cx<T> v = row_apply<T>(c, Y[RI<i, 1>], DD[RI<i, 1>], A[RI<i, 2>], A[RI<i, 1>], A[RI<i, 0>]);
+                Bq[RI<i, 0>] = ok(t - 1) ? L.sinv * v : Z;
+                v = row_apply<T>(c, Y[RI<i, 2>], DD[RI<i, 2>], Bq[RI<i, 2>], Bq[RI<i, 1>], Bq[RI<i, 0>]);
+                Cq[RI<i, 0>] = ok(t - 2) ? L.sinv * v : Z;
+                v = row_apply<T>(c, Y[RI<i, 3>], DD[RI<i, 3>], Cq[RI<i, 2>], Cq[RI<i, 1>], Cq[RI<i, 0>]);
                 const int yr = t - 3;
-                if (c.own && yr >= y0 && yr < yend) gram_add<T>(g, a3, b3, c3, L.sinv * v);
+                if (c.own && yr >= y0 && yr < yend)
+                    gram_add<T>(g, A[RI<i, 3>], Bq[RI<i, 2>], Cq[RI<i, 1>], L.sinv * v);
             });
             t0 += MAHEAD;
         } while (t0 < tn);
@@ -544,12 +525,13 @@ __global__ void __launch_bounds__(MW) k_mg_apply_restrict(const CycleArgs a) {
     const bool ccol = c.own && (c.gx & 1) && (c.gx - 1) / 2 < ncx;
     auto ok = [&](int y) { return c.colv && rowv(L, y); };
 
-    cx<T> a0 = Z, a1 = Z, a2 = Z, a3 = Z;
-    cx<T> b1 = Z, b2 = Z, b3 = Z;
-    cx<T> c2 = Z, c3 = Z, c4 = Z;
-    cx<T> r3 = Z, r4 = Z, r5 = Z;           // r1 at rows t-3, t-4, t-5
-    cx<T> w0 = Z, w1 = Z, w2 = Z, w3 = Z;   // incoming iterate at rows t..t-3 (NZ)
-    cx<T> dd0 = Z, dd1 = Z, dd2 = Z, dd3 = Z;   // diagonals at rows t..t-3
+    // rings by producing step: q0 and the incoming iterate of row s (A, W),
+    // q1 of row s-1 (Bq), q2 of row s-2 (Cq), r1 of row s-3 (Rr), diagonal
+    // and y coefficients of row s (DD, Y)
+    cx<T> A[MAHEAD], W[MAHEAD], Bq[MAHEAD], Cq[MAHEAD], Rr[MAHEAD], DD[MAHEAD];
+    YC<T> Y[MAHEAD];
+#pragma unroll
+    for (int k = 0; k < MAHEAD; ++k) A[k] = W[k] = Bq[k] = Cq[k] = Rr[k] = DD[k] = Z;
     const int tb = y0 - 3;
     const int tn = tb + round_up(yend - y0 + 7, MAHEAD);
     RowF<T, TQ> pf[MAHEAD];
@@ -558,60 +540,47 @@ __global__ void __launch_bounds__(MW) k_mg_apply_restrict(const CycleArgs a) {
         load_f<T, TQ, NZ>(pf[i], L, c, src, up, tb + i);
         __builtin_amdgcn_sched_barrier(0);
     }
-    YC<T> ycur = yrow(yt, y0, tb - 1), y1 = yrow(yt, y0, tb - 2), y2 = yrow(yt, y0, tb - 3), y3 = y2;
+#pragma unroll
+    for (int k = 0; k < MAHEAD; ++k) Y[k] = yrow(yt, y0, tb - MAHEAD + k);
     int t0 = tb;   // at least one group: the march has at least 6 steps
     do {
         unroll<0, MAHEAD>([&](auto I) {
             constexpr int i = decltype(I)::v;
             const int t = t0 + i;
-            a3 = a2;
-            a2 = a1;
-            a1 = a0;
-            a0 = ok(t) ? qs * cvt<T>(pf[i].f) : Z;
-            if constexpr (NZ) {
-                w3 = w2;
-                w2 = w1;
-                w1 = w0;
-                w0 = mk<T>(pin(pf[i].w.r), pin(pf[i].w.i));
-            }
-            dd3 = dd2;
-            dd2 = dd1;
-            dd1 = dd0;
-            const YC<T> yn = yrow(yt, y0, t);
-            dd0 = row_diag(L, c, yn, pin(pf[i].k2));
+            A[RI<i, 0>] = ok(t) ? qs * cvt<T>(pf[i].f) : Z;
+            if constexpr (NZ) W[RI<i, 0>] = mk<T>(pin(pf[i].w.r), pin(pf[i].w.i));
+            Y[RI<i, 0>] = yrow(yt, y0, t);
+            DD[RI<i, 0>] = row_diag(L, c, Y[RI<i, 0>], pin(pf[i].k2));
             __builtin_amdgcn_sched_barrier(0);   // the ring slot is consumed before it is reloaded
             load_f<T, TQ, NZ>(pf[i], L, c, src, up, t + MAHEAD);
-            y3 = y2;
-            y2 = y1;
-            y1 = ycur;
-            ycur = yn;
-            cx<T> v = row_apply<T>(c, y1, dd1, a2, a1, a0);
-            b3 = b2;
-            b2 = b1;
-            b1 = ok(t - 1) ? L.sinv * v : Z;
-            v = row_apply<T>(c, y2, dd2, b3, b2, b1);
-            c4 = c3;
-            c3 = c2;
-            c2 = ok(t - 2) ? L.sinv * v : Z;
-            v = row_apply<T>(c, y3, dd3, c4, c3, c2);
+            cx<T> v = row_apply<T>(c, Y[RI<i, 1>], DD[RI<i, 1>], A[RI<i, 2>], A[RI<i, 1>], A[RI<i, 0>]);
+            Bq[RI<i, 0>] = ok(t - 1) ? L.sinv * v : Z;
+            v = row_apply<T>(c, Y[RI<i, 2>], DD[RI<i, 2>], Bq[RI<i, 2>], Bq[RI<i, 1>], Bq[RI<i, 0>]);
+            Cq[RI<i, 0>] = ok(t - 2) ? L.sinv * v : Z;
+            v = row_apply<T>(c, Y[RI<i, 3>], DD[RI<i, 3>], Cq[RI<i, 2>], Cq[RI<i, 1>], Cq[RI<i, 0>]);
+            // row t - 3: its q0, q1, q2 are A[RI<i, 3>], Bq[RI<i, 2>], Cq[RI<i, 1>]
             const int yr = t - 3;
             const bool m3 = ok(yr);
+            const cx<T> q0 = A[RI<i, 3>], q1 = Bq[RI<i, 2>], q2 = Cq[RI<i, 1>];
             const cx<T> q3 = m3 ? L.sinv * v : Z;
-            r5 = r4;
-            r4 = r3;
-            r3 = m3 ? a3 + c1 * b3 + cc2 * c3 + cc3 * q3 : Z;
+            Rr[RI<i, 0>] = m3 ? q0 + c1 * q1 + cc2 * q2 + cc3 * q3 : Z;
             if (c.own && yr >= y0 && yr < yend) {
-                cx<T> u = L.sinv * (c1 * a3 + cc2 * b3 + cc3 * c3);
-                if constexpr (NZ) u = w3 - u;
+                cx<T> u = L.sinv * (c1 * q0 + cc2 * q1 + cc3 * q2);
+                if constexpr (NZ) u = W[RI<i, 3>] - u;
                 else u = Z - u;
                 u1p[(long long)yr * nx + c.gx] = u;
             }
-            const int yc = yr - 1;
-            const cx<T> vv = T(0.25) * r5 + T(0.5) * r4 + T(0.25) * r3;
-            const cx<T> vl = shfl_up1(vv), vr = shfl_dn1(vv);
-            if ((yc & 1) && yc >= y0 && yc < yend && (yc - 1) / 2 < ncy && ccol) {
-                const int C = (yc - 1) / 2, Cx = (c.gx - 1) / 2;
-                fc[(long long)C * ncx + Cx] = T(0.25) * vl + T(0.5) * vv + T(0.25) * vr;
+            // the coarse row centred at fine row t - 4 exists when that row is
+            // odd: at the even steps of a group (strips start at even rows,
+            // so every group starts at an odd t)
+            if constexpr ((i & 1) == 0) {
+                const int yc = yr - 1;
+                const cx<T> vv = T(0.25) * Rr[RI<i, 2>] + T(0.5) * Rr[RI<i, 1>] + T(0.25) * Rr[RI<i, 0>];
+                const cx<T> vl = shfl_up1(vv), vr = shfl_dn1(vv);
+                if (yc >= y0 && yc < yend && (yc - 1) / 2 < ncy && ccol) {
+                    const int C = (yc - 1) / 2, Cx = (c.gx - 1) / 2;
+                    fc[(long long)C * ncx + Cx] = T(0.25) * vl + T(0.5) * vv + T(0.25) * vr;
+                }
             }
         });
         t0 += MAHEAD;
@@ -652,11 +621,13 @@ __global__ void __launch_bounds__(MW) k_mg_apply_out(const CycleArgs a) {
     const int yend = imin(y0 + TY, ny);
     auto ok = [&](int y) { return c.colv && rowv(L, y); };
 
-    cx<T> a0 = Z, a1 = Z, a2 = Z, a3 = Z;
-    cx<T> b1 = Z, b2 = Z, b3 = Z;
-    cx<T> c2 = Z, c3 = Z, c4 = Z;
-    cx<T> fprev = Z;
-    cx<T> dd0 = Z, dd1 = Z, dd2 = Z, dd3 = Z;   // diagonals at rows t..t-3
+    // rings by producing step: u2 and fscale f of row s (A, F), q0 of row
+    // s-1 (Bq), q1 of row s-2 (Cq), diagonal and y coefficients of row s
+    // (DD, Y)
+    cx<T> A[MAHEAD], F[MAHEAD], Bq[MAHEAD], Cq[MAHEAD], DD[MAHEAD];
+    YC<T> Y[MAHEAD];
+#pragma unroll
+    for (int k = 0; k < MAHEAD; ++k) A[k] = F[k] = Bq[k] = Cq[k] = DD[k] = Z;
     const int tb = y0 - 3;
     const int tn = tb + round_up(yend - y0 + 6, MAHEAD);
     RowU<T, TF, TO> pf[MAHEAD];
@@ -671,44 +642,30 @@ __global__ void __launch_bounds__(MW) k_mg_apply_out(const CycleArgs a) {
         __builtin_amdgcn_sched_barrier(0);
     });
     cr.finish(r0, Lc, ix, tb);
-    YC<T> ycur = yrow(yt, y0, tb - 1), y1 = yrow(yt, y0, tb - 2), y2 = yrow(yt, y0, tb - 3), y3 = y2;
+#pragma unroll
+    for (int k = 0; k < MAHEAD; ++k) Y[k] = yrow(yt, y0, tb - MAHEAD + k);
     int t0 = tb;   // at least one group: the march has at least 6 steps
     do {
         unroll<0, MAHEAD>([&](auto I) {
             constexpr int i = decltype(I)::v;
             const int t = t0 + i;
             const cx<T> ey = cr.template step<i>(Lc, ix, ev, t);
-            a3 = a2;
-            a2 = a1;
-            a1 = a0;
-            a0 = ok(t) ? pf[i].u + ey : Z;
-            dd3 = dd2;
-            dd2 = dd1;
-            dd1 = dd0;
-            const YC<T> yn = yrow(yt, y0, t);
-            dd0 = row_diag(L, c, yn, pin(pf[i].k2));
-            const cx<T> fnew = fs * cvt<T>(pf[i].f);
+            A[RI<i, 0>] = ok(t) ? pf[i].u + ey : Z;
+            Y[RI<i, 0>] = yrow(yt, y0, t);
+            DD[RI<i, 0>] = row_diag(L, c, Y[RI<i, 0>], pin(pf[i].k2));
+            F[RI<i, 0>] = fs * cvt<T>(pf[i].f);
             __builtin_amdgcn_sched_barrier(0);   // the ring slot is consumed before it is reloaded
             load_u<T, TF, TO>(pf[i], L, c, u1, fv, t + MAHEAD);
-            y3 = y2;
-            y2 = y1;
-            y1 = ycur;
-            ycur = yn;
-            cx<T> v = row_apply<T>(c, y1, dd1, a2, a1, a0);
-            b3 = b2;
-            b2 = b1;
-            b1 = ok(t - 1) ? fprev - v : Z;
-            fprev = fnew;
-            v = row_apply<T>(c, y2, dd2, b3, b2, b1);
-            c4 = c3;
-            c3 = c2;
-            c2 = ok(t - 2) ? L.sinv * v : Z;
-            v = row_apply<T>(c, y3, dd3, c4, c3, c2);
+            cx<T> v = row_apply<T>(c, Y[RI<i, 1>], DD[RI<i, 1>], A[RI<i, 2>], A[RI<i, 1>], A[RI<i, 0>]);
+            Bq[RI<i, 0>] = ok(t - 1) ? F[RI<i, 1>] - v : Z;
+            v = row_apply<T>(c, Y[RI<i, 2>], DD[RI<i, 2>], Bq[RI<i, 2>], Bq[RI<i, 1>], Bq[RI<i, 0>]);
+            Cq[RI<i, 0>] = ok(t - 2) ? L.sinv * v : Z;
+            v = row_apply<T>(c, Y[RI<i, 3>], DD[RI<i, 3>], Cq[RI<i, 2>], Cq[RI<i, 1>], Cq[RI<i, 0>]);
             const int yr = t - 3;
             if (c.own && yr >= y0 && yr < yend) {
                 const long long gi = (long long)yr * nx + c.gx;
                 const cx<T> q2 = L.sinv * v;
-                const cx<T> w = a3 - L.sinv * (c1 * b3 + cc2 * c3 + cc3 * q2);
+                const cx<T> w = A[RI<i, 3>] - L.sinv * (c1 * Bq[RI<i, 2>] + cc2 * Cq[RI<i, 1>] + cc3 * q2);
                 if constexpr (ACC)
                     out[gi] = pf[i].o + cvt<TO>(w);
                 else
