@@ -37,7 +37,7 @@ namespace {
 
 using mg::HSTRIDE;
 using mg::MAX_RESTART;
-constexpr long long AUTOTUNE_MIN_POINTS = 4096;
+constexpr long long AUTOTUNE_MIN_POINTS = 1024;
 
 #define CK(expr)                                        \
     do {                                                \
@@ -1786,7 +1786,11 @@ mg_status autotune(mg_ctx* c) {
     hipEvent_t e0, e1;
     CK(hipEventCreate(&e0));
     CK(hipEventCreate(&e1));
-    Exec E{c->stream, nullptr, nullptr, false};
+    // the level's passes replayed as a graph (as the cycle runs them), so
+    // that the comparison of shapes on small levels is not one of host
+    // launch overheads: one replay to warm up, then REPS timed back to back
+    constexpr int REPS = 6;
+    Exec E{c->stream, nullptr, &c->cache, true};
     mg_status st = MG_OK;
     for (int l = 0; l < c->lt && st == MG_OK; ++l) {
         if (c->lv[l].N < AUTOTUNE_MIN_POINTS) break;
@@ -1798,16 +1802,13 @@ mg_status autotune(mg_ctx* c) {
             Rec R{&op, &c->work, c->dim, c->mixed, TAG_ALWAYS};
             st = rec_down(R, 0, it, G_NONE, &l0, l, false, nullptr);
             if (st == MG_OK) st = rec_up(R, 0, it, G_NONE, &l0, l, false);
+            if (st == MG_OK) st = op_run(E, op);
+            if (st == MG_OK && hipEventRecord(e0, c->stream) != hipSuccess) st = MG_E_DEVICE;
+            for (int rep = 0; rep < REPS && st == MG_OK; ++rep) st = op_run(E, op);
+            if (st == MG_OK && hipEventRecord(e1, c->stream) != hipSuccess) st = MG_E_DEVICE;
+            if (st == MG_OK && hipEventSynchronize(e1) != hipSuccess) st = MG_E_DEVICE;
             float tot = 0.0f;
-            for (int rep = 0; rep < 4 && st == MG_OK; ++rep) {
-                if (hipEventRecord(e0, c->stream) != hipSuccess) st = MG_E_DEVICE;
-                if (st == MG_OK) st = op_run(E, op);
-                if (st == MG_OK && hipEventRecord(e1, c->stream) != hipSuccess) st = MG_E_DEVICE;
-                if (st == MG_OK && hipEventSynchronize(e1) != hipSuccess) st = MG_E_DEVICE;
-                float ms = 0.0f;
-                if (st == MG_OK && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) st = MG_E_DEVICE;
-                if (rep > 0) tot += ms;
-            }
+            if (st == MG_OK && hipEventElapsedTime(&tot, e0, e1) != hipSuccess) st = MG_E_DEVICE;
             op_release(op);
             if (tot < best) {
                 best = tot;
@@ -2009,9 +2010,12 @@ mg_status setup(const mg_params* p, const double* k2_dev, void* stream, mg_ctx* 
     }
     c->gsmooth = p->smoother == MG_SMOOTH_GMRES3;
     // coarse tail: from the first level >= 1 with at most TAIL_POINTS points
+    // (2D GMRES(3): SMALL_POINTS, the marching passes being faster than the
+    // tail's global-memory level)
     c->lt = L - 1;
+    const long long tail_max = (c->gsmooth && c->dim == 2) ? mg::SMALL_POINTS : mg::TAIL_POINTS;
     for (int l = 1; l < L; ++l)
-        if (c->lv[l].N <= mg::TAIL_POINTS) {
+        if (c->lv[l].N <= tail_max) {
             c->lt = l;
             break;
         }
