@@ -193,7 +193,9 @@ mg_status mg_apply(mg_ctx *c, int level, int adjoint, const double *x_dev,
 /* Tile shape of the cycle kernels on one level.  Shape ids 0, 1, 2 are
  * 64x16, 64x8, 128x8 (2D) and 16x8x4, 32x4x2, 16x4x4 (3D) for the
  * omega-Jacobi kernels and the 3D GMRES(3) kernels; 2D GMRES(3) contexts
- * take ids 0..3, strips of 56 columns by 32, 16, 8, 4 rows.  omega-Jacobi
+ * take ids 0..4: row-marching strips of 56 columns by 32, 16, 8, 4 rows,
+ * and (id 4) LDS tiles of 32x16 points that form the powers on a shrinking
+ * halo.  omega-Jacobi
  * contexts also take ids 3, 4, 5: plane sweeps of the zero-guess kernels
  * (2D: row segments of 256, 512, 256 points sweeping chunks of 16, 16, 32
  * rows with 320, 576, 320 threads; 3D: columns of 64x8, 32x8, 64x4 points

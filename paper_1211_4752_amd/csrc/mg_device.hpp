@@ -309,9 +309,10 @@ hipError_t launch_prolong_smooth(int dim, bool f32, bool level0, bool zero, bool
 // Plane-sweep variants of the two omega-Jacobi kernels for a zero incoming
 // iterate (mg_jacobi.hip): sweep configuration ids 0 .. NUM_SWEEP_SHAPES - 1.
 constexpr int NUM_SWEEP_SHAPES = 3;
-// Row-marching strips of the 2D GMRES(3) passes (mg_march2d.hip): shape ids
-// 0 .. NUM_MARCH_SHAPES - 1.
-constexpr int NUM_MARCH_SHAPES = 4;
+// Shapes of the 2D GMRES(3) passes: row-marching strips (mg_march2d.hip),
+// ids 0 .. MARCH_TILE - 1, and LDS tiles (mg_tile2d.hip), id MARCH_TILE.
+constexpr int MARCH_TILE = 4;
+constexpr int NUM_MARCH_SHAPES = 5;
 void sweep_counts(int dim, int sweep, const int n[3], int ntiles[3]);
 hipError_t launch_sweep_sr(int dim, bool f32, bool level0, int sweep, const CycleArgs& a, hipStream_t s);
 hipError_t launch_sweep_ps(int dim, bool f32, bool level0, bool accumulate, int sweep, const CycleArgs& a,
@@ -349,6 +350,11 @@ hipError_t launch_sm_apply_out(bool f32, bool level0, bool accumulate, const SmA
 // of 56 columns by 32, 16 or 8 rows (shape id 0, 1, 2); Gram partials per strip at
 // part[(slot * pstride + v) * bstride + tile].
 void march_counts(int shape, const int n[3], int ntiles[3]);
+void tile2d_counts(const int n[3], int ntiles[3]);
+hipError_t tile2d_gram(bool f32, bool level0, bool post, const CycleArgs& a, cx<double>* part, int pstride,
+                       int bstride, hipStream_t s);
+hipError_t tile2d_apply_restrict(bool f32, bool level0, bool nonzero, const CycleArgs& a, hipStream_t s);
+hipError_t tile2d_apply_out(bool f32, bool level0, bool accumulate, const CycleArgs& a, hipStream_t s);
 hipError_t launch_sm2_gram(bool f32, bool level0, bool post, int shape, const CycleArgs& a, cx<double>* part,
                            int pstride, int bstride, hipStream_t s);
 hipError_t launch_sm2_apply_restrict(bool f32, bool level0, bool nonzero, int shape, const CycleArgs& a,

@@ -685,11 +685,15 @@ __global__ void __launch_bounds__(MW) k_mg_apply_out(const CycleArgs a) {
 // Geometry and launchers
 // ---------------------------------------------------------------------------
 namespace {
-constexpr int MARCH_TY[NUM_MARCH_SHAPES] = {32, 16, 8, 4};
+constexpr int MARCH_TY[MARCH_TILE] = {32, 16, 8, 4};
 }
 
 void march_counts(int shape, const int n[3], int nt[3]) {
-    if (shape < 0 || shape >= NUM_MARCH_SHAPES) shape = 0;
+    if (shape == MARCH_TILE) {
+        tile2d_counts(n, nt);
+        return;
+    }
+    if (shape < 0 || shape >= MARCH_TILE) shape = 0;
     nt[0] = (n[0] + MTX - 1) / MTX;
     nt[1] = (n[1] + MARCH_TY[shape] - 1) / MARCH_TY[shape];
     nt[2] = 1;
@@ -716,6 +720,7 @@ static hipError_t mg_gram_launch(int shape, const CycleArgs& a, cx<double>* part
 hipError_t launch_sm2_gram(bool f32, bool level0, bool post, int shape, const CycleArgs& a, cx<double>* part,
                            int pstride, int bstride, hipStream_t s) {
     if (a.st.n <= 0) return hipSuccess;
+    if (shape == MARCH_TILE) return tile2d_gram(f32, level0, post, a, part, pstride, bstride, s);
     if (!f32)
         return post ? mg_gram_launch<double, double, true>(shape, a, part, pstride, bstride, s)
                     : mg_gram_launch<double, double, false>(shape, a, part, pstride, bstride, s);
@@ -737,6 +742,7 @@ static hipError_t mg_ar_launch(int shape, const CycleArgs& a, hipStream_t s) {
 hipError_t launch_sm2_apply_restrict(bool f32, bool level0, bool nonzero, int shape, const CycleArgs& a,
                                      hipStream_t s) {
     if (a.st.n <= 0) return hipSuccess;
+    if (shape == MARCH_TILE) return tile2d_apply_restrict(f32, level0, nonzero, a, s);
     if (!f32)
         return nonzero ? mg_ar_launch<double, double, true>(shape, a, s) : mg_ar_launch<double, double, false>(shape, a, s);
     if (nonzero) return hipErrorInvalidValue;
@@ -753,6 +759,7 @@ static hipError_t mg_ao_launch(int shape, const CycleArgs& a, hipStream_t s) {
 
 hipError_t launch_sm2_apply_out(bool f32, bool level0, bool accumulate, int shape, const CycleArgs& a, hipStream_t s) {
     if (a.st.n <= 0) return hipSuccess;
+    if (shape == MARCH_TILE) return tile2d_apply_out(f32, level0, accumulate, a, s);
     if (!f32)
         return accumulate ? mg_ao_launch<double, double, double, true>(shape, a, s)
                           : mg_ao_launch<double, double, double, false>(shape, a, s);

@@ -303,9 +303,9 @@ def test_full_size_cycle_and_fgmres_prefix():
 
 @pytest.mark.parametrize("precision", ["c128", "mixed"])
 def test_every_tile_shape(precision):
-    """The fused 2D smoothing passes under each strip shape id (32, 16, 8, 4
-    rows), on a grid with ragged tiles on every level (255 -> 127 -> ... ->
-    3); id 4 is refused."""
+    """The fused 2D smoothing passes under each shape id (row-marching strips
+    of 32, 16, 8, 4 rows; id 4: LDS tiles), on a grid with ragged tiles on
+    every level (255 -> 127 -> ... -> 3); id 5 is refused."""
     wl = W.heterogeneous_2d(255, 1)
     s = solver_of(wl, precision=precision)
     levels = H.build_hierarchy(problem_of(wl))
@@ -313,7 +313,7 @@ def test_every_tile_shape(precision):
     f = rnd((1,) + tuple(reversed(wl.n)), 21)
     want = vc.precondition(f[0].ravel())
     bar = 1e-4 if precision == "mixed" else CYCLE_BAR
-    for shape in range(4):
+    for shape in range(5):
         for l in range(s.num_levels):
             s.tile_shape(l, shape)
         z = s.empty()
@@ -322,5 +322,5 @@ def test_every_tile_shape(precision):
         say(precision, "shape", shape, err)
         assert err < bar, (shape, err)
     with pytest.raises(Exception):
-        s.tile_shape(0, 4)
+        s.tile_shape(0, 5)
     s.close()
