@@ -150,7 +150,19 @@ struct CycleArgs {
     CycleSlots st;
     double* norm_part;
     int pstride;
+    // 2D GMRES(3) apply passes on coarse levels: when gpart is set, each
+    // workgroup forms the smoothing coefficients itself from the Gram
+    // partials of the preceding Gram pass (value v of the slot's tile b at
+    // gpart[(slot * gpstride + v) * gbstride + b]) instead of reading the
+    // coefficient record
+    const cx<double>* gpart;
+    int gpstride, gbstride;
+    double gbrk;               // relative pivot of an exhausted Krylov space
 };
+
+// Tiles of a coarse level above which the apply passes leave the
+// coefficient solve to its own launch.
+constexpr int FUSED_COEF_TILES = 128;
 
 // A slot of the vector kernels (residual, norm, GMRES passes, combine).
 struct VecSlot {

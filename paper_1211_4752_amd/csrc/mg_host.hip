@@ -969,6 +969,37 @@ mg_status rec_smooth_coef(Rec& R, int d, int phase, const std::vector<Item>& it,
 }
 
 // 2D fused passes (mg_march2d.hip): Gram pass, coefficient solve, apply pass.
+// On coarse levels with few tiles per rhs the apply pass forms the
+// coefficients itself from the Gram partials (no separate solve launch).
+// (The choice is per slot -- by its own tile count -- so that a batch
+// launch forms every slot's coefficients as the single-context one does.)
+bool fused_coef(int d, const std::vector<int>& cnt) {
+    if (d == 0) return false;
+    for (int n : cnt)
+        if (n <= mg::FUSED_COEF_TILES) return true;
+    return false;
+}
+
+// The coefficient solve launch for the slots the apply pass does not serve.
+void rec_coef_rest(Rec& R, int d, int phase, const std::vector<Item>& it, const std::vector<int>& who,
+                   const std::vector<int>& cnt, int gk) {
+    std::vector<int> w2, c2;
+    for (size_t q = 0; q < who.size(); ++q)
+        if (cnt[q] > mg::FUSED_COEF_TILES) {
+            w2.push_back(who[q]);
+            c2.push_back(cnt[q]);
+        }
+    if (!w2.empty()) rec_coef(R, d, phase, it, w2, c2, gk);
+}
+
+void set_fused_coef(mg::CycleArgs& a, const Rec& R) {
+    a.gpart = R.w->part;
+    a.gpstride = HSTRIDE;
+    a.gbstride = R.w->bstride;
+    // an exhausted Krylov space shows as a relative Cholesky pivot at the
+    // rounding level of the vectors' precision (as in the solve launch)
+    a.gbrk = R.mixed ? 1e-5 : 1e-13;
+}
 mg_status rec_pre_2d(Rec& R, int dir, const std::vector<Item>& it, int gk, const std::vector<L0>* l0, int d,
                      bool nz, const std::vector<int>& who) {
     const int shape = launch_shape(it, who, d);
@@ -1021,9 +1052,15 @@ mg_status rec_pre_2d(Rec& R, int dir, const std::vector<Item>& it, int gk, const
         b.st.s = (const mg::CycleSlot*)(base + off);
         return mg::launch_sm2_gram(mixed, d == 0, false, shape, b, part, HSTRIDE, bstride, s);
     });
-    rec_coef(R, d, 0, it, who, cnt, gk);
+    mg::CycleArgs aa = a;
+    if (fused_coef(d, cnt)) {
+        set_fused_coef(aa, R);
+        rec_coef_rest(R, d, 0, it, who, cnt, gk);
+    } else {
+        rec_coef(R, d, 0, it, who, cnt, gk);
+    }
     add(R, d == 0 ? MG_K_SMOOTH_RESTRICT_FINE : MG_K_COARSE_LEVELS, iba, [=](hipStream_t s, const char* base) {
-        mg::CycleArgs b = a;
+        mg::CycleArgs b = aa;
         b.st.s = (const mg::CycleSlot*)(base + off);
         return mg::launch_sm2_apply_restrict(mixed, d == 0, nz, shape, b, s);
     });
@@ -1081,9 +1118,15 @@ mg_status rec_post_2d(Rec& R, int dir, const std::vector<Item>& it, int gk, cons
         b.st.s = (const mg::CycleSlot*)(base + off);
         return mg::launch_sm2_gram(mixed, d == 0, true, shape, b, part, HSTRIDE, bstride, s);
     });
-    rec_coef(R, d, 1, it, who, cnt, gk);
+    mg::CycleArgs aa = a;
+    if (fused_coef(d, cnt)) {
+        set_fused_coef(aa, R);
+        rec_coef_rest(R, d, 1, it, who, cnt, gk);
+    } else {
+        rec_coef(R, d, 1, it, who, cnt, gk);
+    }
     add(R, d == 0 ? MG_K_PROLONG_SMOOTH_FINE : MG_K_COARSE_LEVELS, iba, [=](hipStream_t s, const char* base) {
-        mg::CycleArgs b = a;
+        mg::CycleArgs b = aa;
         b.st.s = (const mg::CycleSlot*)(base + off);
         return mg::launch_sm2_apply_out(mixed, d == 0, ac, shape, b, s);
     });

@@ -314,5 +314,53 @@ __device__ inline void solve_coef(const cx<double>* G, double brk, cx<double>* o
     out[2] = deg == 3 ? (d0 / d3) * x3 : mk(0.0, 0.0);
 }
 
+// Tiles of slot `slot` of a fused-kernel launch.
+__device__ __forceinline__ int slot_tiles(const CycleArgs& a, int slot) {
+    return (slot + 1 < a.st.n ? a.st.s[slot + 1].tile0 : a.st.ntiles) - a.st.s[slot].tile0;
+}
+
+// The smoothing coefficients of slot `slot` of a 2D GMRES(3) apply launch
+// from the Gram partials of the preceding Gram pass (same slots and tiles,
+// at most FUSED_COEF_TILES of them), formed by one wavefront in two steps:
+// coef_load issues the loads (lane l takes tiles l, l + 64, ...), so that
+// their latency passes while the caller loads its tile; coef_solve sums in a
+// fixed order (lanes, then the wave sum) and solves.  Every lane of every
+// wavefront gets the same values.
+struct CoefLoad {
+    static constexpr int KB = FUSED_COEF_TILES / 64;
+    cx<double> v[KB][NUM_GRAM];
+    int cnt;
+};
+
+__device__ __forceinline__ void coef_load(const CycleArgs& a, int slot, CoefLoad& cl) {
+    const int lane = threadIdx.x & 63;
+    cl.cnt = slot_tiles(a, slot);
+    const cx<double>* P = a.gpart + (long long)slot * a.gpstride * a.gbstride;
+#pragma unroll
+    for (int k = 0; k < CoefLoad::KB; ++k) {
+        const int b = lane + 64 * k;
+        const int bb = b < cl.cnt ? b : 0;
+#pragma unroll
+        for (int g = 0; g < NUM_GRAM; ++g) cl.v[k][g] = P[(long long)g * a.gbstride + bb];
+    }
+}
+
+__device__ __forceinline__ void coef_solve(const CoefLoad& cl, double brk, cx<double>* out) {
+    const int lane = threadIdx.x & 63;
+    cx<double> G[NUM_GRAM];
+#pragma unroll
+    for (int g = 0; g < NUM_GRAM; ++g) {
+        double r = 0.0, i = 0.0;
+#pragma unroll
+        for (int k = 0; k < CoefLoad::KB; ++k) {
+            const bool in = lane + 64 * k < cl.cnt;
+            r += in ? cl.v[k][g].r : 0.0;
+            i += in ? cl.v[k][g].i : 0.0;
+        }
+        G[g] = mk(wave_sum(r), g < 4 ? 0.0 : wave_sum(i));
+    }
+    solve_coef(G, brk, out);
+}
+
 }  // namespace kc
 }  // namespace mg

@@ -494,7 +494,7 @@ __global__ void __launch_bounds__(MW) k_mg_gram(const CycleArgs a, cx<double>* p
 // at row t - 3; the coarse row whose centre is row t - 4 is restricted once
 // rows t-5..t-3 of r1 exist.
 // ---------------------------------------------------------------------------
-template <typename T, typename TQ, bool NZ, int TY>
+template <typename T, typename TQ, bool NZ, int TY, bool FC>
 __global__ void __launch_bounds__(MW) k_mg_apply_restrict(const CycleArgs a) {
     static_assert(TY % 2 == 0 && MAHEAD % 2 == 0 && TY + MAHEAD + 11 <= MW, "strip geometry");
     const int pid = xcd_remap(blockIdx.x, gridDim.x);
@@ -518,7 +518,16 @@ __global__ void __launch_bounds__(MW) k_mg_apply_restrict(const CycleArgs a) {
     const auto u1p = gout(static_cast<cx<T>*>(B.u1));
     const auto fc = gout(static_cast<cx<T>*>(sl.c));
     const int ncx = Lc.n[0], ncy = Lc.n[1];
-    const cx<T> c1 = cvt<T>(B.coef[0]), cc2 = cvt<T>(B.coef[1]), cc3 = cvt<T>(B.coef[2]);
+    cx<T> c1, cc2, cc3;
+    if (FC && slot_tiles(a, slot) <= FUSED_COEF_TILES) {   // from the Gram partials (coarse levels)
+        CoefLoad cl;
+        coef_load(a, slot, cl);
+        cx<double> co[4];
+        coef_solve(cl, a.gbrk, co);
+        c1 = cvt<T>(co[0]), cc2 = cvt<T>(co[1]), cc3 = cvt<T>(co[2]);
+    } else {
+        c1 = cvt<T>(B.coef[0]), cc2 = cvt<T>(B.coef[1]), cc3 = cvt<T>(B.coef[2]);
+    }
     const cx<T> Z = mk<T>(0, 0);
     const int yend = imin(y0 + TY, ny);
     // restriction centres of this strip: odd gx among the owned lanes
@@ -591,7 +600,7 @@ __global__ void __launch_bounds__(MW) k_mg_apply_restrict(const CycleArgs a) {
 // Post-smoothing apply: u2 rows t..t-3, q0 rows t-1..t-3, q1 rows t-2..t-4,
 // q2 at row t-3; out at row t - 3.
 // ---------------------------------------------------------------------------
-template <typename T, typename TF, typename TO, bool ACC, int TY>
+template <typename T, typename TF, typename TO, bool ACC, int TY, bool FC>
 __global__ void __launch_bounds__(MW) k_mg_apply_out(const CycleArgs a) {
     static_assert(TY % 2 == 0 && MAHEAD % 2 == 0 && TY + MAHEAD + 11 <= MW, "strip geometry");
     const int pid = xcd_remap(blockIdx.x, gridDim.x);
@@ -616,7 +625,16 @@ __global__ void __launch_bounds__(MW) k_mg_apply_out(const CycleArgs a) {
     const auto fv = gin(static_cast<const cx<TF>*>(sl.f));
     const auto out = gout(static_cast<cx<TO>*>(sl.out));
     const auto outr = gin(static_cast<const cx<TO>*>(sl.out));
-    const cx<T> c1 = cvt<T>(B.coef[4]), cc2 = cvt<T>(B.coef[5]), cc3 = cvt<T>(B.coef[6]);
+    cx<T> c1, cc2, cc3;
+    if (FC && slot_tiles(a, slot) <= FUSED_COEF_TILES) {   // from the Gram partials (coarse levels)
+        CoefLoad cl;
+        coef_load(a, slot, cl);
+        cx<double> co[4];
+        coef_solve(cl, a.gbrk, co);
+        c1 = cvt<T>(co[0]), cc2 = cvt<T>(co[1]), cc3 = cvt<T>(co[2]);
+    } else {
+        c1 = cvt<T>(B.coef[4]), cc2 = cvt<T>(B.coef[5]), cc3 = cvt<T>(B.coef[6]);
+    }
     const cx<T> Z = mk<T>(0, 0);
     const int yend = imin(y0 + TY, ny);
     auto ok = [&](int y) { return c.colv && rowv(L, y); };
@@ -731,9 +749,9 @@ hipError_t launch_sm2_gram(bool f32, bool level0, bool post, int shape, const Cy
                 : mg_gram_launch<float, float, false>(shape, a, part, pstride, bstride, s);
 }
 
-template <typename T, typename TQ, bool NZ>
+template <typename T, typename TQ, bool NZ, bool FC = false>
 static hipError_t mg_ar_launch(int shape, const CycleArgs& a, hipStream_t s) {
-#define AL(TY) hipLaunchKernelGGL((k_mg_apply_restrict<T, TQ, NZ, TY>), dim3(a.st.ntiles), dim3(MW), 0, s, a);
+#define AL(TY) hipLaunchKernelGGL((k_mg_apply_restrict<T, TQ, NZ, TY, FC>), dim3(a.st.ntiles), dim3(MW), 0, s, a);
     MG_MARCH_SWITCH(AL)
 #undef AL
     return hipGetLastError();
@@ -743,15 +761,20 @@ hipError_t launch_sm2_apply_restrict(bool f32, bool level0, bool nonzero, int sh
                                      hipStream_t s) {
     if (a.st.n <= 0) return hipSuccess;
     if (shape == MARCH_TILE) return tile2d_apply_restrict(f32, level0, nonzero, a, s);
+    if (a.gpart) {   // coarse levels: zero iterate, vectors in the compute precision
+        if (level0 || nonzero) return hipErrorInvalidValue;
+        return f32 ? mg_ar_launch<float, float, false, true>(shape, a, s)
+                   : mg_ar_launch<double, double, false, true>(shape, a, s);
+    }
     if (!f32)
         return nonzero ? mg_ar_launch<double, double, true>(shape, a, s) : mg_ar_launch<double, double, false>(shape, a, s);
     if (nonzero) return hipErrorInvalidValue;
     return level0 ? mg_ar_launch<float, double, false>(shape, a, s) : mg_ar_launch<float, float, false>(shape, a, s);
 }
 
-template <typename T, typename TF, typename TO, bool ACC>
+template <typename T, typename TF, typename TO, bool ACC, bool FC = false>
 static hipError_t mg_ao_launch(int shape, const CycleArgs& a, hipStream_t s) {
-#define OL(TY) hipLaunchKernelGGL((k_mg_apply_out<T, TF, TO, ACC, TY>), dim3(a.st.ntiles), dim3(MW), 0, s, a);
+#define OL(TY) hipLaunchKernelGGL((k_mg_apply_out<T, TF, TO, ACC, TY, FC>), dim3(a.st.ntiles), dim3(MW), 0, s, a);
     MG_MARCH_SWITCH(OL)
 #undef OL
     return hipGetLastError();
@@ -760,6 +783,11 @@ static hipError_t mg_ao_launch(int shape, const CycleArgs& a, hipStream_t s) {
 hipError_t launch_sm2_apply_out(bool f32, bool level0, bool accumulate, int shape, const CycleArgs& a, hipStream_t s) {
     if (a.st.n <= 0) return hipSuccess;
     if (shape == MARCH_TILE) return tile2d_apply_out(f32, level0, accumulate, a, s);
+    if (a.gpart) {   // coarse levels
+        if (level0 || accumulate) return hipErrorInvalidValue;
+        return f32 ? mg_ao_launch<float, float, float, false, true>(shape, a, s)
+                   : mg_ao_launch<double, double, double, false, true>(shape, a, s);
+    }
     if (!f32)
         return accumulate ? mg_ao_launch<double, double, double, true>(shape, a, s)
                           : mg_ao_launch<double, double, double, false>(shape, a, s);

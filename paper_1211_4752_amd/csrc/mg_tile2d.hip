@@ -314,7 +314,12 @@ __global__ void __launch_bounds__(TNT) k_tile_apply_restrict(const CycleArgs a) 
     const auto up = gin(static_cast<const cx<T>*>(sl.u));
     const auto u1p = gout(static_cast<cx<T>*>(B.u1));
     const auto fc = gout(static_cast<cx<T>*>(sl.c));
-    const cx<T> c1 = cvt<T>(B.coef[0]), cc2 = cvt<T>(B.coef[1]), cc3 = cvt<T>(B.coef[2]);
+    // coefficients: from the Gram partials (their loads in flight with the
+    // tile's), else from the coefficient record
+    const bool fused = a.gpart && slot_tiles(a, slot) <= FUSED_COEF_TILES;
+    CoefLoad cl;
+    if (fused) coef_load(a, slot, cl);
+    cx<T> c1 = cvt<T>(B.coef[0]), cc2 = cvt<T>(B.coef[1]), cc3 = cvt<T>(B.coef[2]);
     const cx<T> Z = mk<T>(0, 0);
     auto ingrid = [&](int i, int j) {
         const int gx = gx0 + i, gy = gy0 + j;
@@ -323,6 +328,11 @@ __global__ void __launch_bounds__(TNT) k_tile_apply_restrict(const CycleArgs a) 
     load_coef<T, H>(C, L, gx0, gy0);
     fill_tile<H>(S0, gx0, gy0, nx, ny, [&](int gx, int gy) { return qs * cvt<T>(src[(long long)gy * nx + gx]); });
     __syncthreads();
+    if (fused) {
+        cx<double> co[4];
+        coef_solve(cl, a.gbrk, co);
+        c1 = cvt<T>(co[0]), cc2 = cvt<T>(co[1]), cc3 = cvt<T>(co[2]);
+    }
     auto stage = [&](int h, auto&& fn) {
         const int w = G::W - 2 * h, n = w * (G::HH - 2 * h);
         for (int q = threadIdx.x; q < n; q += TNT) fn(h + q % w, h + q / w);
@@ -399,7 +409,12 @@ __global__ void __launch_bounds__(TNT) k_tile_apply_out(const CycleArgs a) {
     const auto ev = gin(static_cast<const cx<T>*>(sl.c));
     const auto fv = gin(static_cast<const cx<TF>*>(sl.f));
     const auto out = gout(static_cast<cx<TO>*>(sl.out));
-    const cx<T> c1 = cvt<T>(B.coef[4]), cc2 = cvt<T>(B.coef[5]), cc3 = cvt<T>(B.coef[6]);
+    // coefficients: from the Gram partials (their loads in flight with the
+    // tile's), else from the coefficient record
+    const bool fused = a.gpart && slot_tiles(a, slot) <= FUSED_COEF_TILES;
+    CoefLoad cl;
+    if (fused) coef_load(a, slot, cl);
+    cx<T> c1 = cvt<T>(B.coef[4]), cc2 = cvt<T>(B.coef[5]), cc3 = cvt<T>(B.coef[6]);
     const cx<T> Z = mk<T>(0, 0);
     auto ingrid = [&](int i, int j) {
         const int gx = gx0 + i, gy = gy0 + j;
@@ -409,6 +424,11 @@ __global__ void __launch_bounds__(TNT) k_tile_apply_out(const CycleArgs a) {
     fill_tile<H>(S0, gx0, gy0, nx, ny,   // u2
                  [&](int gx, int gy) { return u1[(long long)gy * nx + gx] + prolong_pt<T>(Lc, ev, gx, gy); });
     __syncthreads();
+    if (fused) {
+        cx<double> co[4];
+        coef_solve(cl, a.gbrk, co);
+        c1 = cvt<T>(co[0]), cc2 = cvt<T>(co[1]), cc3 = cvt<T>(co[2]);
+    }
     auto stage = [&](int h, auto&& fn) {
         const int w = G::W - 2 * h, n = w * (G::HH - 2 * h);
         for (int q = threadIdx.x; q < n; q += TNT) fn(h + q % w, h + q / w);
