@@ -241,20 +241,52 @@ __device__ __forceinline__ void chunk_range(long long N, int nblocks, int b, int
 }
 
 
+// v where c holds, else 0, component by component (a select of whole
+// structures would go through scratch memory).
+template <typename T>
+__device__ __forceinline__ cx<T> masked(bool c, cx<T> v) {
+    return mk<T>(c ? v.r : T(0), c ? v.i : T(0));
+}
+
 // 3-point-per-axis stencil of the level operator at point p of x, x scaled by
-// xs and converted to the compute precision T.
+// xs and converted to the compute precision T.  Every load is issued (a
+// neighbour outside the grid reads the point itself) and the missing terms
+// are masked to exact zeros: a load under a branch would make the compiler
+// wait for all loads in flight before its use.
 template <int D, typename T, typename TX, typename LV, typename PX>
 __device__ __forceinline__ cx<T> stencil_at(const LV& L, PX x, T xs, long long p, int gx, int gy, int gz) {
     const int nx = L.n[0], ny = L.n[1], nz = L.n[2];
-    cx<T> ax = diag_at<D>(L, gx, gy, gz, L.k2[p]) * cvt<T>(x[p]);
-    if (gx > 0) ax = ax + L.cm[0][gx] * cvt<T>(x[p - 1]);
-    if (gx < nx - 1) ax = ax + L.cp[0][gx] * cvt<T>(x[p + 1]);
-    if (gy > 0) ax = ax + L.cm[1][gy] * cvt<T>(x[p - nx]);
-    if (gy < ny - 1) ax = ax + L.cp[1][gy] * cvt<T>(x[p + nx]);
+    const bool bxm = gx > 0, bxp = gx < nx - 1, bym = gy > 0, byp = gy < ny - 1;
+    const bool bzm = D == 3 && gz > 0, bzp = D == 3 && gz < nz - 1;
+    const long long sz = (long long)nx * ny;
+    const int az = D == 3 ? gz : 0;
+    // every load first (the scheduler would otherwise sink them to their uses
+    // and wait for them one by one)
+    const auto v0 = x[p];
+    const auto vxm = x[bxm ? p - 1 : p], vxp = x[bxp ? p + 1 : p];
+    const auto vym = x[bym ? p - nx : p], vyp = x[byp ? p + nx : p];
+    const auto vzm = x[bzm ? p - sz : p], vzp = x[bzp ? p + sz : p];
+    const cx<T> cmx = L.cm[0][gx], cpx = L.cp[0][gx], c0x = L.c0[0][gx];
+    const cx<T> cmy = L.cm[1][gy], cpy = L.cp[1][gy], c0y = L.c0[1][gy];
+    cx<T> cmz = mk<T>(0, 0), cpz = cmz, c0z = cmz;   // the z arrays exist in 3D only
     if constexpr (D == 3) {
-        const long long sz = (long long)nx * ny;
-        if (gz > 0) ax = ax + L.cm[2][gz] * cvt<T>(x[p - sz]);
-        if (gz < nz - 1) ax = ax + L.cp[2][gz] * cvt<T>(x[p + sz]);
+        cmz = L.cm[2][az];
+        cpz = L.cp[2][az];
+        c0z = L.c0[2][az];
+    }
+    const T k2 = L.k2[p];
+    __builtin_amdgcn_sched_barrier(0);
+    cx<T> d = c0x + c0y;
+    if constexpr (D == 3) d = d + c0z;
+    d = d - k2 * L.sigma;
+    cx<T> ax = d * cvt<T>(v0);
+    ax = ax + masked(bxm, cmx) * cvt<T>(vxm);
+    ax = ax + masked(bxp, cpx) * cvt<T>(vxp);
+    ax = ax + masked(bym, cmy) * cvt<T>(vym);
+    ax = ax + masked(byp, cpy) * cvt<T>(vyp);
+    if constexpr (D == 3) {
+        ax = ax + masked(bzm, cmz) * cvt<T>(vzm);
+        ax = ax + masked(bzp, cpz) * cvt<T>(vzp);
     }
     return xs * ax;
 }

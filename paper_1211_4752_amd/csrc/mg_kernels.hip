@@ -27,21 +27,12 @@ namespace {
 // Vector kernels: one point per thread, a contiguous chunk of the slot's
 // vector per workgroup.
 // ---------------------------------------------------------------------------
+// (loads unconditional, missing neighbours masked to exact zeros, as in
+// stencil_at)
 template <int D, typename PX>
 __device__ __forceinline__ cx<double> apply_at(const GLevel<double>& L, const PX& x, int p, int gx, int gy,
                                                int gz) {
-    const int nx = L.n[0], ny = L.n[1], nz = L.n[2];
-    cx<double> ax = diag_at<D>(L, gx, gy, gz, L.k2[p]) * x[p];
-    if (gx > 0) ax = ax + L.cm[0][gx] * x[p - 1];
-    if (gx < nx - 1) ax = ax + L.cp[0][gx] * x[p + 1];
-    if (gy > 0) ax = ax + L.cm[1][gy] * x[p - nx];
-    if (gy < ny - 1) ax = ax + L.cp[1][gy] * x[p + nx];
-    if constexpr (D == 3) {
-        const int sz = nx * ny;
-        if (gz > 0) ax = ax + L.cm[2][gz] * x[p - sz];
-        if (gz < nz - 1) ax = ax + L.cp[2][gz] * x[p + sz];
-    }
-    return ax;
+    return stencil_at<D, double, double>(L, x, 1.0, p, gx, gy, gz);
 }
 
 // y = f - A x (f null: y = A x); ||y||^2 partials in rpart.
