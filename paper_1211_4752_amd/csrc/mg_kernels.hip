@@ -273,10 +273,15 @@ __global__ void __launch_bounds__(NT) k_combine(const VecArgs a) {
     const auto t = gout(sl.y);
     chunk_range(N, q.nb, q.b, q.lo, q.hi);
     for (int p = q.lo + (int)threadIdx.x; p < q.hi; p += NT) {
+        // every vector's load issued before the first use (past nv a load
+        // re-reads the last vector, whose coefficient is 0): a load under a
+        // branch would be waited for one at a time
+        cx<double> vv[MAXJ];
+#pragma unroll
+        for (int k = 0; k < MAXJ; ++k) vv[k] = V[(long long)(k < nv ? k : nv - 1) * N + p];
         cx<double> s = mk(0.0, 0.0);
 #pragma unroll
-        for (int i = 0; i < MAXJ; ++i)
-            if (i < nv) s = s + coef[i] * V[(long long)i * N + p];
+        for (int k = 0; k < MAXJ; ++k) s = s + coef[k] * vv[k];
         if constexpr (ACC)
             t[p] = t[p].get() + s;
         else
