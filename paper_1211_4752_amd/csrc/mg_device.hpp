@@ -241,7 +241,7 @@ struct SmArgs {
 struct CoefSlot {
     cx<double>* coef;
     int cnt;
-    int pad_;
+    int pslot;                  // the slot's index in the Gram launch (its partials)
     const int* gate;
 };
 struct SmCoefArgs {

@@ -882,14 +882,17 @@ mg_status rec_gm(Rec& R, int which, const std::vector<Item>& it, const std::vect
 // restriction of its residual, post-smoothing starts from u1 + P e.
 // ---------------------------------------------------------------------------
 
-// Coefficient solve of each slot of a Gram launch (partials per slot: cnt).
+// Coefficient solve of slots of a Gram launch (partials per slot: cnt; the
+// q-th slot solved is slot pslot[q] of the Gram launch, q itself when
+// pslot is null).
 void rec_coef(Rec& R, int d, int phase, const std::vector<Item>& it, const std::vector<int>& who,
-              const std::vector<int>& cnt, int gk) {
+              const std::vector<int>& cnt, int gk, const std::vector<int>* pslot = nullptr) {
     std::vector<mg::CoefSlot> cs(who.size());
     for (size_t q = 0; q < who.size(); ++q) {
         const Item& I = it[who[q]];
         cs[q].coef = gcoef_of(I.c, d, I.rhs, phase);
         cs[q].cnt = cnt[q];
+        cs[q].pslot = pslot ? (*pslot)[q] : (int)q;
         cs[q].gate = gate_of(R, gk, who[q]);
     }
     mg::SmCoefArgs a{};
@@ -983,13 +986,14 @@ bool fused_coef(int d, const std::vector<int>& cnt) {
 // The coefficient solve launch for the slots the apply pass does not serve.
 void rec_coef_rest(Rec& R, int d, int phase, const std::vector<Item>& it, const std::vector<int>& who,
                    const std::vector<int>& cnt, int gk) {
-    std::vector<int> w2, c2;
+    std::vector<int> w2, c2, p2;
     for (size_t q = 0; q < who.size(); ++q)
         if (cnt[q] > mg::FUSED_COEF_TILES) {
             w2.push_back(who[q]);
             c2.push_back(cnt[q]);
+            p2.push_back((int)q);
         }
-    if (!w2.empty()) rec_coef(R, d, phase, it, w2, c2, gk);
+    if (!w2.empty()) rec_coef(R, d, phase, it, w2, c2, gk, &p2);
 }
 
 void set_fused_coef(mg::CycleArgs& a, const Rec& R) {

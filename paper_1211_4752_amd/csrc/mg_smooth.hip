@@ -157,7 +157,7 @@ __global__ void __launch_bounds__(NT) k_sm_coef(const SmCoefArgs a, double brk) 
     cx<double> g[NUM_GRAM];
 #pragma unroll
     for (int v = 0; v < NUM_GRAM; ++v) g[v] = mk(0.0, 0.0);
-    const cx<double>* base = a.part + (long long)slot * a.pstride * a.bstride;
+    const cx<double>* base = a.part + (long long)cs.pslot * a.pstride * a.bstride;
     for (int b = threadIdx.x; b < cnt; b += NT) {
 #pragma unroll
         for (int v = 0; v < NUM_GRAM; ++v) g[v] = g[v] + base[(long long)v * a.bstride + b];

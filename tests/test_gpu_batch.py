@@ -140,6 +140,40 @@ def test_batch_gmres_equals_single(precision):
         assert np.linalg.norm(us[1][0].numpy().ravel() - x) <= 1e-10 * np.linalg.norm(x)
 
 
+def test_batch_coefficient_solve_reads_own_partials():
+    """Tile shape 4 (32 x 16 tiles) on every level: at depth 1 the 63^2 level
+    of the first member has few enough tiles for the apply pass to form its
+    smoothing coefficients, the 319^2 level of the second does not, so the
+    separate coefficient solve serves only the second slot of the Gram
+    launch.  It must read that slot's partials: batch equals single bit for
+    bit."""
+    wls = [W.constant_2d(127, 0.4), W.constant_2d(639, 0.4)]
+
+    def make(wl):
+        s = solver_of(wl)
+        for l in range(s.num_levels):
+            s.tile_shape(l, 4)
+        return s
+
+    mg = _mg()
+    ss = [make(wl) for wl in wls]
+    b = mg.Batch(ss)
+    us = [s.empty() for s in ss]
+    st, its, hists = b.solve(us, [gpu(wl.f) for wl in wls], mode="gmres", rtol=1e-6, maxit=8, restart=20)
+    b.close()
+    for s in ss:
+        s.close()
+    for i, wl in enumerate(wls):
+        s = make(wl)
+        u1 = s.empty()
+        st1, its1, h1 = s.solve(u1, gpu(wl.f), mode="gmres", rtol=1e-6, maxit=8, restart=20)
+        s.close()
+        say("member", i, its[i], its1)
+        assert its[i] == its1, (i, its[i], its1)
+        assert torch.equal(us[i], u1), i
+        assert all(np.array_equal(x, y) for x, y in zip(hists[i], h1)), i
+
+
 def test_batch_standalone_matches_single():
     # constant kh = 0.3 with a wide layer: the standalone cycle converges
     wls = [W.constant_2d(127, 0.3, ecs=16), W.constant_2d(255, 0.3, ecs=32), W.constant_2d(191, 0.3, ecs=24)]
