@@ -178,7 +178,16 @@ struct VecSlot {
     int block0;                 // first workgroup of this slot in the launch
     const int* jp;              // device newest basis index, overrides j when set
     const int* gate;            // slot skipped when *gate == 0
+    int nc;                     // Arnoldi passes: chunks of the slot's vector (its partial sums)
 };
+
+// Arnoldi passes: each slot's vector is cut into a fixed number of chunks,
+// one partial sum each, so the sums do not depend on the launch.  The chunks
+// of the slots that are still live are spread evenly over the launch's
+// workgroups, of which a slot brings ceil(nc / ARN_SPLIT): with every slot
+// live a workgroup takes ARN_SPLIT chunks, and when right-hand sides of a
+// batch have converged the others spread over the whole grid.
+constexpr int ARN_SPLIT = 4;
 
 struct VecSlots {
     int n;
@@ -334,10 +343,11 @@ hipError_t launch_sweep_ps(int dim, bool f32, bool level0, bool accumulate, int 
 // Workgroups per slot of a vector launch over N points: about per points
 // per thread, between 1 and 1024.
 int vec_blocks(long long N, int per = 8);
-// Workgroups per slot of the matvec-dot pass on an n[0] x n[1] (x n[2]) grid:
-// 2D: column blocks of NT times row strips of about per rows; 3D: as
-// vec_blocks.
-int mv_blocks(int dim, const int n[3], int per);
+// Chunks per slot of the Arnoldi passes on an n[0] x n[1] (x n[2]) grid,
+// about per points per thread each.  Matvec pass in 2D (mv): column blocks
+// of NT times row strips of at most per rows, numbered strip-fastest;
+// otherwise contiguous ranges of the N points, at most 1024 * ARN_SPLIT.
+int arnoldi_chunks(bool mv, int dim, const int n[3], long long N, int per);
 hipError_t launch_residual(int dim, const VecArgs& a, hipStream_t s);
 hipError_t launch_norm(const VecArgs& a, hipStream_t s);
 hipError_t launch_matvec_dot(int dim, int jmax, const VecArgs& a, hipStream_t s);

@@ -744,9 +744,14 @@ mg_status rec_tail(Rec& R, int dir, const std::vector<Item>& it, int gk) {
 // ---------------------------------------------------------------------------
 enum Blk { B_VEC = 0, B_DOT = 1, B_MV = 2 };
 
+// Chunks per slot of the Arnoldi passes: vper points per thread per
+// workgroup when every slot is live, so chunks of vper / ARN_SPLIT.
+int chunks_of(const mg_ctx* c, int bk) {
+    return mg::arnoldi_chunks(bk == B_MV, c->dim, c->lv[0].n, c->lv[0].N, c->vper / mg::ARN_SPLIT);
+}
+
 int blocks_of(const mg_ctx* c, int bk) {
-    if (bk == B_DOT) return mg::vec_blocks(c->lv[0].N, c->vper);
-    if (bk == B_MV) return mg::mv_blocks(c->dim, c->lv[0].n, c->vper);
+    if (bk == B_DOT || bk == B_MV) return (chunks_of(c, bk) + mg::ARN_SPLIT - 1) / mg::ARN_SPLIT;
     return mg::vec_blocks(c->lv[0].N);
 }
 
@@ -767,8 +772,12 @@ mg_status rec_vec(Rec& R, int dir, const std::vector<Item>& it, int gk, int bk, 
         s.block0 = blocks;
         s.gate = gate_of(R, gk, (int)k);
         const int nb = blocks_of(I.c, bk);
-        if (nb > R.w->bstride) return MG_E_STATE;
-        if (cnt) (*cnt)[k] = nb;
+        // partial sums per slot: one per chunk of the Arnoldi passes, else
+        // one per workgroup
+        const int np = (bk == B_DOT || bk == B_MV) ? chunks_of(I.c, bk) : nb;
+        s.nc = np;
+        if (np > R.w->bstride) return MG_E_STATE;
+        if (cnt) (*cnt)[k] = np;
         blocks += nb;
         ItemBytes b{(int)k, 0.0, 0.0};
         fill((int)k, s, b);
@@ -1889,10 +1898,9 @@ int max_blocks(const mg_ctx* c) {
         mg::sweep_counts(c->dim, sweep, c->lv[0].n, nt);
         m = std::max(m, nt[0] * nt[1] * nt[2]);
     }
-    for (int per : {16, 32, 64}) {
-        m = std::max(m, mg::mv_blocks(c->dim, c->lv[0].n, per));
-        m = std::max(m, mg::vec_blocks(c->lv[0].N, per));
-    }
+    for (int per : {16, 32, 64})
+        for (bool mv : {false, true})
+            m = std::max(m, mg::arnoldi_chunks(mv, c->dim, c->lv[0].n, c->lv[0].N, per / mg::ARN_SPLIT));
     return m;
 }
 

@@ -105,95 +105,179 @@ __device__ __forceinline__ void block_sum_vec(cx<double> (&acc)[MAXJ], int nv, c
         for (int w = 0; w < NT / 64; ++w) s = s + sm[w * MAXJ + threadIdx.x];
         dst[(long long)threadIdx.x * bstride + b] = s;
     }
+    __syncthreads();   // sm may be written again
 }
 
-// w = A z, h_i = <v_i, w>.
+// ---------------------------------------------------------------------------
+// Live-chunk schedule of the Arnoldi passes (see ARN_SPLIT).
+// ---------------------------------------------------------------------------
+struct ChunkItem {
+    int slot, c;   // chunk c of slot
+};
+
+// Inclusive prefix sum of v over the workgroup; tot = the workgroup's sum.
+__device__ __forceinline__ int block_scan(int v, int* sh, int& tot) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    int x = v;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const int y = __shfl_up(x, d, 64);
+        if (lane >= d) x += y;
+    }
+    if (lane == 63) sh[wave] = x;
+    __syncthreads();
+    int off = 0;
+    tot = 0;
+#pragma unroll
+    for (int w = 0; w < NT / 64; ++w) {
+        const int t = sh[w];
+        if (w < wave) off += t;
+        tot += t;
+    }
+    __syncthreads();
+    return x + off;
+}
+
+__device__ __forceinline__ int live_chunks_of(const VecSlots& st, int s) {
+    return (s < st.n && !gated_off(st.s[s].gate)) ? st.s[s].nc : 0;
+}
+
+// This workgroup's share of the live chunks, at most ARN_SPLIT items in
+// item[] (every thread gets the same count).  The live chunks, slot by
+// slot, are numbered 0 .. L - 1 and workgroup g takes [g L / G, (g + 1) L /
+// G); as G >= L / ARN_SPLIT that is at most ARN_SPLIT chunks.
+__device__ int live_items(const VecSlots& st, ChunkItem* item, int* sh, int* nitem) {
+    int L = 0;
+    for (int g = 0; g < st.n; g += NT) {
+        int tot;
+        block_scan(live_chunks_of(st, g + (int)threadIdx.x), sh, tot);
+        L += tot;
+    }
+    if (L == 0) return 0;
+    const long long pid = xcd_remap(blockIdx.x, gridDim.x);
+    const long long k0 = (long long)L * pid / gridDim.x, k1 = (long long)L * (pid + 1) / gridDim.x;
+    if (threadIdx.x == 0) *nitem = 0;
+    __syncthreads();
+    long long carry = 0;
+    for (int g = 0; g < st.n; g += NT) {
+        const int s = g + (int)threadIdx.x;
+        const int c = live_chunks_of(st, s);
+        int tot;
+        const int inc = block_scan(c, sh, tot);
+        const long long lo = carry + inc - c, hi = carry + inc;
+        const long long a = lo > k0 ? lo : k0, b = hi < k1 ? hi : k1;
+        if (a < b) {
+            const int m = (int)(b - a);
+            const int r = atomicAdd(nitem, m);
+            for (int q = 0; q < m; ++q)
+                if (r + q < ARN_SPLIT) item[r + q] = ChunkItem{s, (int)(a - lo) + q};
+        }
+        carry += tot;
+    }
+    __syncthreads();
+    const int n = __builtin_amdgcn_readfirstlane(*nitem);
+    return n < ARN_SPLIT ? n : ARN_SPLIT;
+}
+
+// item k, read back as wave-uniform values (so the slot's fields are loaded
+// into scalar registers)
+__device__ __forceinline__ ChunkItem item_at(const ChunkItem* item, int k) {
+    const ChunkItem x = item[k];
+    return ChunkItem{__builtin_amdgcn_readfirstlane(x.slot), __builtin_amdgcn_readfirstlane(x.c)};
+}
+
+// w = A z, h_i = <v_i, w>: one partial per chunk.
 template <int D, int MAXJ>
 __global__ void __launch_bounds__(NT) k_matvec_dot(const VecArgs a) {
     __shared__ cx<double> sm[(NT / 64) * MAXJ];
     __shared__ double ssc[MAXJ];   // scale_i, read at the end from LDS
-    VecPos q = vec_pos(a.st);
-    const VecSlot sl = a.st.s[q.slot];
-    if (gated_off(sl.gate)) return;
-    const GLevel<double> L = glevel(*static_cast<const LevelView<double>*>(sl.lv));
-    const long long N = L.N;
-    const int nv = sl.j + 1;
-    if ((int)threadIdx.x < MAXJ) ssc[threadIdx.x] = (int)threadIdx.x < nv ? sl.scale[threadIdx.x] : 0.0;
-    __syncthreads();
-    const auto z = gin(sl.x);
-    const auto w = gout(sl.y);
-    const auto V = gin(sl.V);
-    chunk_range(N, q.nb, q.b, q.lo, q.hi);
-    cx<double> acc[MAXJ];
+    __shared__ ChunkItem item[ARN_SPLIT];
+    __shared__ int sh[NT / 64], nitem;
+    const int ni = live_items(a.st, item, sh, &nitem);
+    for (int k = 0; k < ni; ++k) {
+        const ChunkItem cr = item_at(item, k);
+        const int c = cr.c;
+        const VecSlot sl = a.st.s[cr.slot];
+        const GLevel<double> L = glevel(*static_cast<const LevelView<double>*>(sl.lv));
+        const long long N = L.N;
+        const int nv = sl.j + 1;
+        if (k == 0 || cr.slot != item_at(item, k - 1).slot) {   // stage the slot's scales
+            __syncthreads();   // the previous chunk's readers of ssc are done
+            if ((int)threadIdx.x < MAXJ) ssc[threadIdx.x] = (int)threadIdx.x < nv ? sl.scale[threadIdx.x] : 0.0;
+            __syncthreads();
+        }
+        const auto z = gin(sl.x);
+        const auto w = gout(sl.y);
+        const auto V = gin(sl.V);
+        cx<double>* dst = a.part + (long long)cr.slot * a.pstride * a.bstride;
+        const int nx = L.n[0], ny = L.n[1];
+        cx<double> acc[MAXJ];
 #pragma unroll
-    for (int i = 0; i < MAXJ; ++i) acc[i] = mk(0.0, 0.0);
-    const int nx = L.n[0], ny = L.n[1];
-    if constexpr (D == 2) {
-        // Column marching: workgroup b owns NT consecutive columns of a strip
-        // of rows (b = row strip * ncb + column block); each thread walks
-        // down its column keeping the rows above, at and below in registers,
-        // so every z value is fetched once.  The host sizes the launch with
-        // mv_blocks(), i.e. nb = ncb * (number of row strips).
-        const int ncb = (nx + NT - 1) / NT;
-        const int nrs = q.nb / ncb;
-        const int rows = (ny + nrs - 1) / nrs;
-        const int gx = (q.b % ncb) * NT + (int)threadIdx.x;
-        const int y0 = (q.b / ncb) * rows;
-        const int y1 = y0 + rows < ny ? y0 + rows : ny;
-        if (gx < nx && y0 < y1) {
-            const cx<double> zero = mk(0.0, 0.0);
-            cx<double> zm = y0 > 0 ? z[(y0 - 1) * nx + gx] : zero;
-            cx<double> zc = z[y0 * nx + gx];
-            for (int gy = y0; gy < y1; ++gy) {
-                const int p = gy * nx + gx;
+        for (int i = 0; i < MAXJ; ++i) acc[i] = mk(0.0, 0.0);
+        if constexpr (D == 2) {
+            // Column marching: chunk c owns NT consecutive columns of a
+            // strip of rows (c = column block * nrs + strip); each thread
+            // walks down its column keeping the rows above, at and below
+            // in registers, so every z value is fetched once.
+            const int ncb = (nx + NT - 1) / NT;
+            const int nrs = sl.nc / ncb;
+            const int rows = (ny + nrs - 1) / nrs;
+            const int gx = (c / nrs) * NT + (int)threadIdx.x;
+            const int y0 = (c % nrs) * rows;
+            const int y1 = y0 + rows < ny ? y0 + rows : ny;
+            if (gx < nx && y0 < y1) {
+                const cx<double> zero = mk(0.0, 0.0);
+                cx<double> zm = y0 > 0 ? z[(y0 - 1) * nx + gx] : zero;
+                cx<double> zc = z[y0 * nx + gx];
+                for (int gy = y0; gy < y1; ++gy) {
+                    const int p = gy * nx + gx;
+                    cx<double> vv[MAXJ];
+#pragma unroll
+                    for (int i = 0; i < MAXJ; ++i) vv[i] = (i < nv) ? V[(long long)i * N + p] : zero;
+                    const cx<double> zp = gy + 1 < ny ? z[p + nx] : zero;
+                    // same terms in the same order as apply_at<2>
+                    cx<double> wv = diag_at<2>(L, gx, gy, 0, L.k2[p]) * zc;
+                    if (gx > 0) wv = wv + L.cm[0][gx] * z[p - 1];
+                    if (gx < nx - 1) wv = wv + L.cp[0][gx] * z[p + 1];
+                    if (gy > 0) wv = wv + L.cm[1][gy] * zm;
+                    if (gy < ny - 1) wv = wv + L.cp[1][gy] * zp;
+                    w[p] = wv;
+#pragma unroll
+                    for (int i = 0; i < MAXJ; ++i) acc[i] = acc[i] + cmulc(vv[i], wv);
+                    zm = zc;
+                    zc = zp;
+                }
+            }
+        } else {
+            int lo, hi;
+            chunk_range(N, sl.nc, c, lo, hi);
+            // grid coordinates of p, carried forward by NT points per iteration
+            int p = lo + (int)threadIdx.x;
+            int gx = p % nx, gy = (p / nx) % ny, gz = p / nx / ny;
+            for (; p < hi; p += NT) {
+                // the basis loads do not depend on the stencil: issue them first
                 cx<double> vv[MAXJ];
 #pragma unroll
-                for (int i = 0; i < MAXJ; ++i) vv[i] = (i < nv) ? V[(long long)i * N + p] : zero;
-                const cx<double> zp = gy + 1 < ny ? z[p + nx] : zero;
-                // same terms in the same order as apply_at<2>
-                cx<double> wv = diag_at<2>(L, gx, gy, 0, L.k2[p]) * zc;
-                if (gx > 0) wv = wv + L.cm[0][gx] * z[p - 1];
-                if (gx < nx - 1) wv = wv + L.cp[0][gx] * z[p + 1];
-                if (gy > 0) wv = wv + L.cm[1][gy] * zm;
-                if (gy < ny - 1) wv = wv + L.cp[1][gy] * zp;
+                for (int i = 0; i < MAXJ; ++i) vv[i] = (i < nv) ? V[(long long)i * N + p] : mk(0.0, 0.0);
+                const cx<double> wv = apply_at<D>(L, z, p, gx, gy, gz);
                 w[p] = wv;
 #pragma unroll
                 for (int i = 0; i < MAXJ; ++i) acc[i] = acc[i] + cmulc(vv[i], wv);
-                zm = zc;
-                zc = zp;
+                gx += NT;
+                while (gx >= nx) {
+                    gx -= nx;
+                    if (++gy == ny) {
+                        gy = 0;
+                        ++gz;
+                    }
+                }
             }
         }
 #pragma unroll
         for (int i = 0; i < MAXJ; ++i)
             if (i < nv) acc[i] = ssc[i] * acc[i];
-        block_sum_vec<MAXJ>(acc, nv, sm, a.part + (long long)q.slot * a.pstride * a.bstride, a.bstride, q.b);
-        return;
+        block_sum_vec<MAXJ>(acc, nv, sm, dst, a.bstride, c);
     }
-    // grid coordinates of p, carried forward by NT points per iteration
-    int p = q.lo + (int)threadIdx.x;
-    int gx = p % nx, gy = (p / nx) % ny, gz = p / nx / ny;
-    for (; p < q.hi; p += NT) {
-        // the basis loads do not depend on the stencil: issue them first
-        cx<double> vv[MAXJ];
-#pragma unroll
-        for (int i = 0; i < MAXJ; ++i) vv[i] = (i < nv) ? V[(long long)i * N + p] : mk(0.0, 0.0);
-        const cx<double> wv = apply_at<D>(L, z, p, gx, gy, gz);
-        w[p] = wv;
-#pragma unroll
-        for (int i = 0; i < MAXJ; ++i) acc[i] = acc[i] + cmulc(vv[i], wv);
-        gx += NT;
-        while (gx >= nx) {
-            gx -= nx;
-            if (++gy == ny) {
-                gy = 0;
-                ++gz;
-            }
-        }
-    }
-#pragma unroll
-    for (int i = 0; i < MAXJ; ++i)
-        if (i < nv) acc[i] = ssc[i] * acc[i];
-    block_sum_vec<MAXJ>(acc, nv, sm, a.part + (long long)q.slot * a.pstride * a.bstride, a.bstride, q.b);
 }
 
 // Second pass of the Arnoldi step (classical Gram-Schmidt applied twice
@@ -201,50 +285,61 @@ __global__ void __launch_bounds__(NT) k_matvec_dot(const VecArgs a) {
 // contains the second projection (formed on the device from the Gram
 // matrix of the stored basis), fused with the partials of <v_i, V_{j+1}>
 // (i <= j; the next column of that Gram matrix) and of ||V_{j+1}||^2 (value
-// j + 1).  The coefficients scale_i h_i are staged in LDS.
+// j + 1), one partial per chunk.  The coefficients scale_i h_i are staged
+// in LDS.
 template <int MAXJ>
 __global__ void __launch_bounds__(NT) k_update_gram(const VecArgs a) {
     __shared__ cx<double> sm[(NT / 64) * (MAXJ + 1)];
     __shared__ cx<double> sc[MAXJ];
     __shared__ double ssc[MAXJ];   // scale_i, read at the end from LDS
-    VecPos q = vec_pos(a.st);
-    const VecSlot sl = a.st.s[q.slot];
-    if (gated_off(sl.gate)) return;
-    const long long N = static_cast<const LevelView<double>*>(sl.lv)->N;
-    const int nv = sl.j + 1;
-    const auto w = gin(sl.y);
-    const auto V = gin(sl.V);
-    if ((int)threadIdx.x < MAXJ) {
-        const double sv = (int)threadIdx.x < nv ? sl.scale[threadIdx.x] : 0.0;
-        ssc[threadIdx.x] = sv;
-        sc[threadIdx.x] = (int)threadIdx.x < nv ? sv * sl.hin[threadIdx.x] : mk(0.0, 0.0);
+    __shared__ ChunkItem item[ARN_SPLIT];
+    __shared__ int sh[NT / 64], nitem;
+    const int ni = live_items(a.st, item, sh, &nitem);
+    for (int k = 0; k < ni; ++k) {
+        const ChunkItem cr = item_at(item, k);
+        const int c = cr.c;
+        const VecSlot sl = a.st.s[cr.slot];
+        const long long N = static_cast<const LevelView<double>*>(sl.lv)->N;
+        const int nv = sl.j + 1;
+        const auto w = gin(sl.y);
+        const auto V = gin(sl.V);
+        if (k == 0 || cr.slot != item_at(item, k - 1).slot) {   // stage the slot's coefficients
+            __syncthreads();   // the previous chunk's readers of sc, ssc are done
+            if ((int)threadIdx.x < MAXJ) {
+                const double sv = (int)threadIdx.x < nv ? sl.scale[threadIdx.x] : 0.0;
+                ssc[threadIdx.x] = sv;
+                sc[threadIdx.x] = (int)threadIdx.x < nv ? sv * sl.hin[threadIdx.x] : mk(0.0, 0.0);
+            }
+            __syncthreads();
+        }
+        const auto vout = gout(sl.V + (long long)nv * N);
+        cx<double>* dst = a.part + (long long)cr.slot * a.pstride * a.bstride;
+        int lo, hi;
+        chunk_range(N, sl.nc, c, lo, hi);
+        cx<double> acc[MAXJ + 1];
+#pragma unroll
+        for (int i = 0; i <= MAXJ; ++i) acc[i] = mk(0.0, 0.0);
+        for (int p = lo + (int)threadIdx.x; p < hi; p += NT) {
+            cx<double> vv[MAXJ];
+#pragma unroll
+            for (int i = 0; i < MAXJ; ++i) vv[i] = (i < nv) ? V[(long long)i * N + p] : mk(0.0, 0.0);
+            cx<double> wv = w[p];
+#pragma unroll
+            for (int i = 0; i < MAXJ; ++i) wv = wv - sc[i] * vv[i];
+            vout[p] = wv;
+#pragma unroll
+            for (int i = 0; i < MAXJ; ++i) acc[i] = acc[i] + cmulc(vv[i], wv);
+            acc[MAXJ].r += abs2(wv);
+        }
+#pragma unroll
+        for (int i = 0; i < MAXJ; ++i)
+            if (i < nv) acc[i] = ssc[i] * acc[i];
+        // value nv carries the norm
+        cx<double> out[MAXJ + 1];
+#pragma unroll
+        for (int i = 0; i <= MAXJ; ++i) out[i] = (i < nv) ? acc[i] : (i == nv ? acc[MAXJ] : mk(0.0, 0.0));
+        block_sum_vec<MAXJ + 1>(out, nv + 1, sm, dst, a.bstride, c);
     }
-    __syncthreads();
-    chunk_range(N, q.nb, q.b, q.lo, q.hi);
-    const auto vout = gout(sl.V + (long long)nv * N);
-    cx<double> acc[MAXJ + 1];
-#pragma unroll
-    for (int i = 0; i <= MAXJ; ++i) acc[i] = mk(0.0, 0.0);
-    for (int p = q.lo + (int)threadIdx.x; p < q.hi; p += NT) {
-        cx<double> vv[MAXJ];
-#pragma unroll
-        for (int i = 0; i < MAXJ; ++i) vv[i] = (i < nv) ? V[(long long)i * N + p] : mk(0.0, 0.0);
-        cx<double> wv = w[p];
-#pragma unroll
-        for (int i = 0; i < MAXJ; ++i) wv = wv - sc[i] * vv[i];
-        vout[p] = wv;
-#pragma unroll
-        for (int i = 0; i < MAXJ; ++i) acc[i] = acc[i] + cmulc(vv[i], wv);
-        acc[MAXJ].r += abs2(wv);
-    }
-#pragma unroll
-    for (int i = 0; i < MAXJ; ++i)
-        if (i < nv) acc[i] = ssc[i] * acc[i];
-    // value nv carries the norm
-    cx<double> out[MAXJ + 1];
-#pragma unroll
-    for (int i = 0; i <= MAXJ; ++i) out[i] = (i < nv) ? acc[i] : (i == nv ? acc[MAXJ] : mk(0.0, 0.0));
-    block_sum_vec<MAXJ + 1>(out, nv + 1, sm, a.part + (long long)q.slot * a.pstride * a.bstride, a.bstride, q.b);
 }
 
 // y = 0 (gated).
@@ -390,10 +485,16 @@ void tile_counts(int dim, int shape, const int n[3], int ntiles[3]) {
     ntiles[2] = dim == 3 ? cdivi(n[2], t[2]) : 1;
 }
 
-int mv_blocks(int dim, const int n[3], int per) {
-    if (dim != 2) return vec_blocks((long long)n[0] * n[1] * n[2], per);
-    const int ncb = (n[0] + NT - 1) / NT;
-    return ncb * ((n[1] + per - 1) / per);
+int arnoldi_chunks(bool mv, int dim, const int n[3], long long N, int per) {
+    if (per < 1) per = 1;
+    if (mv && dim == 2) {
+        const int ncb = (n[0] + NT - 1) / NT;
+        return ncb * ((n[1] + per - 1) / per);
+    }
+    long long c = (N + (long long)NT * per - 1) / ((long long)NT * per);
+    if (c > 1024LL * ARN_SPLIT) c = 1024LL * ARN_SPLIT;
+    if (c < 1) c = 1;
+    return (int)c;
 }
 
 int vec_blocks(long long N, int per) {

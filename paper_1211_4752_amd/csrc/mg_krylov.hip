@@ -31,15 +31,30 @@ __device__ __forceinline__ cx<double> conj_(cx<double> z) { return mk(z.r, -z.i)
 __device__ __forceinline__ cx<double> cdivd(cx<double> a, cx<double> b) { return cdiv(a, b); }
 
 // out[v] = sum_b part[(slot * pstride + v) * bstride + b], v < nv, in a fixed
-// order: wave w takes the values v = w, w + 4, ...; lane l adds b = l, l +
-// 64, ... in turn, then a fixed butterfly.  Ends with a barrier.
+// order: wave w of the NTH threads takes the values v = w, w + NTH / 64,
+// ...; lane l adds b = l, l + 64, ... in turn, then a fixed butterfly.  Ends
+// with a barrier.
+template <int NTH>
 __device__ void wg_sum_cx(const cx<double>* part, int slot, int pstride, int bstride, int nv, int cnt,
                           cx<double>* out) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    for (int v = wave; v < nv; v += NT / 64) {
+    for (int v = wave; v < nv; v += NTH / 64) {
         const cx<double>* p = part + ((long long)slot * pstride + v) * bstride;
         double r = 0.0, i = 0.0;
-        for (int b = lane; b < cnt; b += 64) {
+        int b = lane;
+        // four loads in flight, added in the same order as one at a time
+        for (; b + 192 < cnt; b += 256) {
+            const cx<double> x0 = p[b], x1 = p[b + 64], x2 = p[b + 128], x3 = p[b + 192];
+            r += x0.r;
+            i += x0.i;
+            r += x1.r;
+            i += x1.i;
+            r += x2.r;
+            i += x2.i;
+            r += x3.r;
+            i += x3.i;
+        }
+        for (; b < cnt; b += 64) {
             r += p[b].r;
             i += p[b].i;
         }
@@ -137,13 +152,16 @@ __global__ void __launch_bounds__(NT) k_gm_restart(const GmArgs a) {
     }
 }
 
+// The per-step reductions take NTG threads: one or two values per wave.
+constexpr int NTG = 1024;
+
 // h = 2 h1 - G h1 for step j.
-__global__ void __launch_bounds__(NT) k_gm_h(const GmArgs a) {
+__global__ void __launch_bounds__(NTG) k_gm_h(const GmArgs a) {
     __shared__ cx<double> h1[HSTRIDE];
     const GmItem it = a.it[blockIdx.x];
     if (gated_off(&it.fl->live)) return;
     const int nv = a.j + 1;
-    wg_sum_cx(a.part, it.slot, a.pstride, a.bstride, nv, it.cnt, h1);
+    wg_sum_cx<NTG>(a.part, it.slot, a.pstride, a.bstride, nv, it.cnt, h1);
     const int i = threadIdx.x;
     if (i < nv) {
         const GmState* st = it.st;
@@ -154,12 +172,12 @@ __global__ void __launch_bounds__(NT) k_gm_h(const GmArgs a) {
 }
 
 // Hessenberg column, Givens rotation, estimate and stop tests of step j.
-__global__ void __launch_bounds__(NT) k_gm_col(const GmArgs a) {
+__global__ void __launch_bounds__(NTG) k_gm_col(const GmArgs a) {
     __shared__ cx<double> vals[HSTRIDE + 1];
     const GmItem it = a.it[blockIdx.x];
     if (gated_off(&it.fl->live)) return;
     const int j = a.j, nv = j + 1;
-    wg_sum_cx(a.part, it.slot, a.pstride, a.bstride, nv + 1, it.cnt, vals);
+    wg_sum_cx<NTG>(a.part, it.slot, a.pstride, a.bstride, nv + 1, it.cnt, vals);
     if (threadIdx.x != 0) return;
     const GmParams P = *a.prm;
     double* hist = P.hist + (long long)blockIdx.x * P.hstride;
@@ -270,8 +288,8 @@ hipError_t launch_gm(int which, int nitems, const GmArgs& a, hipStream_t s) {
         case GM_INIT: hipLaunchKernelGGL(k_gm_init, grid, blk, 0, s, a, 0); break;
         case SA_INIT: hipLaunchKernelGGL(k_gm_init, grid, blk, 0, s, a, 1); break;
         case GM_RESTART: hipLaunchKernelGGL(k_gm_restart, grid, blk, 0, s, a); break;
-        case GM_H: hipLaunchKernelGGL(k_gm_h, grid, blk, 0, s, a); break;
-        case GM_COL: hipLaunchKernelGGL(k_gm_col, grid, blk, 0, s, a); break;
+        case GM_H: hipLaunchKernelGGL(k_gm_h, grid, dim3(NTG), 0, s, a); break;
+        case GM_COL: hipLaunchKernelGGL(k_gm_col, grid, dim3(NTG), 0, s, a); break;
         case SA_STEP: hipLaunchKernelGGL(k_sa_step, grid, blk, 0, s, a); break;
         default: return hipErrorInvalidValue;
     }
