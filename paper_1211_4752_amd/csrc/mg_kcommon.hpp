@@ -68,6 +68,18 @@ struct GOut {
     __device__ __forceinline__ GRef<T> operator[](long long i) const { return GRef<T>{p + i}; }
     __device__ __forceinline__ explicit operator bool() const { return p != nullptr; }
 };
+// read-only view of streamed complex data (each element read once per
+// pass, not again before it would be evicted): loads carry the nontemporal
+// hint
+struct GStream {
+    gptr<const double> p;
+    __device__ __forceinline__ cx<double> operator[](long long i) const {
+        return mk(__builtin_nontemporal_load(p + 2 * i), __builtin_nontemporal_load(p + 2 * i + 1));
+    }
+};
+__device__ __forceinline__ GStream gstream(const cx<double>* p) {
+    return GStream{(gptr<const double>)p};
+}
 template <typename T>
 __device__ __forceinline__ GIn<T> gin(const T* p) {
     return GIn<T>{(gptr<const T>)p};

@@ -208,7 +208,7 @@ __global__ void __launch_bounds__(NT) k_matvec_dot(const VecArgs a) {
         }
         const auto z = gin(sl.x);
         const auto w = gout(sl.y);
-        const auto V = gin(sl.V);
+        const auto V = gstream(sl.V);
         cx<double>* dst = a.part + (long long)cr.slot * a.pstride * a.bstride;
         const int nx = L.n[0], ny = L.n[1];
         cx<double> acc[MAXJ];
@@ -302,7 +302,7 @@ __global__ void __launch_bounds__(NT) k_update_gram(const VecArgs a) {
         const long long N = static_cast<const LevelView<double>*>(sl.lv)->N;
         const int nv = sl.j + 1;
         const auto w = gin(sl.y);
-        const auto V = gin(sl.V);
+        const auto V = gstream(sl.V);
         if (k == 0 || cr.slot != item_at(item, k - 1).slot) {   // stage the slot's coefficients
             __syncthreads();   // the previous chunk's readers of sc, ssc are done
             if ((int)threadIdx.x < MAXJ) {
@@ -361,7 +361,7 @@ __global__ void __launch_bounds__(NT) k_combine(const VecArgs a) {
     if (gated_off(sl.gate)) return;
     const long long N = static_cast<const LevelView<double>*>(sl.lv)->N;
     const int nv = (sl.jp ? *sl.jp : sl.j) + 1;
-    const auto V = gin(sl.V);
+    const auto V = gstream(sl.V);
     cx<double> coef[MAXJ];
 #pragma unroll
     for (int i = 0; i < MAXJ; ++i) coef[i] = (i < nv) ? sl.coef[i] : mk(0.0, 0.0);
