@@ -260,6 +260,23 @@ __device__ __forceinline__ cx<T> masked(bool c, cx<T> v) {
     return mk<T>(c ? v.r : T(0), c ? v.i : T(0));
 }
 
+// Complex products accumulated by fused multiply-adds, two per component:
+// acc + a b, and acc + conj(a) b.  (Written as (acc + a*b) the compiler
+// fuses only the inner product and adds acc separately.)
+template <typename T>
+__device__ __forceinline__ cx<T> cfma(cx<T> a, cx<T> b, cx<T> acc) {
+    return mk<T>(fma(-a.i, b.i, fma(a.r, b.r, acc.r)), fma(a.i, b.r, fma(a.r, b.i, acc.i)));
+}
+template <typename T>
+__device__ __forceinline__ cx<T> cfmac(cx<T> a, cx<T> b, cx<T> acc) {
+    return mk<T>(fma(a.i, b.i, fma(a.r, b.r, acc.r)), fma(-a.i, b.r, fma(a.r, b.i, acc.i)));
+}
+// acc + |a|^2
+template <typename T>
+__device__ __forceinline__ T fabs2(cx<T> a, T acc) {
+    return fma(a.i, a.i, fma(a.r, a.r, acc));
+}
+
 // 3-point-per-axis stencil of the level operator at point p of x, x scaled by
 // xs and converted to the compute precision T.  Every load is issued (a
 // neighbour outside the grid reads the point itself) and the missing terms

@@ -145,7 +145,7 @@ template <typename T>
 __device__ __forceinline__ cx<T> row_apply(const Lane<T>& c, const YC<T>& y, cx<T> d, cx<T> am, cx<T> a0, cx<T> ap) {
     const cx<T> left = shfl_up1(a0);
     const cx<T> right = shfl_dn1(a0);
-    return d * a0 + c.cmx * left + c.cpx * right + y.cm * am + y.cp * ap;
+    return cfma(y.cp, ap, cfma(y.cm, am, cfma(c.cpx, right, cfma(c.cmx, left, d * a0))));
 }
 
 // A register copy made exactly here.  The ring slot a value was loaded into
@@ -206,16 +206,16 @@ __device__ __forceinline__ void interp_axis(int g, int nc, int& i0, int& i1, T& 
 template <typename T>
 __device__ __forceinline__ void gram_add(cx<double>* g, cx<T> a0, cx<T> a1, cx<T> a2, cx<T> a3) {
     const cx<double> v0 = cvt<double>(a0), v1 = cvt<double>(a1), v2 = cvt<double>(a2), v3 = cvt<double>(a3);
-    g[0].r += abs2(v0);
-    g[1].r += abs2(v1);
-    g[2].r += abs2(v2);
-    g[3].r += abs2(v3);
-    g[4] = g[4] + cmulc(v0, v1);
-    g[5] = g[5] + cmulc(v0, v2);
-    g[6] = g[6] + cmulc(v0, v3);
-    g[7] = g[7] + cmulc(v1, v2);
-    g[8] = g[8] + cmulc(v1, v3);
-    g[9] = g[9] + cmulc(v2, v3);
+    g[0].r = fabs2(v0, g[0].r);
+    g[1].r = fabs2(v1, g[1].r);
+    g[2].r = fabs2(v2, g[2].r);
+    g[3].r = fabs2(v3, g[3].r);
+    g[4] = cfmac(v0, v1, g[4]);
+    g[5] = cfmac(v0, v2, g[5]);
+    g[6] = cfmac(v0, v3, g[6]);
+    g[7] = cfmac(v1, v2, g[7]);
+    g[8] = cfmac(v1, v3, g[8]);
+    g[9] = cfmac(v2, v3, g[9]);
 }
 
 template <typename T>
@@ -572,9 +572,9 @@ __global__ void __launch_bounds__(MW) k_mg_apply_restrict(const CycleArgs a) {
             const bool m3 = ok(yr);
             const cx<T> q0 = A[RI<i, 3>], q1 = Bq[RI<i, 2>], q2 = Cq[RI<i, 1>];
             const cx<T> q3 = m3 ? L.sinv * v : Z;
-            Rr[RI<i, 0>] = m3 ? q0 + c1 * q1 + cc2 * q2 + cc3 * q3 : Z;
+            Rr[RI<i, 0>] = masked(m3, cfma(cc3, q3, cfma(cc2, q2, cfma(c1, q1, q0))));
             if (c.own && yr >= y0 && yr < yend) {
-                cx<T> u = L.sinv * (c1 * q0 + cc2 * q1 + cc3 * q2);
+                cx<T> u = L.sinv * cfma(cc3, q2, cfma(cc2, q1, c1 * q0));
                 if constexpr (NZ) u = W[RI<i, 3>] - u;
                 else u = Z - u;
                 u1p[(long long)yr * nx + c.gx] = u;
@@ -683,7 +683,7 @@ __global__ void __launch_bounds__(MW) k_mg_apply_out(const CycleArgs a) {
             if (c.own && yr >= y0 && yr < yend) {
                 const long long gi = (long long)yr * nx + c.gx;
                 const cx<T> q2 = L.sinv * v;
-                const cx<T> w = A[RI<i, 3>] - L.sinv * (c1 * Bq[RI<i, 2>] + cc2 * Cq[RI<i, 1>] + cc3 * q2);
+                const cx<T> w = A[RI<i, 3>] - L.sinv * cfma(cc3, q2, cfma(cc2, Cq[RI<i, 1>], c1 * Bq[RI<i, 2>]));
                 if constexpr (ACC)
                     out[gi] = pf[i].o + cvt<TO>(w);
                 else

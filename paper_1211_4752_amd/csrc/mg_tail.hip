@@ -175,13 +175,13 @@ template <int D, typename T, typename V>
 __device__ __forceinline__ cx<T> apply_pt(const PtCoef<T>& c, const GLevel<T>& L, const V& x, int p, T sc) {
     const int nx = L.n[0], nxy = L.n[0] * L.n[1];
     cx<T> ax = c.d * x[p];
-    if (c.gx > 0) ax = ax + c.m[0] * x[p - 1];
-    if (c.gx < nx - 1) ax = ax + c.pl[0] * x[p + 1];
-    if (c.gy > 0) ax = ax + c.m[1] * x[p - nx];
-    if (c.gy < L.n[1] - 1) ax = ax + c.pl[1] * x[p + nx];
+    if (c.gx > 0) ax = cfma(c.m[0], x[p - 1], ax);
+    if (c.gx < nx - 1) ax = cfma(c.pl[0], x[p + 1], ax);
+    if (c.gy > 0) ax = cfma(c.m[1], x[p - nx], ax);
+    if (c.gy < L.n[1] - 1) ax = cfma(c.pl[1], x[p + nx], ax);
     if constexpr (D == 3) {
-        if (c.gz > 0) ax = ax + c.m[2] * x[p - nxy];
-        if (c.gz < L.n[2] - 1) ax = ax + c.pl[2] * x[p + nxy];
+        if (c.gz > 0) ax = cfma(c.m[2], x[p - nxy], ax);
+        if (c.gz < L.n[2] - 1) ax = cfma(c.pl[2], x[p + nxy], ax);
     }
     return sc * ax;
 }
@@ -197,16 +197,16 @@ __device__ __forceinline__ cx<T> apply_gl(const GLevel<T>& L, const V& x, int p,
 template <typename T>
 __device__ __forceinline__ void gram_add(cx<double>* g, cx<T> a0, cx<T> a1, cx<T> a2, cx<T> a3) {
     const cx<double> v0 = cvt<double>(a0), v1 = cvt<double>(a1), v2 = cvt<double>(a2), v3 = cvt<double>(a3);
-    g[0].r += abs2(v0);
-    g[1].r += abs2(v1);
-    g[2].r += abs2(v2);
-    g[3].r += abs2(v3);
-    g[4] = g[4] + cmulc(v0, v1);
-    g[5] = g[5] + cmulc(v0, v2);
-    g[6] = g[6] + cmulc(v0, v3);
-    g[7] = g[7] + cmulc(v1, v2);
-    g[8] = g[8] + cmulc(v1, v3);
-    g[9] = g[9] + cmulc(v2, v3);
+    g[0].r = fabs2(v0, g[0].r);
+    g[1].r = fabs2(v1, g[1].r);
+    g[2].r = fabs2(v2, g[2].r);
+    g[3].r = fabs2(v3, g[3].r);
+    g[4] = cfmac(v0, v1, g[4]);
+    g[5] = cfmac(v0, v2, g[5]);
+    g[6] = cfmac(v0, v3, g[6]);
+    g[7] = cfmac(v1, v2, g[7]);
+    g[8] = cfmac(v1, v3, g[8]);
+    g[9] = cfmac(v2, v3, g[9]);
 }
 
 __device__ __forceinline__ double rdlane(double v, int l) {

@@ -121,22 +121,23 @@ __device__ __forceinline__ cx<T> tile_apply(const TCoef<T, H>& C, const GLevel<T
     using G = TGeo<H>;
     const int q = j * G::W + i;
     const cx<T> d = C.x0[i] + C.y0[j] - C.k2[q] * L.sigma;
-    return d * x[q] + C.xm[i] * x[q - 1] + C.xp[i] * x[q + 1] + C.ym[j] * x[q - G::W] + C.yp[j] * x[q + G::W];
+    return cfma(C.yp[j], x[q + G::W],
+                cfma(C.ym[j], x[q - G::W], cfma(C.xp[i], x[q + 1], cfma(C.xm[i], x[q - 1], d * x[q]))));
 }
 
 template <typename T>
 __device__ __forceinline__ void gram_add(cx<double>* g, cx<T> a0, cx<T> a1, cx<T> a2, cx<T> a3) {
     const cx<double> v0 = cvt<double>(a0), v1 = cvt<double>(a1), v2 = cvt<double>(a2), v3 = cvt<double>(a3);
-    g[0].r += abs2(v0);
-    g[1].r += abs2(v1);
-    g[2].r += abs2(v2);
-    g[3].r += abs2(v3);
-    g[4] = g[4] + cmulc(v0, v1);
-    g[5] = g[5] + cmulc(v0, v2);
-    g[6] = g[6] + cmulc(v0, v3);
-    g[7] = g[7] + cmulc(v1, v2);
-    g[8] = g[8] + cmulc(v1, v3);
-    g[9] = g[9] + cmulc(v2, v3);
+    g[0].r = fabs2(v0, g[0].r);
+    g[1].r = fabs2(v1, g[1].r);
+    g[2].r = fabs2(v2, g[2].r);
+    g[3].r = fabs2(v3, g[3].r);
+    g[4] = cfmac(v0, v1, g[4]);
+    g[5] = cfmac(v0, v2, g[5]);
+    g[6] = cfmac(v0, v3, g[6]);
+    g[7] = cfmac(v1, v2, g[7]);
+    g[8] = cfmac(v1, v3, g[8]);
+    g[9] = cfmac(v2, v3, g[9]);
 }
 
 template <typename T>
@@ -357,12 +358,12 @@ __global__ void __launch_bounds__(TNT) k_tile_apply_restrict(const CycleArgs a) 
         const bool own = in && i >= H && i < H + TTX && j >= H && j < H + TTY;
         if (own) {
             const long long gi = (long long)(gy0 + j) * nx + gx0 + i;
-            cx<T> u = L.sinv * (c1 * q0 + cc2 * q1 + cc3 * q2);
+            cx<T> u = L.sinv * cfma(cc3, q2, cfma(cc2, q1, c1 * q0));
             if constexpr (NZ) u = up[gi] - u;
             else u = Z - u;
             u1p[gi] = u;
         }
-        S0[q] = keep(in, q0 + c1 * q1 + cc2 * q2 + cc3 * q3);
+        S0[q] = keep(in, cfma(cc3, q3, cfma(cc2, q2, cfma(c1, q1, q0))));
     });
     __syncthreads();
     // coarse points whose centre (2C + 1) lies on the tile's owned points
@@ -453,7 +454,7 @@ __global__ void __launch_bounds__(TNT) k_tile_apply_out(const CycleArgs a) {
         const int q = j * G::W + i;
         const long long gi = (long long)(gy0 + j) * nx + gx0 + i;
         const cx<T> q2 = L.sinv * tile_apply<T, H>(C, L, S2, i, j);
-        const cx<T> w = S0[q] - L.sinv * (c1 * S1[q] + cc2 * S2[q] + cc3 * q2);
+        const cx<T> w = S0[q] - L.sinv * cfma(cc3, q2, cfma(cc2, S2[q], c1 * S1[q]));
         if constexpr (ACC)
             out[gi] = out[gi].get() + cvt<TO>(w);
         else
