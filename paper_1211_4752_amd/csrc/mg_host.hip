@@ -207,6 +207,11 @@ struct Op {
     hipGraphExec_t exec = nullptr;
     std::vector<hipEvent_t> ev;       // 2 per step, recorded by profiled runs
     bool uploaded = false;
+    // after step `mark` every run records mark_ev (in the graph as an event
+    // node), so that another stream can start its own work once this one
+    // has got that far
+    int mark = -1;
+    hipEvent_t mark_ev = nullptr;
 };
 
 struct OpCache {
@@ -256,6 +261,10 @@ struct mg_ctx {
     Work work;
     Prof prof;
     OpCache cache;
+    // second half of the right-hand sides of a (F)GMRES solve, run on its
+    // own stream half a step behind the first (created on first use)
+    Work work2;
+    hipStream_t stream2 = nullptr;
 };
 
 struct mg_batch {
@@ -344,6 +353,8 @@ void op_release(Op& op) {
     op.exec = nullptr;
     for (hipEvent_t e : op.ev) (void)hipEventDestroy(e);
     op.ev.clear();
+    if (op.mark_ev) (void)hipEventDestroy(op.mark_ev);
+    op.mark_ev = nullptr;
     dfree(op.dtab);
 }
 
@@ -402,7 +413,10 @@ mg_status op_capture(Exec& E, Op& op, hipGraphExec_t* out) {
     hipStream_t cs = E.cache->capture;
     CK(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
     hipError_t err = hipSuccess;
-    for (size_t i = 0; i < op.steps.size() && err == hipSuccess; ++i) err = op.steps[i].fn(cs, op.dtab);
+    for (size_t i = 0; i < op.steps.size() && err == hipSuccess; ++i) {
+        err = op.steps[i].fn(cs, op.dtab);
+        if (err == hipSuccess && (int)i == op.mark) err = hipEventRecord(op.mark_ev, cs);
+    }
     hipGraph_t g = nullptr;
     const hipError_t e2 = hipStreamEndCapture(cs, &g);
     if (err != hipSuccess || e2 != hipSuccess) {
@@ -429,6 +443,7 @@ mg_status op_run(Exec& E, Op& op) {
         op.uploaded = true;
     }
     const bool prof = profiling(E);
+    if (op.mark >= 0 && !op.mark_ev) CK(hipEventCreateWithFlags(&op.mark_ev, hipEventDisableTiming));
     if (prof)
         while (op.ev.size() < 2 * op.steps.size()) {
             hipEvent_t e;
@@ -440,6 +455,7 @@ mg_status op_run(Exec& E, Op& op) {
             if (prof) CK(hipEventRecord(op.ev[2 * i], E.s));
             CK(op.steps[i].fn(E.s, op.dtab));
             if (prof) CK(hipEventRecord(op.ev[2 * i + 1], E.s));
+            if ((int)i == op.mark) CK(hipEventRecord(op.mark_ev, E.s));
         }
         return MG_OK;
     }
@@ -1426,6 +1442,7 @@ mg_status rec_gmres_cycle(Rec& R, int dir, const std::vector<Item>& it, const st
         for (size_t k = 0; k < n; ++k)
             l0[k] = L0{basis(it[k], j), 1.0, scale_of(it[k]) + j, nullptr, flexible ? zbasis(it[k], j) : zvec(it[k])};
         CKS(rec_cycle(R, dir, it, G_LIVE, l0, false, false, nullptr));
+        if (j == 0) R.op->mark = (int)R.op->steps.size() - 1;
         std::vector<int> c1, c2;
         CKS(rec_matvec_dot(R, dir, it, G_LIVE, flexible, j, &c1));
         CKS(rec_gm(R, mg::GM_H, it, &c1, j));
@@ -1585,83 +1602,140 @@ mg_status read_flags(Exec& E, Work& w, int n) {
     return MG_OK;
 }
 
+// Items of a solve that share a work space and a stream.  Several groups
+// of one solve run concurrently, each on its own stream: the body of group
+// g > 0 starts once group 0 has finished the first cycle of its restart
+// cycle, so one group's latency-bound coarse levels overlap the other's
+// bandwidth-bound Arnoldi passes.  Every launch of a group covers only its
+// items, and each item's sums keep their order (partials per item), so the
+// results do not depend on the grouping.
+struct Group {
+    Exec E;
+    Work* w;
+    std::vector<Item> it;
+    std::vector<cx<double>*> U;
+    std::vector<const cx<double>*> F;
+    int off = 0;   // position of the group's first item among the solve's items
+    Op* init = nullptr;
+    Op* body = nullptr;
+};
+
 // Solve for the items: device-driven (F)GMRES(m) or standalone cycles.
-mg_status solve_items(Exec& E, Work& w, int dir, const std::vector<Item>& it, const std::vector<cx<double>*>& U,
-                      const std::vector<const cx<double>*>& F, int mode, double rtol, int maxit, int restart,
-                      int* iters, double* hist) {
+mg_status solve_groups(std::vector<Group>& G, int dir, int mode, double rtol, int maxit, int restart, int* iters,
+                       double* hist) {
     if (maxit < 0 || !(rtol >= 0.0)) return MG_E_INVAL;
-    const int n = (int)it.size();
-    if (n > w.items) return MG_E_STATE;
+    if (G.empty() || G[0].it.empty()) return MG_E_INVAL;
     const bool gm = mode == MG_MODE_GMRES || mode == MG_MODE_FGMRES;
     if (!gm && mode != MG_MODE_STANDALONE) return MG_E_INVAL;
     if (gm && (restart < 1 || restart > MAX_RESTART)) return MG_E_INVAL;
-    const bool flexible = gm && (mode == MG_MODE_FGMRES || it[0].c->gsmooth);
-    const int dim = it[0].c->dim;
-    const bool mixed = it[0].c->mixed;
-    CK(hipStreamSynchronize(E.s));
-    if (gm)
-        for (const Item& I : it) {
-            CKS(ensure_basis(I.c, restart, flexible));
-            CKS(tune_arnoldi(I.c, restart));
-        }
-    const size_t hstride = (size_t)maxit + 1;
-    CKS(ensure_hist(w, (size_t)n * hstride));
-    *w.prm_h = mg::GmParams{rtol, w.hist, (int)hstride, maxit, gm ? restart : 0, flexible ? 1 : 0};
-    CK(hipMemcpyAsync(w.prm, w.prm_h, sizeof(mg::GmParams), hipMemcpyHostToDevice, E.s));
-
-    Op *init = nullptr, *body = nullptr;
-    std::vector<uintptr_t> k0 = item_key(gm ? K_GM_INIT : K_SA_INIT, dir, it, U, F);
-    std::vector<uintptr_t> k1 = item_key(gm ? K_GM_CYCLE : K_SA_CHUNK, dir, it, U, F);
-    if (gm) {
-        k1.push_back((uintptr_t)restart);
-        k1.push_back((uintptr_t)flexible);
+    for (const Group& g : G) {
+        if ((int)g.it.size() > g.w->items || g.it.empty()) return MG_E_STATE;
+        if (G.size() > 1 && (profiling(g.E) || !g.E.graphs)) return MG_E_STATE;
     }
-    CKS(cached(*E.cache, k0, &init, [&](Op& op) {
-        Rec R{&op, &w, dim, mixed, TAG_ALWAYS};
-        return gm ? rec_gmres_init(R, dir, it, U, F) : rec_sa_init(R, it, U, F);
-    }));
-    CKS(cached(*E.cache, k1, &body, [&](Op& op) {
-        Rec R{&op, &w, dim, mixed, TAG_ALWAYS};
-        return gm ? rec_gmres_cycle(R, dir, it, U, F, restart, flexible) : rec_sa_chunk(R, dir, it, U, F, SA_CHUNK);
-    }));
-    CKS(op_run(E, *init));
-    CKS(read_flags(E, w, n));
-    std::vector<int> before(n, 0), live(n, 0), sbefore(n, 0);
-    CKS(op_collect(E, *init, &live));
-    // every run of the body advances each running item by at least one step
+    const Item& I0 = G[0].it[0];
+    const bool flexible = gm && (mode == MG_MODE_FGMRES || I0.c->gsmooth);
+    const int dim = I0.c->dim;
+    const bool mixed = I0.c->mixed;
+    for (const Group& g : G) CK(hipStreamSynchronize(g.E.s));
+    if (gm)
+        for (const Group& g : G)
+            for (const Item& I : g.it) {
+                CKS(ensure_basis(I.c, restart, flexible));
+                CKS(tune_arnoldi(I.c, restart));
+            }
+    const size_t hstride = (size_t)maxit + 1;
+    for (Group& g : G) {
+        Work& w = *g.w;
+        const int n = (int)g.it.size();
+        CKS(ensure_hist(w, (size_t)n * hstride));
+        *w.prm_h = mg::GmParams{rtol, w.hist, (int)hstride, maxit, gm ? restart : 0, flexible ? 1 : 0};
+        CK(hipMemcpyAsync(w.prm, w.prm_h, sizeof(mg::GmParams), hipMemcpyHostToDevice, g.E.s));
+        std::vector<uintptr_t> k0 = item_key(gm ? K_GM_INIT : K_SA_INIT, dir, g.it, g.U, g.F);
+        std::vector<uintptr_t> k1 = item_key(gm ? K_GM_CYCLE : K_SA_CHUNK, dir, g.it, g.U, g.F);
+        if (gm) {
+            k1.push_back((uintptr_t)restart);
+            k1.push_back((uintptr_t)flexible);
+        }
+        CKS(cached(*g.E.cache, k0, &g.init, [&](Op& op) {
+            Rec R{&op, &w, dim, mixed, TAG_ALWAYS};
+            return gm ? rec_gmres_init(R, dir, g.it, g.U, g.F) : rec_sa_init(R, g.it, g.U, g.F);
+        }));
+        CKS(cached(*g.E.cache, k1, &g.body, [&](Op& op) {
+            Rec R{&op, &w, dim, mixed, TAG_ALWAYS};
+            return gm ? rec_gmres_cycle(R, dir, g.it, g.U, g.F, restart, flexible)
+                      : rec_sa_chunk(R, dir, g.it, g.U, g.F, SA_CHUNK);
+        }));
+    }
+    for (Group& g : G) CKS(op_run(g.E, *g.init));
+    for (Group& g : G) CKS(read_flags(g.E, *g.w, (int)g.it.size()));
+    if (G.size() == 1) {
+        std::vector<int> live(G[0].it.size(), 0);
+        CKS(op_collect(G[0].E, *G[0].init, &live));
+    }
+    std::vector<int> before, live, sbefore;
+    // every run of the bodies advances each running item by at least one step
     const long long guard = (long long)maxit + 2;
     for (long long run = 0;; ++run) {
+        std::vector<char> act(G.size(), 0);
         bool any = false;
-        for (int k = 0; k < n; ++k) {
-            const mg::GmFlags& f = w.gfl_h[k];
-            before[k] = f.its;
-            sbefore[k] = f.state;
-            any = any || (gm ? f.state == 0 : f.live != 0);
-        }
+        for (size_t q = 0; q < G.size(); ++q)
+            for (size_t k = 0; k < G[q].it.size(); ++k) {
+                const mg::GmFlags& f = G[q].w->gfl_h[k];
+                if (gm ? f.state == 0 : f.live != 0) act[q] = 1;
+            }
+        for (char a : act) any = any || a;
         if (!any) break;
         if (run >= guard) return MG_E_STATE;
-        CKS(op_run(E, *body));
-        CKS(read_flags(E, w, n));
-        if (profiling(E)) {
+        if (G.size() == 1) {
+            const Group& g = G[0];
+            const int n = (int)g.it.size();
+            before.assign(n, 0);
+            sbefore.assign(n, 0);
             for (int k = 0; k < n; ++k) {
-                const mg::GmFlags& f = w.gfl_h[k];
+                before[k] = g.w->gfl_h[k].its;
+                sbefore[k] = g.w->gfl_h[k].state;
+            }
+        }
+        for (size_t q = 0; q < G.size(); ++q) {
+            if (!act[q]) continue;
+            if (q > 0 && act[0] && G[0].body->mark_ev) CK(hipStreamWaitEvent(G[q].E.s, G[0].body->mark_ev, 0));
+            CKS(op_run(G[q].E, *G[q].body));
+        }
+        for (Group& g : G) CKS(read_flags(g.E, *g.w, (int)g.it.size()));
+        if (G.size() == 1 && profiling(G[0].E)) {
+            Group& g = G[0];
+            const int n = (int)g.it.size();
+            live.assign(n, 0);
+            for (int k = 0; k < n; ++k) {
+                const mg::GmFlags& f = g.w->gfl_h[k];
                 live[k] = f.its - before[k];
                 if (!gm && sbefore[k] == 0 && (f.state == 1 || f.state == 3)) live[k]++;
             }
-            CKS(op_collect(E, *body, &live));
+            CKS(op_collect(g.E, *g.body, &live));
         }
     }
-    if (hist) CK(hipMemcpyAsync(hist, w.hist, (size_t)n * hstride * sizeof(double), hipMemcpyDeviceToHost, E.s));
-    CK(hipStreamSynchronize(E.s));
+    for (Group& g : G)
+        if (hist)
+            CK(hipMemcpyAsync(hist + (size_t)g.off * hstride, g.w->hist, g.it.size() * hstride * sizeof(double),
+                              hipMemcpyDeviceToHost, g.E.s));
+    for (Group& g : G) CK(hipStreamSynchronize(g.E.s));
     mg_status ret = MG_OK;
-    for (int k = 0; k < n; ++k) {
-        const mg::GmFlags& f = w.gfl_h[k];
-        if (iters) iters[k] = f.its;
-        const int state = (!gm && f.state == 0) ? 2 : f.state;
-        if (state == 3) ret = MG_E_DIVERGED;
-        else if (state == 2 && ret == MG_OK) ret = MG_NOT_CONVERGED;
-    }
+    for (const Group& g : G)
+        for (size_t k = 0; k < g.it.size(); ++k) {
+            const mg::GmFlags& f = g.w->gfl_h[k];
+            if (iters) iters[g.off + k] = f.its;
+            const int state = (!gm && f.state == 0) ? 2 : f.state;
+            if (state == 3) ret = MG_E_DIVERGED;
+            else if (state == 2 && ret == MG_OK) ret = MG_NOT_CONVERGED;
+        }
     return ret;
+}
+
+mg_status solve_items(Exec& E, Work& w, int dir, const std::vector<Item>& it, const std::vector<cx<double>*>& U,
+                      const std::vector<const cx<double>*>& F, int mode, double rtol, int maxit, int restart,
+                      int* iters, double* hist) {
+    std::vector<Group> G(1, Group{E, &w, it, U, F, 0, nullptr, nullptr});
+    return solve_groups(G, dir, mode, rtol, maxit, restart, iters, hist);
 }
 
 Exec ctx_exec(mg_ctx* c) { return Exec{c->stream, &c->prof, &c->cache, true}; }
@@ -1679,7 +1753,27 @@ mg_status ctx_solve(mg_ctx* c, int dir, double* u, const double* f, int mode, do
         F.push_back((const cx<double>*)f + (size_t)r * N);
     }
     Exec E = ctx_exec(c);
-    return solve_items(E, c->work, dir, it, U, F, mode, rtol, maxit, restart, iters, hist);
+    const bool gm = mode == MG_MODE_GMRES || mode == MG_MODE_FGMRES;
+    if (!gm || c->nrhs < 2 || profiling(E))
+        return solve_items(E, c->work, dir, it, U, F, mode, rtol, maxit, restart, iters, hist);
+    // two groups of right-hand sides, the second on its own stream
+    const int h = c->nrhs / 2;
+    if (!c->stream2) CK(hipStreamCreateWithFlags(&c->stream2, hipStreamNonBlocking));
+    if (c->work2.items < c->nrhs - h || c->work2.bstride != c->work.bstride) {
+        CK(hipStreamSynchronize(c->stream2));
+        work_free(c->work2);
+        CKS(work_alloc(c->work2, c->nrhs - h, c->work.bstride));
+    }
+    Exec E2 = E;
+    E2.s = c->stream2;
+    std::vector<Group> G;
+    G.push_back(Group{E, &c->work, std::vector<Item>(it.begin(), it.begin() + h),
+                      std::vector<cx<double>*>(U.begin(), U.begin() + h),
+                      std::vector<const cx<double>*>(F.begin(), F.begin() + h), 0, nullptr, nullptr});
+    G.push_back(Group{E2, &c->work2, std::vector<Item>(it.begin() + h, it.end()),
+                      std::vector<cx<double>*>(U.begin() + h, U.end()),
+                      std::vector<const cx<double>*>(F.begin() + h, F.end()), h, nullptr, nullptr});
+    return solve_groups(G, dir, mode, rtol, maxit, restart, iters, hist);
 }
 // The GMRES(3) smoother's buffer table of a context (pointers per rhs and
 // level).
@@ -1761,6 +1855,9 @@ void release(mg_ctx* c) {
     if (c->stage_ev) (void)hipEventDestroy(c->stage_ev);
     c->stage_ev = nullptr;
     work_free(c->work);
+    work_free(c->work2);
+    if (c->stream2) (void)hipStreamDestroy(c->stream2);
+    c->stream2 = nullptr;
 }
 
 
