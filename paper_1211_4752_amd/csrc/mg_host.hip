@@ -221,6 +221,10 @@ struct OpCache {
 
 }  // namespace
 
+// Groups of right-hand sides a multi-rhs (F)GMRES solve of one context is
+// split into (each on its own stream, see solve_groups).
+constexpr int SOLVE_GROUPS = 3;
+
 struct mg_ctx {
     mg_params p{};
     int dim = 2;
@@ -261,16 +265,18 @@ struct mg_ctx {
     Work work;
     Prof prof;
     OpCache cache;
-    // second half of the right-hand sides of a (F)GMRES solve, run on its
-    // own stream half a step behind the first (created on first use)
-    Work work2;
-    hipStream_t stream2 = nullptr;
+    // further groups of the right-hand sides of a (F)GMRES solve, each on
+    // its own stream (created on first use)
+    Work workg[SOLVE_GROUPS - 1];
+    hipStream_t streamg[SOLVE_GROUPS - 1] = {};
 };
 
 struct mg_batch {
     std::vector<mg_ctx*> ctxs;
     Work work;
     OpCache cache;
+    Work workg[SOLVE_GROUPS - 1];             // as in mg_ctx
+    hipStream_t streamg[SOLVE_GROUPS - 1] = {};
 };
 
 namespace {
@@ -1604,8 +1610,8 @@ mg_status read_flags(Exec& E, Work& w, int n) {
 
 // Items of a solve that share a work space and a stream.  Several groups
 // of one solve run concurrently, each on its own stream: the body of group
-// g > 0 starts once group 0 has finished the first cycle of its restart
-// cycle, so one group's latency-bound coarse levels overlap the other's
+// g > 0 starts once group g - 1 has finished the first cycle of its restart
+// cycle, so one group's latency-bound coarse levels overlap another's
 // bandwidth-bound Arnoldi passes.  Every launch of a group covers only its
 // items, and each item's sums keep their order (partials per item), so the
 // results do not depend on the grouping.
@@ -1698,7 +1704,8 @@ mg_status solve_groups(std::vector<Group>& G, int dir, int mode, double rtol, in
         }
         for (size_t q = 0; q < G.size(); ++q) {
             if (!act[q]) continue;
-            if (q > 0 && act[0] && G[0].body->mark_ev) CK(hipStreamWaitEvent(G[q].E.s, G[0].body->mark_ev, 0));
+            if (q > 0 && act[q - 1] && G[q - 1].body->mark_ev)
+                CK(hipStreamWaitEvent(G[q].E.s, G[q - 1].body->mark_ev, 0));
             CKS(op_run(G[q].E, *G[q].body));
         }
         for (Group& g : G) CKS(read_flags(g.E, *g.w, (int)g.it.size()));
@@ -1738,6 +1745,51 @@ mg_status solve_items(Exec& E, Work& w, int dir, const std::vector<Item>& it, co
     return solve_groups(G, dir, mode, rtol, maxit, restart, iters, hist);
 }
 
+// Splits the items of a multi-rhs (F)GMRES solve into up to SOLVE_GROUPS
+// groups of about equal points, in order; group 0 runs on E with w, group
+// g > 0 on streamg[g - 1] with workg[g - 1] (both created or grown here).
+mg_status make_groups(const Exec& E, Work& w, Work* workg, hipStream_t* streamg, const std::vector<Item>& it,
+                      const std::vector<cx<double>*>& U, const std::vector<const cx<double>*>& F,
+                      std::vector<Group>& G) {
+    const int n = (int)it.size();
+    const int ng = std::min(n, SOLVE_GROUPS);
+    double tot = 0.0;
+    for (const Item& I : it) tot += (double)I.c->lv[0].N;
+    std::vector<int> cut(ng + 1, n);
+    cut[0] = 0;
+    double acc = 0.0;
+    int g = 1;
+    for (int k = 0; k < n && g < ng; ++k) {
+        acc += (double)it[k].c->lv[0].N;
+        // close group g - 1 after item k once it holds its share, leaving
+        // at least one item for each later group
+        if (acc >= tot * g / ng - 0.5 && n - (k + 1) >= ng - g) cut[g++] = k + 1;
+    }
+    for (; g < ng; ++g) cut[g] = std::max(cut[g - 1] + 1, n - (ng - g));
+    for (int q = 0; q < ng; ++q) {
+        const int lo = cut[q], hi = cut[q + 1];
+        if (hi <= lo) return MG_E_STATE;
+        Exec Eg = E;
+        Work* wg = &w;
+        if (q > 0) {
+            hipStream_t& sg = streamg[q - 1];
+            Work& wq = workg[q - 1];
+            if (!sg) CK(hipStreamCreateWithFlags(&sg, hipStreamNonBlocking));
+            if (wq.items < hi - lo || wq.bstride != w.bstride) {
+                CK(hipStreamSynchronize(sg));
+                work_free(wq);
+                CKS(work_alloc(wq, hi - lo, w.bstride));
+            }
+            Eg.s = sg;
+            wg = &wq;
+        }
+        G.push_back(Group{Eg, wg, std::vector<Item>(it.begin() + lo, it.begin() + hi),
+                          std::vector<cx<double>*>(U.begin() + lo, U.begin() + hi),
+                          std::vector<const cx<double>*>(F.begin() + lo, F.begin() + hi), lo, nullptr, nullptr});
+    }
+    return MG_OK;
+}
+
 Exec ctx_exec(mg_ctx* c) { return Exec{c->stream, &c->prof, &c->cache, true}; }
 
 mg_status ctx_solve(mg_ctx* c, int dir, double* u, const double* f, int mode, double rtol, int maxit,
@@ -1756,23 +1808,8 @@ mg_status ctx_solve(mg_ctx* c, int dir, double* u, const double* f, int mode, do
     const bool gm = mode == MG_MODE_GMRES || mode == MG_MODE_FGMRES;
     if (!gm || c->nrhs < 2 || profiling(E))
         return solve_items(E, c->work, dir, it, U, F, mode, rtol, maxit, restart, iters, hist);
-    // two groups of right-hand sides, the second on its own stream
-    const int h = c->nrhs / 2;
-    if (!c->stream2) CK(hipStreamCreateWithFlags(&c->stream2, hipStreamNonBlocking));
-    if (c->work2.items < c->nrhs - h || c->work2.bstride != c->work.bstride) {
-        CK(hipStreamSynchronize(c->stream2));
-        work_free(c->work2);
-        CKS(work_alloc(c->work2, c->nrhs - h, c->work.bstride));
-    }
-    Exec E2 = E;
-    E2.s = c->stream2;
     std::vector<Group> G;
-    G.push_back(Group{E, &c->work, std::vector<Item>(it.begin(), it.begin() + h),
-                      std::vector<cx<double>*>(U.begin(), U.begin() + h),
-                      std::vector<const cx<double>*>(F.begin(), F.begin() + h), 0, nullptr, nullptr});
-    G.push_back(Group{E2, &c->work2, std::vector<Item>(it.begin() + h, it.end()),
-                      std::vector<cx<double>*>(U.begin() + h, U.end()),
-                      std::vector<const cx<double>*>(F.begin() + h, F.end()), h, nullptr, nullptr});
+    CKS(make_groups(E, c->work, c->workg, c->streamg, it, U, F, G));
     return solve_groups(G, dir, mode, rtol, maxit, restart, iters, hist);
 }
 // The GMRES(3) smoother's buffer table of a context (pointers per rhs and
@@ -1855,9 +1892,11 @@ void release(mg_ctx* c) {
     if (c->stage_ev) (void)hipEventDestroy(c->stage_ev);
     c->stage_ev = nullptr;
     work_free(c->work);
-    work_free(c->work2);
-    if (c->stream2) (void)hipStreamDestroy(c->stream2);
-    c->stream2 = nullptr;
+    for (int g = 0; g < SOLVE_GROUPS - 1; ++g) {
+        work_free(c->workg[g]);
+        if (c->streamg[g]) (void)hipStreamDestroy(c->streamg[g]);
+        c->streamg[g] = nullptr;
+    }
 }
 
 
@@ -2539,7 +2578,12 @@ mg_status mg_batch_solve(mg_batch* b, double* const* u, const double* const* f, 
     }
     mg_ctx* c0 = b->ctxs[0];
     Exec E{c0->stream, &c0->prof, &b->cache, true};
-    return solve_items(E, b->work, 0, it, U, F, mode, rtol, maxit, restart, iters, hist);
+    const bool gm = mode == MG_MODE_GMRES || mode == MG_MODE_FGMRES;
+    if (!gm || it.size() < 2 || profiling(E))
+        return solve_items(E, b->work, 0, it, U, F, mode, rtol, maxit, restart, iters, hist);
+    std::vector<Group> G;
+    CKS(make_groups(E, b->work, b->workg, b->streamg, it, U, F, G));
+    return solve_groups(G, 0, mode, rtol, maxit, restart, iters, hist);
 }
 
 void mg_batch_destroy(mg_batch* b) {
@@ -2547,6 +2591,11 @@ void mg_batch_destroy(mg_batch* b) {
     if (!b->ctxs.empty()) (void)hipStreamSynchronize(b->ctxs[0]->stream);
     cache_free(b->cache);
     work_free(b->work);
+    for (int g = 0; g < SOLVE_GROUPS - 1; ++g) {
+        if (b->streamg[g]) (void)hipStreamSynchronize(b->streamg[g]);
+        work_free(b->workg[g]);
+        if (b->streamg[g]) (void)hipStreamDestroy(b->streamg[g]);
+    }
     delete b;
 }
 
