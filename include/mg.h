@@ -166,7 +166,10 @@ mg_status mg_cycle_noalloc(mg_ctx *c, double *u_dev, const double *f_dev,
  * step), unused tail entries set to -1.  Standalone mode stops after the
  * first cycle whose incoming iterate met rtol.  Returns MG_OK when every rhs
  * converged, MG_NOT_CONVERGED when one reached maxit, MG_E_DIVERGED when
- * one diverged (others still hold their last iterate). */
+ * one diverged (others still hold their last iterate).  The call waits for
+ * the context's stream on entry and returns once all its work is done; a
+ * GMRES/FGMRES solve of several right-hand sides runs up to three groups of
+ * them concurrently on streams of the library (same results as one group). */
 mg_status mg_solve(mg_ctx *c, double *u_dev, const double *f_dev, int mode,
                    double rtol, int maxit, int restart, int *iters,
                    double *hist);
