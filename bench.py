@@ -19,7 +19,7 @@ process (events captured inside a HIP graph cannot be timed).
 Errors against FP64: a solve to a relative residual of 1e-6 is itself only
 about 1e-5 from the exact discrete solution, in any precision, so each
 mixed-precision result is also solved to 1e-9 and compared with the
-complex128 solution to 1e-12 (the benchmark spec's bar is 1e-6).
+complex128 solution to 1e-12 (the mixed-precision bar is an error of 1e-6).
 
 Extras: the omega-Jacobi form of the same cycle (it does not reach 1e-6 on
 this 2D workload: reported capped), mixed precision with its error against
@@ -513,7 +513,7 @@ def only(args, mg, W, torch, dev):
     elif args.only == "c4":
         res, _ = batched(mg, W, torch, dev, profile=False)
     elif args.only == "c4_jacobi_511":
-        # the benchmark spec's omega-Jacobi cycle on the 64-source 511^2 member
+        # the omega-Jacobi cycle on the 64-source 511^2 member
         wl = W.heterogeneous_2d(511, 64, source_seed=4)
         s = mg.Solver(wl.n, wl.h, torch.tensor(wl.k2, dtype=torch.float64, device=dev), ecs=wl.ecs,
                       ecs_angle=wl.ecs_angle, theta_max=wl.theta_max, nrhs=64, smoother="jacobi",
