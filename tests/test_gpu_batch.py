@@ -174,6 +174,34 @@ def test_batch_coefficient_solve_reads_own_partials():
         assert all(np.array_equal(x, y) for x, y in zip(hists[i], h1)), i
 
 
+@pytest.mark.parametrize("smoother,n,rtol", [("gmres3", 255, 1e-8), ("jacobi", 127, 1e-6)])
+def test_solve_groups_equal_one_group(smoother, n, rtol):
+    """A multi-rhs GMRES solve runs its right-hand sides in up to three
+    groups on separate streams, one V-cycle apart; a profiled solve keeps
+    them in one group.  Results, histories and step counts must agree bit
+    for bit (every sum is per right-hand side).  Five sources: the groups
+    hold 2, 1 and 2 of them."""
+    wl = W.heterogeneous_2d(n, 5, ecs=(n + 1) // 32)
+    s = solver_of(wl, smoother=smoother)
+    f = gpu(wl.f)
+    runs = []
+    for prof in (False, True, False):
+        u = s.empty()
+        if prof:
+            s.profile(True)
+        st, its, hists = s.solve(u, f, mode="gmres", rtol=rtol, maxit=3000, restart=20)
+        if prof:
+            s.profile(False)
+        assert st == "converged", st
+        runs.append((u.cpu(), its, hists))
+    say(smoother, "steps", runs[0][1])
+    for u, its, hists in runs[1:]:
+        assert its == runs[0][1]
+        assert torch.equal(u, runs[0][0])
+        assert all(np.array_equal(a, b) for a, b in zip(hists, runs[0][2]))
+    s.close()
+
+
 def test_batch_standalone_matches_single():
     # constant kh = 0.3 with a wide layer: the standalone cycle converges
     wls = [W.constant_2d(127, 0.3, ecs=16), W.constant_2d(255, 0.3, ecs=32), W.constant_2d(191, 0.3, ecs=24)]
