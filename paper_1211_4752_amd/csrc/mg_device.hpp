@@ -362,6 +362,38 @@ hipError_t launch_reduce(const ReduceArgs& a, int nslots, bool real, hipStream_t
 // GMRES(3) smoother passes (mg_smooth.hip).  level0: f is complex double.
 constexpr int NUM_GRAM = 10;
 hipError_t launch_sm_power(int dim, bool f32, bool level0, int stage, const SmArgs& a, hipStream_t s);
+// 3D finest level: the same powers as a z-march over columns of PZX x PZY
+// points and PZC planes; one workgroup per column piece, power_z_tiles(n)
+// per slot (block0 counts them).
+constexpr int PZX = 64, PZY = 4, PZC = 32;
+constexpr int PZW = PZX + 2, PZH = PZY + 2;   // an LDS plane with its ring
+constexpr int PZR = 2 * PZX + 2 * PZH;        // points of the ring
+__host__ __device__ inline void pz_counts(const int n[3], int& ntx, int& nty, int& ntz) {
+    ntx = (n[0] + PZX - 1) / PZX;
+    nty = (n[1] + PZY - 1) / PZY;
+    ntz = (n[2] + PZC - 1) / PZC;
+}
+// ring point r < PZR of a column: its LDS position (x, then y, with the
+// ring at 0 and PZW - 1 / PZH - 1)
+__host__ __device__ inline void pz_ring(int r, int& lx, int& ly) {
+    if (r < PZX) {
+        lx = r + 1;
+        ly = 0;
+    } else if (r < 2 * PZX) {
+        lx = r - PZX + 1;
+        ly = PZH - 1;
+    } else if (r < 2 * PZX + PZH) {
+        lx = 0;
+        ly = r - 2 * PZX;
+    } else {
+        lx = PZW - 1;
+        ly = r - 2 * PZX - PZH;
+    }
+}
+int power_z_tiles(const int n[3]);
+hipError_t launch_sm_power_z(bool f32, bool level0, int stage, const SmArgs& a, hipStream_t s);
+// and the Gram partials of that level the same way (one per column piece)
+hipError_t launch_sm_gram_z(bool f32, bool level0, const SmArgs& a, hipStream_t s);
 hipError_t launch_sm_gram(int dim, bool f32, bool level0, const SmArgs& a, hipStream_t s);
 hipError_t launch_sm_coef(bool f32, const SmCoefArgs& a, int nslots, hipStream_t s);
 hipError_t launch_sm_apply_restrict(int dim, bool f32, bool level0, bool nonzero, int shape, const CycleArgs& a,

@@ -985,6 +985,35 @@ mg_status rec_smooth_coef(Rec& R, int d, int phase, const std::vector<Item>& it,
     const size_t off = put(*R.op, sl);
     const int dim = R.dim;
     const bool mixed = R.mixed;
+    if (fine && dim == 3) {
+        // the finest 3D level marches along z: its own workgroup count (and
+        // Gram partial count) per slot
+        std::vector<mg::SmSlot> slz(sl);
+        std::vector<int> cz(who.size());
+        int nbz = 0;
+        for (size_t q = 0; q < who.size(); ++q) {
+            slz[q].block0 = nbz;
+            cz[q] = mg::power_z_tiles(it[who[q]].c->lv[d].n);
+            if (cz[q] > R.w->bstride) return MG_E_STATE;
+            nbz += cz[q];
+        }
+        mg::SmArgs az = a;
+        az.st.nblocks = nbz;
+        const size_t offz = put(*R.op, slz);
+        for (int stage = 1; stage <= 2; ++stage)
+            add(R, MG_K_SMOOTH_POWER_FINE, stage == 1 ? ib1 : ib2, [=](hipStream_t s, const char* base) {
+                mg::SmArgs b = az;
+                b.st.s = (const mg::SmSlot*)(base + offz);
+                return mg::launch_sm_power_z(mixed, true, stage, b, s);
+            });
+        add(R, phase ? MG_K_SMOOTH_GRAM_POST_FINE : MG_K_SMOOTH_GRAM_FINE, ibg, [=](hipStream_t s, const char* base) {
+            mg::SmArgs b = az;
+            b.st.s = (const mg::SmSlot*)(base + offz);
+            return mg::launch_sm_gram_z(mixed, true, b, s);
+        });
+        rec_coef(R, d, phase, it, who, cz, gk);
+        return MG_OK;
+    }
     for (int stage = 1; stage <= 2; ++stage)
         add(R, fine ? MG_K_SMOOTH_POWER_FINE : MG_K_COARSE_LEVELS, stage == 1 ? ib1 : ib2,
             [=](hipStream_t s, const char* base) {
@@ -2034,6 +2063,7 @@ int max_blocks(const mg_ctx* c) {
         mg::sweep_counts(c->dim, sweep, c->lv[0].n, nt);
         m = std::max(m, nt[0] * nt[1] * nt[2]);
     }
+    if (c->dim == 3) m = std::max(m, mg::power_z_tiles(c->lv[0].n));
     for (int per : {16, 32, 64})
         for (bool mv : {false, true})
             m = std::max(m, mg::arnoldi_chunks(mv, c->dim, c->lv[0].n, c->lv[0].N, per / mg::ARN_SPLIT));

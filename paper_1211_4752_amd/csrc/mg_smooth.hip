@@ -94,6 +94,205 @@ __global__ void __launch_bounds__(NT) k_sm_power(const SmArgs a, int stage) {
     }
 }
 
+// q_stage = (A/s) q_{stage-1} on the finest 3D level as a z-march.  A
+// workgroup owns a PZX x PZY column of points and up to PZC of its planes;
+// each thread keeps its point's input on planes z-1, z, z+1 in registers,
+// plane z with a one-point ring goes through LDS (two buffers, one barrier
+// per plane), and the next plane's inputs are requested before the current
+// one is formed.  Every input value is fetched from HBM about once (plus the
+// ring) instead of through the pointwise kernel's scattered z neighbours.
+// The terms and their order are those of stencil_at.
+__device__ __forceinline__ int iclampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
+
+template <typename T, typename TI>
+__device__ __forceinline__ void pz_march(const GLevel<T>& L, GIn<cx<TI>> x, T xs, GOut<cx<T>> y, int b,
+                                         cx<T>* P) {
+    const int nx = L.n[0], ny = L.n[1], nz = L.n[2];
+    const long long nxy = (long long)nx * ny;
+    int ntx, nty, ntz;
+    pz_counts(L.n, ntx, nty, ntz);
+    const int tx = b % ntx, ty = (b / ntx) % nty, tz = b / (ntx * nty);
+    const int x0 = tx * PZX, y0 = ty * PZY, z0 = tz * PZC;
+    const int z1 = z0 + PZC < nz ? z0 + PZC : nz;
+    const int t = (int)threadIdx.x;
+    const int lx = t % PZX, ly = t / PZX;
+    const int gx = x0 + lx, gy = y0 + ly;
+    const bool own = gx < nx && gy < ny;
+    const int cgx = gx < nx ? gx : nx - 1, cgy = gy < ny ? gy : ny - 1;
+    const long long pxy = (long long)cgy * nx + cgx;
+    // ring point of this thread (t < PZR): LDS position and clamped grid index
+    const bool ring = t < PZR;
+    int rlx = 0, rly = 0;
+    pz_ring(ring ? t : 0, rlx, rly);
+    const int rgx = iclampi(x0 + rlx - 1, 0, nx - 1), rgy = iclampi(y0 + rly - 1, 0, ny - 1);
+    const long long rxy = (long long)rgy * nx + rgx;
+    auto plane = [&](int z) { return (long long)iclampi(z, 0, nz - 1) * nxy; };
+    // x and y coefficients of this thread's point, the masks of its neighbours
+    const cx<T> cmx = L.cm[0][cgx], cpx = L.cp[0][cgx], c0x = L.c0[0][cgx];
+    const cx<T> cmy = L.cm[1][cgy], cpy = L.cp[1][cgy], c0y = L.c0[1][cgy];
+    const bool bxm = gx > 0, bxp = gx < nx - 1, bym = gy > 0, byp = gy < ny - 1;
+    const int c = (ly + 1) * PZW + lx + 1;
+    cx<T> xm = cvt<T>(x[plane(z0 - 1) + pxy]);
+    cx<T> xc = cvt<T>(x[plane(z0) + pxy]);
+    cx<T> xp = cvt<T>(x[plane(z0 + 1) + pxy]);
+    cx<T> rc = cvt<T>(x[plane(z0) + rxy]);
+    T k2c = L.k2[plane(z0) + pxy];
+    for (int z = z0; z < z1; ++z) {
+        // inputs of the next plane first
+        const cx<T> xn = cvt<T>(x[plane(z + 2) + pxy]);
+        const cx<T> rn = cvt<T>(x[plane(z + 1) + rxy]);
+        const T k2n = L.k2[plane(z + 1) + pxy];
+        const cx<T> cmz = L.cm[2][z], cpz = L.cp[2][z], c0z = L.c0[2][z];
+        cx<T>* Pb = P + (z & 1) * (PZW * PZH);
+        Pb[c] = xc;
+        if (ring) Pb[rly * PZW + rlx] = rc;
+        __syncthreads();
+        const bool bzm = z > 0, bzp = z < nz - 1;
+        cx<T> d = c0x + c0y;
+        d = d + c0z;
+        d = d - k2c * L.sigma;
+        cx<T> ax = d * xc;
+        ax = ax + masked(bxm, cmx) * Pb[c - 1];
+        ax = ax + masked(bxp, cpx) * Pb[c + 1];
+        ax = ax + masked(bym, cmy) * Pb[c - PZW];
+        ax = ax + masked(byp, cpy) * Pb[c + PZW];
+        ax = ax + masked(bzm, cmz) * xm;
+        ax = ax + masked(bzp, cpz) * xp;
+        if (own) y[(long long)z * nxy + pxy] = L.sinv * (xs * ax);
+        xm = xc;
+        xc = xp;
+        xp = xn;
+        rc = rn;
+        k2c = k2n;
+    }
+}
+
+template <typename T, typename TQ>
+__global__ void __launch_bounds__(NT) k_sm_power_z(const SmArgs a, int stage) {
+    static_assert(PZX * PZY == NT, "one point of the column per thread");
+    __shared__ cx<T> P[2 * PZW * PZH];
+    const SmPos q = sm_pos(a.st);
+    const SmSlot sl = a.st.s[q.slot];
+    if (gated_off(sl.gate)) return;
+    const GLevel<T> L = glevel(*static_cast<const LevelView<T>*>(sl.lv));
+    const auto y = gout(static_cast<cx<T>*>(sl.sb->q[stage]));
+    if (stage == 1 && sl.f)
+        pz_march<T, TQ>(L, gin(static_cast<const cx<TQ>*>(sl.f)), (T)fscale_of(sl), y, q.b, P);
+    else
+        pz_march<T, T>(L, gin(static_cast<const cx<T>*>(sl.sb->q[stage > 0 ? stage - 1 : 0])), T(1), y, q.b, P);
+}
+
+// Gram partials of q0..q3 on the finest 3D level, q3 = (A/s) q2 formed by
+// the same z-march as k_sm_power_z; one partial per column piece.
+template <typename T, typename TQ>
+__global__ void __launch_bounds__(NT) k_sm_gram_z(const SmArgs a) {
+    __shared__ cx<T> P[2 * PZW * PZH];
+    __shared__ cx<double> sm[(NT / 64) * NUM_GRAM];
+    const SmPos q = sm_pos(a.st);
+    const SmSlot sl = a.st.s[q.slot];
+    if (gated_off(sl.gate)) return;
+    const GLevel<T> L = glevel(*static_cast<const LevelView<T>*>(sl.lv));
+    const SmoothBufs B = *sl.sb;
+    const auto x = gin(static_cast<const cx<T>*>(B.q[2]));
+    const auto q1p = gin(static_cast<const cx<T>*>(B.q[1]));
+    const bool from_f = sl.f != nullptr;
+    const auto fin = gin(static_cast<const cx<TQ>*>(sl.f));
+    const auto q0p = gin(static_cast<const cx<T>*>(B.q[0]));
+    const T fsc = (T)fscale_of(sl);
+    auto q0_at = [&](long long i) { return from_f ? fsc * cvt<T>(fin[i]) : q0p[i]; };
+    const int nx = L.n[0], ny = L.n[1], nz = L.n[2];
+    const long long nxy = (long long)nx * ny;
+    int ntx, nty, ntz;
+    pz_counts(L.n, ntx, nty, ntz);
+    const int b = q.b;
+    const int tx = b % ntx, ty = (b / ntx) % nty, tz = b / (ntx * nty);
+    const int x0 = tx * PZX, y0 = ty * PZY, z0 = tz * PZC;
+    const int z1 = z0 + PZC < nz ? z0 + PZC : nz;
+    const int t = (int)threadIdx.x;
+    const int lx = t % PZX, ly = t / PZX;
+    const int gx = x0 + lx, gy = y0 + ly;
+    const bool own = gx < nx && gy < ny;
+    const int cgx = gx < nx ? gx : nx - 1, cgy = gy < ny ? gy : ny - 1;
+    const long long pxy = (long long)cgy * nx + cgx;
+    const bool ring = t < PZR;
+    int rlx = 0, rly = 0;
+    pz_ring(ring ? t : 0, rlx, rly);
+    const int rgx = iclampi(x0 + rlx - 1, 0, nx - 1), rgy = iclampi(y0 + rly - 1, 0, ny - 1);
+    const long long rxy = (long long)rgy * nx + rgx;
+    auto plane = [&](int z) { return (long long)iclampi(z, 0, nz - 1) * nxy; };
+    const cx<T> cmx = L.cm[0][cgx], cpx = L.cp[0][cgx], c0x = L.c0[0][cgx];
+    const cx<T> cmy = L.cm[1][cgy], cpy = L.cp[1][cgy], c0y = L.c0[1][cgy];
+    const bool bxm = gx > 0, bxp = gx < nx - 1, bym = gy > 0, byp = gy < ny - 1;
+    const int c = (ly + 1) * PZW + lx + 1;
+    cx<double> g[NUM_GRAM];
+#pragma unroll
+    for (int v = 0; v < NUM_GRAM; ++v) g[v] = mk(0.0, 0.0);
+    cx<T> xm = x[plane(z0 - 1) + pxy];
+    cx<T> xc = x[plane(z0) + pxy];
+    cx<T> xp = x[plane(z0 + 1) + pxy];
+    cx<T> rc = x[plane(z0) + rxy];
+    T k2c = L.k2[plane(z0) + pxy];
+    cx<T> a0 = q0_at(plane(z0) + pxy), a1 = q1p[plane(z0) + pxy];
+    for (int z = z0; z < z1; ++z) {
+        const cx<T> xn = x[plane(z + 2) + pxy];
+        const cx<T> rn = x[plane(z + 1) + rxy];
+        const T k2n = L.k2[plane(z + 1) + pxy];
+        const cx<T> a0n = q0_at(plane(z + 1) + pxy), a1n = q1p[plane(z + 1) + pxy];
+        const cx<T> cmz = L.cm[2][z], cpz = L.cp[2][z], c0z = L.c0[2][z];
+        cx<T>* Pb = P + (z & 1) * (PZW * PZH);
+        Pb[c] = xc;
+        if (ring) Pb[rly * PZW + rlx] = rc;
+        __syncthreads();
+        const bool bzm = z > 0, bzp = z < nz - 1;
+        cx<T> d = c0x + c0y;
+        d = d + c0z;
+        d = d - k2c * L.sigma;
+        cx<T> ax = d * xc;
+        ax = ax + masked(bxm, cmx) * Pb[c - 1];
+        ax = ax + masked(bxp, cpx) * Pb[c + 1];
+        ax = ax + masked(bym, cmy) * Pb[c - PZW];
+        ax = ax + masked(byp, cpy) * Pb[c + PZW];
+        ax = ax + masked(bzm, cmz) * xm;
+        ax = ax + masked(bzp, cpz) * xp;
+        if (own) {
+            const cx<double> v0 = cvt<double>(a0), v1 = cvt<double>(a1), v2 = cvt<double>(xc);
+            const cx<double> v3 = cvt<double>(L.sinv * ax);
+            g[0].r = fabs2(v0, g[0].r);
+            g[1].r = fabs2(v1, g[1].r);
+            g[2].r = fabs2(v2, g[2].r);
+            g[3].r = fabs2(v3, g[3].r);
+            g[4] = cfmac(v0, v1, g[4]);
+            g[5] = cfmac(v0, v2, g[5]);
+            g[6] = cfmac(v0, v3, g[6]);
+            g[7] = cfmac(v1, v2, g[7]);
+            g[8] = cfmac(v1, v3, g[8]);
+            g[9] = cfmac(v2, v3, g[9]);
+        }
+        xm = xc;
+        xc = xp;
+        xp = xn;
+        rc = rn;
+        k2c = k2n;
+        a0 = a0n;
+        a1 = a1n;
+    }
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int v = 0; v < NUM_GRAM; ++v) {
+        const double r = wave_sum(g[v].r);
+        const double i = wave_sum(g[v].i);
+        if (lane == 0) sm[wave * NUM_GRAM + v] = mk(r, i);
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < NUM_GRAM) {
+        cx<double> s = mk(0.0, 0.0);
+#pragma unroll
+        for (int w = 0; w < NT / 64; ++w) s = s + sm[w * NUM_GRAM + threadIdx.x];
+        a.part[((long long)q.slot * a.pstride + threadIdx.x) * a.bstride + q.b] = s;
+    }
+}
+
 // Gram partials of q0..q3, accumulated in FP64.
 template <int D, typename T, typename TQ>
 __global__ void __launch_bounds__(NT) k_sm_gram(const SmArgs a) {
@@ -463,6 +662,37 @@ hipError_t launch_sm_power(int dim, bool f32, bool level0, int stage, const SmAr
     }
 #undef PW
     return hipGetLastError();
+}
+
+hipError_t launch_sm_power_z(bool f32, bool level0, int stage, const SmArgs& a, hipStream_t s) {
+    if (a.st.n <= 0) return hipSuccess;
+    if (stage != 1 && stage != 2) return hipErrorInvalidValue;
+    dim3 grid(a.st.nblocks);
+    if (!f32)
+        hipLaunchKernelGGL((k_sm_power_z<double, double>), grid, dim3(NT), 0, s, a, stage);
+    else if (level0)
+        hipLaunchKernelGGL((k_sm_power_z<float, double>), grid, dim3(NT), 0, s, a, stage);
+    else
+        hipLaunchKernelGGL((k_sm_power_z<float, float>), grid, dim3(NT), 0, s, a, stage);
+    return hipGetLastError();
+}
+
+hipError_t launch_sm_gram_z(bool f32, bool level0, const SmArgs& a, hipStream_t s) {
+    if (a.st.n <= 0) return hipSuccess;
+    dim3 grid(a.st.nblocks);
+    if (!f32)
+        hipLaunchKernelGGL((k_sm_gram_z<double, double>), grid, dim3(NT), 0, s, a);
+    else if (level0)
+        hipLaunchKernelGGL((k_sm_gram_z<float, double>), grid, dim3(NT), 0, s, a);
+    else
+        hipLaunchKernelGGL((k_sm_gram_z<float, float>), grid, dim3(NT), 0, s, a);
+    return hipGetLastError();
+}
+
+int power_z_tiles(const int n[3]) {
+    int ntx, nty, ntz;
+    pz_counts(n, ntx, nty, ntz);
+    return ntx * nty * ntz;
 }
 
 hipError_t launch_sm_gram(int dim, bool f32, bool level0, const SmArgs& a, hipStream_t s) {
