@@ -103,6 +103,7 @@ __global__ void __launch_bounds__(NT) k_sm_power(const SmArgs a, int stage) {
 // ring) instead of through the pointwise kernel's scattered z neighbours.
 // The terms and their order are those of stencil_at.
 __device__ __forceinline__ int iclampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
+__device__ __forceinline__ int imin3(int a, int b) { return a < b ? a : b; }
 
 template <typename T, typename TI>
 __device__ __forceinline__ void pz_march(const GLevel<T>& L, GIn<cx<TI>> x, T xs, GOut<cx<T>> y, int b,
@@ -435,23 +436,63 @@ __global__ void __launch_bounds__(NT) k_sm_apply_restrict(const CycleArgs a) {
     cx<T> c1, c2, c3;
     load_coef<T>(B.coef, c1, c2, c3);
 
-    for (int idx = threadIdx.x; idx < NQ; idx += NT) {
-        const int lx = idx % QX;
-        const int rr = idx / QX;
-        const int ly = rr % QY;
-        const int lz = rr / QY;
-        const int gx = x0 - 1 + lx, gy = y0 - 1 + ly;
-        const int gz = (D == 3) ? z0 - 1 + lz : 0;
-        cx<T> v = mk<T>(0, 0);
-        if (gx >= 0 && gx < nx && gy >= 0 && gy < ny && (D == 2 || (gz >= 0 && gz < nz)))
-            v = q2p[((long long)gz * ny + gy) * nx + gx];
-        sq[idx] = v;
+    {
+        // every load of the tile first (clamped index), then the masked
+        // stores: a load under a branch would be waited for on its own
+        constexpr int KQ = (NQ + NT - 1) / NT;
+        cx<T> v[KQ];
+        bool in[KQ];
+#pragma unroll
+        for (int k = 0; k < KQ; ++k) {
+            const int idx = (int)threadIdx.x + k * NT;
+            const int id = idx < NQ ? idx : NQ - 1;
+            const int lx = id % QX;
+            const int rr = id / QX;
+            const int ly = rr % QY;
+            const int lz = rr / QY;
+            const int gx = x0 - 1 + lx, gy = y0 - 1 + ly;
+            const int gz = (D == 3) ? z0 - 1 + lz : 0;
+            in[k] = gx >= 0 && gx < nx && gy >= 0 && gy < ny && (D == 2 || (gz >= 0 && gz < nz));
+            const int cx_ = gx < 0 ? 0 : (gx < nx ? gx : nx - 1);
+            const int cy_ = gy < 0 ? 0 : (gy < ny ? gy : ny - 1);
+            const int cz_ = gz < 0 ? 0 : (gz < nz ? gz : nz - 1);
+            v[k] = q2p[((long long)cz_ * ny + cy_) * nx + cx_];
+        }
+#pragma unroll
+        for (int k = 0; k < KQ; ++k) {
+            const int idx = (int)threadIdx.x + k * NT;
+            if (idx < NQ) sq[idx] = masked(in[k], v[k]);
+        }
     }
     __syncthreads();
 
     const auto u1p = gout(static_cast<cx<T>*>(B.u1));
     const auto up = gin(static_cast<const cx<T>*>(sl.u));
-    for (int idx = threadIdx.x; idx < NR; idx += NT) {
+    // the point loads of every round first (clamped index), then the rounds
+    constexpr int KR = (NR + NT - 1) / NT;
+    cx<T> lq0[KR], lq1[KR], lu[KR];
+    T lk2[KR];
+#pragma unroll
+    for (int k = 0; k < KR; ++k) {
+        const int idx = (int)threadIdx.x + k * NT;
+        const int id = idx < NR ? idx : NR - 1;
+        const int lx = id % RX;
+        const int rr = id / RX;
+        const int ly = rr % RY;
+        const int lz = rr / RY;
+        const int gx = imin3(x0 + lx, nx - 1), gy = imin3(y0 + ly, ny - 1);
+        const int gz = (D == 3) ? imin3(z0 + lz, nz - 1) : 0;
+        const long long g = ((long long)gz * ny + gy) * nx + gx;
+        lq0[k] = f ? fs * cvt<T>(f[g]) : q0p[g];
+        lq1[k] = q1p[g];
+        lk2[k] = L.k2[g];
+        if constexpr (NZ) lu[k] = up[g];
+        else lu[k] = mk<T>(0, 0);
+    }
+#pragma unroll
+    for (int k = 0; k < KR; ++k) {
+        const int idx = (int)threadIdx.x + k * NT;
+        if (idx >= NR) break;
         const int lx = idx % RX;
         const int rr = idx / RX;
         const int ly = rr % RY;
@@ -461,11 +502,11 @@ __global__ void __launch_bounds__(NT) k_sm_apply_restrict(const CycleArgs a) {
         cx<T> r = mk<T>(0, 0);
         if (gx < nx && gy < ny && (D == 2 || gz < nz)) {
             const long long g = ((long long)gz * ny + gy) * nx + gx;
-            const cx<T> q0 = f ? fs * cvt<T>(f[g]) : q0p[g];
-            const cx<T> q1 = q1p[g];
+            const cx<T> q0 = lq0[k];
+            const cx<T> q1 = lq1[k];
             const int c = ((D == 3 ? lz + 1 : 0) * QY + (ly + 1)) * QX + (lx + 1);
             const cx<T> q2 = sq[c];
-            cx<T> aq = diag_at<D>(L, gx, gy, gz, L.k2[g]) * q2 + L.cm[0][gx] * sq[c - 1] +
+            cx<T> aq = diag_at<D>(L, gx, gy, gz, lk2[k]) * q2 + L.cm[0][gx] * sq[c - 1] +
                        L.cp[0][gx] * sq[c + 1] + L.cm[1][gy] * sq[c - QX] + L.cp[1][gy] * sq[c + QX];
             if constexpr (D == 3) aq = aq + L.cm[2][gz] * sq[c - QX * QY] + L.cp[2][gz] * sq[c + QX * QY];
             const cx<T> q3 = L.sinv * aq;
@@ -473,7 +514,7 @@ __global__ void __launch_bounds__(NT) k_sm_apply_restrict(const CycleArgs a) {
             const bool own = lx < TX && ly < TY && (D == 2 || lz < TZ);
             if (own) {
                 cx<T> u = L.sinv * (c1 * q0 + c2 * q1 + c3 * q2);
-                if constexpr (NZ) u = up[g] - u;
+                if constexpr (NZ) u = lu[k] - u;
                 else u = mk<T>(0, 0) - u;
                 u1p[g] = u;
             }
