@@ -586,20 +586,52 @@ __global__ void __launch_bounds__(NT) k_sm_prolong_resid(const CycleArgs a) {
     const auto u1p = gin(static_cast<const cx<T>*>(B.u1));
     const int cxs = x0 / 2 - 1, cys = y0 / 2 - 1, czs = (D == 3) ? z0 / 2 - 1 : 0;
 
-    for (int idx = threadIdx.x; idx < NE; idx += NT) {
-        const int lx = idx % EX;
-        const int rr = idx / EX;
-        const int ly = rr % EY;
-        const int lz = rr / EY;
-        const int Cx = cxs + lx, Cy = cys + ly, Cz = czs + lz;
-        cx<T> v = mk<T>(0, 0);
-        if (Cx >= 0 && Cx < ncx && Cy >= 0 && Cy < ncy && (D == 2 || (Cz >= 0 && Cz < ncz)))
-            v = ec[((long long)Cz * ncy + Cy) * ncx + Cx];
-        se[idx] = v;
+    // every load of a stage first (clamped index), masked at use: a load
+    // under a bounds branch would be waited for on its own
+    {
+        constexpr int KE = (NE + NT - 1) / NT;
+        cx<T> v[KE];
+        bool in[KE];
+#pragma unroll
+        for (int k = 0; k < KE; ++k) {
+            const int idx = (int)threadIdx.x + k * NT;
+            const int id = idx < NE ? idx : NE - 1;
+            const int lx = id % EX;
+            const int rr = id / EX;
+            const int ly = rr % EY;
+            const int lz = rr / EY;
+            const int Cx = cxs + lx, Cy = cys + ly, Cz = czs + lz;
+            in[k] = Cx >= 0 && Cx < ncx && Cy >= 0 && Cy < ncy && (D == 2 || (Cz >= 0 && Cz < ncz));
+            const int ccx = iclampi(Cx, 0, ncx - 1), ccy = iclampi(Cy, 0, ncy - 1);
+            const int ccz = (D == 3) ? iclampi(Cz, 0, ncz - 1) : 0;
+            v[k] = ec[((long long)ccz * ncy + ccy) * ncx + ccx];
+        }
+#pragma unroll
+        for (int k = 0; k < KE; ++k) {
+            const int idx = (int)threadIdx.x + k * NT;
+            if (idx < NE) se[idx] = masked(in[k], v[k]);
+        }
     }
     __syncthreads();
 
-    for (int idx = threadIdx.x; idx < NW; idx += NT) {
+    constexpr int KW = (NW + NT - 1) / NT;
+    cx<T> lu1[KW];
+#pragma unroll
+    for (int k = 0; k < KW; ++k) {
+        const int idx = (int)threadIdx.x + k * NT;
+        const int id = idx < NW ? idx : NW - 1;
+        const int lx = id % WX;
+        const int rr = id / WX;
+        const int ly = rr % WY;
+        const int lz = rr / WY;
+        const int gx = iclampi(x0 - 1 + lx, 0, nx - 1), gy = iclampi(y0 - 1 + ly, 0, ny - 1);
+        const int gz = (D == 3) ? iclampi(z0 - 1 + lz, 0, nz - 1) : 0;
+        lu1[k] = u1p[((long long)gz * ny + gy) * nx + gx];
+    }
+#pragma unroll
+    for (int k = 0; k < KW; ++k) {
+        const int idx = (int)threadIdx.x + k * NT;
+        if (idx >= NW) break;
         const int lx = idx % WX;
         const int rr = idx / WX;
         const int ly = rr % WY;
@@ -608,7 +640,6 @@ __global__ void __launch_bounds__(NT) k_sm_prolong_resid(const CycleArgs a) {
         const int gz = (D == 3) ? z0 - 1 + lz : 0;
         cx<T> u2 = mk<T>(0, 0);
         if (gx >= 0 && gx < nx && gy >= 0 && gy < ny && (D == 2 || (gz >= 0 && gz < nz))) {
-            const long long g = ((long long)gz * ny + gy) * nx + gx;
             int ix0, ix1, iy0, iy1;
             T wx0, wx1, wy0, wy1;
             interp_1d<T>(gx, cxs, ix0, ix1, wx0, wx1);
@@ -628,7 +659,7 @@ __global__ void __launch_bounds__(NT) k_sm_prolong_resid(const CycleArgs a) {
                      (wz1 * wy0 * wx0) * se[p10 + ix0] + (wz1 * wy0 * wx1) * se[p10 + ix1] +
                      (wz1 * wy1 * wx0) * se[p11 + ix0] + (wz1 * wy1 * wx1) * se[p11 + ix1];
             }
-            u2 = u1p[g] + pe;
+            u2 = lu1[k] + pe;
         }
         s2[idx] = u2;
     }
@@ -636,7 +667,27 @@ __global__ void __launch_bounds__(NT) k_sm_prolong_resid(const CycleArgs a) {
 
     const auto u2p = gout(static_cast<cx<T>*>(B.u2));
     const auto q0p = gout(static_cast<cx<T>*>(B.q[0]));
-    for (int idx = threadIdx.x; idx < TX * TY * TZE; idx += NT) {
+    constexpr int NO = TX * TY * TZE, KO = (NO + NT - 1) / NT;
+    T lk2[KO];
+    cx<T> lf[KO];
+#pragma unroll
+    for (int k = 0; k < KO; ++k) {
+        const int idx = (int)threadIdx.x + k * NT;
+        const int id = idx < NO ? idx : NO - 1;
+        const int lx = id % TX;
+        const int rr = id / TX;
+        const int ly = rr % TY;
+        const int lz = rr / TY;
+        const int gx = imin3(x0 + lx, nx - 1), gy = imin3(y0 + ly, ny - 1);
+        const int gz = (D == 3) ? imin3(z0 + lz, nz - 1) : 0;
+        const long long g = ((long long)gz * ny + gy) * nx + gx;
+        lk2[k] = L.k2[g];
+        lf[k] = cvt<T>(f[g]);
+    }
+#pragma unroll
+    for (int k = 0; k < KO; ++k) {
+        const int idx = (int)threadIdx.x + k * NT;
+        if (idx >= NO) break;
         const int lx = idx % TX;
         const int rr = idx / TX;
         const int ly = rr % TY;
@@ -647,11 +698,11 @@ __global__ void __launch_bounds__(NT) k_sm_prolong_resid(const CycleArgs a) {
             const long long g = ((long long)gz * ny + gy) * nx + gx;
             const int c = ((D == 3 ? lz + 1 : 0) * WY + (ly + 1)) * WX + (lx + 1);
             const cx<T> u2c = s2[c];
-            cx<T> au = diag_at<D>(L, gx, gy, gz, L.k2[g]) * u2c + L.cm[0][gx] * s2[c - 1] +
+            cx<T> au = diag_at<D>(L, gx, gy, gz, lk2[k]) * u2c + L.cm[0][gx] * s2[c - 1] +
                        L.cp[0][gx] * s2[c + 1] + L.cm[1][gy] * s2[c - WX] + L.cp[1][gy] * s2[c + WX];
             if constexpr (D == 3) au = au + L.cm[2][gz] * s2[c - WX * WY] + L.cp[2][gz] * s2[c + WX * WY];
             u2p[g] = u2c;
-            q0p[g] = fs * cvt<T>(f[g]) - au;
+            q0p[g] = fs * lf[k] - au;
         }
     }
 }
