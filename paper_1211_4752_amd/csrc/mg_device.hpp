@@ -344,9 +344,10 @@ hipError_t launch_sweep_ps(int dim, bool f32, bool level0, bool accumulate, int 
 // per thread, between 1 and 1024.
 int vec_blocks(long long N, int per = 8);
 // Chunks per slot of the Arnoldi passes on an n[0] x n[1] (x n[2]) grid,
-// about per points per thread each.  Matvec pass in 2D (mv): column blocks
-// of NT times row strips of at most per rows, numbered strip-fastest;
-// otherwise contiguous ranges of the N points, at most 1024 * ARN_SPLIT.
+// about per points per thread each.  Matvec pass (mv) in 2D: column blocks
+// of NT times row strips of at most per rows, numbered strip-fastest; in
+// 3D: the z-march columns of power_z_tiles (per unused); otherwise
+// contiguous ranges of the N points, at most 1024 * ARN_SPLIT.
 int arnoldi_chunks(bool mv, int dim, const int n[3], long long N, int per);
 hipError_t launch_residual(int dim, const VecArgs& a, hipStream_t s);
 hipError_t launch_norm(const VecArgs& a, hipStream_t s);

@@ -186,10 +186,14 @@ __device__ __forceinline__ ChunkItem item_at(const ChunkItem* item, int k) {
     return ChunkItem{__builtin_amdgcn_readfirstlane(x.slot), __builtin_amdgcn_readfirstlane(x.c)};
 }
 
+__device__ __forceinline__ int clampi3(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
+
 // w = A z, h_i = <v_i, w>: one partial per chunk.
 template <int D, int MAXJ>
 __global__ void __launch_bounds__(NT) k_matvec_dot(const VecArgs a) {
+    static_assert(D == 2 || PZX * PZY == NT, "one point of a 3D column per thread");
     __shared__ cx<double> sm[(NT / 64) * MAXJ];
+    __shared__ cx<double> P[D == 3 ? 2 * PZW * PZH : 1];   // 3D: a plane and its ring, two buffers
     __shared__ double ssc[MAXJ];   // scale_i, read at the end from LDS
     __shared__ ChunkItem item[ARN_SPLIT];
     __shared__ int sh[NT / 64], nitem;
@@ -249,28 +253,73 @@ __global__ void __launch_bounds__(NT) k_matvec_dot(const VecArgs a) {
                 }
             }
         } else {
-            int lo, hi;
-            chunk_range(N, sl.nc, c, lo, hi);
-            // grid coordinates of p, carried forward by NT points per iteration
-            int p = lo + (int)threadIdx.x;
-            int gx = p % nx, gy = (p / nx) % ny, gz = p / nx / ny;
-            for (; p < hi; p += NT) {
+            // 3D: chunk c is a column of PZX x PZY points through up to PZC
+            // planes; plane zz with its one-point ring goes through LDS, the
+            // planes zz +- 1 of each point stay in registers, and the next
+            // plane's inputs are requested first (the terms of apply_at, in
+            // its order)
+            int ntx, nty, ntz;
+            pz_counts(L.n, ntx, nty, ntz);
+            const int nz = L.n[2];
+            const long long nxy = (long long)nx * ny;
+            const int tx = c % ntx, ty = (c / ntx) % nty, tz = c / (ntx * nty);
+            const int x0 = tx * PZX, y0 = ty * PZY, z0 = tz * PZC;
+            const int z1 = z0 + PZC < nz ? z0 + PZC : nz;
+            const int t = (int)threadIdx.x;
+            const int lx = t % PZX, ly = t / PZX;
+            const int gx = x0 + lx, gy = y0 + ly;
+            const bool own = gx < nx && gy < ny;
+            const int cgx = gx < nx ? gx : nx - 1, cgy = gy < ny ? gy : ny - 1;
+            const long long pxy = (long long)cgy * nx + cgx;
+            const bool ring = t < PZR;
+            int rlx = 0, rly = 0;
+            pz_ring(ring ? t : 0, rlx, rly);
+            const int rgx = clampi3(x0 + rlx - 1, 0, nx - 1), rgy = clampi3(y0 + rly - 1, 0, ny - 1);
+            const long long rxy = (long long)rgy * nx + rgx;
+            auto plane = [&](int q) { return (long long)clampi3(q, 0, nz - 1) * nxy; };
+            const cx<double> cmx = L.cm[0][cgx], cpx = L.cp[0][cgx], c0x = L.c0[0][cgx];
+            const cx<double> cmy = L.cm[1][cgy], cpy = L.cp[1][cgy], c0y = L.c0[1][cgy];
+            const bool bxm = gx > 0, bxp = gx < nx - 1, bym = gy > 0, byp = gy < ny - 1;
+            const int ci = (ly + 1) * PZW + lx + 1;
+            cx<double> xm = z[plane(z0 - 1) + pxy], xc = z[plane(z0) + pxy], xp = z[plane(z0 + 1) + pxy];
+            cx<double> rc = z[plane(z0) + rxy];
+            double k2c = L.k2[plane(z0) + pxy];
+            for (int zz = z0; zz < z1; ++zz) {
+                const long long p = (long long)zz * nxy + pxy;
                 // the basis loads do not depend on the stencil: issue them first
                 cx<double> vv[MAXJ];
 #pragma unroll
                 for (int i = 0; i < MAXJ; ++i) vv[i] = (i < nv) ? V[(long long)i * N + p] : mk(0.0, 0.0);
-                const cx<double> wv = apply_at<D>(L, z, p, gx, gy, gz);
-                w[p] = wv;
+                const cx<double> xn = z[plane(zz + 2) + pxy];
+                const cx<double> rn = z[plane(zz + 1) + rxy];
+                const double k2n = L.k2[plane(zz + 1) + pxy];
+                const cx<double> cmz = L.cm[2][zz], cpz = L.cp[2][zz], c0z = L.c0[2][zz];
+                cx<double>* Pb = P + (zz & 1) * (PZW * PZH);
+                Pb[ci] = xc;
+                if (ring) Pb[rly * PZW + rlx] = rc;
+                __syncthreads();
+                const bool bzm = zz > 0, bzp = zz < nz - 1;
+                cx<double> d = c0x + c0y;
+                d = d + c0z;
+                d = d - k2c * L.sigma;
+                cx<double> ax = d * xc;
+                ax = ax + masked(bxm, cmx) * Pb[ci - 1];
+                ax = ax + masked(bxp, cpx) * Pb[ci + 1];
+                ax = ax + masked(bym, cmy) * Pb[ci - PZW];
+                ax = ax + masked(byp, cpy) * Pb[ci + PZW];
+                ax = ax + masked(bzm, cmz) * xm;
+                ax = ax + masked(bzp, cpz) * xp;
+                const cx<double> wv = 1.0 * ax;
+                if (own) {
+                    w[p] = wv;
 #pragma unroll
-                for (int i = 0; i < MAXJ; ++i) acc[i] = acc[i] + cmulc(vv[i], wv);
-                gx += NT;
-                while (gx >= nx) {
-                    gx -= nx;
-                    if (++gy == ny) {
-                        gy = 0;
-                        ++gz;
-                    }
+                    for (int i = 0; i < MAXJ; ++i) acc[i] = acc[i] + cmulc(vv[i], wv);
                 }
+                xm = xc;
+                xc = xp;
+                xp = xn;
+                rc = rn;
+                k2c = k2n;
             }
         }
 #pragma unroll
@@ -486,6 +535,7 @@ void tile_counts(int dim, int shape, const int n[3], int ntiles[3]) {
 }
 
 int arnoldi_chunks(bool mv, int dim, const int n[3], long long N, int per) {
+    if (mv && dim == 3) return power_z_tiles(n);
     if (per < 1) per = 1;
     if (mv && dim == 2) {
         const int ncb = (n[0] + NT - 1) / NT;
