@@ -566,7 +566,7 @@ def main():
                     help="cap on GMRES steps per solve (a capped solve is reported as not converged)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path (the batch of "
+        print("bench.py runs on one GPU only: the library has no multi-GPU path (the batch of "
               "right-hand sides would shard across GPUs without communication).", file=sys.stderr)
         sys.exit(2)
 

@@ -103,7 +103,7 @@ typedef struct mg_params {
                                (sigma = 1); standalone mode and mg_cycle then
                                iterate u <- u + M (f - A u)                  */
     double theta_max;       /* default schedule sigma_l = exp(i l theta_max/L) */
-    int nu1, nu2;           /* smoothing sweeps; this build supports 1, 1    */
+    int nu1, nu2;           /* smoothing sweeps; the library supports 1, 1   */
     double omega[2];        /* complex Jacobi weight (re, im)                */
     int precision;          /* enum mg_precision                             */
     int nrhs;               /* right-hand sides handled by every call (>= 1) */

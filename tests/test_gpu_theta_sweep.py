@@ -4,7 +4,7 @@ GMRES(3) smoother as a standalone solver, constant k, 7 levels, rtol 1e-7).
 Workload reading: the paper's unit physical domain with n = 128 points and
 an ECS layer of n/4 points on each side becomes here a 255^2 grid whose
 middle half is the physical region (layers of 64 cells inside the grid, as
-everywhere in this build) with k h = 30/128 — the same k h, the same 7
+in every workload here) with k h = 30/128 — the same k h, the same 7
 levels and d-theta = theta_max / 7 as the table.  The GPU iteration counts
 and histories are held to the oracle on the same workload; the paper's
 printed counts (tests/golden/table5_theta_sweep.json) are shown beside them
