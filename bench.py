@@ -506,6 +506,16 @@ def paper_models(mg, W, torch, dev):
     return rows
 
 
+def force_shapes(s, arg):
+    """--shapes a,b,c: set the tile shape of each level (so that separate
+    profiler runs of one workload use the same kernels)."""
+    if not arg:
+        return
+    for l, sh in enumerate(int(x) for x in arg.split(",")):
+        if l < s.num_levels:
+            s.tile_shape(l, sh)
+
+
 def only(args, mg, W, torch, dev):
     """A single workload, for profiler runs: one solve after the warm-up."""
     res = {}
@@ -515,6 +525,7 @@ def only(args, mg, W, torch, dev):
                       ecs_angle=wl.ecs_angle, theta_max=wl.theta_max, nrhs=NRHS, smoother=SMOOTHER,
                       precision=args.precision)
         f = torch.tensor(wl.f, dtype=torch.complex128, device=dev)
+        force_shapes(s, args.shapes)
         u = s.empty()
         st, its, _, dt, prof = timed_solve(torch, s, u, f, "gmres", RTOL, args.maxit, profile=True,
                                            graph_time=False)
@@ -525,6 +536,7 @@ def only(args, mg, W, torch, dev):
                       ecs_angle=wl.ecs_angle, theta_max=wl.theta_max, nrhs=1, smoother=args.only[3:],
                       precision=args.precision)
         f = torch.tensor(wl.f, dtype=torch.complex128, device=dev)
+        force_shapes(s, args.shapes)
         u = s.empty()
         st, its, _, dt, prof = timed_solve(torch, s, u, f, "gmres", RTOL, args.maxit, profile=True,
                                            graph_time=False)
@@ -540,6 +552,7 @@ def only(args, mg, W, torch, dev):
                       ecs_angle=wl.ecs_angle, theta_max=wl.theta_max, nrhs=64, smoother="jacobi",
                       precision=args.precision)
         f = torch.tensor(wl.f, dtype=torch.complex128, device=dev)
+        force_shapes(s, args.shapes)
         u = s.empty()
         st, its, _, dt, prof = timed_solve(torch, s, u, f, "gmres", RTOL, args.maxit, profile=True,
                                            graph_time=False)
@@ -562,6 +575,7 @@ def main():
     ap.add_argument("--light", action="store_true", help="with --only c3_*: one solve, no FP64 references")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain device copy of 1 GiB four times (counter calibration)")
+    ap.add_argument("--shapes", default=None, help="with --only: tile shape per level, comma-separated")
     ap.add_argument("--maxit", type=int, default=MAXIT,
                     help="cap on GMRES steps per solve (a capped solve is reported as not converged)")
     args = ap.parse_args()
