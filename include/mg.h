@@ -204,9 +204,10 @@ mg_status mg_apply(mg_ctx *c, int level, int adjoint, const double *x_dev,
  * rows with 320, 576, 320 threads; 3D: columns of 64x8, 32x8, 64x4 points
  * sweeping chunks of 16 planes with 768, 448, 384 threads), with tile shape
  * 0 for the kernels that start from a given iterate.  On the finest level of
- * a 3D GMRES(3) context the power and Gram passes (and in every 3D context
- * the Arnoldi matvec pass) march columns of 64x4 points through 32 planes
- * whatever the shape; the shape sets the tiles of its apply passes.
+ * a 3D GMRES(3) context the power, Gram and pre-smoothing apply passes (and
+ * in every 3D context the Arnoldi matvec pass) march columns of 64x4 points
+ * through 32 planes whatever the shape; the shape sets the tiles of its
+ * prolongation pass.
  * mg_setup picks one per level by timing every shape on the level's own
  * arrays, the level's passes
  * replayed as a graph (levels of at least 1024 points above the coarse

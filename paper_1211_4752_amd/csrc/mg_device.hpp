@@ -399,6 +399,9 @@ hipError_t launch_sm_gram(int dim, bool f32, bool level0, const SmArgs& a, hipSt
 hipError_t launch_sm_coef(bool f32, const SmCoefArgs& a, int nslots, hipStream_t s);
 hipError_t launch_sm_apply_restrict(int dim, bool f32, bool level0, bool nonzero, int shape, const CycleArgs& a,
                                     hipStream_t s);
+// 3D finest level: the same pass as a z-march over the columns of the power
+// passes (power_z_tiles(n) workgroups per slot, tile0 counting them).
+hipError_t launch_sm_apply_restrict_z(bool f32, bool nonzero, const CycleArgs& a, hipStream_t s);
 hipError_t launch_sm_prolong_resid(int dim, bool f32, bool level0, int shape, const CycleArgs& a, hipStream_t s);
 hipError_t launch_sm_apply_out(bool f32, bool level0, bool accumulate, const SmArgs& a, hipStream_t s);
 // 2D passes as row-marching wavefronts (mg_march2d.hip): a tile is a strip

@@ -1261,9 +1261,13 @@ mg_status rec_pre_g(Rec& R, int dir, const std::vector<Item>& it, int gk, const 
         s.sb = sbuf(c, d, I.rhs);
         s.gate = ss[q].gate;
         s.tile0 = tiles;
-        int nt[3];
-        mg::tile_counts(R.dim, shape, c->lv[d].n, nt);
-        tiles += nt[0] * nt[1] * nt[2];
+        if (d == 0) {   // the finest level marches along z
+            tiles += mg::power_z_tiles(c->lv[d].n);
+        } else {
+            int nt[3];
+            mg::tile_counts(R.dim, shape, c->lv[d].n, nt);
+            tiles += nt[0] * nt[1] * nt[2];
+        }
         const double q0b = (d == 0 && !nz) ? 16.0 : ct;
         ib.push_back({k, c->lv[d].N * (q0b + 3.0 * ct + sk + (nz ? 16.0 : 0.0)) + c->lv[d + 1].N * ct, 0.0});
     }
@@ -1276,6 +1280,7 @@ mg_status rec_pre_g(Rec& R, int dir, const std::vector<Item>& it, int gk, const 
     add(R, d == 0 ? MG_K_SMOOTH_RESTRICT_FINE : MG_K_COARSE_LEVELS, ib, [=](hipStream_t s, const char* base) {
         mg::CycleArgs b = a;
         b.st.s = (const mg::CycleSlot*)(base + off);
+        if (d == 0) return mg::launch_sm_apply_restrict_z(mixed, nz, b, s);
         return mg::launch_sm_apply_restrict(dim, mixed, d == 0, nz, shape, b, s);
     });
     return MG_OK;

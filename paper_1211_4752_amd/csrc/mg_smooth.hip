@@ -17,6 +17,7 @@
 //   k_sm_coef        fixed-order reduction, 3 x 3 solve, coefficients on device
 //   pre-smoothing:   k_sm_apply_restrict: u1 and r_new (q3 on an LDS tile),
 //                    full-weighting restriction of r_new to the next level
+//                    (k_sm_apply_restrict_z on the finest 3D level)
 //   post-smoothing:  k_sm_prolong_resid (before the passes above): u2 = u1 +
 //                    P e and q0 = f - A u2 through an LDS tile; k_sm_apply_out
 //                    (after them): the smoothed iterate.
@@ -555,6 +556,223 @@ __global__ void __launch_bounds__(NT) k_sm_apply_restrict(const CycleArgs a) {
 }
 
 // ---------------------------------------------------------------------------
+// The same pre-smoothing end on the finest 3D level as a z-march over the
+// columns of the power passes (PZX x PZY points, up to PZC planes).  Per
+// plane: q2 of the plane with a ring goes through LDS (its z neighbours stay
+// in registers), r1 is formed on the column and on its high x and y edges
+// (the fine points that the restriction of the column's coarse points
+// reaches beyond it), u1 on the column; the coarse points of the column take
+// the 9 in-plane terms of each of their three fine planes as the planes go by
+// (the march runs one plane past its chunk for the last of them), in the
+// order of the tile form.  Every input value is fetched from HBM about once.
+// ---------------------------------------------------------------------------
+template <typename T, typename TQ, bool NZ>
+__global__ void __launch_bounds__(NT) k_sm_apply_restrict_z(const CycleArgs a) {
+    constexpr int QW = PZX + 3, QH = PZY + 3;    // q2 plane: x in [-1, PZX + 1], y in [-1, PZY + 1]
+    constexpr int RW = PZX + 1, RH = PZY + 1;    // r1 plane: x in [0, PZX], y in [0, PZY]
+    constexpr int NE = RW * RH - PZX * PZY;      // r1 points on the column's high x and y edges
+    constexpr int NRG = QW * QH - RW * RH;       // q2 points around the r1 plane
+    constexpr int CXN = PZX / 2, CYN = PZY / 2;  // coarse columns whose centre lies in the column
+    static_assert(PZX * PZY == NT && PZX % 2 == 0 && PZY % 2 == 0 && PZC % 2 == 0, "column geometry");
+    static_assert(NE == PZX + PZY + 1 && NE <= NT && NRG <= NT && CXN * CYN <= NT, "plane geometry");
+    __shared__ cx<T> Q[2][QW * QH];
+    __shared__ cx<T> R[2][RW * RH];
+    __shared__ cx<T> CXS[3][QW], CYS[3][QH];   // cm, c0, cp of the column's x and y positions
+
+    const int pid = xcd_remap(blockIdx.x, gridDim.x);
+    const int slot = find_slot(a.st.s, a.st.n, pid);
+    const CycleSlot sl = a.st.s[slot];
+    if (gated_off(sl.gate)) return;
+    const LevelView<T>* Lp = static_cast<const LevelView<T>*>(sl.lv);
+    const GLevel<T> L = glevel(*Lp);
+    const SmoothBufs B = *sl.sb;
+    const int nx = L.n[0], ny = L.n[1], nz = L.n[2];
+    const long long nxy = (long long)nx * ny;
+    int ntx, nty, ntz;
+    pz_counts(L.n, ntx, nty, ntz);
+    const int b = pid - sl.tile0;
+    const int tx = b % ntx, ty = (b / ntx) % nty, tz = b / (ntx * nty);
+    const int x0 = tx * PZX, y0 = ty * PZY, z0 = tz * PZC;
+    const int z1 = imin3(z0 + PZC, nz);
+    const int zl = z1 < nz ? z1 : nz - 1;   // last plane of the march
+    const auto q2p = gin(static_cast<const cx<T>*>(B.q[2]));
+    const auto q1p = gin(static_cast<const cx<T>*>(B.q[1]));
+    const auto q0p = gin(static_cast<const cx<T>*>(B.q[0]));
+    const auto f = gin(static_cast<const cx<TQ>*>(sl.f));
+    const bool from_f = sl.f != nullptr;
+    const T fs = (T)fscale_of(sl);
+    const auto up = gin(static_cast<const cx<T>*>(sl.u));
+    const auto u1p = gout(static_cast<cx<T>*>(B.u1));
+    cx<T> c1, c2, c3;
+    load_coef<T>(B.coef, c1, c2, c3);
+    auto plane = [&](int z) { return (long long)iclampi(z, 0, nz - 1) * nxy; };
+    for (int i = (int)threadIdx.x; i < 3 * (QW + QH); i += NT) {
+        const int w = i < 3 * QW ? i / QW : (i - 3 * QW) / QH;
+        const int ax = i < 3 * QW ? 0 : 1;
+        const int j = i < 3 * QW ? i % QW : (i - 3 * QW) % QH;
+        const int g = ax == 0 ? iclampi(x0 + j - 1, 0, nx - 1) : iclampi(y0 + j - 1, 0, ny - 1);
+        const cx<T> v = w == 0 ? L.cm[ax][g] : (w == 1 ? L.c0[ax][g] : L.cp[ax][g]);
+        if (ax == 0) CXS[w][j] = v;
+        else CYS[w][j] = v;
+    }
+    auto q0_at = [&](long long i) { return from_f ? fs * cvt<T>(f[i]) : q0p[i]; };
+
+    const int t = (int)threadIdx.x;
+    // a point of the r1 plane: mask, grid index (clamped for loads) and LDS
+    // positions
+    struct Pt {
+        bool in;
+        long long xy;
+        int qx, qy, qc, rc;
+    };
+    auto pt_of = [&](int lx, int ly) {
+        Pt p;
+        const int gx = x0 + lx, gy = y0 + ly;
+        p.in = gx < nx && gy < ny;
+        p.xy = (long long)imin3(gy, ny - 1) * nx + imin3(gx, nx - 1);
+        p.qx = lx + 1;
+        p.qy = ly + 1;
+        p.qc = p.qy * QW + p.qx;
+        p.rc = ly * RW + lx;
+        return p;
+    };
+    const Pt po = pt_of(t % PZX, t / PZX);
+    // the edge points go to the last NE threads, the ring to the first NRG,
+    // the coarse columns to the second wavefront: the waves share the extra work
+    const int te = t - (NT - NE);
+    const bool has_e = te >= 0;
+    const Pt pe = pt_of(te >= 0 && te < PZX ? te : PZX, te >= 0 && te < PZX ? PZY : iclampi(te - PZX, 0, PZY));
+    // q2 ring point of this thread (t < NRG), in LDS plane coordinates
+    const bool has_r = t < NRG;
+    int rqx, rqy;
+    {
+        const int r = has_r ? t : 0;
+        if (r < QH) {
+            rqx = 0;
+            rqy = r;
+        } else if (r < 2 * QH) {
+            rqx = QW - 1;
+            rqy = r - QH;
+        } else if (r < 2 * QH + QW - 2) {
+            rqx = r - 2 * QH + 1;
+            rqy = 0;
+        } else {
+            rqx = r - 2 * QH - (QW - 2) + 1;
+            rqy = QH - 1;
+        }
+    }
+    const int rgx = x0 + rqx - 1, rgy = y0 + rqy - 1;
+    const bool rin = rgx >= 0 && rgx < nx && rgy >= 0 && rgy < ny;
+    const long long rxy = (long long)iclampi(rgy, 0, ny - 1) * nx + iclampi(rgx, 0, nx - 1);
+
+    // registers: q2 of planes z-1, z, z+1 (and z+2 in flight), q0, q1, k2 (u)
+    // of plane z (and z+1 in flight), for the column point (o) and the edge
+    // point (e); the ring's q2 of plane z (and z+1)
+    cx<T> om = masked(po.in, q2p[plane(z0 - 1) + po.xy]), oc = masked(po.in, q2p[plane(z0) + po.xy]);
+    cx<T> op = masked(po.in, q2p[plane(z0 + 1) + po.xy]);
+    cx<T> em = masked(pe.in, q2p[plane(z0 - 1) + pe.xy]), ec = masked(pe.in, q2p[plane(z0) + pe.xy]);
+    cx<T> ep = masked(pe.in, q2p[plane(z0 + 1) + pe.xy]);
+    cx<T> o0 = q0_at(plane(z0) + po.xy), o1 = q1p[plane(z0) + po.xy];
+    cx<T> e0 = q0_at(plane(z0) + pe.xy), e1 = q1p[plane(z0) + pe.xy];
+    T ok2 = L.k2[plane(z0) + po.xy], ek2 = L.k2[plane(z0) + pe.xy];
+    cx<T> ou = mk<T>(0, 0);
+    if constexpr (NZ) ou = up[plane(z0) + po.xy];
+    cx<T> rcv = masked(rin, q2p[plane(z0) + rxy]);
+
+    // restriction: coarse column (Cx, Cy) of this thread (t < CXN * CYN)
+    const int ncx = Lp[1].n[0], ncy = Lp[1].n[1], ncz = Lp[1].n[2];
+    const int tc = t - 64;
+    const int cxl = (tc & 0xffff) % CXN, cyl = ((tc & 0xffff) / CXN) % CYN;
+    const int Cx = x0 / 2 + cxl, Cy = y0 / 2 + cyl;
+    const bool cown = tc >= 0 && tc < CXN * CYN && Cx < ncx && Cy < ncy;
+    const auto fc = gout(static_cast<cx<T>*>(sl.c));
+    cx<T> acc = mk<T>(0, 0);
+    // the 9 in-plane terms of fine plane oz (-1, 0, 1) of a coarse point
+    auto terms = [&](const cx<T>* Rb, int oz) {
+        const T wz = oz == 0 ? T(0.5) : T(0.25);
+#pragma unroll
+        for (int oy = -1; oy <= 1; ++oy) {
+            const T wy = wz * (oy == 0 ? T(0.5) : T(0.25));
+            const int row = (2 * cyl + 1 + oy) * RW + 2 * cxl + 1;
+#pragma unroll
+            for (int ox = -1; ox <= 1; ++ox) {
+                const T w = wy * (ox == 0 ? T(0.5) : T(0.25));
+                acc = acc + w * Rb[row + ox];
+            }
+        }
+    };
+
+    for (int z = z0; z <= zl; ++z) {
+        // inputs of the next plane first
+        const cx<T> on = masked(po.in, q2p[plane(z + 2) + po.xy]);
+        const cx<T> en = masked(pe.in, q2p[plane(z + 2) + pe.xy]);
+        const cx<T> o0n = q0_at(plane(z + 1) + po.xy), o1n = q1p[plane(z + 1) + po.xy];
+        const cx<T> e0n = q0_at(plane(z + 1) + pe.xy), e1n = q1p[plane(z + 1) + pe.xy];
+        const T ok2n = L.k2[plane(z + 1) + po.xy], ek2n = L.k2[plane(z + 1) + pe.xy];
+        cx<T> oun = mk<T>(0, 0);
+        if constexpr (NZ) oun = up[plane(z + 1) + po.xy];
+        const cx<T> rn = masked(rin, q2p[plane(z + 1) + rxy]);
+        const cx<T> cmz = L.cm[2][z], cpz = L.cp[2][z], c0z = L.c0[2][z];
+        const bool bzm = z > 0, bzp = z < nz - 1;
+        cx<T>* Qb = Q[z & 1];
+        cx<T>* Rb = R[z & 1];
+        Qb[po.qc] = oc;
+        if (has_e) Qb[pe.qc] = ec;
+        if (has_r) Qb[rqy * QW + rqx] = rcv;
+        __syncthreads();
+        // r1 (and u1 on the column) at a point of the plane
+        auto form = [&](const Pt& p, cx<T> q2m, cx<T> q2c, cx<T> q2pp, cx<T> q0, cx<T> q1, T k2, bool col,
+                        cx<T> u) {
+            cx<T> d = CXS[1][p.qx] + CYS[1][p.qy];
+            d = d + c0z;
+            d = d - k2 * L.sigma;
+            cx<T> aq = d * q2c + CXS[0][p.qx] * Qb[p.qc - 1] + CXS[2][p.qx] * Qb[p.qc + 1] +
+                       CYS[0][p.qy] * Qb[p.qc - QW] + CYS[2][p.qy] * Qb[p.qc + QW];
+            aq = aq + masked(bzm, cmz) * q2m + masked(bzp, cpz) * q2pp;
+            const cx<T> q3 = L.sinv * aq;
+            const cx<T> r = q0 + c1 * q1 + c2 * q2c + c3 * q3;
+            Rb[p.rc] = masked(p.in, r);
+            if (col && p.in && z < z1) {
+                cx<T> v = L.sinv * (c1 * q0 + c2 * q1 + c3 * q2c);
+                if constexpr (NZ) v = u - v;
+                else v = mk<T>(0, 0) - v;
+                u1p[(long long)z * nxy + p.xy] = v;
+            }
+        };
+        form(po, om, oc, op, o0, o1, ok2, true, ou);
+        if (has_e) form(pe, em, ec, ep, e0, e1, ek2, false, ou);
+        __syncthreads();
+        if (cown) {
+            if ((z & 1) == 0) {
+                const int Ce = z / 2 - 1;   // its third plane
+                if (z > z0) {
+                    terms(Rb, 1);
+                    if (Ce < ncz) fc[((long long)Ce * ncy + Cy) * ncx + Cx] = acc;
+                }
+                acc = mk<T>(0, 0);
+                if (z < z0 + PZC && z / 2 < ncz) terms(Rb, -1);   // its first plane
+            } else {
+                terms(Rb, 0);
+            }
+        }
+        om = oc;
+        oc = op;
+        op = on;
+        em = ec;
+        ec = ep;
+        ep = en;
+        o0 = o0n;
+        o1 = o1n;
+        e0 = e0n;
+        e1 = e1n;
+        ok2 = ok2n;
+        ek2 = ek2n;
+        ou = oun;
+        rcv = rn;
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Post-smoothing start: u2 = u1 + P e through an LDS tile (e on the coarse
 // points around the tile, u2 on [-1, T]); writes u2 and q0 = fscale f - A u2
 // on the tile.  Slot fields: f, fscale, c (coarse correction e), sb.
@@ -830,6 +1048,21 @@ hipError_t launch_sm_apply_restrict(int dim, bool f32, bool level0, bool nonzero
                        : ar_launch<double, double, false>(dim, shape, a, s);
     if (nonzero) return hipErrorInvalidValue;   // the complex64 cycle always starts from zero
     return level0 ? ar_launch<float, double, false>(dim, shape, a, s) : ar_launch<float, float, false>(dim, shape, a, s);
+}
+
+hipError_t launch_sm_apply_restrict_z(bool f32, bool nonzero, const CycleArgs& a, hipStream_t s) {
+    if (a.st.n <= 0) return hipSuccess;
+    dim3 grid(a.st.ntiles);
+    if (!f32) {
+        if (nonzero)
+            hipLaunchKernelGGL((k_sm_apply_restrict_z<double, double, true>), grid, dim3(NT), 0, s, a);
+        else
+            hipLaunchKernelGGL((k_sm_apply_restrict_z<double, double, false>), grid, dim3(NT), 0, s, a);
+    } else {
+        if (nonzero) return hipErrorInvalidValue;   // the complex64 cycle always starts from zero
+        hipLaunchKernelGGL((k_sm_apply_restrict_z<float, double, false>), grid, dim3(NT), 0, s, a);
+    }
+    return hipGetLastError();
 }
 
 template <typename T, typename TF>
